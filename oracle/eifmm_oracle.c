@@ -1,0 +1,1007 @@
+/*
+ * eifmm_oracle.c -- plain CPU FP64 oracle for the EIFMM evaluation pass.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only users of this library.  It shares
+ * no code, header, table or helper with the HIP library in
+ * paper_1408_0210_amd/csrc, and the product path never loads it.
+ *
+ * Written from F. Casenave, "A Fast Summation Method for translation invariant
+ * kernels" (arXiv:1408.0210).  Every routine is plain loops in double precision,
+ * in the order the paper states the computation:
+ *
+ *   orc_direct       eq. (1): f(x_i) = sum_j sigma_j K(x_i, y_j)
+ *   orc_tree         Sec. 3.3: uniform 2^D-tree with kappa+1 levels (Morton keys)
+ *   orc_lists        Sec. 3.2 (neighbourhood N(I)) and Sec. 3.3.2 (interaction list)
+ *   orc_training_sets Sec. 2 (training sets D_x,trial, D_y,trial; the paper leaves
+ *                    them unspecified -- the construction below is a documented reading)
+ *   orc_eim          Algorithm 1 (greedy EIM), the Gamma recursion of Sec. 2,
+ *                    stopping rule on eps_k (end of Sec. 2)
+ *   orc_plan_eval    Algorithm 3 (multilevel EIFMM) plus the near field of
+ *                    eq. (13), with Delta applied by triangular solves (Sec. 4.1)
+ *
+ * Kernel convention: K(x, y) = k(x - y) (translation invariant, Sec. 3.1).
+ * Singular kernels skip every pair at exactly zero distance (self term excluded).
+ *
+ * Return codes: 0 ok, -1 invalid argument, -2 point outside the closed domain or
+ * not finite, -4 EIM reached dmax before the tolerance, -5 out of memory.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+  ORC_LAPLACE = 0, /* 1/r                                 */
+  ORC_YUKAWA = 1,  /* exp(-a r)/r,      p[0] = a          */
+  ORC_GAUSS = 2,   /* exp(-r^2/h2),     p[0] = h2         */
+  ORC_SQDIST = 3,  /* r^2 (finite rank 5)                 */
+  ORC_COSR = 4,    /* cos(w r)/r,       p[0] = w          */
+  ORC_MQ = 5,      /* sqrt(r^2 + c),    p[0] = c          */
+  ORC_COSDOT = 6,  /* cos(w . z) (finite rank 2)          */
+  ORC_EXPDOT = 7   /* exp(a . z) (rank 1, not symmetric)  */
+};
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_EDOMAIN (-2)
+#define ORC_EEIM (-4)
+#define ORC_ENOMEM (-5)
+
+typedef struct {
+  int kind;
+  double p[3];
+} okern;
+
+static int k_singular(int kind) {
+  return kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_COSR;
+}
+
+/* k(z); the squared norm is summed x, y, z in that order. */
+static double k_eval(const okern *K, double zx, double zy, double zz) {
+  double r2 = zx * zx + zy * zy + zz * zz;
+  switch (K->kind) {
+  case ORC_LAPLACE:
+    return 1.0 / sqrt(r2);
+  case ORC_YUKAWA: {
+    double r = sqrt(r2);
+    return exp(-K->p[0] * r) / r;
+  }
+  case ORC_GAUSS:
+    return exp(-r2 / K->p[0]);
+  case ORC_SQDIST:
+    return r2;
+  case ORC_COSR: {
+    double r = sqrt(r2);
+    return cos(K->p[0] * r) / r;
+  }
+  case ORC_MQ:
+    return sqrt(r2 + K->p[0]);
+  case ORC_COSDOT:
+    return cos(K->p[0] * zx + K->p[1] * zy + K->p[2] * zz);
+  case ORC_EXPDOT:
+    return exp(K->p[0] * zx + K->p[1] * zy + K->p[2] * zz);
+  }
+  return NAN;
+}
+
+static okern make_kern(int kind, const double *p) {
+  okern K;
+  K.kind = kind;
+  K.p[0] = p ? p[0] : 0.0;
+  K.p[1] = p ? p[1] : 0.0;
+  K.p[2] = p ? p[2] : 0.0;
+  return K;
+}
+
+/* K(x, y) for points given as triples. */
+static double K2(const okern *K, const double *x, const double *y) {
+  return k_eval(K, x[0] - y[0], x[1] - y[1], x[2] - y[2]);
+}
+
+void orc_kernel_eval(int kind, const double *p, int64_t n, const double *z /* n x 3 */,
+                     double *out) {
+  okern K = make_kern(kind, p);
+  for (int64_t i = 0; i < n; i++) out[i] = k_eval(&K, z[3 * i], z[3 * i + 1], z[3 * i + 2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* eq. (1): direct summation, Neumaier-compensated, sources in input order.  */
+/* Points are SoA: coordinate a of point i at xyz[a * n + i].                */
+/* ------------------------------------------------------------------------ */
+int orc_direct(int kind, const double *p, int64_t nt, const double *xt, int64_t ns,
+               const double *ys, const double *sigma, double *f, int nthreads) {
+  if (nt < 0 || ns < 0 || (nt > 0 && (!xt || !f)) || (ns > 0 && (!ys || !sigma)))
+    return ORC_EINVAL;
+  okern K = make_kern(kind, p);
+  int sing = k_singular(kind);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t i = 0; i < nt; i++) {
+    double xi = xt[i], yi = xt[nt + i], zi = xt[2 * nt + i];
+    double s = 0.0, c = 0.0;
+    for (int64_t j = 0; j < ns; j++) {
+      double zx = xi - ys[j], zy = yi - ys[ns + j], zz = zi - ys[2 * ns + j];
+      if (sing && zx == 0.0 && zy == 0.0 && zz == 0.0) continue;
+      double v = sigma[j] * k_eval(&K, zx, zy, zz);
+      double t = s + v;
+      if (fabs(s) >= fabs(v))
+        c += (s - t) + v;
+      else
+        c += (v - t) + s;
+      s = t;
+    }
+    f[i] = s + c;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree (Sec. 3.3, written in 1D there; here the 3D octree).                  */
+/* Level k splits [lo, lo+L]^3 into 2^k boxes per axis of half-width          */
+/* l_k = 2^(-k-1) L.  A point's leaf index per axis is                         */
+/* min(floor((x - lo) * (2^depth / L)), 2^depth - 1); the Morton key puts bit  */
+/* b of the x index at bit 3b, y at 3b+1, z at 3b+2.                           */
+/* ------------------------------------------------------------------------ */
+static uint32_t morton3(uint32_t nx, uint32_t ny, uint32_t nz, int bits) {
+  uint32_t k = 0;
+  for (int b = 0; b < bits; b++) {
+    k |= ((nx >> b) & 1u) << (3 * b);
+    k |= ((ny >> b) & 1u) << (3 * b + 1);
+    k |= ((nz >> b) & 1u) << (3 * b + 2);
+  }
+  return k;
+}
+
+static void unmorton3(uint32_t k, int bits, int *n) {
+  n[0] = n[1] = n[2] = 0;
+  for (int b = 0; b < bits; b++) {
+    n[0] |= (int)((k >> (3 * b)) & 1u) << b;
+    n[1] |= (int)((k >> (3 * b + 1)) & 1u) << b;
+    n[2] |= (int)((k >> (3 * b + 2)) & 1u) << b;
+  }
+}
+
+typedef struct {
+  uint32_t key;
+  int32_t idx;
+} keyidx;
+
+static int cmp_keyidx(const void *a, const void *b) {
+  const keyidx *u = (const keyidx *)a, *v = (const keyidx *)b;
+  if (u->key != v->key) return u->key < v->key ? -1 : 1;
+  return u->idx < v->idx ? -1 : (u->idx > v->idx ? 1 : 0);
+}
+
+/* keys[i]: leaf key of input point i; perm[s]: input index of the s-th point in
+ * (key, index) order; leaf_start[0..8^depth]: first sorted position of each leaf. */
+int orc_tree(int64_t n, const double *xyz, const double *lo, double L, int depth, uint32_t *keys,
+             int32_t *perm, int64_t *leaf_start) {
+  if (n < 0 || depth < 0 || depth > 10 || !(L > 0.0) || !lo) return ORC_EINVAL;
+  double scale = ldexp(1.0, depth) / L;
+  int64_t side = (int64_t)1 << depth;
+  int64_t nleaf = (int64_t)1 << (3 * depth);
+  keyidx *ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)(n > 0 ? n : 1));
+  if (!ki) return ORC_ENOMEM;
+  for (int64_t i = 0; i < n; i++) {
+    uint32_t c[3];
+    for (int a = 0; a < 3; a++) {
+      double x = xyz[a * n + i];
+      if (!isfinite(x) || x < lo[a] || x > lo[a] + L) {
+        free(ki);
+        return ORC_EDOMAIN;
+      }
+      double t = floor((x - lo[a]) * scale);
+      int64_t q = (int64_t)t;
+      if (q > side - 1) q = side - 1;
+      if (q < 0) q = 0;
+      c[a] = (uint32_t)q;
+    }
+    ki[i].key = morton3(c[0], c[1], c[2], depth);
+    ki[i].idx = (int32_t)i;
+    if (keys) keys[i] = ki[i].key;
+  }
+  qsort(ki, (size_t)n, sizeof(keyidx), cmp_keyidx);
+  for (int64_t s = 0; s < n; s++) perm[s] = ki[s].idx;
+  for (int64_t b = 0; b <= nleaf; b++) leaf_start[b] = 0;
+  for (int64_t s = 0; s < n; s++) leaf_start[ki[s].key + 1]++;
+  for (int64_t b = 0; b < nleaf; b++) leaf_start[b + 1] += leaf_start[b];
+  free(ki);
+  return ORC_OK;
+}
+
+/* Number of points in box `key` of level `level` (boxes are contiguous
+ * ranges of the key-sorted points). */
+static int64_t box_count(const int64_t *leaf_start, int depth, int level, uint32_t key,
+                         int64_t *first) {
+  int sh = 3 * (depth - level);
+  int64_t a = leaf_start[(int64_t)key << sh], b = leaf_start[((int64_t)key + 1) << sh];
+  if (first) *first = a;
+  return b - a;
+}
+
+/* Offset id of delta in [-3,3]^3 with ||delta||_inf >= 2: rank of
+ * (dx+3) + 7 (dy+3) + 49 (dz+3) among the 7^3 - 3^3 = 316 such offsets
+ * (Sec. 4.2 counts 316 distinct M2L matrices in 3D). */
+static int offset_id(int dx, int dy, int dz) {
+  int target = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+  int id = 0;
+  for (int o = 0; o < 343; o++) {
+    int ex = o % 7 - 3, ey = (o / 7) % 7 - 3, ez = o / 49 - 3;
+    int m = abs(ex);
+    if (abs(ey) > m) m = abs(ey);
+    if (abs(ez) > m) m = abs(ez);
+    if (m < 2) continue;
+    if (o == target) return id;
+    id++;
+  }
+  return -1;
+}
+
+void orc_offset_table(int *delta /* 316 x 3 */) {
+  int id = 0;
+  for (int o = 0; o < 343; o++) {
+    int ex = o % 7 - 3, ey = (o / 7) % 7 - 3, ez = o / 49 - 3;
+    int m = abs(ex);
+    if (abs(ey) > m) m = abs(ey);
+    if (abs(ez) > m) m = abs(ez);
+    if (m < 2) continue;
+    delta[3 * id] = ex;
+    delta[3 * id + 1] = ey;
+    delta[3 * id + 2] = ez;
+    id++;
+  }
+}
+
+static int cmp_u32(const void *a, const void *b) {
+  uint32_t u = *(const uint32_t *)a, v = *(const uint32_t *)b;
+  return u < v ? -1 : (u > v ? 1 : 0);
+}
+
+/* Lists at `level` over the active (non-empty) boxes in ascending key order.
+ * near: boxes J with Chebyshev index distance <= 1 (self included) -- the
+ *       neighbourhood N(I), complement of the well-separated set (Sec. 3.2).
+ * il:   boxes J with ||n_J - n_I||_inf >= 2 whose parent is a neighbour of I's
+ *       parent -- the interaction list (Sec. 3.3.2); only for level >= 2.
+ * Each list is sorted by ascending source key; il_off holds the offset id.
+ * Capacities: active 8^level, near 27 * 8^level, il 189 * 8^level. */
+int orc_lists(int depth, const int64_t *leaf_start, int level, int64_t *nactive,
+              uint32_t *active, int64_t *near_ptr, uint32_t *near_src, int64_t *il_ptr,
+              uint32_t *il_src, int16_t *il_off) {
+  if (level < 0 || level > depth) return ORC_EINVAL;
+  int side = 1 << level;
+  int64_t nb = (int64_t)1 << (3 * level);
+  int64_t na = 0, nn = 0, ni = 0;
+  near_ptr[0] = 0;
+  if (il_ptr) il_ptr[0] = 0;
+  uint32_t tmpk[343];
+  int16_t tmpo[343];
+  for (int64_t key = 0; key < nb; key++) {
+    if (box_count(leaf_start, depth, level, (uint32_t)key, NULL) == 0) continue;
+    active[na] = (uint32_t)key;
+    int n[3];
+    unmorton3((uint32_t)key, level, n);
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          int m[3] = {n[0] + dx, n[1] + dy, n[2] + dz};
+          if (m[0] < 0 || m[1] < 0 || m[2] < 0 || m[0] >= side || m[1] >= side || m[2] >= side)
+            continue;
+          uint32_t kj = morton3((uint32_t)m[0], (uint32_t)m[1], (uint32_t)m[2], level);
+          if (box_count(leaf_start, depth, level, kj, NULL) == 0) continue;
+          tmpk[cnt++] = kj;
+        }
+    qsort(tmpk, (size_t)cnt, sizeof(uint32_t), cmp_u32);
+    for (int c = 0; c < cnt; c++) near_src[nn++] = tmpk[c];
+    near_ptr[na + 1] = nn;
+    if (il_ptr && level >= 2) {
+      cnt = 0;
+      for (int dz = -3; dz <= 3; dz++)
+        for (int dy = -3; dy <= 3; dy++)
+          for (int dx = -3; dx <= 3; dx++) {
+            int cheb = abs(dx);
+            if (abs(dy) > cheb) cheb = abs(dy);
+            if (abs(dz) > cheb) cheb = abs(dz);
+            if (cheb < 2) continue;
+            int m[3] = {n[0] + dx, n[1] + dy, n[2] + dz};
+            if (m[0] < 0 || m[1] < 0 || m[2] < 0 || m[0] >= side || m[1] >= side ||
+                m[2] >= side)
+              continue;
+            int pc = 0;
+            for (int a = 0; a < 3; a++) {
+              int dp = (m[a] >> 1) - (n[a] >> 1);
+              if (abs(dp) > pc) pc = abs(dp);
+            }
+            if (pc > 1) continue;
+            uint32_t kj = morton3((uint32_t)m[0], (uint32_t)m[1], (uint32_t)m[2], level);
+            if (box_count(leaf_start, depth, level, kj, NULL) == 0) continue;
+            tmpk[cnt] = kj;
+            tmpo[cnt] = (int16_t)offset_id(dx, dy, dz);
+            cnt++;
+          }
+      /* sort by source key (insertion sort keeps the (key, id) pairs together) */
+      for (int a = 1; a < cnt; a++) {
+        uint32_t kk = tmpk[a];
+        int16_t oo = tmpo[a];
+        int b = a - 1;
+        while (b >= 0 && tmpk[b] > kk) {
+          tmpk[b + 1] = tmpk[b];
+          tmpo[b + 1] = tmpo[b];
+          b--;
+        }
+        tmpk[b + 1] = kk;
+        tmpo[b + 1] = oo;
+      }
+      for (int c = 0; c < cnt; c++) {
+        il_src[ni] = tmpk[c];
+        il_off[ni] = tmpo[c];
+        ni++;
+      }
+      il_ptr[na + 1] = ni;
+    } else if (il_ptr) {
+      il_ptr[na + 1] = ni;
+    }
+    na++;
+  }
+  *nactive = na;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Training sets (Sec. 2 leaves them unspecified).  Reading used here, in    */
+/* units of l_k (the half-width of a level-k box):                           */
+/*   D_y = J_0^k = [-1,1]^3, D_x = I_0^k = {u : 3 <= ||u||_inf <= 2^(k+1)-1}. */
+/*   "surface" kernels (1/r, exp(-ar)/r, r^2): maximum principle, so the      */
+/*     residual peaks on boundaries -- T_y is the surface of J_0 with an 11x11 */
+/*     grid per face; T_x is a set of cube shells ||u||_inf = rho.            */
+/*   "volume" kernels: T_y is an 11^3 grid of J_0; T_x adds shells between.   */
+/* Shell radii: SHELLS below that are < 2^(k+1)-1, then 2^(k+1)-1 itself;     */
+/* face grids have 19x19 points for rho < 6 and 9x9 beyond.                  */
+/* Point order: shells ascending; faces x-,x+,y-,y+,z-,z+; first free axis    */
+/* outer; a point on several faces is emitted only on the lowest-axis face.   */
+/* ------------------------------------------------------------------------ */
+static const double SHELLS_S[] = {3,   3.5, 4,   5,   6.5, 8.5, 11,  15,   20,   27,
+                                  36,  48,  64,  86,  116, 155, 208, 279,  374,  502,
+                                  673, 902, 1209, 1621, 2173};
+static const double SHELLS_V[] = {3,    3.25, 3.5, 3.75, 4,   4.5, 5,   5.5,  6,    6.5,
+                                  7.25, 8,    9,   10,   11,  12.5, 14, 16,   18,   20,
+                                  23,   27,   32,  38,   45,  54,  64,  76,   90,   108,
+                                  128,  152,  181, 215,  256, 304, 362, 431,  512,  609,
+                                  724,  861,  1024, 1218, 1448, 1722, 2048};
+
+static int kernel_is_volume(int kind) {
+  return !(kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_SQDIST);
+}
+
+static int64_t emit_shell(double rho, int m, double *out) {
+  int64_t c = 0;
+  for (int ax = 0; ax < 3; ax++) {
+    int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    for (int s = -1; s <= 1; s += 2) {
+      for (int i = 0; i < m; i++) {
+        if (o0 < ax && (i == 0 || i == m - 1)) continue;
+        for (int j = 0; j < m; j++) {
+          if (o1 < ax && (j == 0 || j == m - 1)) continue;
+          if (out) {
+            double u[3];
+            u[ax] = s * rho;
+            u[o0] = rho * (double)(2 * i - (m - 1)) / (double)(m - 1);
+            u[o1] = rho * (double)(2 * j - (m - 1)) / (double)(m - 1);
+            out[3 * c] = u[0];
+            out[3 * c + 1] = u[1];
+            out[3 * c + 2] = u[2];
+          }
+          c++;
+        }
+      }
+    }
+  }
+  return c;
+}
+
+static int64_t emit_volume(int m, double *out) {
+  int64_t c = 0;
+  for (int iz = 0; iz < m; iz++)
+    for (int iy = 0; iy < m; iy++)
+      for (int ix = 0; ix < m; ix++) {
+        if (out) {
+          out[3 * c] = (double)(2 * ix - (m - 1)) / (double)(m - 1);
+          out[3 * c + 1] = (double)(2 * iy - (m - 1)) / (double)(m - 1);
+          out[3 * c + 2] = (double)(2 * iz - (m - 1)) / (double)(m - 1);
+        }
+        c++;
+      }
+  return c;
+}
+
+/* Training points in units of l_k, AoS (n x 3).  Call with NULL buffers to get
+ * the counts. */
+int orc_training_sets(int kind, int level, double *tx, int64_t *ntx, double *ty, int64_t *nty) {
+  if (level < 2 || level > 12) return ORC_EINVAL;
+  int vol = kernel_is_volume(kind);
+  double top = (double)((1 << (level + 1)) - 1);
+  const double *sh = vol ? SHELLS_V : SHELLS_S;
+  int nsh = vol ? (int)(sizeof(SHELLS_V) / sizeof(double)) : (int)(sizeof(SHELLS_S) / sizeof(double));
+  int64_t c = 0;
+  for (int s = 0; s <= nsh; s++) {
+    double rho;
+    if (s < nsh) {
+      if (!(sh[s] < top)) continue;
+      rho = sh[s];
+    } else {
+      rho = top;
+    }
+    int m = rho < 6.0 ? 19 : 9;
+    c += emit_shell(rho, m, tx ? tx + 3 * c : NULL);
+  }
+  *ntx = c;
+  if (vol)
+    *nty = emit_volume(11, ty);
+  else
+    *nty = emit_shell(1.0, 11, ty);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 (greedy EIM) over the training sets, with the L-infinity norm  */
+/* (a reading: Sec. 2 allows L-inf or L2).  The residual (delta_k K)(x, y) on */
+/* the training grid is kept as a matrix R and updated with the new basis     */
+/* function:  (delta_{k+1}K)(x,y) = (delta_k K)(x,y) - lambda_{k+1}(x) q_{k+1}(y) */
+/* where q_{k+1} = (delta_k K)(x_{k+1},.)/(delta_k K)(x_{k+1},y_{k+1}) and    */
+/* lambda_{k+1}(x) = (delta_k K)(x, y_{k+1}) (B has unit diagonal).           */
+/* Ties in the argmax go to the lowest training index.                        */
+/* Stopping (end of Sec. 2): stop before adding point k+1 when                */
+/* eps_k = max_y |(delta_k K)(x_{k+1}, y)| <= tau * scale, with scale =        */
+/* max |K| over the training grid of this level (relative mode) or the given  */
+/* abs_scale.  Gamma follows the recursion of Sec. 2: Gamma_{k+1,k+1} is the  */
+/* new pivot and row k+1 holds alpha with B alpha = K(x_{k+1}, y_l), l <= k.  */
+/* Outputs: d, training indices ia/ib, X (I_0 points) and Y (J_0 points) in    */
+/* physical units (d x 3), B and Gamma (dmax x dmax row-major, leading dim     */
+/* dmax), eps history eps[0..d] (eps[k] = max |delta_k K| over the grid).      */
+/* ------------------------------------------------------------------------ */
+int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax,
+            double abs_scale, int *d_out, int64_t *ia, int64_t *ib, double *X, double *Y,
+            double *Bm, double *Gm, double *eps, double *scale_out) {
+  if (!(tau > 0.0) || dmax < 1 || level < 2) return ORC_EINVAL;
+  okern K = make_kern(kind, p);
+  int64_t ntx, nty;
+  orc_training_sets(kind, level, NULL, &ntx, NULL, &nty);
+  double *tx = (double *)malloc(sizeof(double) * 3 * (size_t)ntx);
+  double *ty = (double *)malloc(sizeof(double) * 3 * (size_t)nty);
+  double *R = (double *)malloc(sizeof(double) * (size_t)ntx * (size_t)nty);
+  double *q = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)nty);
+  if (!tx || !ty || !R || !q) {
+    free(tx); free(ty); free(R); free(q);
+    return ORC_ENOMEM;
+  }
+  orc_training_sets(kind, level, tx, &ntx, ty, &nty);
+  double lk = ldexp(L, -level - 1);
+  for (int64_t a = 0; a < 3 * ntx; a++) tx[a] *= lk;
+  for (int64_t b = 0; b < 3 * nty; b++) ty[b] *= lk;
+
+  /* delta_0 K = K on the training grid */
+  for (int64_t a = 0; a < ntx; a++)
+    for (int64_t b = 0; b < nty; b++) R[a * nty + b] = K2(&K, tx + 3 * a, ty + 3 * b);
+
+  memset(Bm, 0, sizeof(double) * (size_t)dmax * (size_t)dmax);
+  memset(Gm, 0, sizeof(double) * (size_t)dmax * (size_t)dmax);
+  double scale = 0.0;
+  int d = 0, status = ORC_OK;
+  for (;;) {
+    /* x_{d+1} = argmax_x ||(delta_d K)(x, .)||_inf, then y_{d+1} = argmax_y */
+    int64_t as = 0, bs = 0;
+    double best = -1.0;
+    for (int64_t a = 0; a < ntx; a++) {
+      double rowmax = 0.0;
+      int64_t rowarg = 0;
+      for (int64_t b = 0; b < nty; b++) {
+        double v = fabs(R[a * nty + b]);
+        if (v > rowmax) {
+          rowmax = v;
+          rowarg = b;
+        }
+      }
+      if (rowmax > best) {
+        best = rowmax;
+        as = a;
+        bs = rowarg;
+      }
+    }
+    if (d == 0) scale = abs_scale > 0.0 ? abs_scale : best;
+    if (eps) eps[d] = best;
+    if (best <= tau * scale) break;
+    if (d == dmax) {
+      status = ORC_EEIM;
+      break;
+    }
+    double gam = R[as * nty + bs];
+    int k = d; /* 0-based index of the new point */
+    ia[k] = as;
+    ib[k] = bs;
+    for (int c = 0; c < 3; c++) {
+      X[3 * k + c] = tx[3 * as + c];
+      Y[3 * k + c] = ty[3 * bs + c];
+    }
+    /* q_{k+1}(y) = (delta_k K)(x_{k+1}, y) / (delta_k K)(x_{k+1}, y_{k+1}) */
+    double *qk = q + (size_t)k * (size_t)nty;
+    for (int64_t b = 0; b < nty; b++) qk[b] = R[as * nty + b] / gam;
+    /* B_{k+1, m} = q_m(y_{k+1}), m <= k+1 */
+    for (int m = 0; m <= k; m++) Bm[k * dmax + m] = q[(size_t)m * (size_t)nty + bs];
+    /* Gamma row k+1: alpha with sum_m B_{l,m} alpha_m = K(x_{k+1}, y_l), l <= k */
+    for (int l = 0; l < k; l++) {
+      double s = K2(&K, X + 3 * k, Y + 3 * l);
+      for (int m = 0; m < l; m++) s -= Bm[l * dmax + m] * Gm[k * dmax + m];
+      Gm[k * dmax + l] = s; /* unit diagonal of B */
+    }
+    Gm[k * dmax + k] = gam;
+    /* residual update */
+    for (int64_t a = 0; a < ntx; a++) {
+      double lam = R[a * nty + bs];
+      for (int64_t b = 0; b < nty; b++) R[a * nty + b] -= lam * qk[b];
+    }
+    d++;
+  }
+  *d_out = d;
+  if (scale_out) *scale_out = scale;
+  free(tx); free(ty); free(R); free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Triangular solves that apply Delta = B^{-T} Gamma^{-1} and its transpose    */
+/* without forming an inverse (Sec. 4.1).  ld = leading dimension.            */
+/* ------------------------------------------------------------------------ */
+/* w = Delta v : Gamma z = v (forward), then B^T w = z (backward). */
+static void apply_delta(int d, int ld, const double *Bm, const double *Gm, const double *v,
+                        double *w) {
+  for (int i = 0; i < d; i++) {
+    double s = v[i];
+    for (int j = 0; j < i; j++) s -= Gm[i * ld + j] * w[j];
+    w[i] = s / Gm[i * ld + i];
+  }
+  for (int i = d - 1; i >= 0; i--) {
+    double s = w[i];
+    for (int j = i + 1; j < d; j++) s -= Bm[j * ld + i] * w[j];
+    w[i] = s;
+  }
+}
+
+/* w = Delta^T v : B z = v (forward, unit diagonal), then Gamma^T w = z. */
+static void apply_delta_t(int d, int ld, const double *Bm, const double *Gm, const double *v,
+                          double *w) {
+  for (int i = 0; i < d; i++) {
+    double s = v[i];
+    for (int j = 0; j < i; j++) s -= Bm[i * ld + j] * w[j];
+    w[i] = s;
+  }
+  for (int i = d - 1; i >= 0; i--) {
+    double s = w[i];
+    for (int j = i + 1; j < d; j++) s -= Gm[j * ld + i] * w[j];
+    w[i] = s / Gm[i * ld + i];
+  }
+}
+
+void orc_apply_delta(int d, int ld, const double *Bm, const double *Gm, const double *v,
+                     double *w, int transpose) {
+  if (transpose)
+    apply_delta_t(d, ld, Bm, Gm, v, w);
+  else
+    apply_delta(d, ld, Bm, Gm, v, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Plan: per-level EIM results (levels 2..depth).                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int d;
+  double *X, *Y, *B, *G, *eps;
+  int64_t *ia, *ib;
+  double scale;
+} olevel;
+
+typedef struct {
+  okern K;
+  double lo[3], L, tau;
+  int depth, dmax, tol_mode;
+  olevel lv[16];
+} orc_plan;
+
+void orc_plan_free(orc_plan *P) {
+  if (!P) return;
+  for (int k = 0; k < 16; k++) {
+    free(P->lv[k].X); free(P->lv[k].Y); free(P->lv[k].B); free(P->lv[k].G);
+    free(P->lv[k].eps); free(P->lv[k].ia); free(P->lv[k].ib);
+  }
+  free(P);
+}
+
+/* tol_mode 0: relative to each level's own max |K| over its training grid;
+ * tol_mode 1: relative to the finest level's max |K| (one absolute threshold). */
+orc_plan *orc_plan_create(int kind, const double *p, const double *lo, double L, int depth,
+                          double tau, int dmax, int tol_mode, int *status) {
+  *status = ORC_EINVAL;
+  if (depth < 0 || depth > 10 || !(L > 0.0) || !(tau > 0.0) || dmax < 1) return NULL;
+  orc_plan *P = (orc_plan *)calloc(1, sizeof(orc_plan));
+  if (!P) {
+    *status = ORC_ENOMEM;
+    return NULL;
+  }
+  P->K = make_kern(kind, p);
+  for (int a = 0; a < 3; a++) P->lo[a] = lo[a];
+  P->L = L;
+  P->tau = tau;
+  P->depth = depth;
+  P->dmax = dmax;
+  P->tol_mode = tol_mode;
+  double abs_scale = 0.0;
+  *status = ORC_OK;
+  for (int k = depth; k >= 2; k--) {
+    olevel *lv = &P->lv[k];
+    lv->X = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
+    lv->Y = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
+    lv->B = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
+    lv->G = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
+    lv->eps = (double *)malloc(sizeof(double) * ((size_t)dmax + 1));
+    lv->ia = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
+    lv->ib = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
+    if (!lv->X || !lv->Y || !lv->B || !lv->G || !lv->eps || !lv->ia || !lv->ib) {
+      *status = ORC_ENOMEM;
+      orc_plan_free(P);
+      return NULL;
+    }
+    int st = orc_eim(kind, p, k, L, tau, dmax, tol_mode == 1 ? abs_scale : 0.0, &lv->d, lv->ia,
+                     lv->ib, lv->X, lv->Y, lv->B, lv->G, lv->eps, &lv->scale);
+    if (st != ORC_OK) {
+      *status = st;
+      orc_plan_free(P);
+      return NULL;
+    }
+    if (k == depth && tol_mode == 1) abs_scale = lv->scale;
+  }
+  return P;
+}
+
+int orc_plan_level(const orc_plan *P, int k, int *d, double *X, double *Y, double *B,
+                   double *G, int64_t *ia, int64_t *ib, double *eps) {
+  if (!P || k < 2 || k > P->depth) return ORC_EINVAL;
+  const olevel *lv = &P->lv[k];
+  int dd = lv->d, dm = P->dmax;
+  *d = dd;
+  if (X) memcpy(X, lv->X, sizeof(double) * 3 * (size_t)dd);
+  if (Y) memcpy(Y, lv->Y, sizeof(double) * 3 * (size_t)dd);
+  for (int i = 0; i < dd; i++)
+    for (int j = 0; j < dd; j++) {
+      if (B) B[i * dd + j] = lv->B[i * dm + j];
+      if (G) G[i * dd + j] = lv->G[i * dm + j];
+    }
+  if (ia) memcpy(ia, lv->ia, sizeof(int64_t) * (size_t)dd);
+  if (ib) memcpy(ib, lv->ib, sizeof(int64_t) * (size_t)dd);
+  if (eps) memcpy(eps, lv->eps, sizeof(double) * ((size_t)dd + 1));
+  return ORC_OK;
+}
+
+/* Centre of box `key` at level k. */
+static void box_centre(const orc_plan *P, int k, uint32_t key, double *c) {
+  int n[3];
+  unmorton3(key, k, n);
+  double h = ldexp(P->L, -k); /* box side 2 l_k */
+  for (int a = 0; a < 3; a++) c[a] = P->lo[a] + ((double)n[a] + 0.5) * h;
+}
+
+/* Offset (in units of l_k... as a physical vector) of child i from its parent:
+ * child index bit a set means the upper half along axis a, centre shifted by
+ * +l_k, otherwise by -l_k; k is the child's level. */
+static void child_shift(const orc_plan *P, int k, int i, double *s) {
+  double lk = ldexp(P->L, -k - 1);
+  for (int a = 0; a < 3; a++) s[a] = ((i >> a) & 1) ? lk : -lk;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 3 plus the near field (eq. (12)-(13)), one right-hand side.      */
+/* xyz: 3 x n SoA input points (targets = sources); sigma[n]; f[n] output in  */
+/* input order.  Optional dumps (NULL to skip), dense over all boxes of each  */
+/* level in key order, levels 2..depth concatenated, box-major with d_k        */
+/* values per box:  W (step 1-2), What (step 3), g (step 4), l (step 5);      */
+/* lhat (step 6, level depth only); fnear / ffar in input order.              */
+/* ------------------------------------------------------------------------ */
+int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double *sigma,
+                  double *f, double *dW, double *dWh, double *dg, double *dl, double *dlh,
+                  double *dfn, double *dff, int nthreads) {
+  if (!P || n < 0) return ORC_EINVAL;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  const okern *K = &P->K;
+  int depth = P->depth, sing = k_singular(K->kind);
+  int64_t nleaf = (int64_t)1 << (3 * depth);
+  uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *ls = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
+  double *ps = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1)); /* sorted AoS */
+  double *ss = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *fs = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *fn = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  if (!keys || !perm || !ls || !ps || !ss || !fs || !fn) {
+    free(keys); free(perm); free(ls); free(ps); free(ss); free(fs); free(fn);
+    return ORC_ENOMEM;
+  }
+  int st = orc_tree(n, xyz, P->lo, P->L, depth, keys, perm, ls);
+  if (st != ORC_OK) {
+    free(keys); free(perm); free(ls); free(ps); free(ss); free(fs); free(fn);
+    return st;
+  }
+  for (int64_t s = 0; s < n; s++) {
+    for (int a = 0; a < 3; a++) ps[3 * s + a] = xyz[a * n + perm[s]];
+    ss[s] = sigma[perm[s]];
+  }
+
+  /* per-level dense storage */
+  double *W[16] = {0}, *Wh[16] = {0}, *g[16] = {0}, *l[16] = {0};
+  int ok = 1;
+  for (int k = 2; k <= depth; k++) {
+    size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].d;
+    W[k] = (double *)calloc(sz, sizeof(double));
+    Wh[k] = (double *)calloc(sz, sizeof(double));
+    g[k] = (double *)calloc(sz, sizeof(double));
+    l[k] = (double *)calloc(sz, sizeof(double));
+    if (!W[k] || !Wh[k] || !g[k] || !l[k]) ok = 0;
+  }
+  double *lh = NULL;
+  if (depth >= 2) {
+    lh = (double *)calloc((size_t)nleaf * (size_t)P->lv[depth].d, sizeof(double));
+    if (!lh) ok = 0;
+  }
+  if (!ok) {
+    st = ORC_ENOMEM;
+    goto done;
+  }
+
+  if (depth >= 2) {
+    /* Step 1 (P2M): W_m^I = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I). */
+    {
+      const olevel *lv = &P->lv[depth];
+      int d = lv->d;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+      for (int64_t key = 0; key < nleaf; key++) {
+        int64_t a = ls[key], b = ls[key + 1];
+        if (a == b) continue;
+        double c[3];
+        box_centre(P, depth, (uint32_t)key, c);
+        for (int m = 0; m < d; m++) {
+          double s = 0.0;
+          for (int64_t j = a; j < b; j++) {
+            double yc[3] = {ps[3 * j] - c[0], ps[3 * j + 1] - c[1], ps[3 * j + 2] - c[2]};
+            s += ss[j] * K2(K, lv->X + 3 * m, yc);
+          }
+          W[depth][(size_t)key * (size_t)d + (size_t)m] = s;
+        }
+      }
+    }
+    /* Step 3 at the leaf level, then Step 2 (M2M) and Step 3 going up:
+     * W_m^{I^k} = sum_{J child} sum_p K(x_m^{I_0^k} + c_I - c_J, y_p^{J_0^{k+1}}) What_p^J
+     * with What^J = Delta^{k+1} W^J (the Delta-contraction of eq. (17)). */
+    for (int k = depth; k >= 2; k--) {
+      const olevel *lv = &P->lv[k];
+      int d = lv->d;
+      int64_t nb = (int64_t)1 << (3 * k);
+      if (k < depth) {
+        const olevel *lc = &P->lv[k + 1];
+        int dc = lc->d;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+        for (int64_t key = 0; key < nb; key++) {
+          if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+          for (int i = 0; i < 8; i++) {
+            uint32_t ck = (uint32_t)(key * 8 + i);
+            if (box_count(ls, depth, k + 1, ck, NULL) == 0) continue;
+            double sh[3];
+            child_shift(P, k + 1, i, sh); /* c_J - c_I */
+            const double *whc = Wh[k + 1] + (size_t)ck * (size_t)dc;
+            for (int m = 0; m < d; m++) {
+              double xm[3] = {lv->X[3 * m] - sh[0], lv->X[3 * m + 1] - sh[1],
+                              lv->X[3 * m + 2] - sh[2]};
+              double s = 0.0;
+              for (int pp = 0; pp < dc; pp++) s += K2(K, xm, lc->Y + 3 * pp) * whc[pp];
+              W[k][(size_t)key * (size_t)d + (size_t)m] += s;
+            }
+          }
+        }
+      }
+      /* Step 3: What^I = Delta^{I_0^k, J_0^k} W^I */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+      for (int64_t key = 0; key < nb; key++) {
+        if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+        apply_delta(d, P->dmax, lv->B, lv->G, W[k] + (size_t)key * (size_t)d,
+                    Wh[k] + (size_t)key * (size_t)d);
+      }
+    }
+    /* Step 4 (M2L): g_{m'}^I = sum_{J in IL(I)} sum_l K(x_{m'}^{J_0}, y_l^{J_0} + c_J - c_I) What_l^J.
+     * For a symmetric kernel x^{J_0} = y^{J_0} = Y.  The 316 matrices
+     * K^delta_{m' l} = K(Y_{m'}, Y_l + 2 l_k delta) are tabulated once per level (Sec. 4.2). */
+    int dtab[316 * 3];
+    orc_offset_table(dtab);
+    for (int k = 2; k <= depth; k++) {
+      const olevel *lv = &P->lv[k];
+      int d = lv->d;
+      int side = 1 << k;
+      int64_t nb = (int64_t)1 << (3 * k);
+      double h = ldexp(P->L, -k); /* 2 l_k */
+      double *Kd = (double *)malloc(sizeof(double) * 316 * (size_t)d * (size_t)d);
+      if (!Kd) {
+        st = ORC_ENOMEM;
+        goto done;
+      }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+      for (int o = 0; o < 316; o++) {
+        double dv[3] = {dtab[3 * o] * h, dtab[3 * o + 1] * h, dtab[3 * o + 2] * h};
+        for (int mp = 0; mp < d; mp++)
+          for (int ll = 0; ll < d; ll++) {
+            double yl[3] = {lv->Y[3 * ll] + dv[0], lv->Y[3 * ll + 1] + dv[1],
+                            lv->Y[3 * ll + 2] + dv[2]};
+            Kd[((size_t)o * (size_t)d + (size_t)mp) * (size_t)d + (size_t)ll] =
+                K2(K, lv->Y + 3 * mp, yl);
+          }
+      }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+      for (int64_t key = 0; key < nb; key++) {
+        if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+        int nI[3];
+        unmorton3((uint32_t)key, k, nI);
+        double *gI = g[k] + (size_t)key * (size_t)d;
+        for (int o = 0; o < 316; o++) {
+          int nJ[3] = {nI[0] + dtab[3 * o], nI[1] + dtab[3 * o + 1], nI[2] + dtab[3 * o + 2]};
+          int inside = 1, pc = 0;
+          for (int a = 0; a < 3; a++) {
+            if (nJ[a] < 0 || nJ[a] >= side) inside = 0;
+            int dp = abs((nJ[a] >> 1) - (nI[a] >> 1));
+            if (dp > pc) pc = dp;
+          }
+          if (!inside || pc > 1) continue;
+          uint32_t kj = morton3((uint32_t)nJ[0], (uint32_t)nJ[1], (uint32_t)nJ[2], k);
+          if (box_count(ls, depth, k, kj, NULL) == 0) continue;
+          const double *wj = Wh[k] + (size_t)kj * (size_t)d;
+          const double *A = Kd + (size_t)o * (size_t)d * (size_t)d;
+          for (int mp = 0; mp < d; mp++) {
+            double s = 0.0;
+            for (int ll = 0; ll < d; ll++) s += A[(size_t)mp * (size_t)d + (size_t)ll] * wj[ll];
+            gI[mp] += s;
+          }
+        }
+      }
+      free(Kd);
+    }
+    /* Step 5 (L2L): l^{I^2} = g^{I^2}; for k = 3..depth
+     * l_{m'}^{I^k} = g_{m'}^{I^k} + sum_{p'} K(x_{m'}^{J_0^k} + c_I - c_P, y_{p'}^{I_0^{k-1}}) lhat_{p'}^P,
+     * lhat^P = Delta^{J_0^{k-1}, I_0^{k-1}} l^P; for a symmetric kernel
+     * x^{J_0} = Y, y^{I_0} = X and Delta^{J_0,I_0} = (Delta^{I_0,J_0})^T. */
+    {
+      int64_t nb2 = (int64_t)1 << 6;
+      memcpy(l[2], g[2], sizeof(double) * (size_t)nb2 * (size_t)P->lv[2].d);
+    }
+    for (int k = 3; k <= depth; k++) {
+      const olevel *lv = &P->lv[k], *lp = &P->lv[k - 1];
+      int d = lv->d, dp = lp->d;
+      int64_t nb = (int64_t)1 << (3 * k);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+      for (int64_t key = 0; key < nb; key++) {
+        if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+        uint32_t pk = (uint32_t)(key >> 3);
+        double *lhp = (double *)malloc(sizeof(double) * (size_t)dp);
+        apply_delta_t(dp, P->dmax, lp->B, lp->G, l[k - 1] + (size_t)pk * (size_t)dp, lhp);
+        double sh[3];
+        child_shift(P, k, (int)(key & 7), sh); /* c_I - c_P */
+        for (int mp = 0; mp < d; mp++) {
+          double ym[3] = {lv->Y[3 * mp] + sh[0], lv->Y[3 * mp + 1] + sh[1],
+                          lv->Y[3 * mp + 2] + sh[2]};
+          double s = 0.0;
+          for (int pp = 0; pp < dp; pp++) s += K2(K, ym, lp->X + 3 * pp) * lhp[pp];
+          l[k][(size_t)key * (size_t)d + (size_t)mp] =
+              g[k][(size_t)key * (size_t)d + (size_t)mp] + s;
+        }
+        free(lhp);
+      }
+    }
+    /* Step 6: lhat^I = Delta^{J_0^kappa, I_0^kappa} l^I;
+     * Step 7 (L2P): f_F(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I. */
+    {
+      const olevel *lv = &P->lv[depth];
+      int d = lv->d;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+      for (int64_t key = 0; key < nleaf; key++) {
+        int64_t a = ls[key], b = ls[key + 1];
+        if (a == b) continue;
+        double *lhI = lh + (size_t)key * (size_t)d;
+        apply_delta_t(d, P->dmax, lv->B, lv->G, l[depth] + (size_t)key * (size_t)d, lhI);
+        double c[3];
+        box_centre(P, depth, (uint32_t)key, c);
+        for (int64_t i = a; i < b; i++) {
+          double xc[3] = {ps[3 * i] - c[0], ps[3 * i + 1] - c[1], ps[3 * i + 2] - c[2]};
+          double s = 0.0;
+          for (int lp = 0; lp < d; lp++) s += K2(K, xc, lv->X + 3 * lp) * lhI[lp];
+          fs[i] = s;
+        }
+      }
+    }
+  }
+  /* Near field, eq. (13): f_N(x_i) = sum over the neighbourhood N(I) of the
+   * leaf containing x_i (Chebyshev distance <= 1 at the leaf level). */
+  {
+    int side = 1 << depth;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+    for (int64_t key = 0; key < nleaf; key++) {
+      int64_t a = ls[key], b = ls[key + 1];
+      if (a == b) continue;
+      int nI[3];
+      unmorton3((uint32_t)key, depth, nI);
+      uint32_t nbk[27];
+      int cnt = 0;
+      for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dx = -1; dx <= 1; dx++) {
+            int m[3] = {nI[0] + dx, nI[1] + dy, nI[2] + dz};
+            if (m[0] < 0 || m[1] < 0 || m[2] < 0 || m[0] >= side || m[1] >= side || m[2] >= side)
+              continue;
+            nbk[cnt++] = morton3((uint32_t)m[0], (uint32_t)m[1], (uint32_t)m[2], depth);
+          }
+      qsort(nbk, (size_t)cnt, sizeof(uint32_t), cmp_u32);
+      for (int64_t i = a; i < b; i++) {
+        double s = 0.0;
+        for (int c = 0; c < cnt; c++) {
+          for (int64_t j = ls[nbk[c]]; j < ls[nbk[c] + 1]; j++) {
+            double zx = ps[3 * i] - ps[3 * j], zy = ps[3 * i + 1] - ps[3 * j + 1],
+                   zz = ps[3 * i + 2] - ps[3 * j + 2];
+            if (sing && zx == 0.0 && zy == 0.0 && zz == 0.0) continue;
+            s += ss[j] * k_eval(K, zx, zy, zz);
+          }
+        }
+        fn[i] = s;
+      }
+    }
+  }
+  for (int64_t s = 0; s < n; s++) {
+    f[perm[s]] = fs[s] + fn[s];
+    if (dfn) dfn[perm[s]] = fn[s];
+    if (dff) dff[perm[s]] = fs[s];
+  }
+  {
+    size_t off = 0;
+    for (int k = 2; k <= depth; k++) {
+      size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].d;
+      if (dW) memcpy(dW + off, W[k], sz * sizeof(double));
+      if (dWh) memcpy(dWh + off, Wh[k], sz * sizeof(double));
+      if (dg) memcpy(dg + off, g[k], sz * sizeof(double));
+      if (dl) memcpy(dl + off, l[k], sz * sizeof(double));
+      off += sz;
+    }
+    if (dlh && lh) memcpy(dlh, lh, sizeof(double) * (size_t)nleaf * (size_t)P->lv[depth].d);
+  }
+  st = ORC_OK;
+done:
+  for (int k = 0; k < 16; k++) {
+    free(W[k]); free(Wh[k]); free(g[k]); free(l[k]);
+  }
+  free(lh);
+  free(keys); free(perm); free(ls); free(ps); free(ss); free(fs); free(fn);
+  return st;
+}

@@ -1,0 +1,102 @@
+"""Seeded synthetic inputs for the evaluation pass.
+
+This module only draws random numbers; it holds none of the method's arithmetic.
+Both the HIP path and the CPU oracle consume what it returns, so the two sides
+always see identical inputs.
+
+Point sets follow the paper's test-cases (Sec. 5.2: points drawn uniformly in a
+cube) shifted to the unit cube [0,1]^3, plus isotropic Gaussian clusters clipped
+to the cube.  Potentials sigma are uniform in [-1, 1].  All draws use numpy's
+PCG64 generator; points come back as SoA arrays of shape (3, n), float64.
+"""
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_points(n, seed):
+    """n points uniform in [0,1)^3."""
+    return np.ascontiguousarray(_rng(seed).random((n, 3)).T)
+
+
+def cluster_points(n, ncl, width, seed_centres, seed_points):
+    """n points from ncl isotropic Gaussian clusters (std `width`), centres uniform
+    in [0,1)^3, clipped to [0,1]^3, then shuffled.  n is split as evenly as possible
+    (the first n % ncl clusters get one extra point)."""
+    centres = _rng(seed_centres).random((ncl, 3))
+    r = _rng(seed_points)
+    counts = [n // ncl + (1 if c < n % ncl else 0) for c in range(ncl)]
+    parts = [centres[c] + width * r.standard_normal((counts[c], 3)) for c in range(ncl)]
+    pts = np.clip(np.concatenate(parts), 0.0, 1.0)
+    pts = pts[r.permutation(n)]
+    return np.ascontiguousarray(pts.T)
+
+
+def potentials(n, seed):
+    """sigma_j uniform in [-1, 1)."""
+    return _rng(seed).uniform(-1.0, 1.0, n)
+
+
+def potentials_multi(n, seeds):
+    """Column-major (n x nrhs) block: column r drawn with seeds[r]."""
+    return np.ascontiguousarray(np.stack([potentials(n, s) for s in seeds], axis=1).T).T
+
+
+# Workload recipes (sizes, seeds, kernels) used by the tests and the benchmark.
+WORKLOADS = {
+    # FP64, single right-hand side, oracle-sized: 2000 points, depth 3.
+    "uniform2k_laplace_d3": dict(n=2000, dist="uniform", seed_pts=1, seed_sigma=2,
+                                 kernel="laplace", param=0.0, depth=3, tau=1e-6),
+    # FP64 single RHS, 1e6 uniform points, depth 5 (~30 points per leaf).
+    "uniform1m_laplace_d5": dict(n=1_000_000, dist="uniform", seed_pts=3, seed_sigma=4,
+                                 kernel="laplace", param=0.0, depth=5, tau=1e-6),
+    # Mixed precision, 16 Gaussian clusters (width 0.03), exp(-r)/r.
+    "cluster1m_yukawa": dict(n=1_000_000, dist="cluster", ncl=16, width=0.03, seed_centres=5,
+                             seed_pts=6, seed_sigma=7, kernel="yukawa", param=1.0, depth=5,
+                             tau=1e-6),
+    # Many right-hand sides: 2^20 uniform points, 64 sigma vectors, depth 5.
+    "uniform1m_laplace_d5_rhs64": dict(n=1 << 20, dist="uniform", seed_pts=8,
+                                       seed_sigma=list(range(100, 164)), kernel="laplace",
+                                       param=0.0, depth=5, tau=1e-6),
+}
+
+
+def make_points(w):
+    if w["dist"] == "uniform":
+        return uniform_points(w["n"], w["seed_pts"])
+    return cluster_points(w["n"], w["ncl"], w["width"], w["seed_centres"], w["seed_pts"])
+
+
+def make_sigma(w):
+    s = w["seed_sigma"]
+    if isinstance(s, list):
+        return potentials_multi(w["n"], s)
+    return potentials(w["n"], s)
+
+
+def uneven_batch(nprob=256, seed=9, nmin=1e3, nmax=2e5):
+    """Uneven batch recipe: N log-uniform in [nmin, nmax]; exactly half the problems
+    uniform and half from 4 Gaussian clusters (width 0.03), assigned by a seeded
+    permutation; half 1/r and half exp(-r^2/0.01) by an independent permutation.
+    Returns a list of dicts with points (3, n) and sigma (n,)."""
+    ss = np.random.SeedSequence(seed)
+    top = _rng(ss.spawn(1)[0])
+    ns = np.rint(np.exp(top.uniform(np.log(nmin), np.log(nmax), nprob))).astype(np.int64)
+    dist = np.array(["uniform"] * (nprob // 2) + ["cluster"] * (nprob - nprob // 2))
+    dist = dist[top.permutation(nprob)]
+    kern = np.array(["laplace"] * (nprob // 2) + ["gauss"] * (nprob - nprob // 2))
+    kern = kern[top.permutation(nprob)]
+    out = []
+    for i, child in enumerate(ss.spawn(nprob)):
+        a, b, c, e = child.generate_state(4)
+        n = int(ns[i])
+        if dist[i] == "uniform":
+            pts = uniform_points(n, int(a))
+        else:
+            pts = cluster_points(n, 4, 0.03, int(a), int(b))
+        out.append(dict(n=n, dist=str(dist[i]), kernel=str(kern[i]),
+                        param=0.01 if kern[i] == "gauss" else 0.0,
+                        points=pts, sigma=potentials(n, int(c))))
+    return out

@@ -1,0 +1,46 @@
+"""The oracle's pins must reject plausible mistakes.  Each case plants one
+mistake in a copy of the oracle source (on the CPU), builds it, and checks that
+the pin tests fail against it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "eifmm_oracle.c")
+
+MUTANTS = {
+    "l2l_uses_delta_not_delta_t": ("apply_delta_t(dp, P->dmax, lp->B, lp->G, l[k - 1]",
+                                   "apply_delta(dp, P->dmax, lp->B, lp->G, l[k - 1]"),
+    "m2m_child_shift_sign": ("double xm[3] = {lv->X[3 * m] - sh[0]",
+                             "double xm[3] = {lv->X[3 * m] + sh[0]"),
+    "m2l_offset_sign": ("double yl[3] = {lv->Y[3 * ll] + dv[0]",
+                        "double yl[3] = {lv->Y[3 * ll] - dv[0]"),
+    "p2m_centre_sign": ("double yc[3] = {ps[3 * j] - c[0]", "double yc[3] = {ps[3 * j] + c[0]"),
+    "gamma_recursion_sign": ("Gm[k * dmax + l] = s; /* unit", "Gm[k * dmax + l] = -s; /* unit"),
+    "near_field_keeps_self": (
+        "if (sing && zx == 0.0 && zy == 0.0 && zz == 0.0) continue;\n            s += ss[j]",
+        "if (0) continue;\n            s += ss[j]"),
+    "interaction_list_parent_rule": ("if (!inside || pc > 1) continue;",
+                                     "if (!inside || pc > 2) continue;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    a, b = MUTANTS[name]
+    src = open(SRC).read()
+    assert a in src
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(a, b, 1))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-std=c99",
+                    "-D_DEFAULT_SOURCE", "-o", str(so), str(mut), "-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pass.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_eim.py"),
+                        "-k", "finite_rank or gamma or interpolation or c1_accuracy"],
+                       env=env, capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode != 0, f"mutant {name} survived:\n{r.stdout[-2000:]}"
