@@ -1,0 +1,185 @@
+/*
+ * eifmm.h -- C ABI of the MI355X EIFMM evaluation library (libeifmm.so).
+ *
+ * The library computes the fast summation of F. Casenave, "A Fast Summation
+ * Method for translation invariant kernels" (arXiv:1408.0210), eq. (1):
+ *
+ *     f(x_i) = sum_{j=1..N} sigma_j K(x_i, x_j),   i = 1..N,
+ *
+ * for translation-invariant 3D kernels K(x, y) = k(x - y), with targets equal
+ * to sources (the N-body setting of Sec. 1).  Following the problem statement
+ * of Sec. 1, the domain Omega and N are fixed per plan while the points and the
+ * potentials change from query to query:
+ *
+ *     eifmm_plan_create   per-level EIM (Algorithm 1) and operator tables,
+ *                         host FP64, uploaded once                (Sec. 2, 4.1, 4.2)
+ *     eifmm_set_points    octree build on the GPU: Morton keys, stable sort,
+ *                         leaf ranges, active boxes, near lists   (Sec. 3.3)
+ *     eifmm_evaluate      Algorithm 3 steps 1-7 plus the near field of eq. (13),
+ *                         all on the GPU                          (Sec. 3.3.4)
+ *
+ * Conventions
+ *   - Device pointers are HIP device pointers (e.g. from PyTorch tensors).
+ *     Points are SoA: coordinate a of point i at xyz[a * n + i], FP64.
+ *     sigma and f are column-major n x nrhs FP64 blocks with leading
+ *     dimensions ld and ldf (>= n).
+ *   - The caller owns every buffer it passes; the library keeps no caller
+ *     pointer after a call returns (points are copied into internal
+ *     Morton-ordered storage).  The library owns its tables and workspaces
+ *     until eifmm_plan_destroy.
+ *   - Calls enqueue work on the given HIP stream (NULL = default stream) and
+ *     return before it finishes, except eifmm_set_points, which waits for the
+ *     tree build so it can report invalid points, and the export calls, which
+ *     copy to host memory and wait.
+ *   - Every call returns 0 (EIFMM_OK) or a negative status.  A failed call
+ *     leaves the plan usable (or, for plan_create, nothing to destroy).
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef EIFMM_H
+#define EIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define EIFMM_OK 0
+#define EIFMM_EINVAL (-1)  /* null pointer, bad size, nrhs > max_rhs, struct_size mismatch */
+#define EIFMM_EDOMAIN (-2) /* a point outside the closed domain, or not finite            */
+#define EIFMM_ESTATE (-3)  /* evaluate before set_points, or a host-only plan             */
+#define EIFMM_EEIM (-4)    /* EIM reached dmax before the tolerance                       */
+#define EIFMM_ENOMEM (-5)  /* host or device allocation failed                            */
+#define EIFMM_EHIP (-6)    /* a HIP call failed; eifmm_stats.hip_error holds the code     */
+
+/* kernels k(z), r = |z| */
+#define EIFMM_K_LAPLACE 0 /* 1/r, singular (pairs at r = 0 are skipped)          */
+#define EIFMM_K_YUKAWA 1  /* exp(-a r)/r, a = kernel_param, singular             */
+#define EIFMM_K_GAUSS 2   /* exp(-r^2/h2), h2 = kernel_param                     */
+#define EIFMM_K_SQDIST 3  /* r^2: rank-5 test kernel, the EIM is exact           */
+
+/* precision of the pass */
+#define EIFMM_PREC_FP64 0  /* every step in FP64                                   */
+#define EIFMM_PREC_MIXED 1 /* M2L on FP32 MFMA with FP32 accumulation, P2P in FP32
+                              with leaf-local coordinates and compensated sums;
+                              EIM, triangular solves, M2M, L2L, P2M, L2P and the
+                              final f in FP64                                     */
+
+/* flags */
+#define EIFMM_FLAG_HOST_ONLY 1 /* plan_create runs the host setup only (no device
+                                  tables); only eifmm_get_level/get_stats work   */
+
+#define EIFMM_MAX_DEPTH 8
+
+typedef struct eifmm_plan_s *eifmm_plan; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t struct_size;  /* sizeof(eifmm_config)                                    */
+  int32_t kernel;       /* EIFMM_K_*                                               */
+  double kernel_param;  /* a (Yukawa) or h2 (Gauss); ignored otherwise              */
+  double lo[3];         /* domain [lo, lo+L]^3 (closed; Sec. 1: fixed per plan)     */
+  double L;             /* side of the cube, > 0                                    */
+  int64_t n;            /* N, fixed per plan (Sec. 1)                               */
+  int32_t depth;        /* kappa: leaf level, 0..EIFMM_MAX_DEPTH; the far field uses
+                           levels 2..kappa, kappa < 2 is near field only (Sec. 3.3) */
+  int32_t max_rhs;      /* largest nrhs accepted by evaluate (>= 1)                 */
+  double eim_tol;       /* tau > 0: the greedy stops when eps_k <= tau * scale       */
+  int32_t tol_mode;     /* 0: scale = max |K| over the level's training grid;
+                           1: scale = that of the finest level, for all levels      */
+  int32_t precision;    /* EIFMM_PREC_*                                             */
+  int32_t dmax;         /* cap on d_k (0 = 1024); reaching it is EIFMM_EEIM          */
+  int32_t flags;        /* EIFMM_FLAG_*                                             */
+} eifmm_config;
+
+/* evaluation phases timed when timing is enabled (eifmm_set_timing) */
+#define EIFMM_PH_TREE 0  /* keys, sort, gather, leaf ranges, lists (set_points)   */
+#define EIFMM_PH_P2P 1   /* near field, eq. (13)                                  */
+#define EIFMM_PH_P2M 2   /* Algorithm 3 step 1                                    */
+#define EIFMM_PH_M2M 3   /* step 2                                                */
+#define EIFMM_PH_WHAT 4  /* step 3 (triangular solves)                            */
+#define EIFMM_PH_M2L 5   /* step 4                                                */
+#define EIFMM_PH_L2L 6   /* step 5                                                */
+#define EIFMM_PH_LHAT 7  /* step 6 (triangular solves)                            */
+#define EIFMM_PH_L2P 8   /* step 7 plus f = f_far + f_near in input order         */
+#define EIFMM_NPHASE 9
+
+typedef struct {
+  int32_t struct_size;               /* sizeof(eifmm_stats)                      */
+  int32_t depth;
+  int32_t d[EIFMM_MAX_DEPTH + 1];    /* d_k for k = 2..depth (0 elsewhere)        */
+  int32_t dpad[EIFMM_MAX_DEPTH + 1]; /* padded row count used on the device       */
+  double eim_err[EIFMM_MAX_DEPTH + 1]; /* final training error / scale per level  */
+  double setup_ms;                   /* plan_create host time                     */
+  double phase_ms[EIFMM_NPHASE];     /* accumulated GPU time per phase            */
+  int64_t phase_calls[EIFMM_NPHASE]; /* timed launches of each phase              */
+  double m2l_flops;                  /* algorithmic M2L flops of the last evaluate
+                                        (2 d_k^2 per interaction pair per RHS)    */
+  int64_t active_boxes[EIFMM_MAX_DEPTH + 1]; /* non-empty boxes per level        */
+  int64_t il_pairs[EIFMM_MAX_DEPTH + 1];     /* interaction-list pairs per level */
+  int64_t near_pairs;                /* ordered leaf pairs in the near lists      */
+  int32_t hip_error;                 /* last hipError_t seen (0 = none)           */
+  int32_t reserved;
+} eifmm_stats;
+
+/* Per-level EIM plan: runs Algorithm 1 for k = 2..depth on the training sets,
+ * factors K(X^k, Y^k) = Gamma B^T (the Delta = B^{-T} Gamma^{-1} of eq. (5)),
+ * builds the 8 M2M and 8 L2L operators per level by triangular solves (Sec. 4.1)
+ * and the 316 translation-invariant M2L matrices per level (Sec. 4.2), then
+ * uploads them and allocates workspaces for n points and max_rhs.  *out is set
+ * only on success. */
+int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out);
+
+/* Builds the octree for n points xyz (device, 3 x n SoA FP64): Morton keys of
+ * the leaf cells, a stable sort by (key, input index), Morton-ordered copies,
+ * leaf ranges, active boxes per level and the near lists.  Returns
+ * EIFMM_EDOMAIN if a point is outside [lo, lo+L]^3 or not finite (the plan then
+ * has no points).  Waits for the build. */
+int eifmm_set_points(eifmm_plan plan, const double *xyz_dev, void *hip_stream);
+
+/* f = K sigma for nrhs right-hand sides: sigma_dev (n x nrhs, column-major,
+ * leading dimension ld) in input order; f_dev (n x nrhs, leading dimension ldf)
+ * is overwritten in input order.  Requires set_points; nrhs <= max_rhs. */
+int eifmm_evaluate(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
+                   double *f_dev, int64_t ldf, void *hip_stream);
+
+/* Enables (1) or disables (0) per-phase HIP-event timing; resets the totals. */
+int eifmm_set_timing(eifmm_plan plan, int32_t enable);
+
+/* Copies statistics (waits for pending timed work). */
+int eifmm_get_stats(eifmm_plan plan, eifmm_stats *out);
+
+/* Host copies of level k's EIM data: d, X (I_0 points) and Y (J_0 points) as
+ * d x 3 physical coordinates, training indices ia/ib, B and Gamma (d x d
+ * row-major).  Any output may be NULL; call with all NULL to get d. */
+int eifmm_get_level(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
+                    int64_t *ib, double *B, double *Gamma);
+
+/* Host copies of the current tree: perm[n] (input index of each Morton-ordered
+ * point), leaf_start[8^depth + 1], keys[n] (leaf key of each sorted point). */
+int eifmm_export_tree(eifmm_plan plan, int32_t *perm, int64_t *leaf_start, uint32_t *keys);
+
+/* Builds (on the device) and copies the lists of `level`: active boxes in key
+ * order, near lists (Chebyshev distance <= 1) and, for level >= 2, interaction
+ * lists with offset ids (rank of (dx+3)+7(dy+3)+49(dz+3) among the 316 offsets),
+ * each sorted by source key.  Capacities: active 8^level, near 27 * 8^level,
+ * il 189 * 8^level.  *nactive receives the active count. */
+int eifmm_export_lists(eifmm_plan plan, int32_t level, int64_t *nactive, uint32_t *active,
+                       int64_t *near_ptr, uint32_t *near_src, int64_t *il_ptr, uint32_t *il_src,
+                       int16_t *il_off);
+
+/* Host copy of one expansion of the last evaluate, right-hand side `rhs`, as a
+ * dense 8^k x d_k array in key order (zeros for empty boxes).  which: 0 = W,
+ * 1 = What (= Delta W), 2 = g (M2L output), 3 = l, 4 = lhat (level depth only). */
+int eifmm_export_expansion(eifmm_plan plan, int32_t which, int32_t k, int32_t rhs, double *out);
+
+/* Releases the plan and all its device memory. */
+int eifmm_plan_destroy(eifmm_plan plan);
+
+/* Static description of a status code. */
+const char *eifmm_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EIFMM_H */

@@ -1,0 +1,40 @@
+// devutil.hpp -- small device helpers shared by the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eifmm {
+
+// Morton interleave of three 10-bit indices: bit b of v goes to bit 3b.
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v ^ (v >> 2)) & 0x030C30C3u;
+  v = (v ^ (v >> 4)) & 0x0300F00Fu;
+  v = (v ^ (v >> 8)) & 0xFF0000FFu;
+  v = (v ^ (v >> 16)) & 0x000003FFu;
+  return v;
+}
+
+__host__ __device__ inline uint32_t morton_encode(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// index along axis a (0 = x, 1 = y, 2 = z) of a Morton key
+__host__ __device__ inline uint32_t morton_axis(uint32_t key, int a) { return compact3(key >> a); }
+
+// Exclusive prefix sums over n entries (in may equal out); tmp needs
+// (n + 1023) / 1024 + 1 ints.  Enqueued on stream s.
+void scan_exclusive_i32(const int *in, int *out, int64_t n, int *tmp, hipStream_t s);
+void scan_exclusive_u32(const unsigned *in, unsigned *out, int64_t n, int *tmp, hipStream_t s);
+
+}  // namespace eifmm

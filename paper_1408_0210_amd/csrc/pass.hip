@@ -1,0 +1,987 @@
+// pass.hip -- the EIFMM evaluation pass (Algorithm 3 plus the near field).
+//
+// Expansions of level k live in slot-major arrays [slot][rhs][dp_k] (slot =
+// rank of a non-empty box in key order; dp_k = d_k padded to 16 with zeros).
+// Steps and kernels:
+//   near field, eq. (13)        k_p2p64 / k_p2p32   one wave per target leaf
+//   1  P2M                      k_p2m               one workgroup per leaf
+//   2  M2M (Sec. 4.1 operators) k_gemm<MODE_M2M>    MFMA, 8 children per parent
+//   3  What = Delta W           k_solve             blocked triangular solves
+//   4  M2L (Sec. 4.2 matrices)  k_gemm<MODE_M2L>    MFMA, 189 offsets per class
+//   5  L2L                      k_gemm<MODE_L2L>    MFMA, adds g
+//   6  lhat = Delta^T l         k_solve
+//   7  L2P and f = f_far + f_near in input order    k_l2p
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "devutil.hpp"
+#include "plan.hpp"
+
+namespace eifmm {
+
+// ------------------------------------------------------------------ kernels k
+template <int KIND>
+struct KF {
+  static constexpr bool singular = (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA);
+  // p: Yukawa a, Gauss 1/h2
+  __device__ static inline double eval(double r2, double p) {
+    if constexpr (KIND == EIFMM_K_LAPLACE) {
+      return rsqrt(r2);
+    } else if constexpr (KIND == EIFMM_K_YUKAWA) {
+      double ri = rsqrt(r2);
+      return exp(-p * (r2 * ri)) * ri;
+    } else if constexpr (KIND == EIFMM_K_GAUSS) {
+      return exp(-r2 * p);
+    } else {
+      return r2;
+    }
+  }
+  __device__ static inline float evalf(float r2, float p) {
+    if constexpr (KIND == EIFMM_K_LAPLACE) {
+      return rsqrtf(r2);
+    } else if constexpr (KIND == EIFMM_K_YUKAWA) {
+      float ri = rsqrtf(r2);
+      return expf(-p * (r2 * ri)) * ri;
+    } else if constexpr (KIND == EIFMM_K_GAUSS) {
+      return expf(-r2 * p);
+    } else {
+      return r2;
+    }
+  }
+};
+
+__host__ __device__ inline double dev_param(int kind, double p) {
+  return kind == EIFMM_K_GAUSS ? 1.0 / p : p;
+}
+
+// ------------------------------------------------------------------ sigma
+__global__ void k_gather_sigma(int64_t n, int nrhs, const double *__restrict__ sigma, int64_t ld,
+                               const int *__restrict__ perm, double *__restrict__ sig) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  int64_t s = e / nrhs;
+  int r = (int)(e - s * nrhs);
+  sig[e] = sigma[(int64_t)perm[s] + (int64_t)r * ld];
+}
+
+// ------------------------------------------------------------------ near field
+// One 64-lane workgroup per non-empty target leaf; lanes own targets; sources of
+// the neighbour leaves (ascending key) are staged through LDS 64 at a time.
+template <int KIND, int RB>
+__global__ __launch_bounds__(64) void k_p2p64(const uint32_t *__restrict__ act,
+                                              const int *__restrict__ ls,
+                                              const int *__restrict__ near_ptr,
+                                              const int *__restrict__ near_src,
+                                              const double *__restrict__ xyz, int64_t n,
+                                              const double *__restrict__ sig, int nrhs,
+                                              double *__restrict__ fnear, double p) {
+  __shared__ double sx[64], sy[64], sz[64], ss[64 * RB];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const uint32_t key = act[j];
+  const int a = ls[key], b = ls[key + 1];
+  const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
+  for (int t0 = a; t0 < b; t0 += 64) {
+    const int i = t0 + lane;
+    const bool tv = i < b;
+    const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0,
+                 zi = tv ? xyz[2 * n + i] : 0.0;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+      double acc[RB];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        const uint32_t skey = act[near_src[q]];
+        const int c0 = ls[skey], c1 = ls[skey + 1];
+        for (int s0 = c0; s0 < c1; s0 += 64) {
+          const int cnt = min(64, c1 - s0);
+          __syncthreads();
+          if (lane < cnt) {
+            const int sidx = s0 + lane;
+            sx[lane] = xyz[sidx];
+            sy[lane] = xyz[n + sidx];
+            sz[lane] = xyz[2 * n + sidx];
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr)
+              ss[lane * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
+          }
+          __syncthreads();
+          for (int u = 0; u < cnt; ++u) {
+            const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double kv = KF<KIND>::eval(r2, p);
+            if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
+          }
+        }
+      }
+      if (tv) {
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+          if (r0 + rr < nrhs) fnear[(int64_t)i * nrhs + r0 + rr] = acc[rr];
+      }
+    }
+  }
+}
+
+// FP32 near field: coordinates relative to the target leaf centre (source
+// leaf-local coordinates plus the exact offset between the two centres), FP32
+// kernel values, Neumaier-compensated FP32 sums returned as hi + lo in FP64.
+template <int KIND, int RB>
+__global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
+                                              const int *__restrict__ ls,
+                                              const int *__restrict__ near_ptr,
+                                              const int *__restrict__ near_src,
+                                              const float *__restrict__ xl, int64_t n,
+                                              const double *__restrict__ sig, int nrhs,
+                                              double *__restrict__ fnear, float h, float p) {
+  __shared__ float sx[64], sy[64], sz[64], ss[64 * RB];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const uint32_t key = act[j];
+  const int a = ls[key], b = ls[key + 1];
+  const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
+  const int tn0 = (int)morton_axis(key, 0), tn1 = (int)morton_axis(key, 1),
+            tn2 = (int)morton_axis(key, 2);
+  for (int t0 = a; t0 < b; t0 += 64) {
+    const int i = t0 + lane;
+    const bool tv = i < b;
+    const float xi = tv ? xl[i] : 0.f, yi = tv ? xl[n + i] : 0.f, zi = tv ? xl[2 * n + i] : 0.f;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+      float sum[RB], cmp[RB];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) sum[rr] = cmp[rr] = 0.f;
+      for (int q = q0; q < q1; ++q) {
+        const uint32_t skey = act[near_src[q]];
+        const int c0 = ls[skey], c1 = ls[skey + 1];
+        const float ox = (float)((int)morton_axis(skey, 0) - tn0) * h;
+        const float oy = (float)((int)morton_axis(skey, 1) - tn1) * h;
+        const float oz = (float)((int)morton_axis(skey, 2) - tn2) * h;
+        for (int s0 = c0; s0 < c1; s0 += 64) {
+          const int cnt = min(64, c1 - s0);
+          __syncthreads();
+          if (lane < cnt) {
+            const int sidx = s0 + lane;
+            sx[lane] = xl[sidx] + ox;
+            sy[lane] = xl[n + sidx] + oy;
+            sz[lane] = xl[2 * n + sidx] + oz;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr)
+              ss[lane * RB + rr] =
+                  (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
+          }
+          __syncthreads();
+          for (int u = 0; u < cnt; ++u) {
+            const float dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float kv = KF<KIND>::evalf(r2, p);
+            if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              const float v = ss[u * RB + rr] * kv;
+              const float tsum = sum[rr] + v;
+              cmp[rr] += (fabsf(sum[rr]) >= fabsf(v)) ? ((sum[rr] - tsum) + v)
+                                                      : ((v - tsum) + sum[rr]);
+              sum[rr] = tsum;
+            }
+          }
+        }
+      }
+      if (tv) {
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+          if (r0 + rr < nrhs)
+            fnear[(int64_t)i * nrhs + r0 + rr] = (double)sum[rr] + (double)cmp[rr];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ P2M
+// W^I_m = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I)  (Algorithm 3, step 1)
+// One 256-thread workgroup per leaf; thread t owns rows m = t + 256 u.
+template <int KIND, int RB>
+__global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
+                                             const int *__restrict__ ls,
+                                             const double *__restrict__ X, int d, int dp,
+                                             const double *__restrict__ xyz, int64_t n,
+                                             const double *__restrict__ sig, int nrhs,
+                                             double *__restrict__ W, double lo0, double lo1,
+                                             double lo2, double h, double p) {
+  __shared__ double px[64], py[64], pz[64], ps[64 * RB];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const uint32_t key = act[j];
+  const int a = ls[key], b = ls[key + 1];
+  const double cx = lo0 + ((double)morton_axis(key, 0) + 0.5) * h;
+  const double cy = lo1 + ((double)morton_axis(key, 1) + 0.5) * h;
+  const double cz = lo2 + ((double)morton_axis(key, 2) + 0.5) * h;
+  const int nu = (dp + 255) / 256;
+  double xm[4], ym[4], zm[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int m = t + 256 * u;
+    const bool ok = u < nu && m < d;
+    xm[u] = ok ? X[3 * m] : 0.0;
+    ym[u] = ok ? X[3 * m + 1] : 0.0;
+    zm[u] = ok ? X[3 * m + 2] : 0.0;
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    double acc[4][RB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) acc[u][rr] = 0.0;
+    for (int s0 = a; s0 < b; s0 += 64) {
+      const int cnt = min(64, b - s0);
+      __syncthreads();
+      if (t < cnt) {
+        const int s = s0 + t;
+        px[t] = xyz[s] - cx;
+        py[t] = xyz[n + s] - cy;
+        pz[t] = xyz[2 * n + s] - cz;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+          ps[t * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)s * nrhs + r0 + rr] : 0.0;
+      }
+      __syncthreads();
+      for (int q = 0; q < cnt; ++q) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u < nu) {
+            const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
+            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, p);
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) acc[u][rr] += ps[q * RB + rr] * kv;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = t + 256 * u;
+      if (u < nu && m < dp) {
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+          if (r0 + rr < nrhs) W[((int64_t)j * nrhs + r0 + rr) * dp + m] = m < d ? acc[u][rr] : 0.0;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ L2P + combine
+// f(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I + f_near(x_i), written to
+// the input position of x_i (Algorithm 3, step 7).
+template <int KIND, int RB>
+__global__ __launch_bounds__(64) void k_l2p(const uint32_t *__restrict__ act,
+                                            const int *__restrict__ ls,
+                                            const double *__restrict__ X, int d, int dp,
+                                            const double *__restrict__ lhat,
+                                            const double *__restrict__ xyz, int64_t n,
+                                            const double *__restrict__ fnear,
+                                            const int *__restrict__ perm, double *__restrict__ f,
+                                            int64_t ldf, int nrhs, double lo0, double lo1,
+                                            double lo2, double h, double p) {
+  extern __shared__ double sm[];
+  double *sX = sm, *sl = sm + 3 * dp;
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const uint32_t key = act[j];
+  const int a = ls[key], b = ls[key + 1];
+  const double cx = lo0 + ((double)morton_axis(key, 0) + 0.5) * h;
+  const double cy = lo1 + ((double)morton_axis(key, 1) + 0.5) * h;
+  const double cz = lo2 + ((double)morton_axis(key, 2) + 0.5) * h;
+  for (int e = lane; e < 3 * d; e += 64) sX[e] = X[e];
+  for (int t0 = a; t0 < b; t0 += 64) {
+    const int i = t0 + lane;
+    const bool tv = i < b;
+    const double xc = tv ? xyz[i] - cx : 0.0, yc = tv ? xyz[n + i] - cy : 0.0,
+                 zc = tv ? xyz[2 * n + i] - cz : 0.0;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+      __syncthreads();
+      for (int e = lane; e < RB * d; e += 64) {
+        const int rr = e / d, l = e - rr * d;
+        sl[rr * dp + l] = (r0 + rr < nrhs) ? lhat[((int64_t)j * nrhs + r0 + rr) * dp + l] : 0.0;
+      }
+      __syncthreads();
+      double acc[RB];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
+      for (int l = 0; l < d; ++l) {
+        const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
+        const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, p);
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
+      }
+      if (tv) {
+        const int64_t o = perm[i];
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr)
+          if (r0 + rr < nrhs)
+            f[o + (int64_t)(r0 + rr) * ldf] = acc[rr] + fnear[(int64_t)i * nrhs + r0 + rr];
+      }
+    }
+  }
+}
+
+// depth < 2: no far field, f = f_near in input order
+__global__ void k_combine_near(int64_t n, int nrhs, const double *__restrict__ fnear,
+                               const int *__restrict__ perm, double *__restrict__ f, int64_t ldf) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  int64_t s = e / nrhs;
+  int r = (int)(e - s * nrhs);
+  f[(int64_t)perm[s] + (int64_t)r * ldf] = fnear[e];
+}
+
+__global__ void k_f32_to_f64(int64_t m, const float *__restrict__ in, double *__restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) out[e] = (double)in[e];
+}
+
+// ------------------------------------------------------------------ triangular solves
+// One thread per column (box, rhs).  Forward substitution with the lower
+// factor, then backward substitution with the upper factor, both blocked in
+// 16 x 16 tiles: a tile row of the unknowns stays in registers, the factor
+// tiles are read at uniform addresses.
+//   Delta   v: Gamma z = v, then B^T w = z        (UF = false, UB = true)
+//   Delta^T v: B z = v,     then Gamma^T w = z    (UF = true,  UB = false)
+struct SolveDesc {
+  const double *in;
+  double *out;
+  float *out32;
+  const double *Tf, *Tb;
+  int ncols, dp, blk_start, pad;
+};
+struct SolveArgs {
+  SolveDesc lv[kMaxLevels];
+  int nlev;
+};
+
+template <bool UF, bool UB>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
+  int li = 0;
+  for (int q = 1; q < A.nlev; ++q)
+    if ((int)blockIdx.x >= A.lv[q].blk_start) li = q;
+  const SolveDesc &D = A.lv[li];
+  const int c = ((int)blockIdx.x - D.blk_start) * 256 + (int)threadIdx.x;
+  if (c >= D.ncols) return;
+  const int dp = D.dp, nb = dp >> 4;
+  const double *x = D.in + (int64_t)c * dp;
+  double *y = D.out + (int64_t)c * dp;
+  for (int bi = 0; bi < nb; ++bi) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = x[16 * bi + q];
+    for (int bj = 0; bj < bi; ++bj) {
+      const double *T = D.Tf + ((int64_t)bi * nb + bj) * 256;
+      double z[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) z[q] = y[16 * bj + q];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * z[jj];
+    }
+    const double *T = D.Tf + ((int64_t)bi * nb + bi) * 256;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+#pragma unroll
+      for (int jj = 0; jj < i; ++jj) v[i] -= T[i * 16 + jj] * v[jj];
+      if (!UF) v[i] = v[i] / T[i * 16 + i];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y[16 * bi + q] = v[q];
+  }
+  for (int bi = nb - 1; bi >= 0; --bi) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = y[16 * bi + q];
+    for (int bj = bi + 1; bj < nb; ++bj) {
+      const double *T = D.Tb + ((int64_t)bi * nb + bj) * 256;
+      double z[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) z[q] = y[16 * bj + q];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * z[jj];
+    }
+    const double *T = D.Tb + ((int64_t)bi * nb + bi) * 256;
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+#pragma unroll
+      for (int jj = i + 1; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * v[jj];
+      if (!UB) v[i] = v[i] / T[i * 16 + i];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y[16 * bi + q] = v[q];
+    if (D.out32) {
+      float *y32 = D.out32 + (int64_t)c * dp;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) y32[16 * bi + q] = (float)v[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ gathered GEMM
+// C[:, col] (+)= sum_t A_t B_t[:, col] for the columns of a target group, where
+// B_t[:, col] is the expansion of the source box that term t pairs with the
+// column's target box (M2L: the box at offset delta; M2M: child t; L2L: the
+// parent).  A workgroup computes a 96-row x 128-column tile with 16x16x4 MFMAs;
+// 4 waves in a 2 x 2 arrangement each own 3 x 4 output blocks.  Operand chunks
+// of 16 k values pass through LDS in MFMA fragment order; the next chunk is
+// loaded into registers while the current one is multiplied.
+constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2;
+constexpr int GT_RB = 6, GT_CB = 8, GT_COLS = 16 * GT_CB;
+
+template <typename T>
+struct Mfma;
+// Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result layouts differ: FP64 keeps rows (l / 16) + 4 q of column l % 16 in
+// register q, FP32 rows 4 (l / 16) + q.
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double2 t;
+};
+template <>
+struct Pair<float> {
+  typedef float2 t;
+};
+
+template <typename T, int MODE>
+__device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
+                                       int r, const int8_t *__restrict__ dvec) {
+  if (!cvalid) return nullptr;
+  uint32_t skey;
+  if constexpr (MODE == MODE_M2L) {
+    const int id = J.terms[term];
+    const int side = 1 << J.level;
+    const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
+    const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
+    const int m2 = (int)morton_axis(tkey, 2) + dvec[3 * id + 2];
+    if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return nullptr;
+    skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
+  } else if constexpr (MODE == MODE_M2M) {
+    skey = tkey * 8u + (uint32_t)term;
+  } else {
+    skey = tkey >> 3;
+  }
+  const int s = J.src_slot[skey];
+  if (s < 0) return nullptr;
+  return (const T *)J.Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
+}
+
+template <typename T, int MODE>
+__device__ inline const T *gemm_operand(const GemmJob &J, int term) {
+  int64_t idx;
+  if constexpr (MODE == MODE_M2L)
+    idx = J.terms[term];
+  else if constexpr (MODE == MODE_M2M)
+    idx = term;
+  else
+    idx = J.cls;
+  return (const T *)J.A + idx * J.a_stride;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
+                                                 int ntiles, const int8_t *__restrict__ dvec) {
+  typedef typename Mfma<T>::v4 V4;
+  typedef typename Pair<T>::t P2;
+  __shared__ T As[GT_RB * 4 * 64];
+  __shared__ T Bs[4 * GT_CB * 64];
+
+  // tiles of one job are contiguous and land on one XCD (blocks go round-robin
+  // over the 8 XCDs)
+  const int per = (ntiles + 7) / 8;
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= ntiles) return;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tiles_start <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmJob J = jobs[lo];
+  const int local = tile - J.tiles_start;
+  const int rowtile = local % J.nrowtiles, coltile = local / J.nrowtiles;
+  const int rb0 = rowtile * GT_RB, col0 = coltile * GT_COLS;
+  const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
+  const int ncols = J.ntgt * J.nrhs;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+
+  // the column this thread loads
+  const int jl = t >> 1, hh = t & 1;
+  const int jc = col0 + jl;
+  const bool cvalid = jc < ncols;
+  int r = 0;
+  uint32_t tkey = 0;
+  if (cvalid) {
+    const int tt = jc / J.nrhs;
+    r = jc - tt * J.nrhs;
+    const int ts = J.tgt ? J.tgt[tt] : tt;
+    tkey = J.tgt_keys[ts];
+  }
+
+  V4 acc[3][4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = V4{0, 0, 0, 0};
+  bool rowok[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) rowok[i] = rb0 + 3 * wr + i < nrb;
+
+  const int total = J.nterms * nkc;
+  P2 ra[3], rbv[4];
+  const T *srcp = nullptr;
+  const T *Ap = nullptr;
+  auto fetch = [&](int it) {
+    const int term = it / nkc, kc = it - term * nkc;
+    if (kc == 0) {
+      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, r, dvec);
+      Ap = gemm_operand<T, MODE>(J, term);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = 2 * t + 512 * q;
+      const int rb = rb0 + (e >> 8);
+      if (rb < nrb)
+        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + (e & 255));
+      else
+        ra[q] = P2{0, 0};
+    }
+    if (srcp) {
+      const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
+    }
+  };
+
+  if (total > 0) fetch(0);
+  for (int it = 0; it < total; ++it) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) *(P2 *)(As + 2 * t + 512 * q) = ra[q];
+    {
+      const int cb = jl >> 4, c16 = jl & 15;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int kl = 8 * hh + 2 * q + e;
+          const T v = e ? rbv[q].y : rbv[q].x;
+          Bs[((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (it + 1 < total) fetch(it + 1);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      T a[3], b[4];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a[i] = As[((3 * wr + i) * 4 + ks) * 64 + lane];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) b[jj] = Bs[(ks * GT_CB + 4 * wc + jj) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (rowok[i]) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
+        }
+    }
+  }
+
+  // write the tile (result layout per Mfma<T>::row)
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int jo = col0 + 16 * (4 * wc + jj) + (lane & 15);
+    if (jo >= ncols) continue;
+    const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
+    const int ts = J.tgt ? J.tgt[tt] : tt;
+    const int64_t cbase = ((int64_t)ts * J.nrhs + ro) * J.dpm;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (!rowok[i]) continue;
+      const int rbase = 16 * (rb0 + 3 * wr + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t o = cbase + rbase + Mfma<T>::row(lane, q);
+        T v = acc[i][jj][q];
+        if constexpr (MODE == MODE_L2L) {
+          if (J.cadd_f32)
+            v += (T)((const float *)J.Cadd)[o];
+          else
+            v += (T)((const double *)J.Cadd)[o];
+        }
+        ((T *)J.C)[o] = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+
+// Per-phase HIP events; elapsed times are collected by timing_drain.
+struct Timer {
+  Plan &P;
+  hipStream_t s;
+  EventPair ep;
+  Timer(Plan &P_, hipStream_t s_, int ph) : P(P_), s(s_) {
+    if (!P.timing) return;
+    if (P.ev_pending.size() > 4096) timing_drain(P);
+    if (P.ev_free.empty()) {
+      EventPair e;
+      hipEventCreate(&e.a);
+      hipEventCreate(&e.b);
+      P.ev_free.push_back(e);
+    }
+    ep = P.ev_free.back();
+    P.ev_free.pop_back();
+    ep.phase = ph;
+    hipEventRecord(ep.a, s);
+  }
+  ~Timer() {
+    if (!P.timing) return;
+    hipEventRecord(ep.b, s);
+    P.ev_pending.push_back(ep);
+  }
+};
+
+int tiles_of(const GemmJob &J) { return J.ncoltiles * J.nrowtiles; }
+
+void finish_job(GemmJob &J, int &tiles) {
+  const int ncols = J.ntgt * J.nrhs;
+  J.ncoltiles = (ncols + GT_COLS - 1) / GT_COLS;
+  J.nrowtiles = (J.dpm / 16 + GT_RB - 1) / GT_RB;
+  J.tiles_start = tiles;
+  tiles += tiles_of(J);
+}
+
+}  // namespace
+
+// Job tables of a (points, nrhs) pair, uploaded once and reused.
+int build_jobs(Plan &P, int nrhs) {
+  const int depth = P.depth;
+  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
+  std::vector<GemmJob> h;
+  auto &jt = P.jobs;
+  jt = JobTables{};
+  // M2M, one job per parent level k = depth-1 .. 2
+  for (int k = depth - 1; k >= 2; --k) {
+    int tiles = 0;
+    GemmJob J{};
+    J.A = P.ld[k].m2m;
+    J.Bsrc = P.ld[k + 1].W;
+    J.C = P.ld[k].W;
+    J.tgt = nullptr;
+    J.tgt_keys = P.ld[k].act;
+    J.src_slot = P.ld[k + 1].slot;
+    J.a_stride = (int64_t)P.lh[k].dp * P.lh[k + 1].dp;
+    J.ntgt = (int)P.nact[k];
+    J.nterms = 8;
+    J.dpm = P.lh[k].dp;
+    J.dpk = P.lh[k + 1].dp;
+    J.level = k;
+    J.mode = MODE_M2M;
+    J.nrhs = nrhs;
+    finish_job(J, tiles);
+    jt.m2m_first[k] = (int)h.size();
+    jt.m2m_n[k] = 1;
+    jt.m2m_tiles[k] = tiles;
+    h.push_back(J);
+  }
+  // M2L, every level in one launch, finest level first
+  {
+    int tiles = 0;
+    jt.m2l_first = (int)h.size();
+    double flops = 0;
+    for (int k = depth; k >= 2; --k) {
+      for (int c = 0; c < 8; ++c) {
+        const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
+        if (nt == 0) continue;
+        GemmJob J{};
+        J.A = mixed ? (const void *)P.ld[k].kfrag32 : (const void *)P.ld[k].kfrag;
+        J.Bsrc = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
+        J.C = mixed ? (void *)P.ld[k].g32 : (void *)P.ld[k].g;
+        J.tgt = P.ld[k].cls + P.cls_off[k][c];
+        J.tgt_keys = P.ld[k].act;
+        J.src_slot = P.ld[k].slot;
+        J.terms = P.dlist + 189 * c;
+        J.a_stride = (int64_t)P.lh[k].dp * P.lh[k].dp;
+        J.ntgt = (int)nt;
+        J.nterms = 189;
+        J.dpm = J.dpk = P.lh[k].dp;
+        J.level = k;
+        J.cls = c;
+        J.mode = MODE_M2L;
+        J.nrhs = nrhs;
+        finish_job(J, tiles);
+        h.push_back(J);
+      }
+      flops += 2.0 * P.lh[k].d * (double)P.lh[k].d * (double)P.il_pairs[k] * nrhs;
+    }
+    jt.m2l_n = (int)h.size() - jt.m2l_first;
+    jt.m2l_tiles = tiles;
+    P.m2l_flops = flops;
+  }
+  // L2L, per child level k = 3 .. depth, one job per child class
+  for (int k = 3; k <= depth; ++k) {
+    int tiles = 0;
+    jt.l2l_first[k] = (int)h.size();
+    for (int c = 0; c < 8; ++c) {
+      const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
+      if (nt == 0) continue;
+      GemmJob J{};
+      J.A = P.ld[k - 1].l2l;
+      J.Bsrc = P.ld[k - 1].l;
+      J.C = P.ld[k].l;
+      J.Cadd = mixed ? (const void *)P.ld[k].g32 : (const void *)P.ld[k].g;
+      J.cadd_f32 = mixed ? 1 : 0;
+      J.tgt = P.ld[k].cls + P.cls_off[k][c];
+      J.tgt_keys = P.ld[k].act;
+      J.src_slot = P.ld[k - 1].slot;
+      J.a_stride = (int64_t)P.lh[k].dp * P.lh[k - 1].dp;
+      J.ntgt = (int)nt;
+      J.nterms = 1;
+      J.dpm = P.lh[k].dp;
+      J.dpk = P.lh[k - 1].dp;
+      J.level = k;
+      J.cls = c;
+      J.mode = MODE_L2L;
+      J.nrhs = nrhs;
+      finish_job(J, tiles);
+      h.push_back(J);
+    }
+    jt.l2l_n[k] = (int)h.size() - jt.l2l_first[k];
+    jt.l2l_tiles[k] = tiles;
+  }
+  if (P.job_dev) hipFree(P.job_dev);
+  P.job_dev = nullptr;
+  if (!h.empty()) {
+    if (hipMalloc(&P.job_dev, sizeof(GemmJob) * h.size()) != hipSuccess) return EIFMM_ENOMEM;
+    if (hipMemcpy(P.job_dev, h.data(), sizeof(GemmJob) * h.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return EIFMM_EHIP;
+  }
+  jt.nrhs = nrhs;
+  return EIFMM_OK;
+}
+
+namespace {
+
+template <typename T, int MODE>
+void launch_gemm(Plan &P, int first, int n, int tiles, hipStream_t s) {
+  if (n == 0 || tiles == 0) return;
+  const int grid = ((tiles + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_gemm<T, MODE>), dim3(grid), dim3(256), 0, s, P.job_dev + first, n, tiles,
+                     P.dvec);
+}
+
+template <int KIND>
+void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
+  const int depth = P.depth;
+  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
+  const double kp = dev_param(KIND, P.cfg.kernel_param);
+  const int64_t n = P.n;
+  const int nleafa = (int)P.nact[depth];
+  const double hleaf = std::ldexp(P.cfg.L, -depth);
+  LevelDev &LL = P.ld[depth];
+  // near field
+  if (nleafa > 0) {
+    Timer tm(P, s, EIFMM_PH_P2P);
+    if (mixed) {
+      if (nrhs == 1)
+        hipLaunchKernelGGL((k_p2p32<KIND, 1>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+                           P.near_ptr, P.near_src, P.xloc, n, P.sig, nrhs, P.fnear, (float)hleaf,
+                           (float)kp);
+      else
+        hipLaunchKernelGGL((k_p2p32<KIND, 8>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+                           P.near_ptr, P.near_src, P.xloc, n, P.sig, nrhs, P.fnear, (float)hleaf,
+                           (float)kp);
+    } else {
+      if (nrhs == 1)
+        hipLaunchKernelGGL((k_p2p64<KIND, 1>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+                           P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
+      else
+        hipLaunchKernelGGL((k_p2p64<KIND, 8>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+                           P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
+    }
+  }
+  if (depth < 2) {
+    const int64_t m = n * nrhs;
+    if (m > 0)
+      hipLaunchKernelGGL(k_combine_near, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n,
+                         nrhs, P.fnear, P.idx, f, ldf);
+    return;
+  }
+  const LevelHost &HL = P.lh[depth];
+  // step 1: P2M
+  if (nleafa > 0) {
+    Timer tm(P, s, EIFMM_PH_P2M);
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_p2m<KIND, 1>), dim3(nleafa), dim3(256), 0, s, LL.act, P.leaf_start,
+                         LL.X, HL.d, HL.dp, P.xyz, n, P.sig, nrhs, LL.W, P.cfg.lo[0], P.cfg.lo[1],
+                         P.cfg.lo[2], hleaf, kp);
+    else
+      hipLaunchKernelGGL((k_p2m<KIND, 8>), dim3(nleafa), dim3(256), 0, s, LL.act, P.leaf_start,
+                         LL.X, HL.d, HL.dp, P.xyz, n, P.sig, nrhs, LL.W, P.cfg.lo[0], P.cfg.lo[1],
+                         P.cfg.lo[2], hleaf, kp);
+  }
+  // step 2: M2M
+  {
+    Timer tm(P, s, EIFMM_PH_M2M);
+    for (int k = depth - 1; k >= 2; --k)
+      launch_gemm<double, MODE_M2M>(P, P.jobs.m2m_first[k], P.jobs.m2m_n[k], P.jobs.m2m_tiles[k],
+                                    s);
+  }
+  // step 3: What = Delta W on every level
+  {
+    Timer tm(P, s, EIFMM_PH_WHAT);
+    SolveArgs A{};
+    int blk = 0, q = 0;
+    for (int k = 2; k <= depth; ++k) {
+      const int nc = (int)(P.nact[k] * nrhs);
+      if (nc == 0) continue;
+      SolveDesc &D = A.lv[q++];
+      D.in = P.ld[k].W;
+      D.out = P.ld[k].Wh;
+      D.out32 = mixed ? P.ld[k].Wh32 : nullptr;
+      D.Tf = P.ld[k].tri[0];
+      D.Tb = P.ld[k].tri[1];
+      D.ncols = nc;
+      D.dp = P.lh[k].dp;
+      D.blk_start = blk;
+      blk += (nc + 255) / 256;
+    }
+    A.nlev = q;
+    if (blk > 0) hipLaunchKernelGGL((k_solve<false, true>), dim3(blk), dim3(256), 0, s, A);
+  }
+  // step 4: M2L
+  {
+    Timer tm(P, s, EIFMM_PH_M2L);
+    if (mixed)
+      launch_gemm<float, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s);
+    else
+      launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s);
+  }
+  // step 5: l^2 = g^2, then L2L downwards
+  {
+    Timer tm(P, s, EIFMM_PH_L2L);
+    if (mixed) {
+      const int64_t m = P.nact[2] * nrhs * P.lh[2].dp;
+      if (m > 0)
+        hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m,
+                           P.ld[2].g32, P.ld[2].l);
+    }
+    for (int k = 3; k <= depth; ++k)
+      launch_gemm<double, MODE_L2L>(P, P.jobs.l2l_first[k], P.jobs.l2l_n[k], P.jobs.l2l_tiles[k],
+                                    s);
+  }
+  // step 6: lhat = Delta^T l on the leaf level
+  {
+    Timer tm(P, s, EIFMM_PH_LHAT);
+    SolveArgs A{};
+    const int nc = nleafa * nrhs;
+    A.lv[0].in = LL.l;
+    A.lv[0].out = P.lhat;
+    A.lv[0].out32 = nullptr;
+    A.lv[0].Tf = LL.tri[2];
+    A.lv[0].Tb = LL.tri[3];
+    A.lv[0].ncols = nc;
+    A.lv[0].dp = HL.dp;
+    A.lv[0].blk_start = 0;
+    A.nlev = 1;
+    if (nc > 0)
+      hipLaunchKernelGGL((k_solve<true, false>), dim3((nc + 255) / 256), dim3(256), 0, s, A);
+  }
+  // step 7: L2P and the final sum
+  if (nleafa > 0) {
+    Timer tm(P, s, EIFMM_PH_L2P);
+    const int rb = nrhs == 1 ? 1 : 8;
+    const size_t shm = sizeof(double) * (3 * (size_t)HL.dp + (size_t)rb * HL.dp);
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_l2p<KIND, 1>), dim3(nleafa), dim3(64), shm, s, LL.act, P.leaf_start,
+                         LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
+                         P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
+    else
+      hipLaunchKernelGGL((k_l2p<KIND, 8>), dim3(nleafa), dim3(64), shm, s, LL.act, P.leaf_start,
+                         LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
+                         P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
+  }
+}
+
+}  // namespace
+
+void timing_drain(Plan &P) {
+  for (auto &e : P.ev_pending) {
+    hipEventSynchronize(e.b);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e.a, e.b);
+    P.phase_ms[e.phase] += ms;
+    P.phase_calls[e.phase] += 1;
+    P.ev_free.push_back(e);
+  }
+  P.ev_pending.clear();
+}
+
+int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
+             hipStream_t s) {
+  if (P.jobs.nrhs != nrhs) {
+    int st = build_jobs(P, nrhs);
+    if (st != EIFMM_OK) return st;
+  }
+  const int64_t m = P.n * nrhs;
+  if (m > 0)
+    hipLaunchKernelGGL(k_gather_sigma, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, P.n,
+                       nrhs, sigma, ld, P.idx, P.sig);
+  switch (P.cfg.kernel) {
+    case EIFMM_K_LAPLACE:
+      run_kind<EIFMM_K_LAPLACE>(P, nrhs, f, ldf, s);
+      break;
+    case EIFMM_K_YUKAWA:
+      run_kind<EIFMM_K_YUKAWA>(P, nrhs, f, ldf, s);
+      break;
+    case EIFMM_K_GAUSS:
+      run_kind<EIFMM_K_GAUSS>(P, nrhs, f, ldf, s);
+      break;
+    default:
+      run_kind<EIFMM_K_SQDIST>(P, nrhs, f, ldf, s);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
+  P.last_rhs = nrhs;
+  return EIFMM_OK;
+}
+
+}  // namespace eifmm

@@ -1,0 +1,144 @@
+// plan.hpp -- internal state of an EIFMM plan (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/eifmm.h"
+
+namespace eifmm {
+
+constexpr int kMaxLevels = EIFMM_MAX_DEPTH + 1;
+constexpr int kNumOffsets = 316;  // 7^3 - 3^3 distinct M2L offsets (Sec. 4.2)
+
+// Host copy of one level's EIM data (Algorithm 1 and the factors of eq. (5)).
+struct LevelHost {
+  int d = 0;   // number of interpolation points d_k
+  int dp = 0;  // d rounded up to a multiple of 16 (MFMA row blocks)
+  double scale = 0, err = 0;
+  std::vector<double> X, Y;     // d x 3, physical units: X in I_0^k, Y in J_0^k
+  std::vector<int64_t> ia, ib;  // training-set indices of X and Y
+  std::vector<double> B, G;     // d x d row-major: unit-lower B and lower Gamma
+  // operator tables, padded to dp and laid out for the device (see setup.cpp)
+  std::vector<double> kfrag;    // 316 M2L matrices K^delta, fragment order
+  std::vector<double> m2m;      // level k < depth: 8 ops d_k x d_{k+1}, fragment order
+  std::vector<double> l2l;      // level k < depth: 8 ops d_{k+1} x d_k, fragment order
+  std::vector<double> tri[4];   // blocked Gamma, B^T, B, Gamma^T (16 x 16 tiles)
+};
+
+// Device copy of one level's tables.
+struct LevelDev {
+  double *kfrag = nullptr;
+  float *kfrag32 = nullptr;
+  double *m2m = nullptr, *l2l = nullptr;
+  double *tri[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *X = nullptr;  // d x 3 (leaf level: P2M / L2P)
+  // per-query workspaces
+  size_t cap = 0;        // max active boxes at this level: min(8^k, n)
+  uint32_t *act = nullptr;   // active box keys, ascending
+  int *slot = nullptr;       // [8^k] slot of each key, -1 if empty
+  int *cls = nullptr;        // slots grouped by child class (key & 7), ascending key
+  double *W = nullptr, *Wh = nullptr, *g = nullptr, *l = nullptr;
+  float *Wh32 = nullptr, *g32 = nullptr;
+};
+
+// One target group of a gathered GEMM launch (see pass.hip).
+struct GemmJob {
+  const void *A;        // fragment-ordered operand(s)
+  const void *Bsrc;     // source expansions [slot * nrhs + r][dpk]
+  void *C;              // output [slot * nrhs + r][dpm]
+  const void *Cadd;     // added to the product (L2L: g), may be null
+  const int *tgt;       // target slots
+  const uint32_t *tgt_keys;  // active keys of the target level (indexed by slot)
+  const int *src_slot;  // slot map of the source level (indexed by key)
+  const int16_t *terms; // M2L: offset ids of the class; null otherwise
+  int64_t a_stride;     // elements per operand matrix
+  int ntgt, nterms, dpm, dpk;
+  int level, cls, mode, nrhs;
+  int tiles_start, ncoltiles, nrowtiles, src_level;
+  int cadd_f32, pad0;
+};
+
+// Index ranges of the gathered-GEMM jobs of one (points, nrhs) pair.
+struct JobTables {
+  int nrhs = -1;
+  int m2m_first[kMaxLevels] = {}, m2m_n[kMaxLevels] = {}, m2m_tiles[kMaxLevels] = {};
+  int l2l_first[kMaxLevels] = {}, l2l_n[kMaxLevels] = {}, l2l_tiles[kMaxLevels] = {};
+  int m2l_first = 0, m2l_n = 0, m2l_tiles = 0;
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  int phase = 0;
+};
+
+struct Plan {
+  eifmm_config cfg{};
+  int device = 0;
+  bool host_only = false;
+  int depth = 0;
+  LevelHost lh[kMaxLevels];
+  LevelDev ld[kMaxLevels];
+  double setup_ms = 0;
+
+  // tree / points (device)
+  int64_t n = 0;
+  int ntiles_sort = 0;
+  double *xyz = nullptr;        // sorted points, SoA 3 x n
+  float *xloc = nullptr;        // leaf-local FP32 coordinates, SoA 3 x n
+  uint32_t *keys = nullptr, *keys_tmp = nullptr;
+  int *idx = nullptr, *idx_tmp = nullptr;  // idx = perm after the sort
+  unsigned *hist = nullptr;
+  int *leaf_start = nullptr;    // [8^depth + 1]
+  int *scan_tmp = nullptr;       // block totals of the prefix sums
+  int *blkcnt = nullptr;         // per-block counts of the active-box compaction
+  int *list_cnt = nullptr;       // per-box entry counts of a list build
+  int *counts_dev = nullptr;    // small counter block
+  int *errflag = nullptr;
+  int *near_ptr = nullptr;      // leaf level near lists (CSR over active slots)
+  int *near_src = nullptr;      // source leaf slots
+  size_t near_cap = 0;
+  bool points_set = false;
+  int64_t nact[kMaxLevels] = {0};
+  int64_t cls_off[kMaxLevels][9] = {{0}};
+  int64_t near_total = 0;
+  int64_t il_pairs[kMaxLevels] = {0};
+
+  // per-evaluate buffers
+  int max_rhs = 1;
+  double *sig = nullptr;    // sorted sigma [n][nrhs]
+  double *fnear = nullptr;  // near field [n][nrhs]
+  double *lhat = nullptr;   // leaf level [slot][nrhs][dp]
+  int16_t *dlist = nullptr; // [8][189] offset ids per child class
+  int8_t *dvec = nullptr;   // [316][3]
+  int16_t *code2id = nullptr; // [343] (dx+3)+7(dy+3)+49(dz+3) -> offset id or -1
+
+  // gathered-GEMM job tables (rebuilt when the points or nrhs change)
+  JobTables jobs;
+  GemmJob *job_dev = nullptr;
+  double m2l_flops = 0;
+
+  // stats
+  bool timing = false;
+  std::vector<EventPair> ev_free, ev_pending;
+  double phase_ms[EIFMM_NPHASE] = {0};
+  int64_t phase_calls[EIFMM_NPHASE] = {0};
+  int last_hip_error = 0;
+  int last_rhs = 0;
+};
+
+// setup.cpp
+int build_tables(Plan &P);
+
+// device-side entry points (tree.hip, pass.hip)
+int tree_build(Plan &P, const double *xyz_in, hipStream_t s);
+int lists_export(Plan &P, int level, int64_t *nactive, uint32_t *active, int64_t *near_ptr,
+                 uint32_t *near_src, int64_t *il_ptr, uint32_t *il_src, int16_t *il_off);
+int build_jobs(Plan &P, int nrhs);
+void timing_drain(Plan &P);
+int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
+             hipStream_t s);
+
+}  // namespace eifmm

@@ -1,0 +1,409 @@
+// setup.cpp -- host FP64 precomputation of a plan (runs once per plan).
+//
+//  * training sets: the paper leaves D_x,trial / D_y,trial open (Sec. 2); this
+//    library uses cube-surface shells in I_0^k and the surface (or a volume
+//    grid) of J_0^k, in units of l_k so that a homogeneous kernel selects the
+//    same scaled points on every level;
+//  * Algorithm 1 in the L-infinity norm, which is cross approximation with
+//    complete pivoting on the training matrix: pick the largest residual
+//    entry (lowest row, then lowest column on ties), subtract the rank-1 term,
+//    stop once the largest residual is <= tau * scale (end of Sec. 2);
+//  * M = K(X, Y) factored without pivoting as M = Gamma B^T (Crout), so that
+//    Delta = B^{-T} Gamma^{-1} = M^{-1} (eq. (5));
+//  * M2M / L2L operators K M^{-1} and K M^{-T} formed row by row with
+//    triangular solves, never with an explicit inverse (Sec. 4.1);
+//  * the 316 M2L matrices K^delta = K(Y, Y + 2 l_k delta) (Sec. 4.2).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "plan.hpp"
+
+namespace eifmm {
+namespace {
+
+// Host kernel k(z); the squared norm is summed x, y, z.
+inline double kern_host(int kind, double p, double zx, double zy, double zz) {
+  double r2 = zx * zx + zy * zy + zz * zz;
+  switch (kind) {
+    case EIFMM_K_LAPLACE:
+      return 1.0 / std::sqrt(r2);
+    case EIFMM_K_YUKAWA: {
+      double r = std::sqrt(r2);
+      return std::exp(-p * r) / r;
+    }
+    case EIFMM_K_GAUSS:
+      return std::exp(-r2 / p);
+    case EIFMM_K_SQDIST:
+      return r2;
+  }
+  return NAN;
+}
+
+int hw_threads() {
+  unsigned t = std::thread::hardware_concurrency();
+  if (t == 0) t = 4;
+  if (t > 64) t = 64;
+  return (int)t;
+}
+
+template <class F>
+void parallel_for(int64_t n, F fn) {
+  int nt = hw_threads();
+  if (n < 2 * nt) nt = 1;
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; t++) {
+    int64_t a = t * chunk, b = std::min<int64_t>(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=, &fn]() { fn(a, b); });
+  }
+  for (auto &x : th) x.join();
+}
+
+// ---- training sets ---------------------------------------------------------
+// Cube surface ||u||_inf = rho with an m x m grid per face.  Faces in the order
+// x-, x+, y-, y+, z-, z+; on each face the lower free axis varies slowest; a
+// grid point lying on several faces belongs to the face of the lowest axis.
+void add_shell(double rho, int m, std::vector<double> &out) {
+  static const int free_axes[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int a0 = free_axes[ax][0], a1 = free_axes[ax][1];
+    for (int side = 0; side < 2; ++side) {
+      const double face = side ? rho : -rho;
+      for (int i = 0; i < m; ++i) {
+        const bool edge0 = (i == 0 || i == m - 1);
+        if (a0 < ax && edge0) continue;
+        for (int j = 0; j < m; ++j) {
+          const bool edge1 = (j == 0 || j == m - 1);
+          if (a1 < ax && edge1) continue;
+          double u[3];
+          u[ax] = face;
+          u[a0] = rho * double(2 * i - (m - 1)) / double(m - 1);
+          u[a1] = rho * double(2 * j - (m - 1)) / double(m - 1);
+          out.insert(out.end(), u, u + 3);
+        }
+      }
+    }
+  }
+}
+
+void add_volume(int m, std::vector<double> &out) {
+  for (int iz = 0; iz < m; ++iz)
+    for (int iy = 0; iy < m; ++iy)
+      for (int ix = 0; ix < m; ++ix) {
+        out.push_back(double(2 * ix - (m - 1)) / double(m - 1));
+        out.push_back(double(2 * iy - (m - 1)) / double(m - 1));
+        out.push_back(double(2 * iz - (m - 1)) / double(m - 1));
+      }
+}
+
+bool volume_kernel(int kind) { return kind == EIFMM_K_GAUSS; }
+
+// Shell radii in units of l_k; level k keeps those below 2^(k+1) - 1 and then
+// adds the outer boundary 2^(k+1) - 1 of I_0^k itself.
+const double kShellsSurface[] = {3,   3.5, 4,   5,   6.5, 8.5, 11,  15,   20,   27,
+                                 36,  48,  64,  86,  116, 155, 208, 279,  374,  502,
+                                 673, 902, 1209, 1621, 2173};
+const double kShellsVolume[] = {3,    3.25, 3.5, 3.75, 4,   4.5, 5,   5.5,  6,    6.5,
+                                7.25, 8,    9,   10,   11,  12.5, 14, 16,   18,   20,
+                                23,   27,   32,  38,   45,  54,  64,  76,   90,   108,
+                                128,  152,  181, 215,  256, 304, 362, 431,  512,  609,
+                                724,  861,  1024, 1218, 1448, 1722, 2048};
+
+void training_sets(int kind, int level, double lk, std::vector<double> &tx,
+                   std::vector<double> &ty) {
+  const double outer = double((1 << (level + 1)) - 1);
+  const bool vol = volume_kernel(kind);
+  const double *radii = vol ? kShellsVolume : kShellsSurface;
+  const size_t nr = vol ? sizeof(kShellsVolume) / sizeof(double)
+                        : sizeof(kShellsSurface) / sizeof(double);
+  tx.clear();
+  ty.clear();
+  for (size_t s = 0; s < nr; ++s)
+    if (radii[s] < outer) add_shell(radii[s], radii[s] < 6.0 ? 19 : 9, tx);
+  add_shell(outer, outer < 6.0 ? 19 : 9, tx);
+  if (vol)
+    add_volume(11, ty);
+  else
+    add_shell(1.0, 11, ty);
+  for (auto &v : tx) v *= lk;
+  for (auto &v : ty) v *= lk;
+}
+
+// ---- Algorithm 1 as complete-pivot cross approximation ----------------------
+int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, double abs_scale,
+               LevelHost &out) {
+  const double lk = std::ldexp(L, -level - 1);
+  std::vector<double> tx, ty;
+  training_sets(kind, level, lk, tx, ty);
+  const int64_t nx = (int64_t)tx.size() / 3, ny = (int64_t)ty.size() / 3;
+  std::vector<double> R((size_t)(nx * ny));
+  parallel_for(nx, [&](int64_t a0, int64_t a1) {
+    for (int64_t a = a0; a < a1; ++a)
+      for (int64_t b = 0; b < ny; ++b)
+        R[a * ny + b] = kern_host(kind, p, tx[3 * a] - ty[3 * b], tx[3 * a + 1] - ty[3 * b + 1],
+                                  tx[3 * a + 2] - ty[3 * b + 2]);
+  });
+  const int nth = hw_threads();
+  struct Best {
+    double v;
+    int64_t a, b;
+  };
+  std::vector<Best> part(nth);
+  std::vector<double> qrow((size_t)ny);
+  out.ia.clear();
+  out.ib.clear();
+  double scale = 0;
+  int status = EIFMM_OK;
+  for (;;) {
+    // largest |residual|, lowest (row, column) on ties
+    int64_t chunk = (nx + nth - 1) / nth;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) {
+      th.emplace_back([&, t]() {
+        Best bt{-1.0, 0, 0};
+        int64_t a0 = t * chunk, a1 = std::min(nx, a0 + chunk);
+        for (int64_t a = a0; a < a1; ++a) {
+          const double *row = &R[a * ny];
+          for (int64_t b = 0; b < ny; ++b) {
+            double v = std::fabs(row[b]);
+            if (v > bt.v) bt = {v, a, b};
+          }
+        }
+        part[t] = bt;
+      });
+    }
+    for (auto &x : th) x.join();
+    Best best{-1.0, 0, 0};
+    for (int t = 0; t < nth; ++t)
+      if (part[t].v > best.v) best = part[t];  // parts are in row order
+    if (out.ia.empty()) scale = abs_scale > 0 ? abs_scale : best.v;
+    if (best.v <= tau * scale) break;
+    if ((int)out.ia.size() == dmax) {
+      status = EIFMM_EEIM;
+      break;
+    }
+    const int64_t as = best.a, bs = best.b;
+    const double piv = R[as * ny + bs];
+    out.ia.push_back(as);
+    out.ib.push_back(bs);
+    for (int64_t b = 0; b < ny; ++b) qrow[b] = R[as * ny + b] / piv;
+    parallel_for(nx, [&](int64_t a0, int64_t a1) {
+      for (int64_t a = a0; a < a1; ++a) {
+        double *row = &R[a * ny];
+        const double c = row[bs];
+        for (int64_t b = 0; b < ny; ++b) row[b] -= c * qrow[b];
+      }
+    });
+  }
+  // training error left after the last accepted point
+  double emax = 0;
+  for (double v : R) emax = std::max(emax, std::fabs(v));
+  const int d = (int)out.ia.size();
+  out.d = d;
+  out.scale = scale;
+  out.err = scale > 0 ? emax / scale : 0;
+  out.X.resize(3 * (size_t)d);
+  out.Y.resize(3 * (size_t)d);
+  for (int i = 0; i < d; ++i)
+    for (int c = 0; c < 3; ++c) {
+      out.X[3 * i + c] = tx[3 * out.ia[i] + c];
+      out.Y[3 * i + c] = ty[3 * out.ib[i] + c];
+    }
+  return status;
+}
+
+// Crout factorisation M = Gamma B^T (Gamma lower, B unit lower), no pivoting:
+// the greedy order already makes every leading minor nonzero.
+void crout(int kind, double p, LevelHost &lv) {
+  const int d = lv.d;
+  std::vector<double> M((size_t)d * d), BT((size_t)d * d, 0.0);
+  lv.G.assign((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      M[(size_t)i * d + j] =
+          kern_host(kind, p, lv.X[3 * i] - lv.Y[3 * j], lv.X[3 * i + 1] - lv.Y[3 * j + 1],
+                    lv.X[3 * i + 2] - lv.Y[3 * j + 2]);
+  for (int j = 0; j < d; ++j) {
+    for (int i = j; i < d; ++i) {
+      double s = M[(size_t)i * d + j];
+      for (int k = 0; k < j; ++k) s -= lv.G[(size_t)i * d + k] * BT[(size_t)k * d + j];
+      lv.G[(size_t)i * d + j] = s;
+    }
+    BT[(size_t)j * d + j] = 1.0;
+    for (int i = j + 1; i < d; ++i) {
+      double s = M[(size_t)j * d + i];
+      for (int k = 0; k < j; ++k) s -= lv.G[(size_t)j * d + k] * BT[(size_t)k * d + i];
+      BT[(size_t)j * d + i] = s / lv.G[(size_t)j * d + j];
+    }
+  }
+  lv.B.assign((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) lv.B[(size_t)i * d + j] = BT[(size_t)j * d + i];
+}
+
+// x <- M^{-1} x  (Gamma z = x, then B^T x = z)
+void solve_minv(const LevelHost &lv, double *x) {
+  const int d = lv.d;
+  for (int i = 0; i < d; ++i) {
+    double s = x[i];
+    for (int j = 0; j < i; ++j) s -= lv.G[(size_t)i * d + j] * x[j];
+    x[i] = s / lv.G[(size_t)i * d + i];
+  }
+  for (int i = d - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int j = i + 1; j < d; ++j) s -= lv.B[(size_t)j * d + i] * x[j];
+    x[i] = s;
+  }
+}
+
+// x <- M^{-T} x  (B z = x, then Gamma^T x = z)
+void solve_mtinv(const LevelHost &lv, double *x) {
+  const int d = lv.d;
+  for (int i = 0; i < d; ++i) {
+    double s = x[i];
+    for (int j = 0; j < i; ++j) s -= lv.B[(size_t)i * d + j] * x[j];
+    x[i] = s;
+  }
+  for (int i = d - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int j = i + 1; j < d; ++j) s -= lv.G[(size_t)j * d + i] * x[j];
+    x[i] = s / lv.G[(size_t)i * d + i];
+  }
+}
+
+// Dense rows x cols (row-major) -> MFMA fragment order for a 16x16x4 A operand:
+// [rb = rows/16][ks = cols/4][lane 64], lane l holding (16 rb + l % 16, 4 ks + l / 16);
+// padded rows / columns are zero.
+void to_fragments(const double *A, int rows, int cols, int rpad, int cpad, double *out) {
+  const int nrb = rpad / 16, nks = cpad / 4;
+  for (int rb = 0; rb < nrb; ++rb)
+    for (int ks = 0; ks < nks; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        int r = 16 * rb + (l & 15), c = 4 * ks + (l >> 4);
+        out[((size_t)rb * nks + ks) * 64 + l] =
+            (r < rows && c < cols) ? A[(size_t)r * cols + c] : 0.0;
+      }
+}
+
+// Blocked copy of a d x d matrix padded to dp with the identity, 16 x 16 tiles:
+// out[((bi * nb) + bj) * 256 + i * 16 + j] = T[16 bi + i][16 bj + j].
+void to_blocks(const std::vector<double> &T, int d, int dp, bool transpose,
+               std::vector<double> &out) {
+  const int nb = dp / 16;
+  out.assign((size_t)dp * dp, 0.0);
+  for (int bi = 0; bi < nb; ++bi)
+    for (int bj = 0; bj < nb; ++bj)
+      for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 16; ++j) {
+          int r = 16 * bi + i, c = 16 * bj + j;
+          double v;
+          if (r < d && c < d)
+            v = transpose ? T[(size_t)c * d + r] : T[(size_t)r * d + c];
+          else
+            v = (r == c) ? 1.0 : 0.0;
+          out[((size_t)bi * nb + bj) * 256 + i * 16 + j] = v;
+        }
+}
+
+}  // namespace
+
+int build_tables(Plan &P) {
+  auto t0 = std::chrono::steady_clock::now();
+  const eifmm_config &c = P.cfg;
+  const int depth = c.depth, kind = c.kernel;
+  const double p = c.kernel_param, L = c.L;
+  const int dmax = c.dmax > 0 ? c.dmax : 1024;
+  double abs_scale = 0;
+  for (int k = depth; k >= 2; --k) {
+    LevelHost &lv = P.lh[k];
+    int st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale : 0.0, lv);
+    if (st != EIFMM_OK) return st;
+    if (k == depth && c.tol_mode == 1) abs_scale = lv.scale;
+    crout(kind, p, lv);
+    lv.dp = ((lv.d + 15) / 16) * 16;
+    if (lv.dp == 0) lv.dp = 16;
+  }
+  // translation-invariant M2L matrices K^delta (Sec. 4.2): rows m' (target check
+  // points Y_m'), columns l (source equivalent points Y_l + 2 l_k delta)
+  int delta[kNumOffsets][3];
+  {
+    int id = 0;
+    for (int dz = -3; dz <= 3; ++dz)
+      for (int dy = -3; dy <= 3; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+          int m = std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz)));
+          if (m < 2) continue;
+          delta[id][0] = dx;
+          delta[id][1] = dy;
+          delta[id][2] = dz;
+          ++id;
+        }
+  }
+  for (int k = 2; k <= depth; ++k) {
+    LevelHost &lv = P.lh[k];
+    const int d = lv.d, dp = lv.dp;
+    const double h = std::ldexp(L, -k);  // box side 2 l_k
+    lv.kfrag.assign((size_t)kNumOffsets * dp * dp, 0.0);
+    parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
+      std::vector<double> A((size_t)d * d);
+      for (int64_t o = o0; o < o1; ++o) {
+        const double sx = delta[o][0] * h, sy = delta[o][1] * h, sz = delta[o][2] * h;
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j)
+            A[(size_t)i * d + j] = kern_host(kind, p, lv.Y[3 * i] - (lv.Y[3 * j] + sx),
+                                             lv.Y[3 * i + 1] - (lv.Y[3 * j + 1] + sy),
+                                             lv.Y[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
+        to_fragments(A.data(), d, d, dp, dp, &lv.kfrag[(size_t)o * dp * dp]);
+      }
+    });
+    to_blocks(lv.G, d, dp, false, lv.tri[0]);  // Gamma      (forward, Delta)
+    to_blocks(lv.B, d, dp, true, lv.tri[1]);   // B^T        (backward, Delta)
+    to_blocks(lv.B, d, dp, false, lv.tri[2]);  // B          (forward, Delta^T)
+    to_blocks(lv.G, d, dp, true, lv.tri[3]);   // Gamma^T    (backward, Delta^T)
+  }
+  // M2M (Sec. 4.1): for parent level k and child i with c_C - c_P = s_i,
+  //   M2M_i = K(X^k - s_i, Y^{k+1}) (M^{k+1})^{-1}        (d_k x d_{k+1})
+  // L2L: L2L_i = K(Y^{k+1} + s_i, X^k) (M^k)^{-T}          (d_{k+1} x d_k)
+  for (int k = 2; k < depth; ++k) {
+    LevelHost &lp = P.lh[k], &lc = P.lh[k + 1];
+    const int dk = lp.d, dc = lc.d;
+    const double lc_half = std::ldexp(L, -k - 2);  // l_{k+1}
+    lp.m2m.assign((size_t)8 * lp.dp * lc.dp, 0.0);
+    lp.l2l.assign((size_t)8 * lc.dp * lp.dp, 0.0);
+    parallel_for(8, [&](int64_t i0, int64_t i1) {
+      std::vector<double> A((size_t)dk * dc), Bm((size_t)dc * dk), row;
+      for (int64_t i = i0; i < i1; ++i) {
+        double s[3];
+        for (int a = 0; a < 3; ++a) s[a] = ((i >> a) & 1) ? lc_half : -lc_half;
+        for (int m = 0; m < dk; ++m) {
+          row.assign((size_t)dc, 0.0);
+          for (int q = 0; q < dc; ++q)
+            row[q] = kern_host(kind, p, (lp.X[3 * m] - s[0]) - lc.Y[3 * q],
+                               (lp.X[3 * m + 1] - s[1]) - lc.Y[3 * q + 1],
+                               (lp.X[3 * m + 2] - s[2]) - lc.Y[3 * q + 2]);
+          solve_mtinv(lc, row.data());  // row M^{-1} = (M^{-T} row^T)^T
+          std::memcpy(&A[(size_t)m * dc], row.data(), sizeof(double) * dc);
+        }
+        to_fragments(A.data(), dk, dc, lp.dp, lc.dp, &lp.m2m[(size_t)i * lp.dp * lc.dp]);
+        for (int m = 0; m < dc; ++m) {
+          row.assign((size_t)dk, 0.0);
+          for (int q = 0; q < dk; ++q)
+            row[q] = kern_host(kind, p, (lc.Y[3 * m] + s[0]) - lp.X[3 * q],
+                               (lc.Y[3 * m + 1] + s[1]) - lp.X[3 * q + 1],
+                               (lc.Y[3 * m + 2] + s[2]) - lp.X[3 * q + 2]);
+          solve_minv(lp, row.data());  // row M^{-T} = (M^{-1} row^T)^T
+          std::memcpy(&Bm[(size_t)m * dk], row.data(), sizeof(double) * dk);
+        }
+        to_fragments(Bm.data(), dc, dk, lc.dp, lp.dp, &lp.l2l[(size_t)i * lc.dp * lp.dp]);
+      }
+    });
+  }
+  P.setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return EIFMM_OK;
+}
+
+}  // namespace eifmm

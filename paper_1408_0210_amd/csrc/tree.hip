@@ -1,0 +1,527 @@
+// tree.hip -- octree build on the GPU (Sec. 3.3: a 2^D-tree with depth+1 levels).
+//
+// Points are binned into the leaf cells of a uniform octree over [lo, lo+L]^3,
+// keyed by Morton order (bit b of the x index at bit 3b, y at 3b+1, z at 3b+2),
+// sorted stably by (key, input index) with an LSD radix sort, gathered into
+// Morton order, and summarised per level:
+//   leaf_start[key]  first sorted point of each leaf (boxes of any level are
+//                    contiguous ranges of sorted points);
+//   act[k]           keys of the non-empty boxes of level k, ascending;
+//   slot[k][key]     position of a box in act[k], or -1 when empty;
+//   cls[k]           slots grouped by child class (key & 7), ascending key;
+//   near lists       boxes at Chebyshev index distance <= 1 (Sec. 3.2);
+//   interaction lists (export only) children of the parent's neighbours that
+//                    are well separated (Sec. 3.3.2).
+#include <algorithm>
+#include <cstring>
+
+#include "devutil.hpp"
+#include "plan.hpp"
+
+namespace eifmm {
+
+// ---------------------------------------------------------------- keys
+__global__ void k_keys(int64_t n, const double *__restrict__ xyz, double lo0, double lo1,
+                       double lo2, double L, double scale, int side, uint32_t *__restrict__ keys,
+                       int *__restrict__ idx, int *__restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lo[3] = {lo0, lo1, lo2};
+  uint32_t c[3];
+  bool bad = false;
+  for (int a = 0; a < 3; ++a) {
+    double x = xyz[a * n + i];
+    // closed domain [lo, lo+L]; NaN and +-inf fail the comparison
+    if (!(x >= lo[a] && x <= lo[a] + L)) {
+      bad = true;
+      c[a] = 0;
+      continue;
+    }
+    // one FP64 subtraction and one FP64 multiplication, then floor and clamp
+    double t = floor(__dmul_rn(__dsub_rn(x, lo[a]), scale));
+    int q = (int)t;
+    q = q > side - 1 ? side - 1 : (q < 0 ? 0 : q);
+    c[a] = (uint32_t)q;
+  }
+  if (bad) atomicOr(err, 1);
+  keys[i] = morton_encode(c[0], c[1], c[2]);
+  idx[i] = (int)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+// Tile of kSortTile keys per block (256 threads x 4 rounds); digits of 8 bits.
+constexpr int kSortTile = 1024;
+
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t *__restrict__ keys, int64_t n,
+                                                   int shift, unsigned *__restrict__ hist,
+                                                   int ntiles) {
+  __shared__ unsigned cnt[256];
+  const int t = threadIdx.x, tile = blockIdx.x;
+  cnt[t] = 0;
+  __syncthreads();
+  for (int r = 0; r < kSortTile / 256; ++r) {
+    int64_t e = (int64_t)tile * kSortTile + r * 256 + t;
+    if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)t * ntiles + tile] = cnt[t];
+}
+
+// Stable scatter: within a round, lanes of a wave with equal digits are ranked
+// by lane order (ballot match), waves by wave order, rounds by round order.
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *__restrict__ kin,
+                                                      const int *__restrict__ iin,
+                                                      uint32_t *__restrict__ kout,
+                                                      int *__restrict__ iout, int64_t n,
+                                                      int shift,
+                                                      const unsigned *__restrict__ hist,
+                                                      int ntiles) {
+  __shared__ unsigned run[256];
+  __shared__ unsigned wcnt[4][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, tile = blockIdx.x;
+  run[t] = hist[(int64_t)t * ntiles + tile];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortTile / 256; ++r) {
+    for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    int64_t e = (int64_t)tile * kSortTile + r * 256 + t;
+    bool valid = e < n;
+    uint32_t key = valid ? kin[e] : 0u;
+    int id = valid ? iin[e] : 0;
+    unsigned dig = (key >> shift) & 255u;
+    uint64_t mask = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dig >> b) & 1u;
+      uint64_t bal = __ballot(bit);
+      mask &= bit ? bal : ~bal;
+    }
+    unsigned rank = (unsigned)__popcll(mask & lt);
+    if (valid && rank == 0) wcnt[w][dig] = (unsigned)__popcll(mask);
+    __syncthreads();
+    unsigned pos = 0;
+    if (valid) {
+      pos = run[dig] + rank;
+      for (int q = 0; q < w; ++q) pos += wcnt[q][dig];
+    }
+    __syncthreads();
+    run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    if (valid) {
+      kout[pos] = key;
+      iout[pos] = id;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- gather
+__global__ void k_gather_points(int64_t n, const double *__restrict__ xin,
+                                const int *__restrict__ perm, const uint32_t *__restrict__ keys,
+                                double *__restrict__ xs, float *__restrict__ xl, double lo0,
+                                double lo1, double lo2, double h) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+  const uint32_t key = keys[s];
+  const double lo[3] = {lo0, lo1, lo2};
+  for (int a = 0; a < 3; ++a) {
+    double x = xin[a * n + i];
+    xs[a * n + s] = x;
+    double c = lo[a] + ((double)morton_axis(key, a) + 0.5) * h;
+    xl[a * n + s] = (float)(x - c);
+  }
+}
+
+// leaf_start[k] = first sorted position with key >= k, k = 0..nleaf
+__global__ void k_leaf_start(int64_t n, const uint32_t *__restrict__ keys, int64_t nleaf,
+                             int *__restrict__ ls) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nleaf) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  ls[k] = (int)lo;
+}
+
+// ---------------------------------------------------------------- active boxes
+__device__ inline bool box_active(const int *__restrict__ ls, int shift, int64_t b) {
+  return ls[(b + 1) << shift] > ls[b << shift];
+}
+
+// per block of 256 boxes: active count per child class and in total
+__global__ __launch_bounds__(256) void k_act_count(const int *__restrict__ ls, int shift,
+                                                   int64_t nb, int *__restrict__ blkcnt) {
+  __shared__ int c[9];
+  const int t = threadIdx.x;
+  if (t < 9) c[t] = 0;
+  __syncthreads();
+  int64_t b = (int64_t)blockIdx.x * 256 + t;
+  if (b < nb && box_active(ls, shift, b)) {
+    atomicAdd(&c[8], 1);
+    atomicAdd(&c[b & 7], 1);
+  }
+  __syncthreads();
+  if (t < 9) blkcnt[(int64_t)blockIdx.x * 9 + t] = c[t];
+}
+
+// single block: exclusive scan of each of the 9 columns over the blocks; the
+// class offsets and totals go to counts[0..8] (offset of class c, total at 8)
+__global__ __launch_bounds__(1024) void k_act_scan(int *__restrict__ blkcnt, int nblk,
+                                                   int *__restrict__ counts) {
+  __shared__ int part[1024];
+  __shared__ int tot[9];
+  const int t = threadIdx.x;
+  for (int col = 0; col < 9; ++col) {
+    int per = (nblk + 1023) / 1024;
+    int a = t * per, b = min(nblk, a + per);
+    int s = 0;
+    for (int i = a; i < b; ++i) s += blkcnt[(int64_t)i * 9 + col];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int v = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = a; i < b; ++i) {
+      int v = blkcnt[(int64_t)i * 9 + col];
+      blkcnt[(int64_t)i * 9 + col] = run;
+      run += v;
+    }
+    if (t == 1023) tot[col] = part[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    int off = 0;
+    for (int c = 0; c < 8; ++c) {
+      counts[c] = off;
+      off += tot[c];
+    }
+    counts[8] = tot[8];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_act_scatter(const int *__restrict__ ls, int shift,
+                                                     int64_t nb, const int *__restrict__ blkoff,
+                                                     const int *__restrict__ counts,
+                                                     uint32_t *__restrict__ act,
+                                                     int *__restrict__ slot,
+                                                     int *__restrict__ cls) {
+  __shared__ int wtot[4][9];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t b = (int64_t)blockIdx.x * 256 + t;
+  bool a = b < nb && box_active(ls, shift, b);
+  int c = (int)(b & 7);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t ball = __ballot(a);
+  uint64_t bc[8];
+  for (int q = 0; q < 8; ++q) bc[q] = __ballot(a && c == q);
+  if (lane == 0) {
+    wtot[w][8] = (int)__popcll(ball);
+    for (int q = 0; q < 8; ++q) wtot[w][q] = (int)__popcll(bc[q]);
+  }
+  __syncthreads();
+  if (b >= nb) return;
+  if (!a) {
+    slot[b] = -1;
+    return;
+  }
+  int rt = (int)__popcll(ball & lt), rc = (int)__popcll(bc[c] & lt);
+  for (int q = 0; q < w; ++q) {
+    rt += wtot[q][8];
+    rc += wtot[q][c];
+  }
+  int pos = blkoff[(int64_t)blockIdx.x * 9 + 8] + rt;
+  act[pos] = (uint32_t)b;
+  slot[b] = pos;
+  cls[counts[c] + blkoff[(int64_t)blockIdx.x * 9 + c] + rc] = pos;
+}
+
+// interaction-list entries of level `level` summed into *out (statistics):
+// for a box of child class c the offsets are delta_a in [-2-c_a, 3-c_a] with
+// ||delta||_inf >= 2 (the children of the parent's neighbours that are well
+// separated, Sec. 3.3.2)
+__global__ __launch_bounds__(256) void k_il_count(int level, const uint32_t *__restrict__ act,
+                                                  const int *__restrict__ nact,
+                                                  const int *__restrict__ slot,
+                                                  int *__restrict__ out) {
+  __shared__ int tot;
+  if (threadIdx.x == 0) tot = 0;
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = 0;
+  if (j < *nact) {
+    const int side = 1 << level;
+    const uint32_t key = act[j];
+    int n[3], p[3];
+    for (int a = 0; a < 3; ++a) {
+      n[a] = (int)morton_axis(key, a);
+      p[a] = n[a] & 1;
+    }
+    for (int dz = -2 - p[2]; dz <= 3 - p[2]; ++dz)
+      for (int dy = -2 - p[1]; dy <= 3 - p[1]; ++dy)
+        for (int dx = -2 - p[0]; dx <= 3 - p[0]; ++dx) {
+          if (max(abs(dx), max(abs(dy), abs(dz))) < 2) continue;
+          const int m0 = n[0] + dx, m1 = n[1] + dy, m2 = n[2] + dz;
+          if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) continue;
+          if (slot[morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2)] >= 0) ++c;
+        }
+  }
+  if (c) atomicAdd(&tot, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
+}
+
+// ---------------------------------------------------------------- lists
+// mode 0: near list (Chebyshev <= 1, self included); mode 1: interaction list.
+// Entries are source slots (ascending slot = ascending key) and, for mode 1,
+// offset ids.
+template <int MODE>
+__global__ void k_list(int level, const uint32_t *__restrict__ act, const int *__restrict__ nact,
+                       const int *__restrict__ slot, const int *__restrict__ ptr,
+                       int *__restrict__ cnt, int *__restrict__ src,
+                       int16_t *__restrict__ off, const int16_t *__restrict__ code2id) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= *nact) {
+    if (cnt && j == *nact) cnt[j] = 0;
+    return;
+  }
+  const int side = 1 << level;
+  const uint32_t key = act[j];
+  const int n0 = (int)morton_axis(key, 0), n1 = (int)morton_axis(key, 1),
+            n2 = (int)morton_axis(key, 2);
+  int s_loc[189];
+  int16_t o_loc[189];
+  int c = 0;
+  const int R = MODE == 0 ? 1 : 3;
+  for (int dz = -R; dz <= R; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int m0 = n0 + dx, m1 = n1 + dy, m2 = n2 + dz;
+        if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) continue;
+        if (MODE == 1) {
+          int cheb = max(abs(dx), max(abs(dy), abs(dz)));
+          if (cheb < 2) continue;
+          int pc = max(abs((m0 >> 1) - (n0 >> 1)),
+                       max(abs((m1 >> 1) - (n1 >> 1)), abs((m2 >> 1) - (n2 >> 1))));
+          if (pc > 1) continue;
+        }
+        int sl = slot[morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2)];
+        if (sl < 0) continue;
+        if (src) {
+          s_loc[c] = sl;
+          if (MODE == 1) o_loc[c] = code2id[(dx + 3) + 7 * (dy + 3) + 49 * (dz + 3)];
+        }
+        ++c;
+      }
+  if (cnt) {
+    cnt[j] = c;
+    return;
+  }
+  // insertion sort by source slot
+  for (int a = 1; a < c; ++a) {
+    int s = s_loc[a];
+    int16_t o = MODE == 1 ? o_loc[a] : 0;
+    int b = a - 1;
+    while (b >= 0 && s_loc[b] > s) {
+      s_loc[b + 1] = s_loc[b];
+      if (MODE == 1) o_loc[b + 1] = o_loc[b];
+      --b;
+    }
+    s_loc[b + 1] = s;
+    if (MODE == 1) o_loc[b + 1] = o;
+  }
+  const int base = ptr[j];
+  for (int a = 0; a < c; ++a) {
+    src[base + a] = s_loc[a];
+    if (MODE == 1) off[base + a] = o_loc[a];
+  }
+}
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+int sort_points(Plan &P, hipStream_t s) {
+  const int64_t n = P.n;
+  const int bits = 3 * P.depth;
+  const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+  uint32_t *ka = P.keys, *kb = P.keys_tmp;
+  int *ia = P.idx, *ib = P.idx_tmp;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(256), 0, s, ka, n, shift, P.hist, ntiles);
+    scan_exclusive_u32(P.hist, P.hist, (int64_t)256 * ntiles, P.scan_tmp, s);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(256), 0, s, ka, ia, kb, ib, n, shift,
+                       P.hist, ntiles);
+    std::swap(ka, kb);
+    std::swap(ia, ib);
+  }
+  if (ka != P.keys) {  // odd pass count: result sits in the tmp buffers
+    std::swap(P.keys, P.keys_tmp);
+    std::swap(P.idx, P.idx_tmp);
+  }
+  return EIFMM_OK;
+}
+
+void build_active(Plan &P, int k, hipStream_t s) {
+  const int64_t nb = (int64_t)1 << (3 * k);
+  const int shift = 3 * (P.depth - k);
+  const int nblk = (int)((nb + 255) / 256);
+  int *blk = P.blkcnt;  // nblk * 9 ints
+  int *counts = P.counts_dev + 16 * k;
+  hipLaunchKernelGGL(k_act_count, dim3(nblk), dim3(256), 0, s, P.leaf_start, shift, nb, blk);
+  hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(1024), 0, s, blk, nblk, counts);
+  hipLaunchKernelGGL(k_act_scatter, dim3(nblk), dim3(256), 0, s, P.leaf_start, shift, nb, blk,
+                     counts, P.ld[k].act, P.ld[k].slot, P.ld[k].cls);
+}
+
+// CSR list for level k into (ptr, src, off); returns the entry count.
+int64_t build_list(Plan &P, int k, int mode, int *ptr, int *src, int16_t *off, size_t cap,
+                   hipStream_t s) {
+  LevelDev &L = P.ld[k];
+  const int *nact = P.counts_dev + 16 * k + 8;
+  const int grid = (int)((L.cap + 1 + 127) / 128);
+  int *cnt = P.list_cnt;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_list<0>, dim3(grid), dim3(128), 0, s, k, L.act, nact, L.slot, nullptr,
+                       cnt, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL(k_list<1>, dim3(grid), dim3(128), 0, s, k, L.act, nact, L.slot, nullptr,
+                       cnt, nullptr, nullptr, P.code2id);
+  scan_exclusive_i32(cnt, ptr, (int64_t)L.cap + 1, P.scan_tmp, s);
+  int total = 0;
+  hipMemcpyAsync(&total, ptr + P.nact[k], sizeof(int), hipMemcpyDeviceToHost, s);
+  hipStreamSynchronize(s);
+  if ((size_t)total > cap) return -1;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_list<0>, dim3(grid), dim3(128), 0, s, k, L.act, nact, L.slot, ptr,
+                       nullptr, src, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL(k_list<1>, dim3(grid), dim3(128), 0, s, k, L.act, nact, L.slot, ptr,
+                       nullptr, src, off, P.code2id);
+  return total;
+}
+
+}  // namespace
+
+int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
+  const int64_t n = P.n;
+  const int depth = P.depth;
+  const int side = 1 << depth;
+  const double scale = std::ldexp(1.0, depth) / P.cfg.L;
+  hipMemsetAsync(P.errflag, 0, sizeof(int), s);
+  hipMemsetAsync(P.counts_dev, 0, sizeof(int) * 16 * kMaxLevels, s);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz_in,
+                       P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], P.cfg.L, scale, side, P.keys, P.idx,
+                       P.errflag);
+    sort_points(P, s);
+    hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       xyz_in, P.idx, P.keys, P.xyz, P.xloc, P.cfg.lo[0], P.cfg.lo[1],
+                       P.cfg.lo[2], std::ldexp(P.cfg.L, -depth));
+  }
+  const int64_t nleaf = (int64_t)1 << (3 * depth);
+  hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s, n,
+                     P.keys, nleaf, P.leaf_start);
+  for (int k = std::min(2, depth); k <= depth; ++k) build_active(P, k, s);
+  for (int k = 2; k <= depth; ++k) {
+    const int grid = (int)((P.ld[k].cap + 255) / 256);
+    hipLaunchKernelGGL(k_il_count, dim3(grid), dim3(256), 0, s, k, P.ld[k].act,
+                       P.counts_dev + 16 * k + 8, P.ld[k].slot, P.counts_dev + 16 * k + 9);
+  }
+  int host_counts[16 * kMaxLevels + 1];
+  hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
+                 s);
+  int err = 0;
+  hipMemcpyAsync(&err, P.errflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
+  if (err) return EIFMM_EDOMAIN;
+  for (int k = std::min(2, depth); k <= depth; ++k) {
+    P.nact[k] = host_counts[16 * k + 8];
+    for (int c = 0; c < 8; ++c) P.cls_off[k][c] = host_counts[16 * k + c];
+    P.cls_off[k][8] = P.nact[k];
+    P.il_pairs[k] = k >= 2 ? host_counts[16 * k + 9] : 0;
+  }
+  // near lists of the leaf level (used by the near-field pass)
+  int64_t tot = build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, s);
+  if (tot < 0) return EIFMM_ENOMEM;
+  P.near_total = tot;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
+  return EIFMM_OK;
+}
+
+int lists_export(Plan &P, int level, int64_t *nactive, uint32_t *active, int64_t *near_ptr,
+                 uint32_t *near_src, int64_t *il_ptr, uint32_t *il_src, int16_t *il_off) {
+  hipStream_t s = nullptr;
+  if (level < 0 || level > P.depth) return EIFMM_EINVAL;
+  const int lo_level = std::min(2, P.depth);
+  if (level < lo_level) {
+    // levels 0 and 1 are not kept per query; build them on the fly
+    build_active(P, level, s);
+    int hc[16];
+    hipMemcpy(hc, P.counts_dev + 16 * level, sizeof(int) * 16, hipMemcpyDeviceToHost);
+    P.nact[level] = hc[8];
+  }
+  LevelDev &L = P.ld[level];
+  const int64_t na = P.nact[level];
+  *nactive = na;
+  std::vector<uint32_t> act(na);
+  hipMemcpy(act.data(), L.act, sizeof(uint32_t) * na, hipMemcpyDeviceToHost);
+  if (active) std::memcpy(active, act.data(), sizeof(uint32_t) * na);
+  const size_t cap_near = (size_t)27 * (na + 1), cap_il = (size_t)189 * (na + 1);
+  int *dptr = nullptr, *dsrc = nullptr;
+  int16_t *doff = nullptr;
+  if (hipMalloc(&dptr, sizeof(int) * (L.cap + 2)) != hipSuccess) return EIFMM_ENOMEM;
+  if (hipMalloc(&dsrc, sizeof(int) * std::max(cap_near, cap_il)) != hipSuccess ||
+      hipMalloc(&doff, sizeof(int16_t) * cap_il) != hipSuccess) {
+    hipFree(dptr);
+    hipFree(dsrc);
+    return EIFMM_ENOMEM;
+  }
+  int rc = EIFMM_OK;
+  for (int mode = 0; mode < 2 && rc == EIFMM_OK; ++mode) {
+    int64_t *optr = mode == 0 ? near_ptr : il_ptr;
+    uint32_t *osrc = mode == 0 ? near_src : il_src;
+    if (!optr) continue;
+    if (mode == 1 && level < 2) {
+      for (int64_t j = 0; j <= na; ++j) optr[j] = 0;
+      continue;
+    }
+    int64_t tot = build_list(P, level, mode, dptr, dsrc, doff, mode == 0 ? cap_near : cap_il, s);
+    if (tot < 0) {
+      rc = EIFMM_ENOMEM;
+      break;
+    }
+    std::vector<int> hp(na + 1), hs(tot);
+    hipMemcpy(hp.data(), dptr, sizeof(int) * (na + 1), hipMemcpyDeviceToHost);
+    hipMemcpy(hs.data(), dsrc, sizeof(int) * tot, hipMemcpyDeviceToHost);
+    for (int64_t j = 0; j <= na; ++j) optr[j] = hp[j];
+    if (osrc)
+      for (int64_t q = 0; q < tot; ++q) osrc[q] = act[hs[q]];
+    if (mode == 1 && il_off) hipMemcpy(il_off, doff, sizeof(int16_t) * tot, hipMemcpyDeviceToHost);
+  }
+  hipFree(dptr);
+  hipFree(dsrc);
+  hipFree(doff);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
+  return rc;
+}
+
+}  // namespace eifmm

@@ -1,0 +1,240 @@
+"""Python binding of libeifmm.so (include/eifmm.h): argument marshalling only.
+
+Every step of the evaluation runs in the library's HIP kernels; this module
+passes device pointers of PyTorch tensors and the current HIP stream.  There is
+no fallback: if the built library is missing, loading fails with an error.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeifmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "eifmm.h")
+
+KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+FLAG_HOST_ONLY = 1
+MAX_DEPTH = 8
+NPHASE = 9
+PHASES = ["tree", "p2p", "p2m", "m2m", "what", "m2l", "l2l", "lhat", "l2p"]
+STATUS = {0: "OK", -1: "EINVAL", -2: "EDOMAIN", -3: "ESTATE", -4: "EEIM", -5: "ENOMEM",
+          -6: "EHIP"}
+
+
+class EifmmError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({_status_str(code)})")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("kernel_param", ctypes.c_double), ("lo", ctypes.c_double * 3),
+                ("L", ctypes.c_double), ("n", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("eim_tol", ctypes.c_double),
+                ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("d", ctypes.c_int32 * (MAX_DEPTH + 1)), ("dpad", ctypes.c_int32 * (MAX_DEPTH + 1)),
+                ("eim_err", ctypes.c_double * (MAX_DEPTH + 1)), ("setup_ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * NPHASE), ("phase_calls", ctypes.c_int64 * NPHASE),
+                ("m2l_flops", ctypes.c_double),
+                ("active_boxes", ctypes.c_int64 * (MAX_DEPTH + 1)),
+                ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
+                ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (no build here: run __graft_entry__.build() first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime and links it by an unversioned name; it
+        # has to be loaded first so the library binds to that same runtime instead
+        # of a second copy (two runtimes in one process do not share the device).
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.eifmm_plan_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
+        L.eifmm_set_points.argtypes = [vp, vp, vp]
+        L.eifmm_evaluate.argtypes = [vp, vp, i32, i64, vp, i64, vp]
+        L.eifmm_set_timing.argtypes = [vp, i32]
+        L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.eifmm_get_level.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
+        L.eifmm_export_tree.argtypes = [vp, vp, vp, vp]
+        L.eifmm_export_lists.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp]
+        L.eifmm_export_expansion.argtypes = [vp, i32, i32, i32, vp]
+        L.eifmm_plan_destroy.argtypes = [vp]
+        L.eifmm_status_str.argtypes = [ctypes.c_int]
+        L.eifmm_status_str.restype = ctypes.c_char_p
+        for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_evaluate", "eifmm_set_timing",
+                  "eifmm_get_stats", "eifmm_get_level", "eifmm_export_tree", "eifmm_export_lists",
+                  "eifmm_export_expansion", "eifmm_plan_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _status_str(code):
+    try:
+        return lib().eifmm_status_str(code).decode()
+    except Exception:  # library not loadable
+        return "?"
+
+
+def _check(code, what):
+    if code != 0:
+        raise EifmmError(code, what)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """One fixed (kernel, domain, N, depth, tau) setting; points and potentials vary."""
+
+    def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
+                 tol_mode=0, dmax=0, host_only=False):
+        c = Config()
+        c.struct_size = ctypes.sizeof(Config)
+        c.kernel = KERNELS[kernel]
+        c.kernel_param = float(param)
+        for a in range(3):
+            c.lo[a] = float(lo[a])
+        c.L = float(L)
+        c.n = int(n)
+        c.depth = int(depth)
+        c.max_rhs = int(max_rhs)
+        c.eim_tol = float(tau)
+        c.tol_mode = int(tol_mode)
+        c.precision = PRECISIONS[precision]
+        c.dmax = int(dmax)
+        c.flags = FLAG_HOST_ONLY if host_only else 0
+        self.cfg = c
+        self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
+        self.kernel, self.precision = kernel, precision
+        h = ctypes.c_void_p()
+        _check(lib().eifmm_plan_create(ctypes.byref(c), ctypes.byref(h)), "eifmm_plan_create")
+        self._h = h
+
+    # -- per query -----------------------------------------------------------
+    def set_points(self, xyz):
+        """xyz: CUDA float64 tensor of shape (3, n), contiguous."""
+        assert xyz.is_cuda and xyz.dtype.is_floating_point and xyz.element_size() == 8
+        assert tuple(xyz.shape) == (3, self.n) and xyz.is_contiguous()
+        _check(lib().eifmm_set_points(self._h, ctypes.c_void_p(xyz.data_ptr()), _stream()),
+               "eifmm_set_points")
+
+    def evaluate(self, sigma, out=None):
+        """sigma: CUDA float64 tensor (n,) or (nrhs, n) (column-major n x nrhs).
+        Returns f with the same shape, in input order."""
+        import torch
+        assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
+        nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
+        assert sigma.shape[-1] == self.n
+        if out is None:
+            out = torch.empty_like(sigma)
+        _check(lib().eifmm_evaluate(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs, self.n,
+                                    ctypes.c_void_p(out.data_ptr()), self.n, _stream()),
+               "eifmm_evaluate")
+        return out
+
+    def evaluate_raw(self, sigma_ptr, nrhs, ld, f_ptr, ldf, stream=None):
+        """Direct pass-through of eifmm_evaluate (for tests of the argument checks)."""
+        return lib().eifmm_evaluate(self._h, sigma_ptr, nrhs, ld, f_ptr, ldf, stream)
+
+    # -- statistics and exports ------------------------------------------------
+    def set_timing(self, on=True):
+        _check(lib().eifmm_set_timing(self._h, 1 if on else 0), "eifmm_set_timing")
+
+    def stats(self):
+        s = Stats()
+        s.struct_size = ctypes.sizeof(Stats)
+        _check(lib().eifmm_get_stats(self._h, ctypes.byref(s)), "eifmm_get_stats")
+        lv = range(2, self.depth + 1)
+        return dict(d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
+                    eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
+                    phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},
+                    phase_calls={PHASES[q]: s.phase_calls[q] for q in range(NPHASE)},
+                    m2l_flops=s.m2l_flops,
+                    active_boxes={k: s.active_boxes[k] for k in range(self.depth + 1)},
+                    il_pairs={k: s.il_pairs[k] for k in lv}, near_pairs=s.near_pairs,
+                    hip_error=s.hip_error)
+
+    def level(self, k):
+        d = ctypes.c_int32()
+        _check(lib().eifmm_get_level(self._h, k, ctypes.byref(d), None, None, None, None, None,
+                                     None), "eifmm_get_level")
+        d = d.value
+        X, Y = np.empty((d, 3)), np.empty((d, 3))
+        ia, ib = np.empty(d, dtype=np.int64), np.empty(d, dtype=np.int64)
+        B, G = np.empty((d, d)), np.empty((d, d))
+        _check(lib().eifmm_get_level(self._h, k, None, _np_ptr(X), _np_ptr(Y), _np_ptr(ia),
+                                     _np_ptr(ib), _np_ptr(B), _np_ptr(G)), "eifmm_get_level")
+        return dict(d=d, X=X, Y=Y, ia=ia, ib=ib, B=B, G=G)
+
+    def export_tree(self):
+        perm = np.empty(self.n, dtype=np.int32)
+        keys = np.empty(self.n, dtype=np.uint32)
+        ls = np.empty((1 << (3 * self.depth)) + 1, dtype=np.int64)
+        _check(lib().eifmm_export_tree(self._h, _np_ptr(perm), _np_ptr(ls), _np_ptr(keys)),
+               "eifmm_export_tree")
+        return perm, ls, keys
+
+    def export_lists(self, level):
+        nb = 1 << (3 * level)
+        na = ctypes.c_int64()
+        active = np.empty(nb, dtype=np.uint32)
+        near_ptr = np.empty(nb + 1, dtype=np.int64)
+        near_src = np.empty(27 * nb, dtype=np.uint32)
+        il_ptr = np.empty(nb + 1, dtype=np.int64)
+        il_src = np.empty(189 * nb, dtype=np.uint32)
+        il_off = np.empty(189 * nb, dtype=np.int16)
+        _check(lib().eifmm_export_lists(self._h, level, ctypes.byref(na), _np_ptr(active),
+                                        _np_ptr(near_ptr), _np_ptr(near_src), _np_ptr(il_ptr),
+                                        _np_ptr(il_src), _np_ptr(il_off)), "eifmm_export_lists")
+        a = na.value
+        nn, ni = int(near_ptr[a]), int(il_ptr[a])
+        return dict(active=active[:a].copy(), near_ptr=near_ptr[:a + 1].copy(),
+                    near_src=near_src[:nn].copy(), il_ptr=il_ptr[:a + 1].copy(),
+                    il_src=il_src[:ni].copy(), il_off=il_off[:ni].copy())
+
+    def export_expansion(self, which, k, rhs=0):
+        """which in ('W', 'What', 'g', 'l', 'lhat'): dense (8^k, d_k) array."""
+        w = ["W", "What", "g", "l", "lhat"].index(which)
+        d = self.level(k)["d"]
+        out = np.empty((1 << (3 * k), d))
+        _check(lib().eifmm_export_expansion(self._h, w, k, rhs, _np_ptr(out)),
+               "eifmm_export_expansion")
+        return out
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.eifmm_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def declared_symbols(header=HEADER):
+    """Names of the functions declared in include/eifmm.h."""
+    import re
+    txt = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(eifmm_\w+)\s*\(", txt, re.M)))

@@ -1,0 +1,226 @@
+"""GPU parity of the HIP evaluation pass against the CPU oracle (through the C ABI).
+
+Tolerances:
+  * tree, leaf ranges, lists: bit-exact (integer work);
+  * FP64 pass vs the oracle's Algorithm 3 on the same EIM points: both evaluate
+    the same formula in a different order; cond(M_k) ~ 2e9 at tau = 1e-6 and the
+    triangular solves are backward stable, so the expansions may differ by
+    about cond * eps ~ 1e-7 relative in What while the potentials, which are
+    well conditioned in What, agree to ~1e-12; the bound used is 1e-10;
+  * any pass vs the direct sum: the requested accuracy 1e-6 (rel-L2).
+"""
+import numpy as np
+import pytest
+
+from paper_1408_0210_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1408_0210_amd import eifmm
+    eifmm.lib()
+    return eifmm
+
+
+def _gpu_eval(E, torch_dev, kernel, param, x, s, depth, tau, precision="fp64", plan=None,
+              max_rhs=1):
+    torch, dev = torch_dev
+    n = x.shape[1]
+    if plan is None:
+        plan = E.Plan(kernel, param, [0, 0, 0], 1.0, n, depth, tau, max_rhs=max_rhs,
+                      precision=precision)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = plan.evaluate(torch.from_numpy(np.ascontiguousarray(s)).to(dev))
+    torch.cuda.synchronize()
+    return plan, f.cpu().numpy()
+
+
+TREE_CASES = {
+    "uniform2k_d3": lambda: (W.uniform_points(2000, 1), 3),
+    "cluster3k_d4_faces": lambda: (_faces(W.cluster_points(3000, 3, 0.08, 31, 32)), 4),
+    "single_point_d2": lambda: (np.array([[0.3], [0.7], [1.0]]), 2),
+    "uniform500_d0": lambda: (W.uniform_points(500, 33), 0),
+    "uniform500_d1": lambda: (W.uniform_points(500, 34), 1),
+    "uniform100k_d5": lambda: (W.uniform_points(100_000, 35), 5),
+}
+
+
+def _faces(x):
+    """Add points exactly on the domain faces, edges, a corner, and duplicates."""
+    x = x.copy()
+    x[0, :10] = 1.0
+    x[1, 10:20] = 0.0
+    x[:, 20:25] = 1.0
+    x[:, 25:30] = x[:, 30:35]
+    return x
+
+
+@pytest.mark.parametrize("case", sorted(TREE_CASES))
+def test_tree_and_lists_bit_exact(case, E, torch_dev, oracle_lib):
+    torch, dev = torch_dev
+    x, depth = TREE_CASES[case]()
+    n = x.shape[1]
+    plan = E.Plan("laplace", 0, [0, 0, 0], 1.0, n, depth, 1e-2)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    perm, ls, keys = plan.export_tree()
+    okeys, operm, ols = oracle_lib.tree(x, [0, 0, 0], 1.0, depth)
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(ls, ols)
+    np.testing.assert_array_equal(keys, okeys[operm])
+    for level in range(0, depth + 1):
+        g = plan.export_lists(level)
+        o = oracle_lib.lists(ols, depth, level)
+        for name in ("active", "near_ptr", "near_src"):
+            np.testing.assert_array_equal(g[name], o[name], err_msg=f"{name} level {level}")
+        if level >= 2:
+            for name in ("il_ptr", "il_src", "il_off"):
+                np.testing.assert_array_equal(g[name], o[name], err_msg=f"{name} level {level}")
+            st = plan.stats()
+            assert st["il_pairs"][level] == len(o["il_src"])
+    plan.close()
+
+
+@pytest.mark.parametrize("depth,dist", [(3, "uniform"), (4, "cluster")])
+def test_finite_rank_pass_exact(depth, dist, E, torch_dev, oracle_lib):
+    """k(z) = |z|^2 is interpolated exactly (rank 5): the GPU pass must equal the
+    direct sum to rounding, which checks every index and translation path."""
+    x = W.uniform_points(3000, 41) if dist == "uniform" else W.cluster_points(3000, 3, 0.05, 42, 43)
+    s = W.potentials(3000, 44)
+    plan, f = _gpu_eval(E, torch_dev, "sqdist", 0, x, s, depth, 1e-8)
+    assert all(v == 5 for v in plan.stats()["d"].values())
+    fd = oracle_lib.direct("sqdist", 0, x, x, s)
+    assert _rel(f, fd) < 1e-12
+    plan.close()
+
+
+def test_near_field_only(E, torch_dev, oracle_lib):
+    """depth < 2: no well-separated pairs, the pass is the near field alone."""
+    x = W.uniform_points(3000, 45)
+    s = W.potentials(3000, 46)
+    for depth in (0, 1):
+        plan, f = _gpu_eval(E, torch_dev, "laplace", 0, x, s, depth, 1e-6)
+        assert _rel(f, oracle_lib.direct("laplace", 0, x, x, s)) < 1e-13
+        plan.close()
+
+
+def test_c1_fp64_vs_oracle(E, torch_dev, c1_inputs, c1_plan, c1_direct):
+    """2000 uniform points, 1/r, depth 3, tau 1e-6, FP64."""
+    x, s, w = c1_inputs
+    plan, f = _gpu_eval(E, torch_dev, w["kernel"], w["param"], x, s, w["depth"], w["tau"])
+    for k in range(2, w["depth"] + 1):
+        a, b = plan.level(k), c1_plan.levels[k]
+        assert a["d"] == b["d"]
+        np.testing.assert_array_equal(a["ia"], b["ia"])
+        np.testing.assert_array_equal(a["ib"], b["ib"])
+    fo = c1_plan.evaluate(x, s)
+    assert _rel(f, fo) < 1e-10
+    assert _rel(f, c1_direct) < 1e-6
+    plan.close()
+
+
+def test_c1_stages_vs_oracle(E, torch_dev, c1_inputs, c1_plan):
+    """Each expansion of Algorithm 3 (W, What, g, l, lhat) against the oracle."""
+    x, s, w = c1_inputs
+    plan, f = _gpu_eval(E, torch_dev, w["kernel"], w["param"], x, s, w["depth"], w["tau"])
+    _, D = c1_plan.evaluate(x, s, dumps=True)
+    tol = {"W": 1e-12, "What": 1e-5, "g": 1e-10, "l": 1e-10}
+    for k in range(2, w["depth"] + 1):
+        for name in ("W", "What", "g", "l"):
+            e = _rel(plan.export_expansion(name, k), D[name][k])
+            assert e < tol[name], (name, k, e)
+    e = _rel(plan.export_expansion("lhat", w["depth"]), D["lhat"])
+    assert e < 1e-5, e
+    plan.close()
+
+
+def test_multi_rhs_matches_single(E, torch_dev, oracle_lib):
+    """nrhs = 5 (several column tiles with a ragged tail) equals 5 single passes."""
+    torch, dev = torch_dev
+    x = W.uniform_points(2500, 51)
+    S = np.stack([W.potentials(2500, 60 + r) for r in range(5)])
+    plan = E.Plan("laplace", 0, [0, 0, 0], 1.0, 2500, 3, 1e-4, max_rhs=8)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    F = plan.evaluate(torch.from_numpy(S).to(dev)).cpu().numpy()
+    for r in range(5):
+        f1 = plan.evaluate(torch.from_numpy(S[r].copy()).to(dev)).cpu().numpy()
+        assert _rel(F[r], f1) < 1e-14
+    fd = oracle_lib.direct("laplace", 0, x, x, S[3])
+    assert _rel(F[3], fd) < 1e-4
+    plan.close()
+
+
+@pytest.mark.parametrize("kernel,param,tau", [("yukawa", 1.0, 1e-6), ("gauss", 0.1, 1e-6)])
+def test_other_kernels_vs_oracle(kernel, param, tau, E, torch_dev, oracle_lib):
+    x = W.cluster_points(2000, 4, 0.1, 71, 72)
+    s = W.potentials(2000, 73)
+    plan, f = _gpu_eval(E, torch_dev, kernel, param, x, s, 3, tau)
+    O = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, 3, tau)
+    assert _rel(f, O.evaluate(x, s)) < 1e-10
+    assert _rel(f, oracle_lib.direct(kernel, param, x, x, s)) < 1e-5
+    plan.close()
+
+
+def test_mixed_precision_small(E, torch_dev, c1_inputs, c1_direct):
+    x, s, w = c1_inputs
+    plan, f = _gpu_eval(E, torch_dev, w["kernel"], w["param"], x, s, w["depth"], w["tau"],
+                        precision="mixed")
+    assert _rel(f, c1_direct) < 1e-6
+    plan.close()
+
+
+def test_deterministic(E, torch_dev, c1_inputs):
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    for prec in ("fp64", "mixed"):
+        plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                      precision=prec)
+        plan.set_points(torch.from_numpy(x).to(dev))
+        st = torch.from_numpy(s).to(dev)
+        a = plan.evaluate(st).cpu().numpy()
+        b = plan.evaluate(st).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+        plan.close()
+
+
+def test_error_paths(E, torch_dev):
+    torch, dev = torch_dev
+    x = W.uniform_points(100, 81)
+    plan = E.Plan("laplace", 0, [0, 0, 0], 1.0, 100, 2, 1e-3, max_rhs=2)
+    s = torch.from_numpy(W.potentials(100, 82)).to(dev)
+    with pytest.raises(E.EifmmError) as e:
+        plan.evaluate(s)
+    assert e.value.code == -3  # evaluate before set_points
+    bad = x.copy()
+    bad[2, 7] = 1.5
+    with pytest.raises(E.EifmmError) as e:
+        plan.set_points(torch.from_numpy(bad).to(dev))
+    assert e.value.code == -2
+    bad[2, 7] = np.nan
+    with pytest.raises(E.EifmmError) as e:
+        plan.set_points(torch.from_numpy(bad).to(dev))
+    assert e.value.code == -2
+    with pytest.raises(E.EifmmError):
+        plan.evaluate(s)  # the failed set_points left no points
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = torch.empty(3, 100, dtype=torch.float64, device=dev)
+    s3 = torch.zeros(3, 100, dtype=torch.float64, device=dev)
+    assert plan.evaluate_raw(s3.data_ptr(), 3, 100, f.data_ptr(), 100) == -1  # nrhs > max_rhs
+    assert plan.evaluate_raw(s3.data_ptr(), 1, 50, f.data_ptr(), 100) == -1   # ld < n
+    assert plan.evaluate_raw(None, 1, 100, f.data_ptr(), 100) == -1
+    plan.evaluate(s)  # still usable
+    torch.cuda.synchronize()
+    plan.close()
