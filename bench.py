@@ -1,0 +1,209 @@
+"""Benchmark of the EIFMM evaluation pass on one MI355X.
+
+Default workload: 1,000,000 points uniform in the unit cube, sigma uniform in
+[-1, 1], K = 1/r, octree depth 5, EIM tolerance 1e-6, FP64, one right-hand side.
+A step is one query: the octree build for the points (set_points) plus the whole
+evaluation pass (evaluate).  value = N^2 / t (effective interactions per second).
+
+Also reported on the same line:
+  roofline      the M2L kernel (the dominant launch): algorithmic flops per
+                launch (2 d_k^2 per interaction pair per right-hand side, summed
+                over levels) over its mean launch time from HIP events recorded on
+                the stream the library launches on, against the MFMA peak of its
+                dtype; traffic from the committed rocprofv3 counter summary;
+  cpu_baseline  the CPU oracle's direct sum timed on this host on a bounded
+                sample of targets (all N sources), whose values also give the
+                sampled rel-L2 error of the GPU result;
+  batched_mixed the many-query variant: 2^20 points, 64 sigma vectors, M2L on
+                FP32 MFMA (mixed precision), tree built once, per-RHS rate.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective interactions/s (N²/t) at rel-L2 err 1e-6, 1e6 pts; batched/FP32 vs plain"
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA peaks, FP64 and FP32
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "m2l_traffic.json")
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _rel_sample(f, idx, ref):
+    return float(np.linalg.norm(f[idx] - ref) / np.linalg.norm(ref))
+
+
+def cpu_baseline(kernel, param, x, s, gpu_f, target_seconds=10.0):
+    """Time the oracle direct sum on a bounded sample of targets; reuse its values
+    as the reference for the sampled accuracy of the GPU result."""
+    import oracle
+    n = x.shape[1]
+    cores = min(os.cpu_count() or 1, 16)
+    rng = np.random.default_rng(12345)
+    probe = rng.choice(n, 64, replace=False)
+    t0 = time.perf_counter()
+    oracle.direct(kernel, param, x[:, probe].copy(), x, s, threads=cores)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    m = int(min(n, max(256, 64 * target_seconds / dt)))
+    idx = np.sort(rng.choice(n, m, replace=False))
+    t0 = time.perf_counter()
+    ref = oracle.direct(kernel, param, x[:, idx].copy(), x, s, threads=cores)
+    dt = time.perf_counter() - t0
+    rate = m * n / dt
+    err = _rel_sample(gpu_f, idx, ref) if gpu_f is not None else None
+    return dict(value=rate, unit="interactions/s", cores=cores, kind="oracle",
+                sample=f"direct sum of {m} random targets against all {n} sources "
+                       f"({dt:.1f} s), rate scaled to N^2/t"), err, idx, ref
+
+
+def run_plain(args):
+    import torch
+    from paper_1408_0210_amd import eifmm as E
+    from paper_1408_0210_amd import workloads as W
+    w = dict(W.WORKLOADS[args.workload])
+    tau = args.tau if args.tau else w["tau"]
+    x, s = W.make_points(w), W.make_sigma(w)
+    n = w["n"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], tau,
+                  precision=args.precision)
+    setup_s = time.perf_counter() - t0
+    xd = torch.from_numpy(x).to(dev)
+    sd = torch.from_numpy(s).to(dev)
+    f = torch.empty_like(sd)
+    for _ in range(args.warmup):
+        plan.set_points(xd)
+        plan.evaluate(sd, out=f)
+    _sync()
+    plan.set_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _sync()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.set_points(xd)
+        plan.evaluate(sd, out=f)
+    ev1.record()
+    _sync()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    st = plan.stats()
+    plan.set_timing(False)
+    fh = f.cpu().numpy()
+    return dict(w=w, tau=tau, n=n, ms=ms, stats=st, setup_s=setup_s, f=fh, x=x, s=s, plan=plan)
+
+
+def run_batched(args):
+    """Many right-hand sides on one fixed point set, mixed precision."""
+    import torch
+    from paper_1408_0210_amd import eifmm as E
+    from paper_1408_0210_amd import workloads as W
+    w = dict(W.WORKLOADS["uniform1m_laplace_d5_rhs64"])
+    x, S = W.make_points(w), W.make_sigma(w)  # S: (n, 64) column-major
+    n, R = w["n"], S.shape[1]
+    dev = torch.device("cuda:0")
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], args.batched_tau,
+                  max_rhs=R, precision="mixed")
+    xd = torch.from_numpy(x).to(dev)
+    sd = torch.from_numpy(np.ascontiguousarray(S.T)).to(dev)  # (64, n)
+    f = torch.empty_like(sd)
+    plan.set_points(xd)
+    for _ in range(max(1, args.warmup)):
+        plan.evaluate(sd, out=f)
+    _sync()
+    plan.set_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    steps = max(1, args.batched_steps)
+    for _ in range(steps):
+        plan.evaluate(sd, out=f)
+    ev1.record()
+    _sync()
+    ms = ev0.elapsed_time(ev1) / steps
+    st = plan.stats()
+    fh = f.cpu().numpy()
+    # sampled accuracy on four right-hand sides against the oracle direct sum
+    import oracle
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, 1000, replace=False))
+    errs = []
+    for r in (0, 21, 42, 63):
+        ref = oracle.direct(w["kernel"], w["param"], x[:, idx].copy(), x, S[:, r].copy(),
+                            threads=min(os.cpu_count() or 1, 16))
+        errs.append(_rel_sample(fh[r], idx, ref))
+    m2l_ms = st["phase_ms"]["m2l"] / max(1, st["phase_calls"]["m2l"])
+    plan.close()
+    return dict(value=R * float(n) ** 2 / (ms * 1e-3), unit="interactions/s", nrhs=R, n=n,
+                ms_per_step=ms, precision="mixed", tau=args.batched_tau,
+                rel_l2_sampled_max=max(errs),
+                m2l_frac=st["m2l_flops"] / (m2l_ms * 1e-3) / (PEAK_TFLOPS["mixed"] * 1e12),
+                note="tree built once; t covers evaluate of 64 RHS; value = 64 N^2 / t")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uniform1m_laplace_d5")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tau", type=float, default=0.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS mixed run")
+    ap.add_argument("--batched-tau", type=float, default=1e-6)
+    ap.add_argument("--batched-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
+              "(the path has no multi-GPU mode)", file=sys.stderr)
+        sys.exit(2)
+
+    r = run_plain(args)
+    st, n, ms = r["stats"], r["n"], r["ms"]
+    print(f"[bench] {args.workload} precision={args.precision} tau={r['tau']} "
+          f"d={st['d']} ms/step={ms:.3f} setup={r['setup_s']:.1f}s", file=sys.stderr, flush=True)
+    m2l_calls = max(1, st["phase_calls"]["m2l"])
+    m2l_ms = st["phase_ms"]["m2l"] / m2l_calls
+    achieved = st["m2l_flops"] / (m2l_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        tr = json.load(open(PROFILE_TRAFFIC))
+        key = f"{args.workload}:{args.precision}"
+        if key in tr and tr[key].get("valid", False):
+            traffic = tr[key]["bytes_per_launch"]
+    phases = {k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]}
+    out = {
+        "metric": METRIC, "value": float(n) ** 2 / (ms * 1e-3), "unit": "interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "depth": r["w"]["depth"],
+                   "kernel": r["w"]["kernel"], "tau": r["tau"], "nrhs": 1,
+                   "precision": args.precision, "d": st["d"],
+                   "step": "set_points + evaluate", "phase_ms": phases},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_gemm M2L (all levels, one launch)",
+                     "flops_per_launch": st["m2l_flops"], "ms_per_launch": m2l_ms},
+    }
+    if not args.no_cpu:
+        cb, err, _, _ = cpu_baseline(r["w"]["kernel"], r["w"]["param"], r["x"], r["s"], r["f"])
+        out["cpu_baseline"] = cb
+        out["config"]["rel_l2_sampled"] = err
+    r["plan"].close()
+    if not args.no_batched:
+        out["batched_mixed"] = run_batched(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,17 +178,12 @@ int device_setup(eifmm_plan h) {
     const size_t m = D.cap * (size_t)R * (size_t)P.lh[k].dp;
     TRY(dalloc(&D.W, m, tr));
     TRY(dalloc(&D.Wh, m, tr));
-    if (mixed) {
-      TRY(dalloc(&D.Wh32, m, tr));
-      TRY(dalloc(&D.g32, m, tr));
+    if (mixed) TRY(dalloc(&D.Wh32, m, tr));
+    TRY(dalloc(&D.g, m, tr));
+    if (k == 2)
+      D.l = D.g;  // l^2 = g^2 (Algorithm 3, step 5)
+    else
       TRY(dalloc(&D.l, m, tr));
-    } else {
-      TRY(dalloc(&D.g, m, tr));
-      if (k == 2)
-        D.l = D.g;  // l^2 = g^2 (Algorithm 3, step 5)
-      else
-        TRY(dalloc(&D.l, m, tr));
-    }
   }
   if (depth >= 2)
     TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dp, tr));
@@ -375,24 +370,16 @@ int eifmm_export_expansion(eifmm_plan h, int32_t which, int32_t k, int32_t rhs, 
   const LevelDev &D = P.ld[k];
   const int d = P.lh[k].d, dp = P.lh[k].dp, R = P.last_rhs;
   const int64_t na = P.nact[k];
-  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
   std::vector<double> buf((size_t)na * R * dp);
-  const void *src = nullptr;
-  bool f32 = false;
+  const double *src = nullptr;
   switch (which) {
     case 0: src = D.W; break;
     case 1: src = D.Wh; break;
-    case 2: src = mixed ? (const void *)D.g32 : (const void *)D.g; f32 = mixed; break;
+    case 2: src = D.g; break;
     case 3: src = D.l; break;
     default: src = P.lhat; break;
   }
-  if (f32) {
-    std::vector<float> tmp(buf.size());
-    hipMemcpy(tmp.data(), src, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost);
-    for (size_t q = 0; q < tmp.size(); ++q) buf[q] = tmp[q];
-  } else {
-    hipMemcpy(buf.data(), src, sizeof(double) * buf.size(), hipMemcpyDeviceToHost);
-  }
+  hipMemcpy(buf.data(), src, sizeof(double) * buf.size(), hipMemcpyDeviceToHost);
   std::vector<uint32_t> act(na);
   hipMemcpy(act.data(), D.act, sizeof(uint32_t) * na, hipMemcpyDeviceToHost);
   const int64_t nb = (int64_t)1 << (3 * k);

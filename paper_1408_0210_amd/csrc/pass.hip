@@ -332,23 +332,22 @@ __global__ void k_combine_near(int64_t n, int nrhs, const double *__restrict__ f
   f[(int64_t)perm[s] + (int64_t)r * ldf] = fnear[e];
 }
 
-__global__ void k_f32_to_f64(int64_t m, const float *__restrict__ in, double *__restrict__ out) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < m) out[e] = (double)in[e];
-}
-
 // ------------------------------------------------------------------ triangular solves
-// One thread per column (box, rhs).  Forward substitution with the lower
-// factor, then backward substitution with the upper factor, both blocked in
-// 16 x 16 tiles: a tile row of the unknowns stays in registers, the factor
-// tiles are read at uniform addresses.
-//   Delta   v: Gamma z = v, then B^T w = z        (UF = false, UB = true)
-//   Delta^T v: B z = v,     then Gamma^T w = z    (UF = true,  UB = false)
+// One wave per 16 columns (box, rhs).  Forward substitution with the lower
+// factor, then backward substitution with the upper factor, in 16-row tiles:
+//   r_bi = v_bi - sum_{bj < bi} T[bi][bj] z_bj        (MFMA, -T tiles in the table)
+//   z_bi = T[bi][bi]^{-1} r_bi                       (MFMA with the inverted tile)
+// The solved tiles of the 16 columns stay in LDS.  In the FP64 16x16x4 MFMA the
+// result register q of lane l holds row (l / 16) + 4 q of column l % 16, which
+// is exactly the B operand that lane supplies at k-step q, so tiles feed the
+// next product without data movement.
+//   Delta   v: Gamma z = v, then B^T w = z
+//   Delta^T v: B z = v,     then Gamma^T w = z
 struct SolveDesc {
   const double *in;
   double *out;
   float *out32;
-  const double *Tf, *Tb;
+  const double *Tf, *Tb;  // fragment tables (setup.cpp)
   int ncols, dp, blk_start, pad;
 };
 struct SolveArgs {
@@ -356,68 +355,66 @@ struct SolveArgs {
   int nlev;
 };
 
-template <bool UF, bool UB>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
+__global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  extern __shared__ double zs[];  // [nb][4][64]
   int li = 0;
   for (int q = 1; q < A.nlev; ++q)
     if ((int)blockIdx.x >= A.lv[q].blk_start) li = q;
   const SolveDesc &D = A.lv[li];
-  const int c = ((int)blockIdx.x - D.blk_start) * 256 + (int)threadIdx.x;
-  if (c >= D.ncols) return;
-  const int dp = D.dp, nb = dp >> 4;
-  const double *x = D.in + (int64_t)c * dp;
-  double *y = D.out + (int64_t)c * dp;
+  const int lane = threadIdx.x;
+  const int c = ((int)blockIdx.x - D.blk_start) * 16 + (lane & 15);
+  const bool cv = c < D.ncols;
+  const int dp = D.dp, nb = dp >> 4, rs = lane >> 4;
+  const double *x = D.in + (int64_t)(cv ? c : 0) * dp;
+  double *y = D.out + (int64_t)(cv ? c : 0) * dp;
   for (int bi = 0; bi < nb; ++bi) {
-    double v[16];
+    v4 acc;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = x[16 * bi + q];
+    for (int q = 0; q < 4; ++q) acc[q] = cv ? x[16 * bi + rs + 4 * q] : 0.0;
+    const double *Ar = D.Tf + (int64_t)bi * nb * 256 + lane;
     for (int bj = 0; bj < bi; ++bj) {
-      const double *T = D.Tf + ((int64_t)bi * nb + bj) * 256;
-      double z[16];
+      const double *Ab = Ar + bj * 256;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) z[q] = y[16 * bj + q];
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * z[jj];
+      for (int ks = 0; ks < 4; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
+                                                   0, 0, 0);
     }
-    const double *T = D.Tf + ((int64_t)bi * nb + bi) * 256;
+    const double *Ad = Ar + bi * 256;
+    v4 z = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int ks = 0; ks < 4; ++ks)
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(Ad[ks * 64], acc[ks], z, 0, 0, 0);
 #pragma unroll
-      for (int jj = 0; jj < i; ++jj) v[i] -= T[i * 16 + jj] * v[jj];
-      if (!UF) v[i] = v[i] / T[i * 16 + i];
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) y[16 * bi + q] = v[q];
+    for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = z[q];
   }
   for (int bi = nb - 1; bi >= 0; --bi) {
-    double v[16];
+    v4 acc;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = y[16 * bi + q];
+    for (int q = 0; q < 4; ++q) acc[q] = zs[(bi * 4 + q) * 64 + lane];
+    const double *Ar = D.Tb + (int64_t)bi * nb * 256 + lane;
     for (int bj = bi + 1; bj < nb; ++bj) {
-      const double *T = D.Tb + ((int64_t)bi * nb + bj) * 256;
-      double z[16];
+      const double *Ab = Ar + bj * 256;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) z[q] = y[16 * bj + q];
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * z[jj];
+      for (int ks = 0; ks < 4; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
+                                                   0, 0, 0);
     }
-    const double *T = D.Tb + ((int64_t)bi * nb + bi) * 256;
+    const double *Ad = Ar + bi * 256;
+    v4 w = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 15; i >= 0; --i) {
+    for (int ks = 0; ks < 4; ++ks)
+      w = __builtin_amdgcn_mfma_f64_16x16x4f64(Ad[ks * 64], acc[ks], w, 0, 0, 0);
 #pragma unroll
-      for (int jj = i + 1; jj < 16; ++jj) v[i] -= T[i * 16 + jj] * v[jj];
-      if (!UB) v[i] = v[i] / T[i * 16 + i];
-    }
+    for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = w[q];
+    if (cv) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) y[16 * bi + q] = v[q];
-    if (D.out32) {
-      float *y32 = D.out32 + (int64_t)c * dp;
+      for (int q = 0; q < 4; ++q) y[16 * bi + rs + 4 * q] = w[q];
+      if (D.out32) {
+        float *y32 = D.out32 + (int64_t)c * dp;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) y32[16 * bi + q] = (float)v[q];
+        for (int q = 0; q < 4; ++q) y32[16 * bi + rs + 4 * q] = (float)w[q];
+      }
     }
   }
 }
@@ -429,7 +426,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
 // parent).  A workgroup computes a 96-row x 128-column tile with 16x16x4 MFMAs;
 // 4 waves in a 2 x 2 arrangement each own 3 x 4 output blocks.  Operand chunks
 // of 16 k values pass through LDS in MFMA fragment order; the next chunk is
-// loaded into registers while the current one is multiplied.
+// loaded into registers while the current one is multiplied.  With FOLD (FP32
+// operands) each term's product is accumulated by the MFMA in FP32 and then
+// added to an FP64 sum over the terms, so FP32 rounding grows with one matrix
+// product (d_k terms) rather than with the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2;
 constexpr int GT_RB = 6, GT_CB = 8, GT_COLS = 16 * GT_CB;
 
@@ -501,7 +501,7 @@ __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
   return (const T *)J.A + idx * J.a_stride;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool FOLD>
 __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
                                                  int ntiles, const int8_t *__restrict__ dvec) {
   typedef typename Mfma<T>::v4 V4;
@@ -545,10 +545,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   }
 
   V4 acc[3][4];
+  typedef double D4 __attribute__((ext_vector_type(4)));
+  D4 sum[3][4];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = V4{0, 0, 0, 0};
+    for (int jj = 0; jj < 4; ++jj) {
+      acc[i][jj] = V4{0, 0, 0, 0};
+      if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
+    }
   bool rowok[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) rowok[i] = rb0 + 3 * wr + i < nrb;
@@ -615,6 +620,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
           for (int jj = 0; jj < 4; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
+    if constexpr (FOLD) {
+      if ((it + 1) % nkc == 0) {  // a term is complete
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
+            acc[i][jj] = V4{0, 0, 0, 0};
+          }
+      }
+    }
   }
 
   // write the tile (result layout per Mfma<T>::row)
@@ -632,14 +649,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t o = cbase + rbase + Mfma<T>::row(lane, q);
-        T v = acc[i][jj][q];
-        if constexpr (MODE == MODE_L2L) {
-          if (J.cadd_f32)
-            v += (T)((const float *)J.Cadd)[o];
-          else
-            v += (T)((const double *)J.Cadd)[o];
-        }
-        ((T *)J.C)[o] = v;
+        double v;
+        if constexpr (FOLD)
+          v = sum[i][jj][q];
+        else
+          v = (double)acc[i][jj][q];
+        if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
+        J.C[o] = v;
       }
     }
   }
@@ -729,7 +745,7 @@ int build_jobs(Plan &P, int nrhs) {
         GemmJob J{};
         J.A = mixed ? (const void *)P.ld[k].kfrag32 : (const void *)P.ld[k].kfrag;
         J.Bsrc = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
-        J.C = mixed ? (void *)P.ld[k].g32 : (void *)P.ld[k].g;
+        J.C = P.ld[k].g;
         J.tgt = P.ld[k].cls + P.cls_off[k][c];
         J.tgt_keys = P.ld[k].act;
         J.src_slot = P.ld[k].slot;
@@ -762,8 +778,7 @@ int build_jobs(Plan &P, int nrhs) {
       J.A = P.ld[k - 1].l2l;
       J.Bsrc = P.ld[k - 1].l;
       J.C = P.ld[k].l;
-      J.Cadd = mixed ? (const void *)P.ld[k].g32 : (const void *)P.ld[k].g;
-      J.cadd_f32 = mixed ? 1 : 0;
+      J.Cadd = P.ld[k].g;
       J.tgt = P.ld[k].cls + P.cls_off[k][c];
       J.tgt_keys = P.ld[k].act;
       J.src_slot = P.ld[k - 1].slot;
@@ -800,8 +815,9 @@ template <typename T, int MODE>
 void launch_gemm(Plan &P, int first, int n, int tiles, hipStream_t s) {
   if (n == 0 || tiles == 0) return;
   const int grid = ((tiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_gemm<T, MODE>), dim3(grid), dim3(256), 0, s, P.job_dev + first, n, tiles,
-                     P.dvec);
+  constexpr bool fold = sizeof(T) == 4;
+  hipLaunchKernelGGL((k_gemm<T, MODE, fold>), dim3(grid), dim3(256), 0, s, P.job_dev + first, n,
+                     tiles, P.dvec);
 }
 
 template <int KIND>
@@ -866,6 +882,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_WHAT);
     SolveArgs A{};
     int blk = 0, q = 0;
+    size_t shm = 0;
     for (int k = 2; k <= depth; ++k) {
       const int nc = (int)(P.nact[k] * nrhs);
       if (nc == 0) continue;
@@ -878,10 +895,11 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
       D.ncols = nc;
       D.dp = P.lh[k].dp;
       D.blk_start = blk;
-      blk += (nc + 255) / 256;
+      blk += (nc + 15) / 16;
+      shm = std::max(shm, sizeof(double) * 4 * 64 * (size_t)(P.lh[k].dp / 16));
     }
     A.nlev = q;
-    if (blk > 0) hipLaunchKernelGGL((k_solve<false, true>), dim3(blk), dim3(256), 0, s, A);
+    if (blk > 0) hipLaunchKernelGGL(k_trsm, dim3(blk), dim3(64), shm, s, A);
   }
   // step 4: M2L
   {
@@ -894,12 +912,6 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
   // step 5: l^2 = g^2, then L2L downwards
   {
     Timer tm(P, s, EIFMM_PH_L2L);
-    if (mixed) {
-      const int64_t m = P.nact[2] * nrhs * P.lh[2].dp;
-      if (m > 0)
-        hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m,
-                           P.ld[2].g32, P.ld[2].l);
-    }
     for (int k = 3; k <= depth; ++k)
       launch_gemm<double, MODE_L2L>(P, P.jobs.l2l_first[k], P.jobs.l2l_n[k], P.jobs.l2l_tiles[k],
                                     s);
@@ -919,7 +931,8 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     A.lv[0].blk_start = 0;
     A.nlev = 1;
     if (nc > 0)
-      hipLaunchKernelGGL((k_solve<true, false>), dim3((nc + 255) / 256), dim3(256), 0, s, A);
+      hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64),
+                         sizeof(double) * 4 * 64 * (size_t)(HL.dp / 16), s, A);
   }
   // step 7: L2P and the final sum
   if (nleafa > 0) {

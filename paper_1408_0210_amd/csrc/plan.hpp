@@ -25,7 +25,7 @@ struct LevelHost {
   std::vector<double> kfrag;    // 316 M2L matrices K^delta, fragment order
   std::vector<double> m2m;      // level k < depth: 8 ops d_k x d_{k+1}, fragment order
   std::vector<double> l2l;      // level k < depth: 8 ops d_{k+1} x d_k, fragment order
-  std::vector<double> tri[4];   // blocked Gamma, B^T, B, Gamma^T (16 x 16 tiles)
+  std::vector<double> tri[4];   // solve tables: Gamma, B^T, B, Gamma^T (setup.cpp)
 };
 
 // Device copy of one level's tables.
@@ -41,15 +41,15 @@ struct LevelDev {
   int *slot = nullptr;       // [8^k] slot of each key, -1 if empty
   int *cls = nullptr;        // slots grouped by child class (key & 7), ascending key
   double *W = nullptr, *Wh = nullptr, *g = nullptr, *l = nullptr;
-  float *Wh32 = nullptr, *g32 = nullptr;
+  float *Wh32 = nullptr;  // FP32 copy of What (mixed precision M2L)
 };
 
 // One target group of a gathered GEMM launch (see pass.hip).
 struct GemmJob {
   const void *A;        // fragment-ordered operand(s)
   const void *Bsrc;     // source expansions [slot * nrhs + r][dpk]
-  void *C;              // output [slot * nrhs + r][dpm]
-  const void *Cadd;     // added to the product (L2L: g), may be null
+  double *C;            // output [slot * nrhs + r][dpm]
+  const double *Cadd;   // added to the product (L2L: g), may be null
   const int *tgt;       // target slots
   const uint32_t *tgt_keys;  // active keys of the target level (indexed by slot)
   const int *src_slot;  // slot map of the source level (indexed by key)
@@ -58,7 +58,6 @@ struct GemmJob {
   int ntgt, nterms, dpm, dpk;
   int level, cls, mode, nrhs;
   int tiles_start, ncoltiles, nrowtiles, src_level;
-  int cadd_f32, pad0;
 };
 
 // Index ranges of the gathered-GEMM jobs of one (points, nrhs) pair.

@@ -288,24 +288,52 @@ void to_fragments(const double *A, int rows, int cols, int rpad, int cpad, doubl
       }
 }
 
-// Blocked copy of a d x d matrix padded to dp with the identity, 16 x 16 tiles:
-// out[((bi * nb) + bj) * 256 + i * 16 + j] = T[16 bi + i][16 bj + j].
-void to_blocks(const std::vector<double> &T, int d, int dp, bool transpose,
-               std::vector<double> &out) {
+// Operand table of a blocked triangular solve with 16 x 16 tiles, for the MFMA
+// solver: T (d x d, or its transpose) is padded to dp with the identity; tile
+// (bi, bj) of the triangle holds -T[bi][bj] off the diagonal and the inverse of
+// the diagonal tile T[bi][bi] on it (the inverse of a 16 x 16 triangular tile,
+// by substitution; the full triangular factor is never inverted).  Tiles are
+// stored in A-operand fragment order: out[((bi nb + bj) 4 + ks) 64 + lane] is
+// element (lane % 16, 4 ks + lane / 16) of the tile.
+void trsm_table(const std::vector<double> &T, int d, int dp, bool transpose, bool lower,
+                std::vector<double> &out) {
   const int nb = dp / 16;
+  auto at = [&](int r, int c) -> double {
+    if (r < d && c < d) return transpose ? T[(size_t)c * d + r] : T[(size_t)r * d + c];
+    return r == c ? 1.0 : 0.0;
+  };
   out.assign((size_t)dp * dp, 0.0);
+  double tile[16][16], inv[16][16];
   for (int bi = 0; bi < nb; ++bi)
-    for (int bj = 0; bj < nb; ++bj)
+    for (int bj = 0; bj < nb; ++bj) {
+      if (lower ? bj > bi : bj < bi) continue;
       for (int i = 0; i < 16; ++i)
-        for (int j = 0; j < 16; ++j) {
-          int r = 16 * bi + i, c = 16 * bj + j;
-          double v;
-          if (r < d && c < d)
-            v = transpose ? T[(size_t)c * d + r] : T[(size_t)r * d + c];
-          else
-            v = (r == c) ? 1.0 : 0.0;
-          out[((size_t)bi * nb + bj) * 256 + i * 16 + j] = v;
+        for (int j = 0; j < 16; ++j) tile[i][j] = at(16 * bi + i, 16 * bj + j);
+      if (bi == bj) {
+        // columns of the inverse by substitution on the identity
+        for (int c = 0; c < 16; ++c) {
+          if (lower) {
+            for (int i = 0; i < 16; ++i) {
+              double s = (i == c) ? 1.0 : 0.0;
+              for (int j = 0; j < i; ++j) s -= tile[i][j] * inv[j][c];
+              inv[i][c] = s / tile[i][i];
+            }
+          } else {
+            for (int i = 15; i >= 0; --i) {
+              double s = (i == c) ? 1.0 : 0.0;
+              for (int j = i + 1; j < 16; ++j) s -= tile[i][j] * inv[j][c];
+              inv[i][c] = s / tile[i][i];
+            }
+          }
         }
+      }
+      double *o = &out[((size_t)bi * nb + bj) * 256];
+      for (int ks = 0; ks < 4; ++ks)
+        for (int l = 0; l < 64; ++l) {
+          const int r = l & 15, c = 4 * ks + (l >> 4);
+          o[ks * 64 + l] = (bi == bj) ? inv[r][c] : -tile[r][c];
+        }
+    }
 }
 
 }  // namespace
@@ -359,10 +387,10 @@ int build_tables(Plan &P) {
         to_fragments(A.data(), d, d, dp, dp, &lv.kfrag[(size_t)o * dp * dp]);
       }
     });
-    to_blocks(lv.G, d, dp, false, lv.tri[0]);  // Gamma      (forward, Delta)
-    to_blocks(lv.B, d, dp, true, lv.tri[1]);   // B^T        (backward, Delta)
-    to_blocks(lv.B, d, dp, false, lv.tri[2]);  // B          (forward, Delta^T)
-    to_blocks(lv.G, d, dp, true, lv.tri[3]);   // Gamma^T    (backward, Delta^T)
+    trsm_table(lv.G, d, dp, false, true, lv.tri[0]);   // Gamma    (forward, Delta)
+    trsm_table(lv.B, d, dp, true, false, lv.tri[1]);   // B^T      (backward, Delta)
+    trsm_table(lv.B, d, dp, false, true, lv.tri[2]);   // B        (forward, Delta^T)
+    trsm_table(lv.G, d, dp, true, false, lv.tri[3]);   // Gamma^T  (backward, Delta^T)
   }
   // M2M (Sec. 4.1): for parent level k and child i with c_C - c_P = s_i,
   //   M2M_i = K(X^k - s_i, Y^{k+1}) (M^{k+1})^{-1}        (d_k x d_{k+1})
