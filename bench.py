@@ -160,7 +160,17 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS mixed run")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        _sync()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
               "(the path has no multi-GPU mode)", file=sys.stderr)
@@ -176,9 +186,13 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
+        import hashlib
         tr = json.load(open(PROFILE_TRAFFIC))
         key = f"{args.workload}:{args.precision}"
-        if key in tr and tr[key].get("valid", False):
+        src = os.path.join(ROOT, "paper_1408_0210_amd", "csrc", "pass.hip")
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        # counters taken on another version of the kernels do not describe this one
+        if key in tr and tr[key].get("valid", False) and tr[key].get("source_sha256") == cur:
             traffic = tr[key]["bytes_per_launch"]
     phases = {k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]}
     out = {
