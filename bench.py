@@ -76,7 +76,7 @@ def run_plain(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], tau,
-                  precision=args.precision)
+                  precision=args.precision, compress_tol=args.compress_tol)
     setup_s = time.perf_counter() - t0
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(s).to(dev)
@@ -111,7 +111,7 @@ def run_batched(args):
     n, R = w["n"], S.shape[1]
     dev = torch.device("cuda:0")
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], args.batched_tau,
-                  max_rhs=R, precision="mixed")
+                  max_rhs=R, precision="mixed", compress_tol=args.compress_tol)
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(np.ascontiguousarray(S.T)).to(dev)  # (64, n)
     f = torch.empty_like(sd)
@@ -143,6 +143,7 @@ def run_batched(args):
     plan.close()
     return dict(value=R * float(n) ** 2 / (ms * 1e-3), unit="interactions/s", nrhs=R, n=n,
                 ms_per_step=ms, precision="mixed", tau=args.batched_tau,
+                compress_tol=args.compress_tol, rank=st["rank"],
                 rel_l2_sampled_max=max(errs),
                 m2l_frac=st["m2l_flops"] / (m2l_ms * 1e-3) / (PEAK_TFLOPS["mixed"] * 1e12),
                 note="tree built once; t covers evaluate of 64 RHS; value = 64 N^2 / t")
@@ -160,6 +161,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS mixed run")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--compress-tol", type=float, default=1e-6,
+                    help="M2L compression tolerance (Sec. 4.2); 0 disables it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -179,7 +182,8 @@ def main():
     r = run_plain(args)
     st, n, ms = r["stats"], r["n"], r["ms"]
     print(f"[bench] {args.workload} precision={args.precision} tau={r['tau']} "
-          f"d={st['d']} ms/step={ms:.3f} setup={r['setup_s']:.1f}s", file=sys.stderr, flush=True)
+          f"d={st['d']} rank={st['rank']} ms/step={ms:.3f} setup={r['setup_s']:.1f}s",
+          file=sys.stderr, flush=True)
     m2l_calls = max(1, st["phase_calls"]["m2l"])
     m2l_ms = st["phase_ms"]["m2l"] / m2l_calls
     achieved = st["m2l_flops"] / (m2l_ms * 1e-3) / 1e12
@@ -203,6 +207,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "depth": r["w"]["depth"],
                    "kernel": r["w"]["kernel"], "tau": r["tau"], "nrhs": 1,
                    "precision": args.precision, "d": st["d"],
+                   "compress_tol": args.compress_tol, "rank": st["rank"],
                    "step": "set_points + evaluate", "phase_ms": phases},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,

@@ -90,6 +90,11 @@ typedef struct {
   int32_t precision;    /* EIFMM_PREC_*                                             */
   int32_t dmax;         /* cap on d_k (0 = 1024); reaching it is EIFMM_EEIM          */
   int32_t flags;        /* EIFMM_FLAG_*                                             */
+  double compress_tol;  /* > 0: compress the M2L matrices (Sec. 4.2, first stage):
+                           SVD of [K^delta_1 .. K^delta_316] per level; the rank r
+                           is the larger of the two filters (s_j/s_0 > eps, and the
+                           prefix holding 1 - eps of the sum of singular values),
+                           rounded up to the MFMA tile granularity; 0 = off      */
 } eifmm_config;
 
 /* evaluation phases timed when timing is enabled (eifmm_set_timing) */
@@ -102,19 +107,24 @@ typedef struct {
 #define EIFMM_PH_L2L 6   /* step 5                                                */
 #define EIFMM_PH_LHAT 7  /* step 6 (triangular solves)                            */
 #define EIFMM_PH_L2P 8   /* step 7 plus f = f_far + f_near in input order         */
-#define EIFMM_NPHASE 9
+#define EIFMM_PH_PROJ 9  /* compression projections U^T What and U g' (Sec. 4.2)  */
+#define EIFMM_NPHASE 10
 
 typedef struct {
   int32_t struct_size;               /* sizeof(eifmm_stats)                      */
   int32_t depth;
   int32_t d[EIFMM_MAX_DEPTH + 1];    /* d_k for k = 2..depth (0 elsewhere)        */
   int32_t dpad[EIFMM_MAX_DEPTH + 1]; /* padded row count used on the device       */
+  int32_t rank[EIFMM_MAX_DEPTH + 1]; /* M2L compression rank per level (0 = none) */
   double eim_err[EIFMM_MAX_DEPTH + 1]; /* final training error / scale per level  */
   double setup_ms;                   /* plan_create host time                     */
   double phase_ms[EIFMM_NPHASE];     /* accumulated GPU time per phase            */
   int64_t phase_calls[EIFMM_NPHASE]; /* timed launches of each phase              */
   double m2l_flops;                  /* algorithmic M2L flops of the last evaluate
-                                        (2 d_k^2 per interaction pair per RHS)    */
+                                        (2 d_k^2, or 2 r_k^2 when compressed, per
+                                        interaction pair per RHS)                 */
+  double proj_flops;                 /* compression projections of the last
+                                        evaluate (4 d_k r_k per box per RHS)      */
   int64_t active_boxes[EIFMM_MAX_DEPTH + 1]; /* non-empty boxes per level        */
   int64_t il_pairs[EIFMM_MAX_DEPTH + 1];     /* interaction-list pairs per level */
   int64_t near_pairs;                /* ordered leaf pairs in the near lists      */
@@ -154,6 +164,11 @@ int eifmm_get_stats(eifmm_plan plan, eifmm_stats *out);
  * row-major).  Any output may be NULL; call with all NULL to get d. */
 int eifmm_get_level(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
                     int64_t *ib, double *B, double *Gamma);
+
+/* Host copies of level k's M2L compression (Sec. 4.2): *r (0 when off), the d_k
+ * singular values of [K^delta_1 .. K^delta_316] in descending order, and U
+ * (d_k x r row-major: the kept left singular vectors).  Outputs may be NULL. */
+int eifmm_get_compression(eifmm_plan plan, int32_t k, int32_t *r, double *sv, double *U);
 
 /* Host copies of the current tree: perm[n] (input index of each Morton-ordered
  * point), leaf_start[8^depth + 1], keys[n] (leaf key of each sorted point). */

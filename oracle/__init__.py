@@ -75,6 +75,7 @@ def lib():
         L.orc_plan_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.orc_plan_free.argtypes = [vp]
         L.orc_plan_free.restype = None
+        L.orc_plan_set_compression.argtypes = [vp, i32, i32, vp]
         _lib = L
     return _lib
 
@@ -214,10 +215,41 @@ def apply_delta(B, G, v, transpose=False):
     return w
 
 
+def m2l_matrices(kernel, param, Y, level, L=1.0):
+    """The 316 translation-invariant M2L matrices of a level (Sec. 4.2):
+    K^delta[m', l] = K(Y_m', Y_l + 2 l_k delta), in offset-id order."""
+    h = L * 2.0 ** (-level)
+    dt = offset_table().astype(np.float64)
+    z = Y[None, :, None, :] - (Y[None, None, :, :] + h * dt[:, None, None, :])
+    return kernel_eval(kernel, param, z.reshape(-1, 3)).reshape(316, len(Y), len(Y))
+
+
+def compression_rank(s, eps):
+    """Rank kept by the two filters of Sec. 4.2 on singular values s (descending):
+    (i) the values with s_j / s_0 > eps, (ii) the shortest prefix whose sum reaches
+    (1 - eps) of the total; both are applied and the larger rank is kept."""
+    r1 = int((s / s[0] > eps).sum())
+    cs = np.cumsum(s) / s.sum()
+    r2 = int(min(len(s), np.searchsorted(cs, 1.0 - eps) + 1))
+    return max(r1, r2)
+
+
+def compression_basis(kernel, param, Y, level, eps, L=1.0, rank=None):
+    """Sec. 4.2, first stage, with an exact SVD in place of the bivariate ACA:
+    K_fat = [K^delta_1 ... K^delta_316] = U S V^T; keep the leading r columns of U
+    (r from the filters, or `rank` when given)."""
+    Kd = m2l_matrices(kernel, param, Y, level, L)
+    Kfat = np.concatenate(list(Kd), axis=1)
+    U, s, _ = np.linalg.svd(Kfat, full_matrices=False)
+    r = compression_rank(s, eps) if rank is None else int(rank)
+    return np.ascontiguousarray(U[:, :r]), s, r
+
+
 class Plan:
     """Per-level EIM data (levels 2..depth) and the Algorithm-3 evaluation."""
 
-    def __init__(self, kernel, param, lo, L, depth, tau, dmax=1024, tol_mode=0):
+    def __init__(self, kernel, param, lo, L, depth, tau, dmax=1024, tol_mode=0, compress_tol=0.0,
+                 compress_rank=None):
         self.kernel, self.param = kernel, _params(param)
         self.lo = np.ascontiguousarray(lo, dtype=np.float64)
         self.L, self.depth, self.tau = float(L), int(depth), float(tau)
@@ -227,6 +259,16 @@ class Plan:
         if not self._h:
             raise OracleError(st.value, "plan_create")
         self.levels = {k: self._level(k) for k in range(2, self.depth + 1)}
+        self.compress_tol = float(compress_tol)
+        if compress_tol > 0:
+            for k in range(2, self.depth + 1):
+                rk = compress_rank.get(k) if isinstance(compress_rank, dict) else compress_rank
+                U, sv, r = compression_basis(kernel, self.param, self.levels[k]["Y"], k,
+                                             compress_tol, self.L, rank=rk)
+                self.levels[k].update(U=U, sv=sv, r=r)
+                st = lib().orc_plan_set_compression(self._h, k, r, _p(U))
+                if st:
+                    raise OracleError(st, "set_compression")
 
     def _level(self, k):
         d = ctypes.c_int()

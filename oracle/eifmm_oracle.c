@@ -603,6 +603,8 @@ typedef struct {
   double *X, *Y, *B, *G, *eps;
   int64_t *ia, *ib;
   double scale;
+  int r;      /* M2L compression rank (0: uncompressed) */
+  double *U;  /* d x r orthonormal basis of the M2L matrices (Sec. 4.2) */
 } olevel;
 
 typedef struct {
@@ -616,9 +618,27 @@ void orc_plan_free(orc_plan *P) {
   if (!P) return;
   for (int k = 0; k < 16; k++) {
     free(P->lv[k].X); free(P->lv[k].Y); free(P->lv[k].B); free(P->lv[k].G);
-    free(P->lv[k].eps); free(P->lv[k].ia); free(P->lv[k].ib);
+    free(P->lv[k].eps); free(P->lv[k].ia); free(P->lv[k].ib); free(P->lv[k].U);
   }
   free(P);
+}
+
+/* M2L compression of level k (Sec. 4.2, first stage): U (d x r, row-major) spans
+ * the dominant left singular vectors of [K^delta_1 ... K^delta_316]; for a
+ * symmetric kernel the compressed matrices are C^delta = U^T K^delta U and the
+ * M2L step becomes g = U sum_J C^delta (U^T What^J).  r = 0 removes it. */
+int orc_plan_set_compression(orc_plan *P, int k, int r, const double *U) {
+  if (!P || k < 2 || k > P->depth || r < 0 || r > P->lv[k].d) return ORC_EINVAL;
+  olevel *lv = &P->lv[k];
+  free(lv->U);
+  lv->U = NULL;
+  lv->r = 0;
+  if (r == 0) return ORC_OK;
+  lv->U = (double *)malloc(sizeof(double) * (size_t)lv->d * (size_t)r);
+  if (!lv->U) return ORC_ENOMEM;
+  memcpy(lv->U, U, sizeof(double) * (size_t)lv->d * (size_t)r);
+  lv->r = r;
+  return ORC_OK;
 }
 
 /* tol_mode 0: relative to each level's own max |K| over its training grid;
@@ -855,6 +875,56 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
                 K2(K, lv->Y + 3 * mp, yl);
           }
       }
+      /* compressed form: C^delta = U^T K^delta U (r x r), What' = U^T What */
+      const int r = lv->r;
+      const int dd = r > 0 ? r : d; /* size of the transferred expansions */
+      const double *Ad = Kd;
+      double *Cd = NULL, *Whp = NULL, *gp = NULL;
+      if (r > 0) {
+        Cd = (double *)malloc(sizeof(double) * 316 * (size_t)r * (size_t)r);
+        Whp = (double *)calloc((size_t)nb * (size_t)r, sizeof(double));
+        gp = (double *)calloc((size_t)nb * (size_t)r, sizeof(double));
+        if (!Cd || !Whp || !gp) {
+          free(Kd); free(Cd); free(Whp); free(gp);
+          st = ORC_ENOMEM;
+          goto done;
+        }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (int o = 0; o < 316; o++) {
+          const double *A = Kd + (size_t)o * (size_t)d * (size_t)d;
+          double *KU = (double *)malloc(sizeof(double) * (size_t)d * (size_t)r);
+          for (int i = 0; i < d; i++)
+            for (int b = 0; b < r; b++) {
+              double t = 0.0;
+              for (int j = 0; j < d; j++) t += A[(size_t)i * d + j] * lv->U[(size_t)j * r + b];
+              KU[(size_t)i * r + b] = t;
+            }
+          for (int a = 0; a < r; a++)
+            for (int b = 0; b < r; b++) {
+              double t = 0.0;
+              for (int i = 0; i < d; i++) t += lv->U[(size_t)i * r + a] * KU[(size_t)i * r + b];
+              Cd[((size_t)o * r + a) * r + b] = t;
+            }
+          free(KU);
+        }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+        for (int64_t key = 0; key < nb; key++) {
+          if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+          for (int a = 0; a < r; a++) {
+            double t = 0.0;
+            for (int i = 0; i < d; i++)
+              t += lv->U[(size_t)i * r + a] * Wh[k][(size_t)key * (size_t)d + (size_t)i];
+            Whp[(size_t)key * r + a] = t;
+          }
+        }
+        Ad = Cd;
+      }
+      const double *Wsrc = r > 0 ? Whp : Wh[k];
+      double *gdst = r > 0 ? gp : g[k];
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8)
 #endif
@@ -862,7 +932,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
         if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
         int nI[3];
         unmorton3((uint32_t)key, k, nI);
-        double *gI = g[k] + (size_t)key * (size_t)d;
+        double *gI = gdst + (size_t)key * (size_t)dd;
         for (int o = 0; o < 316; o++) {
           int nJ[3] = {nI[0] + dtab[3 * o], nI[1] + dtab[3 * o + 1], nI[2] + dtab[3 * o + 2]};
           int inside = 1, pc = 0;
@@ -874,14 +944,29 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           if (!inside || pc > 1) continue;
           uint32_t kj = morton3((uint32_t)nJ[0], (uint32_t)nJ[1], (uint32_t)nJ[2], k);
           if (box_count(ls, depth, k, kj, NULL) == 0) continue;
-          const double *wj = Wh[k] + (size_t)kj * (size_t)d;
-          const double *A = Kd + (size_t)o * (size_t)d * (size_t)d;
-          for (int mp = 0; mp < d; mp++) {
+          const double *wj = Wsrc + (size_t)kj * (size_t)dd;
+          const double *A = Ad + (size_t)o * (size_t)dd * (size_t)dd;
+          for (int mp = 0; mp < dd; mp++) {
             double s = 0.0;
-            for (int ll = 0; ll < d; ll++) s += A[(size_t)mp * (size_t)d + (size_t)ll] * wj[ll];
+            for (int ll = 0; ll < dd; ll++) s += A[(size_t)mp * (size_t)dd + (size_t)ll] * wj[ll];
             gI[mp] += s;
           }
         }
+      }
+      if (r > 0) {
+        /* g = U g' */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+        for (int64_t key = 0; key < nb; key++) {
+          if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
+          for (int i = 0; i < d; i++) {
+            double t = 0.0;
+            for (int a = 0; a < r; a++) t += lv->U[(size_t)i * r + a] * gp[(size_t)key * r + a];
+            g[k][(size_t)key * (size_t)d + (size_t)i] = t;
+          }
+        }
+        free(Cd); free(Whp); free(gp);
       }
       free(Kd);
     }

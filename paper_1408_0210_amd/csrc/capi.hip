@@ -60,6 +60,7 @@ int validate(const eifmm_config *c) {
   if (c->tol_mode < 0 || c->tol_mode > 1) return EIFMM_EINVAL;
   if (c->precision != EIFMM_PREC_FP64 && c->precision != EIFMM_PREC_MIXED) return EIFMM_EINVAL;
   if (c->dmax < 0 || c->dmax > 4096) return EIFMM_EINVAL;
+  if (!(c->compress_tol >= 0) || !std::isfinite(c->compress_tol)) return EIFMM_EINVAL;
   return EIFMM_OK;
 }
 
@@ -139,6 +140,10 @@ int device_setup(eifmm_plan h) {
       TRY(upload(&D.l2l, H.l2l.data(), H.l2l.size(), tr));
     }
     TRY(upload(&D.X, H.X.data(), H.X.size(), tr));
+    if (H.r > 0) {
+      TRY(upload(&D.ufrag, H.ufrag.data(), H.ufrag.size(), tr));
+      TRY(upload(&D.utfrag, H.utfrag.data(), H.utfrag.size(), tr));
+    }
   }
   // point workspaces
   const int64_t nn = std::max<int64_t>(n, 1);
@@ -178,7 +183,14 @@ int device_setup(eifmm_plan h) {
     const size_t m = D.cap * (size_t)R * (size_t)P.lh[k].dp;
     TRY(dalloc(&D.W, m, tr));
     TRY(dalloc(&D.Wh, m, tr));
-    if (mixed) TRY(dalloc(&D.Wh32, m, tr));
+    const size_t mr = D.cap * (size_t)R * (size_t)P.lh[k].rp;
+    if (P.lh[k].r > 0) {
+      TRY(dalloc(&D.Whp, mr, tr));
+      TRY(dalloc(&D.gp, mr, tr));
+      if (mixed) TRY(dalloc(&D.Whp32, mr, tr));
+    } else if (mixed) {
+      TRY(dalloc(&D.Wh32, m, tr));
+    }
     TRY(dalloc(&D.g, m, tr));
     if (k == 2)
       D.l = D.g;  // l^2 = g^2 (Algorithm 3, step 5)
@@ -291,6 +303,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
   for (int k = 2; k <= P.depth; ++k) {
     s.d[k] = P.lh[k].d;
     s.dpad[k] = P.lh[k].dp;
+    s.rank[k] = P.lh[k].r;
     s.eim_err[k] = P.lh[k].err;
   }
   s.setup_ms = P.setup_ms;
@@ -299,6 +312,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
     s.phase_calls[q] = P.phase_calls[q];
   }
   s.m2l_flops = P.m2l_flops;
+  s.proj_flops = P.proj_flops;
   for (int k = 0; k <= P.depth; ++k) {
     s.active_boxes[k] = P.nact[k];
     s.il_pairs[k] = P.il_pairs[k];
@@ -322,6 +336,17 @@ int eifmm_get_level(eifmm_plan h, int32_t k, int32_t *d, double *X, double *Y, i
   if (ib) std::memcpy(ib, L.ib.data(), sizeof(int64_t) * L.ib.size());
   if (B) std::memcpy(B, L.B.data(), sizeof(double) * L.B.size());
   if (G) std::memcpy(G, L.G.data(), sizeof(double) * L.G.size());
+  return EIFMM_OK;
+}
+
+int eifmm_get_compression(eifmm_plan h, int32_t k, int32_t *r, double *sv, double *U) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (k < 2 || k > P.depth) return EIFMM_EINVAL;
+  const LevelHost &L = P.lh[k];
+  if (r) *r = L.r;
+  if (sv && !L.sv.empty()) std::memcpy(sv, L.sv.data(), sizeof(double) * L.sv.size());
+  if (U && L.r > 0) std::memcpy(U, L.U.data(), sizeof(double) * L.U.size());
   return EIFMM_OK;
 }
 

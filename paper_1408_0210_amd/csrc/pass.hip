@@ -420,27 +420,29 @@ __global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
 }
 
 // ------------------------------------------------------------------ gathered GEMM
-// C[:, col] (+)= sum_t A_t B_t[:, col] for the columns of a target group, where
-// B_t[:, col] is the expansion of the source box that term t pairs with the
-// column's target box (M2L: the box at offset delta; M2M: child t; L2L: the
-// parent).  A workgroup computes a 96-row x 128-column tile with 16x16x4 MFMAs;
-// 4 waves in a 2 x 2 arrangement each own 3 x 4 output blocks.  Operand chunks
-// of 16 k values pass through LDS in MFMA fragment order; the next chunk is
-// loaded into registers while the current one is multiplied.  With FOLD (FP32
-// operands) each term's product is accumulated by the MFMA in FP32 and then
-// added to an FP64 sum over the terms, so FP32 rounding grows with one matrix
-// product (d_k terms) rather than with the whole interaction list.
-constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2;
-constexpr int GT_RB = 6, GT_CB = 8, GT_COLS = 16 * GT_CB;
+// C[:, col] (+)= sum_t A_t B_t[:, col] for the columns (box, RHS) of a target
+// group, where B_t[:, col] is the expansion of the source box that term t pairs
+// with the column's target box: M2L the box at offset delta; M2M child t; L2L the
+// parent; PROJ the box itself (compression projections).  A workgroup computes a
+// (16 RBT)-row x 128-column tile with 16x16x4 MFMAs; each of the 4 waves owns 32
+// columns and all RBT row blocks.  Operand chunks of 16 k values pass through LDS
+// in MFMA fragment order; the next chunk is loaded into registers while the
+// current one is multiplied.  With FOLD (FP32 operands) each term's product is
+// accumulated by the MFMA in FP32 and then added to an FP64 sum over the terms,
+// so FP32 rounding grows with one matrix product (d_k terms) rather than with
+// the whole interaction list.
+constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
+constexpr int GT_CB = 8, GT_COLS = 16 * GT_CB;
 
-template <typename T>
-struct Mfma;
 // Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result layouts differ: FP64 keeps rows (l / 16) + 4 q of column l % 16 in
 // register q, FP32 rows 4 (l / 16) + q.
+template <typename T>
+struct Mfma;
 template <>
 struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
+  typedef double2 p2;
   __device__ static inline v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -449,43 +451,38 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
+  typedef float2 p2;
   __device__ static inline v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-template <typename T>
-struct Pair;
-template <>
-struct Pair<double> {
-  typedef double2 t;
-};
-template <>
-struct Pair<float> {
-  typedef float2 t;
-};
-
 template <typename T, int MODE>
 __device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
-                                       int r, const int8_t *__restrict__ dvec) {
+                                       int ts, int r, const int8_t *__restrict__ dvec) {
   if (!cvalid) return nullptr;
-  uint32_t skey;
-  if constexpr (MODE == MODE_M2L) {
-    const int id = J.terms[term];
-    const int side = 1 << J.level;
-    const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
-    const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
-    const int m2 = (int)morton_axis(tkey, 2) + dvec[3 * id + 2];
-    if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return nullptr;
-    skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
-  } else if constexpr (MODE == MODE_M2M) {
-    skey = tkey * 8u + (uint32_t)term;
+  int s;
+  if constexpr (MODE == MODE_PROJ) {
+    s = ts;
   } else {
-    skey = tkey >> 3;
+    uint32_t skey;
+    if constexpr (MODE == MODE_M2L) {
+      const int id = J.terms[term];
+      const int side = 1 << J.level;
+      const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
+      const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
+      const int m2 = (int)morton_axis(tkey, 2) + dvec[3 * id + 2];
+      if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return nullptr;
+      skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
+    } else if constexpr (MODE == MODE_M2M) {
+      skey = tkey * 8u + (uint32_t)term;
+    } else {
+      skey = tkey >> 3;
+    }
+    s = J.src_slot[skey];
+    if (s < 0) return nullptr;
   }
-  const int s = J.src_slot[skey];
-  if (s < 0) return nullptr;
   return (const T *)J.Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
 }
 
@@ -496,17 +493,22 @@ __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
     idx = J.terms[term];
   else if constexpr (MODE == MODE_M2M)
     idx = term;
-  else
+  else if constexpr (MODE == MODE_L2L)
     idx = J.cls;
+  else
+    idx = 0;
   return (const T *)J.A + idx * J.a_stride;
 }
 
-template <typename T, int MODE, bool FOLD>
+template <typename T, int MODE, bool FOLD, int RBT>
 __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
                                                  int ntiles, const int8_t *__restrict__ dvec) {
   typedef typename Mfma<T>::v4 V4;
-  typedef typename Pair<T>::t P2;
-  __shared__ T As[GT_RB * 4 * 64];
+  typedef typename Mfma<T>::p2 P2;
+  typedef double D4 __attribute__((ext_vector_type(4)));
+  constexpr int NA = RBT * 128;         // A chunk, in pairs
+  constexpr int QA = (NA + 255) / 256;  // pairs per thread
+  __shared__ T As[RBT * 4 * 64];
   __shared__ T Bs[4 * GT_CB * 64];
 
   // tiles of one job are contiguous and land on one XCD (blocks go round-robin
@@ -525,55 +527,53 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   const GemmJob J = jobs[lo];
   const int local = tile - J.tiles_start;
   const int rowtile = local % J.nrowtiles, coltile = local / J.nrowtiles;
-  const int rb0 = rowtile * GT_RB, col0 = coltile * GT_COLS;
+  const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
   const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
   const int ncols = J.ntgt * J.nrhs;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
 
   // the column this thread loads
   const int jl = t >> 1, hh = t & 1;
   const int jc = col0 + jl;
   const bool cvalid = jc < ncols;
-  int r = 0;
+  int r = 0, ts = 0;
   uint32_t tkey = 0;
   if (cvalid) {
     const int tt = jc / J.nrhs;
     r = jc - tt * J.nrhs;
-    const int ts = J.tgt ? J.tgt[tt] : tt;
-    tkey = J.tgt_keys[ts];
+    ts = J.tgt ? J.tgt[tt] : tt;
+    if (MODE != MODE_PROJ) tkey = J.tgt_keys[ts];
   }
 
-  V4 acc[3][4];
-  typedef double D4 __attribute__((ext_vector_type(4)));
-  D4 sum[3][4];
+  V4 acc[RBT][2];
+  D4 sum[RBT][2];
+  bool rowok[RBT];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < RBT; ++i) {
+    rowok[i] = rb0 + i < nrb;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
+    for (int jj = 0; jj < 2; ++jj) {
       acc[i][jj] = V4{0, 0, 0, 0};
       if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
     }
-  bool rowok[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) rowok[i] = rb0 + 3 * wr + i < nrb;
+  }
 
   const int total = J.nterms * nkc;
-  P2 ra[3], rbv[4];
+  P2 ra[QA], rbv[4];
   const T *srcp = nullptr;
   const T *Ap = nullptr;
   auto fetch = [&](int it) {
     const int term = it / nkc, kc = it - term * nkc;
     if (kc == 0) {
-      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, r, dvec);
+      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, ts, r, dvec);
       Ap = gemm_operand<T, MODE>(J, term);
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int e = 2 * t + 512 * q;
-      const int rb = rb0 + (e >> 8);
-      if (rb < nrb)
-        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + (e & 255));
+    for (int q = 0; q < QA; ++q) {
+      const int e = t + 256 * q;  // pair index in the chunk
+      const int rb = rb0 + (e >> 7);
+      if (e < NA && rb < nrb)
+        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
       else
         ra[q] = P2{0, 0};
     }
@@ -591,7 +591,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   for (int it = 0; it < total; ++it) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 3; ++q) *(P2 *)(As + 2 * t + 512 * q) = ra[q];
+    for (int q = 0; q < QA; ++q) {
+      const int e = t + 256 * q;
+      if (e < NA) *(P2 *)(As + 2 * e) = ra[q];
+    }
     {
       const int cb = jl >> 4, c16 = jl & 15;
 #pragma unroll
@@ -608,24 +611,24 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
     if (it + 1 < total) fetch(it + 1);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      T a[3], b[4];
+      T a[RBT], b[2];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) a[i] = As[((3 * wr + i) * 4 + ks) * 64 + lane];
+      for (int i = 0; i < RBT; ++i) a[i] = As[(i * 4 + ks) * 64 + lane];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) b[jj] = Bs[(ks * GT_CB + 4 * wc + jj) * 64 + lane];
+      for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[(ks * GT_CB + 2 * w + jj) * 64 + lane];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < RBT; ++i)
         if (rowok[i]) {
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
+          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
     if constexpr (FOLD) {
       if ((it + 1) % nkc == 0) {  // a term is complete
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < RBT; ++i)
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
+          for (int jj = 0; jj < 2; ++jj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
             acc[i][jj] = V4{0, 0, 0, 0};
@@ -636,16 +639,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
 
   // write the tile (result layout per Mfma<T>::row)
 #pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int jo = col0 + 16 * (4 * wc + jj) + (lane & 15);
+  for (int jj = 0; jj < 2; ++jj) {
+    const int jo = col0 + 16 * (2 * w + jj) + (lane & 15);
     if (jo >= ncols) continue;
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
-    const int ts = J.tgt ? J.tgt[tt] : tt;
-    const int64_t cbase = ((int64_t)ts * J.nrhs + ro) * J.dpm;
+    const int tso = J.tgt ? J.tgt[tt] : tt;
+    const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < RBT; ++i) {
       if (!rowok[i]) continue;
-      const int rbase = 16 * (rb0 + 3 * wr + i);
+      const int rbase = 16 * (rb0 + i);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t o = cbase + rbase + Mfma<T>::row(lane, q);
@@ -656,6 +659,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
           v = (double)acc[i][jj][q];
         if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
         J.C[o] = v;
+        if (J.C32) J.C32[o] = (float)v;
       }
     }
   }
@@ -692,10 +696,10 @@ struct Timer {
 
 int tiles_of(const GemmJob &J) { return J.ncoltiles * J.nrowtiles; }
 
-void finish_job(GemmJob &J, int &tiles) {
+void finish_job(GemmJob &J, int &tiles, int rbt) {
   const int ncols = J.ntgt * J.nrhs;
   J.ncoltiles = (ncols + GT_COLS - 1) / GT_COLS;
-  J.nrowtiles = (J.dpm / 16 + GT_RB - 1) / GT_RB;
+  J.nrowtiles = (J.dpm / 16 + rbt - 1) / rbt;
   J.tiles_start = tiles;
   tiles += tiles_of(J);
 }
@@ -727,45 +731,106 @@ int build_jobs(Plan &P, int nrhs) {
     J.level = k;
     J.mode = MODE_M2M;
     J.nrhs = nrhs;
-    finish_job(J, tiles);
+    jt.m2m_rbt[k] = pick_rbt(J.dpm / 16);
+    finish_job(J, tiles, jt.m2m_rbt[k]);
     jt.m2m_first[k] = (int)h.size();
     jt.m2m_n[k] = 1;
     jt.m2m_tiles[k] = tiles;
     h.push_back(J);
   }
+  // compression projections What' = U^T What, one job per compressed level
+  {
+    int tiles = 0;
+    jt.pre_first = (int)h.size();
+    jt.pre_rbt = pick_rbt(P.lh[depth].rp / 16 > 0 ? P.lh[depth].rp / 16 : 1);
+    double pf = 0;
+    for (int k = depth; k >= 2; --k) {
+      if (P.lh[k].r == 0 || P.nact[k] == 0) continue;
+      GemmJob J{};
+      J.A = P.ld[k].utfrag;
+      J.Bsrc = P.ld[k].Wh;
+      J.C = P.ld[k].Whp;
+      J.C32 = mixed ? P.ld[k].Whp32 : nullptr;
+      J.ntgt = (int)P.nact[k];
+      J.nterms = 1;
+      J.dpm = P.lh[k].rp;
+      J.dpk = P.lh[k].dp;
+      J.level = k;
+      J.mode = MODE_PROJ;
+      J.nrhs = nrhs;
+      finish_job(J, tiles, jt.pre_rbt);
+      h.push_back(J);
+      pf += 4.0 * P.lh[k].d * (double)P.lh[k].r * (double)P.nact[k] * nrhs;
+    }
+    jt.pre_n = (int)h.size() - jt.pre_first;
+    jt.pre_tiles = tiles;
+    P.proj_flops = pf;
+  }
   // M2L, every level in one launch, finest level first
   {
     int tiles = 0;
     jt.m2l_first = (int)h.size();
+    const LevelHost &F = P.lh[depth];
+    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dp) / 16);
     double flops = 0;
     for (int k = depth; k >= 2; --k) {
+      const bool cz = P.lh[k].r > 0;
+      const int dm = cz ? P.lh[k].rp : P.lh[k].dp;
       for (int c = 0; c < 8; ++c) {
         const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
         if (nt == 0) continue;
         GemmJob J{};
         J.A = mixed ? (const void *)P.ld[k].kfrag32 : (const void *)P.ld[k].kfrag;
-        J.Bsrc = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
-        J.C = P.ld[k].g;
+        if (cz)
+          J.Bsrc = mixed ? (const void *)P.ld[k].Whp32 : (const void *)P.ld[k].Whp;
+        else
+          J.Bsrc = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
+        J.C = cz ? P.ld[k].gp : P.ld[k].g;
         J.tgt = P.ld[k].cls + P.cls_off[k][c];
         J.tgt_keys = P.ld[k].act;
         J.src_slot = P.ld[k].slot;
         J.terms = P.dlist + 189 * c;
-        J.a_stride = (int64_t)P.lh[k].dp * P.lh[k].dp;
+        J.a_stride = (int64_t)dm * dm;
         J.ntgt = (int)nt;
         J.nterms = 189;
-        J.dpm = J.dpk = P.lh[k].dp;
+        J.dpm = J.dpk = dm;
         J.level = k;
         J.cls = c;
         J.mode = MODE_M2L;
         J.nrhs = nrhs;
-        finish_job(J, tiles);
+        finish_job(J, tiles, jt.m2l_rbt);
         h.push_back(J);
       }
-      flops += 2.0 * P.lh[k].d * (double)P.lh[k].d * (double)P.il_pairs[k] * nrhs;
+      const double rk = cz ? P.lh[k].r : P.lh[k].d;
+      flops += 2.0 * rk * rk * (double)P.il_pairs[k] * nrhs;
     }
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
     P.m2l_flops = flops;
+  }
+  // g = U g' on compressed levels
+  {
+    int tiles = 0;
+    jt.post_first = (int)h.size();
+    jt.post_rbt = pick_rbt(P.lh[depth].dp / 16);
+    for (int k = depth; k >= 2; --k) {
+      if (P.lh[k].r == 0 || P.nact[k] == 0) continue;
+      GemmJob J{};
+      J.A = P.ld[k].ufrag;
+      J.Bsrc = P.ld[k].gp;
+      J.C = P.ld[k].g;
+      J.ntgt = (int)P.nact[k];
+      J.nterms = 1;
+      J.dpm = P.lh[k].dp;
+      J.dpk = P.lh[k].rp;
+      J.level = k;
+      J.mode = MODE_PROJ;
+      J.nrhs = nrhs;
+      finish_job(J, tiles, jt.post_rbt);
+      h.push_back(J);
+    }
+    jt.post_n = (int)h.size() - jt.post_first;
+    jt.post_tiles = tiles;
   }
   // L2L, per child level k = 3 .. depth, one job per child class
   for (int k = 3; k <= depth; ++k) {
@@ -791,7 +856,8 @@ int build_jobs(Plan &P, int nrhs) {
       J.cls = c;
       J.mode = MODE_L2L;
       J.nrhs = nrhs;
-      finish_job(J, tiles);
+      jt.l2l_rbt[k] = pick_rbt(J.dpm / 16);
+      finish_job(J, tiles, jt.l2l_rbt[k]);
       h.push_back(J);
     }
     jt.l2l_n[k] = (int)h.size() - jt.l2l_first[k];
@@ -811,13 +877,23 @@ int build_jobs(Plan &P, int nrhs) {
 
 namespace {
 
-template <typename T, int MODE>
-void launch_gemm(Plan &P, int first, int n, int tiles, hipStream_t s) {
-  if (n == 0 || tiles == 0) return;
+template <typename T, int MODE, int RBT>
+void launch_gemm_rbt(Plan &P, int first, int n, int tiles, hipStream_t s) {
   const int grid = ((tiles + 7) / 8) * 8;
   constexpr bool fold = sizeof(T) == 4;
-  hipLaunchKernelGGL((k_gemm<T, MODE, fold>), dim3(grid), dim3(256), 0, s, P.job_dev + first, n,
-                     tiles, P.dvec);
+  hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(grid), dim3(256), 0, s,
+                     P.job_dev + first, n, tiles, P.dvec);
+}
+
+template <typename T, int MODE>
+void launch_gemm(Plan &P, int first, int n, int tiles, hipStream_t s, int rbt = 6) {
+  if (n == 0 || tiles == 0) return;
+  switch (rbt) {
+    case 4: launch_gemm_rbt<T, MODE, 4>(P, first, n, tiles, s); break;
+    case 5: launch_gemm_rbt<T, MODE, 5>(P, first, n, tiles, s); break;
+    case 7: launch_gemm_rbt<T, MODE, 7>(P, first, n, tiles, s); break;
+    default: launch_gemm_rbt<T, MODE, 6>(P, first, n, tiles, s); break;
+  }
 }
 
 template <int KIND>
@@ -875,7 +951,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_M2M);
     for (int k = depth - 1; k >= 2; --k)
       launch_gemm<double, MODE_M2M>(P, P.jobs.m2m_first[k], P.jobs.m2m_n[k], P.jobs.m2m_tiles[k],
-                                    s);
+                                    s, P.jobs.m2m_rbt[k]);
   }
   // step 3: What = Delta W on every level
   {
@@ -889,7 +965,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
       SolveDesc &D = A.lv[q++];
       D.in = P.ld[k].W;
       D.out = P.ld[k].Wh;
-      D.out32 = mixed ? P.ld[k].Wh32 : nullptr;
+      D.out32 = (mixed && P.lh[k].r == 0) ? P.ld[k].Wh32 : nullptr;
       D.Tf = P.ld[k].tri[0];
       D.Tb = P.ld[k].tri[1];
       D.ncols = nc;
@@ -901,20 +977,33 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     A.nlev = q;
     if (blk > 0) hipLaunchKernelGGL(k_trsm, dim3(blk), dim3(64), shm, s, A);
   }
-  // step 4: M2L
+  // step 4: M2L (with the compression projections around it when enabled)
+  if (P.jobs.pre_n) {
+    Timer tm(P, s, EIFMM_PH_PROJ);
+    launch_gemm<double, MODE_PROJ>(P, P.jobs.pre_first, P.jobs.pre_n, P.jobs.pre_tiles, s,
+                                   P.jobs.pre_rbt);
+  }
   {
     Timer tm(P, s, EIFMM_PH_M2L);
     if (mixed)
-      launch_gemm<float, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s);
+      launch_gemm<float, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s,
+                                   P.jobs.m2l_rbt);
     else
-      launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s);
+      launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s,
+                                    P.jobs.m2l_rbt);
+
+  }
+  if (P.jobs.post_n) {
+    Timer tm(P, s, EIFMM_PH_PROJ);
+    launch_gemm<double, MODE_PROJ>(P, P.jobs.post_first, P.jobs.post_n, P.jobs.post_tiles, s,
+                                   P.jobs.post_rbt);
   }
   // step 5: l^2 = g^2, then L2L downwards
   {
     Timer tm(P, s, EIFMM_PH_L2L);
     for (int k = 3; k <= depth; ++k)
       launch_gemm<double, MODE_L2L>(P, P.jobs.l2l_first[k], P.jobs.l2l_n[k], P.jobs.l2l_tiles[k],
-                                    s);
+                                    s, P.jobs.l2l_rbt[k]);
   }
   // step 6: lhat = Delta^T l on the leaf level
   {

@@ -26,6 +26,12 @@ struct LevelHost {
   std::vector<double> m2m;      // level k < depth: 8 ops d_k x d_{k+1}, fragment order
   std::vector<double> l2l;      // level k < depth: 8 ops d_{k+1} x d_k, fragment order
   std::vector<double> tri[4];   // solve tables: Gamma, B^T, B, Gamma^T (setup.cpp)
+  // M2L compression (Sec. 4.2): rank r (0 = off), padded rp; C^delta = U^T K^delta U
+  int r = 0, rp = 0;
+  std::vector<double> sv;       // singular values of [K^delta_1 .. K^delta_316]
+  std::vector<double> U;        // d x r, row-major
+  std::vector<double> ufrag;    // U   (dp x rp), fragment order: g = U g'
+  std::vector<double> utfrag;   // U^T (rp x dp), fragment order: What' = U^T What
 };
 
 // Device copy of one level's tables.
@@ -42,6 +48,10 @@ struct LevelDev {
   int *cls = nullptr;        // slots grouped by child class (key & 7), ascending key
   double *W = nullptr, *Wh = nullptr, *g = nullptr, *l = nullptr;
   float *Wh32 = nullptr;  // FP32 copy of What (mixed precision M2L)
+  // compressed M2L
+  double *ufrag = nullptr, *utfrag = nullptr;
+  double *Whp = nullptr, *gp = nullptr;  // What' = U^T What and g' (rp per box and RHS)
+  float *Whp32 = nullptr;
 };
 
 // One target group of a gathered GEMM launch (see pass.hip).
@@ -49,6 +59,7 @@ struct GemmJob {
   const void *A;        // fragment-ordered operand(s)
   const void *Bsrc;     // source expansions [slot * nrhs + r][dpk]
   double *C;            // output [slot * nrhs + r][dpm]
+  float *C32;           // optional FP32 copy of the output
   const double *Cadd;   // added to the product (L2L: g), may be null
   const int *tgt;       // target slots
   const uint32_t *tgt_keys;  // active keys of the target level (indexed by slot)
@@ -65,7 +76,10 @@ struct JobTables {
   int nrhs = -1;
   int m2m_first[kMaxLevels] = {}, m2m_n[kMaxLevels] = {}, m2m_tiles[kMaxLevels] = {};
   int l2l_first[kMaxLevels] = {}, l2l_n[kMaxLevels] = {}, l2l_tiles[kMaxLevels] = {};
-  int m2l_first = 0, m2l_n = 0, m2l_tiles = 0;
+  int m2m_rbt[kMaxLevels] = {}, l2l_rbt[kMaxLevels] = {};
+  int m2l_first = 0, m2l_n = 0, m2l_tiles = 0, m2l_rbt = 6;
+  int pre_first = 0, pre_n = 0, pre_tiles = 0, pre_rbt = 6;     // What' = U^T What
+  int post_first = 0, post_n = 0, post_tiles = 0, post_rbt = 6; // g = U g'
 };
 
 struct EventPair {
@@ -117,7 +131,7 @@ struct Plan {
   // gathered-GEMM job tables (rebuilt when the points or nrhs change)
   JobTables jobs;
   GemmJob *job_dev = nullptr;
-  double m2l_flops = 0;
+  double m2l_flops = 0, proj_flops = 0;
 
   // stats
   bool timing = false;
@@ -130,6 +144,7 @@ struct Plan {
 
 // setup.cpp
 int build_tables(Plan &P);
+int pick_rbt(int nrb);
 
 // device-side entry points (tree.hip, pass.hip)
 int tree_build(Plan &P, const double *xyz_in, hipStream_t s);

@@ -12,7 +12,12 @@
 //    Delta = B^{-T} Gamma^{-1} = M^{-1} (eq. (5));
 //  * M2M / L2L operators K M^{-1} and K M^{-T} formed row by row with
 //    triangular solves, never with an explicit inverse (Sec. 4.1);
-//  * the 316 M2L matrices K^delta = K(Y, Y + 2 l_k delta) (Sec. 4.2).
+//  * the 316 M2L matrices K^delta = K(Y, Y + 2 l_k delta) (Sec. 4.2), and, when
+//    asked for, their compression (Sec. 4.2, first stage): the leading left
+//    singular vectors U of [K^delta_1 .. K^delta_316] (Householder QR of the
+//    transpose, then a one-sided Jacobi SVD of R^T -- an exact SVD in place of the
+//    paper's bivariate ACA) and C^delta = U^T K^delta U.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -336,7 +341,111 @@ void trsm_table(const std::vector<double> &T, int d, int dp, bool transpose, boo
     }
 }
 
+// Singular values (descending) and left singular vectors (U, d x d row-major,
+// column p = vector p) of the d x m matrix whose rows are given in A (row-major,
+// m >= d; A is overwritten).  Householder QR of A^T = Q R, then a one-sided
+// Jacobi SVD of R^T: R^T V = U diag(s), so A = R^T Q^T = U diag(s) (Q V)^T.
+void svd_rows(std::vector<double> &A, int d, int64_t m, std::vector<double> &U,
+              std::vector<double> &s) {
+  std::vector<double> R((size_t)d * d, 0.0), v;
+  for (int j = 0; j < d; ++j) {
+    double *cj = &A[(size_t)j * m];
+    double n2 = 0.0;
+    for (int64_t i = j; i < m; ++i) n2 += cj[i] * cj[i];
+    const double alpha = cj[j] >= 0 ? -std::sqrt(n2) : std::sqrt(n2);
+    v.assign(cj + j, cj + m);
+    v[0] -= alpha;
+    double vtv = 0.0;
+    for (double x : v) vtv += x * x;
+    R[(size_t)j * d + j] = alpha;
+    if (vtv == 0.0) continue;
+    parallel_for(d - j - 1, [&](int64_t a0, int64_t a1) {
+      for (int64_t c = j + 1 + a0; c < j + 1 + a1; ++c) {
+        double *cc = &A[(size_t)c * m];
+        double dot = 0.0;
+        for (int64_t i = j; i < m; ++i) dot += v[i - j] * cc[i];
+        const double f = 2.0 * dot / vtv;
+        for (int64_t i = j; i < m; ++i) cc[i] -= f * v[i - j];
+      }
+    });
+    for (int c = j + 1; c < d; ++c) R[(size_t)j * d + c] = A[(size_t)c * m + j];
+  }
+  // columns of G = R^T are the rows of R
+  std::vector<double> G(R);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < d - 1; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        double *gp = &G[(size_t)p * d], *gq = &G[(size_t)q * d];
+        double a = 0, b = 0, c = 0;
+        for (int i = 0; i < d; ++i) {
+          a += gp[i] * gp[i];
+          b += gq[i] * gq[i];
+          c += gp[i] * gq[i];
+        }
+        if (std::fabs(c) <= 1e-15 * std::sqrt(a * b) || c == 0.0) continue;
+        rotated = true;
+        const double zeta = (b - a) / (2.0 * c);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = 0; i < d; ++i) {
+          const double x = gp[i], y = gq[i];
+          gp[i] = cs * x - sn * y;
+          gq[i] = sn * x + cs * y;
+        }
+      }
+    if (!rotated) break;
+  }
+  std::vector<std::pair<double, int>> order(d);
+  for (int p = 0; p < d; ++p) {
+    double n2 = 0;
+    for (int i = 0; i < d; ++i) n2 += G[(size_t)p * d + i] * G[(size_t)p * d + i];
+    order[p] = {std::sqrt(n2), p};
+  }
+  std::sort(order.begin(), order.end(),
+            [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+              return x.first > y.first || (x.first == y.first && x.second < y.second);
+            });
+  s.resize(d);
+  U.assign((size_t)d * d, 0.0);
+  for (int k = 0; k < d; ++k) {
+    s[k] = order[k].first;
+    const double *gp = &G[(size_t)order[k].second * d];
+    for (int i = 0; i < d; ++i) U[(size_t)i * d + k] = s[k] > 0 ? gp[i] / s[k] : 0.0;
+  }
+}
+
+// Rank kept by the two filters of Sec. 4.2 (the larger of the two): the values
+// with s_j / s_0 > eps, and the shortest prefix holding 1 - eps of the sum.
+int filter_rank(const std::vector<double> &s, double eps) {
+  const int n = (int)s.size();
+  int r1 = 0;
+  for (int j = 0; j < n; ++j)
+    if (s[j] / s[0] > eps) r1 = j + 1;
+  double tot = 0;
+  for (double x : s) tot += x;
+  int r2 = n;
+  double acc = 0;
+  for (int j = 0; j < n; ++j) {
+    acc += s[j];
+    if (acc / tot >= 1.0 - eps) {
+      r2 = j + 1;
+      break;
+    }
+  }
+  return std::max(r1, r2);
+}
+
 }  // namespace
+
+// Row blocks per gathered-GEMM tile for nrb 16-row blocks: a divisor when possible.
+int pick_rbt(int nrb) {
+  if (nrb % 6 == 0) return 6;
+  if (nrb % 5 == 0) return 5;
+  if (nrb % 4 == 0) return 4;
+  if (nrb % 7 == 0) return 7;
+  return 6;
+}
 
 int build_tables(Plan &P) {
   auto t0 = std::chrono::steady_clock::now();
@@ -374,17 +483,77 @@ int build_tables(Plan &P) {
     LevelHost &lv = P.lh[k];
     const int d = lv.d, dp = lv.dp;
     const double h = std::ldexp(L, -k);  // box side 2 l_k
-    lv.kfrag.assign((size_t)kNumOffsets * dp * dp, 0.0);
+    auto kdelta = [&](int o, std::vector<double> &A) {
+      const double sx = delta[o][0] * h, sy = delta[o][1] * h, sz = delta[o][2] * h;
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+          A[(size_t)i * d + j] = kern_host(kind, p, lv.Y[3 * i] - (lv.Y[3 * j] + sx),
+                                           lv.Y[3 * i + 1] - (lv.Y[3 * j + 1] + sy),
+                                           lv.Y[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
+    };
+    lv.r = lv.rp = 0;
+    if (c.compress_tol > 0 && d > 0) {
+      // K_fat = [K^delta_1 .. K^delta_316]: row i holds K^delta[i][:] for every delta
+      const int64_t m = (int64_t)kNumOffsets * d;
+      std::vector<double> Kfat((size_t)d * m);
+      parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
+        std::vector<double> A((size_t)d * d);
+        for (int64_t o = o0; o < o1; ++o) {
+          kdelta((int)o, A);
+          for (int i = 0; i < d; ++i)
+            std::memcpy(&Kfat[(size_t)i * m + (size_t)o * d], &A[(size_t)i * d], sizeof(double) * d);
+        }
+      });
+      std::vector<double> Ufull;
+      svd_rows(Kfat, d, m, Ufull, lv.sv);
+      // rank from the filters, rounded up to whole 16-row blocks that split evenly
+      // into GEMM tiles (extra singular vectors only improve the approximation)
+      int nrb = (filter_rank(lv.sv, c.compress_tol) + 15) / 16;
+      while (nrb * 16 < d && nrb % 6 && nrb % 5 && nrb % 4 && nrb % 7) ++nrb;
+      lv.r = std::min(d, nrb * 16);
+      lv.rp = ((lv.r + 15) / 16) * 16;
+      lv.U.assign((size_t)d * lv.r, 0.0);
+      for (int i = 0; i < d; ++i)
+        for (int a = 0; a < lv.r; ++a) lv.U[(size_t)i * lv.r + a] = Ufull[(size_t)i * d + a];
+      std::vector<double> Ut((size_t)lv.r * d);
+      for (int a = 0; a < lv.r; ++a)
+        for (int i = 0; i < d; ++i) Ut[(size_t)a * d + i] = lv.U[(size_t)i * lv.r + a];
+      lv.ufrag.assign((size_t)dp * lv.rp, 0.0);
+      lv.utfrag.assign((size_t)lv.rp * dp, 0.0);
+      to_fragments(lv.U.data(), d, lv.r, dp, lv.rp, lv.ufrag.data());
+      to_fragments(Ut.data(), lv.r, d, lv.rp, dp, lv.utfrag.data());
+    }
+    const int r = lv.r, rp = lv.rp;
+    const int dm = r > 0 ? rp : dp;  // size of the transferred expansions
+    lv.kfrag.assign((size_t)kNumOffsets * dm * dm, 0.0);
     parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
-      std::vector<double> A((size_t)d * d);
+      std::vector<double> A((size_t)d * d), KU, C;
       for (int64_t o = o0; o < o1; ++o) {
-        const double sx = delta[o][0] * h, sy = delta[o][1] * h, sz = delta[o][2] * h;
+        kdelta((int)o, A);
+        if (r == 0) {
+          to_fragments(A.data(), d, d, dp, dp, &lv.kfrag[(size_t)o * dp * dp]);
+          continue;
+        }
+        // C^delta = U^T K^delta U
+        KU.assign((size_t)d * r, 0.0);
         for (int i = 0; i < d; ++i)
-          for (int j = 0; j < d; ++j)
-            A[(size_t)i * d + j] = kern_host(kind, p, lv.Y[3 * i] - (lv.Y[3 * j] + sx),
-                                             lv.Y[3 * i + 1] - (lv.Y[3 * j + 1] + sy),
-                                             lv.Y[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
-        to_fragments(A.data(), d, d, dp, dp, &lv.kfrag[(size_t)o * dp * dp]);
+          for (int j = 0; j < d; ++j) {
+            const double a = A[(size_t)i * d + j];
+            const double *uj = &lv.U[(size_t)j * r];
+            double *ki = &KU[(size_t)i * r];
+            for (int b = 0; b < r; ++b) ki[b] += a * uj[b];
+          }
+        C.assign((size_t)r * r, 0.0);
+        for (int i = 0; i < d; ++i) {
+          const double *ui = &lv.U[(size_t)i * r];
+          const double *ki = &KU[(size_t)i * r];
+          for (int a = 0; a < r; ++a) {
+            const double u = ui[a];
+            double *ca = &C[(size_t)a * r];
+            for (int b = 0; b < r; ++b) ca[b] += u * ki[b];
+          }
+        }
+        to_fragments(C.data(), r, r, rp, rp, &lv.kfrag[(size_t)o * rp * rp]);
       }
     });
     trsm_table(lv.G, d, dp, false, true, lv.tri[0]);   // Gamma    (forward, Delta)

@@ -17,8 +17,8 @@ KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_HOST_ONLY = 1
 MAX_DEPTH = 8
-NPHASE = 9
-PHASES = ["tree", "p2p", "p2m", "m2m", "what", "m2l", "l2l", "lhat", "l2p"]
+NPHASE = 10
+PHASES = ["tree", "p2p", "p2m", "m2m", "what", "m2l", "l2l", "lhat", "l2p", "proj"]
 STATUS = {0: "OK", -1: "EINVAL", -2: "EDOMAIN", -3: "ESTATE", -4: "EEIM", -5: "ENOMEM",
           -6: "EHIP"}
 
@@ -35,15 +35,17 @@ class Config(ctypes.Structure):
                 ("L", ctypes.c_double), ("n", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("eim_tol", ctypes.c_double),
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("compress_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("d", ctypes.c_int32 * (MAX_DEPTH + 1)), ("dpad", ctypes.c_int32 * (MAX_DEPTH + 1)),
+                ("rank", ctypes.c_int32 * (MAX_DEPTH + 1)),
                 ("eim_err", ctypes.c_double * (MAX_DEPTH + 1)), ("setup_ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * NPHASE), ("phase_calls", ctypes.c_int64 * NPHASE),
-                ("m2l_flops", ctypes.c_double),
+                ("m2l_flops", ctypes.c_double), ("proj_flops", ctypes.c_double),
                 ("active_boxes", ctypes.c_int64 * (MAX_DEPTH + 1)),
                 ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
                 ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -70,6 +72,7 @@ def lib():
         L.eifmm_set_timing.argtypes = [vp, i32]
         L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.eifmm_get_level.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
+        L.eifmm_get_compression.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp]
         L.eifmm_export_tree.argtypes = [vp, vp, vp, vp]
         L.eifmm_export_lists.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp]
         L.eifmm_export_expansion.argtypes = [vp, i32, i32, i32, vp]
@@ -77,7 +80,8 @@ def lib():
         L.eifmm_status_str.argtypes = [ctypes.c_int]
         L.eifmm_status_str.restype = ctypes.c_char_p
         for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_evaluate", "eifmm_set_timing",
-                  "eifmm_get_stats", "eifmm_get_level", "eifmm_export_tree", "eifmm_export_lists",
+                  "eifmm_get_stats", "eifmm_get_level", "eifmm_get_compression",
+                  "eifmm_export_tree", "eifmm_export_lists",
                   "eifmm_export_expansion", "eifmm_plan_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -109,7 +113,7 @@ class Plan:
     """One fixed (kernel, domain, N, depth, tau) setting; points and potentials vary."""
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
-                 tol_mode=0, dmax=0, host_only=False):
+                 tol_mode=0, dmax=0, host_only=False, compress_tol=0.0):
         c = Config()
         c.struct_size = ctypes.sizeof(Config)
         c.kernel = KERNELS[kernel]
@@ -125,6 +129,7 @@ class Plan:
         c.precision = PRECISIONS[precision]
         c.dmax = int(dmax)
         c.flags = FLAG_HOST_ONLY if host_only else 0
+        c.compress_tol = float(compress_tol)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.kernel, self.precision = kernel, precision
@@ -168,6 +173,7 @@ class Plan:
         _check(lib().eifmm_get_stats(self._h, ctypes.byref(s)), "eifmm_get_stats")
         lv = range(2, self.depth + 1)
         return dict(d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
+                    rank={k: s.rank[k] for k in lv}, proj_flops=s.proj_flops,
                     eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
                     phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},
                     phase_calls={PHASES[q]: s.phase_calls[q] for q in range(NPHASE)},
@@ -187,6 +193,17 @@ class Plan:
         _check(lib().eifmm_get_level(self._h, k, None, _np_ptr(X), _np_ptr(Y), _np_ptr(ia),
                                      _np_ptr(ib), _np_ptr(B), _np_ptr(G)), "eifmm_get_level")
         return dict(d=d, X=X, Y=Y, ia=ia, ib=ib, B=B, G=G)
+
+    def compression(self, k):
+        """(r, singular values, U) of level k's M2L compression."""
+        d = self.level(k)["d"]
+        r = ctypes.c_int32()
+        _check(lib().eifmm_get_compression(self._h, k, ctypes.byref(r), None, None),
+               "eifmm_get_compression")
+        sv, U = np.empty(d), np.empty((d, max(r.value, 0)))
+        _check(lib().eifmm_get_compression(self._h, k, None, _np_ptr(sv), _np_ptr(U)),
+               "eifmm_get_compression")
+        return r.value, sv, U
 
     def export_tree(self):
         perm = np.empty(self.n, dtype=np.int32)

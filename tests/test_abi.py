@@ -77,3 +77,21 @@ def test_host_setup_matches_oracle(E, oracle_lib, kernel, param, depth, tau):
         assert np.abs(a["G"] - b["G"]).max() <= 1e-12 * scale
         assert np.abs(a["B"] - b["B"]).max() <= 1e-12
     P.close()
+
+
+def test_host_compression_matches_oracle_svd(E, oracle_lib):
+    """The library's SVD (Householder QR, then one-sided Jacobi) against numpy's:
+    singular values and the projector onto the kept vectors; the kept rank is the
+    filter rank rounded up to whole 16-row blocks that split into GEMM tiles."""
+    P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-4)
+    k = 2
+    r, sv, U = P.compression(k)
+    Y = P.level(k)["Y"]
+    Uo, svo, ro = oracle_lib.compression_basis("laplace", 0, Y, k, 1e-4)
+    m = svo / svo[0] > 1e-12
+    assert np.abs(sv[m] - svo[m]).max() <= 1e-12 * svo[0]
+    assert ro <= r <= min(P.level(k)["d"], ro + 16 * 4) and r % 16 == 0 or r == P.level(k)["d"]
+    Uf, _, _ = oracle_lib.compression_basis("laplace", 0, Y, k, 1e-4, rank=r)
+    assert np.abs(U @ U.T - Uf @ Uf.T).max() < 1e-9
+    assert np.abs(U.T @ U - np.eye(r)).max() < 1e-12
+    P.close()

@@ -224,3 +224,45 @@ def test_error_paths(E, torch_dev):
     plan.evaluate(s)  # still usable
     torch.cuda.synchronize()
     plan.close()
+
+
+def test_compressed_fp64_vs_oracle(E, torch_dev, oracle_lib, c1_inputs, c1_direct):
+    """M2L compression (Sec. 4.2): the GPU pass against the oracle's compressed pass
+    with the same kept rank per level."""
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  compress_tol=1e-6)
+    ranks = plan.stats()["rank"]
+    assert all(0 < r < plan.stats()["d"][k] for k, r in ranks.items())
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
+    O = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
+                        compress_tol=1e-6, compress_rank=ranks)
+    assert _rel(f, O.evaluate(x, s)) < 1e-10
+    assert _rel(f, c1_direct) < 1e-6
+    plan.close()
+
+
+def test_compressed_mixed_and_multi_rhs(E, torch_dev, oracle_lib, c1_inputs, c1_direct):
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  compress_tol=1e-6, precision="mixed", max_rhs=3)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    S = np.stack([s, W.potentials(w["n"], 90), -s])
+    F = plan.evaluate(torch.from_numpy(S).to(dev)).cpu().numpy()
+    assert _rel(F[0], c1_direct) < 1e-6
+    assert _rel(F[2], -c1_direct) < 1e-6
+    plan.close()
+
+
+def test_compressed_finite_rank_exact(E, torch_dev, oracle_lib):
+    torch, dev = torch_dev
+    x = W.uniform_points(3000, 41)
+    s = W.potentials(3000, 44)
+    plan = E.Plan("sqdist", 0, [0, 0, 0], 1.0, 3000, 3, 1e-8, compress_tol=1e-12)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
+    assert _rel(f, oracle_lib.direct("sqdist", 0, x, x, s)) < 1e-11
+    plan.close()

@@ -132,3 +132,63 @@ def test_domain_membership(c1_plan):
             assert np.all(a >= 3 * lk1 - 1e-15) and np.all(a <= L - lk1 + 1e-15)
             b = np.abs(lev[k + 1]["Y"] + sh).max(1)
             assert np.all(b <= lk + 1e-15)
+
+
+@pytest.fixture(scope="module")
+def c1_compressed(oracle_lib, c1_inputs):
+    _, _, w = c1_inputs
+    return oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
+                           compress_tol=1e-6)
+
+
+def test_compression_without_truncation_is_exact(oracle_lib, c1_inputs, c1_plan):
+    """Keeping every singular vector (U U^T = I) reproduces the uncompressed M2L."""
+    x, s, w = c1_inputs
+    P = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
+                        compress_tol=1e-14)
+    assert all(P.levels[k]["r"] == P.levels[k]["d"] for k in P.levels)
+    assert _rel(P.evaluate(x, s), c1_plan.evaluate(x, s)) < 1e-13
+
+
+def test_compression_accuracy_and_rank(c1_compressed, c1_inputs, c1_direct):
+    """Sec. 4.2 compression at eps = 1e-6 keeps far fewer vectors than d and the
+    pass stays within the requested accuracy."""
+    x, s, w = c1_inputs
+    for k, lv in c1_compressed.levels.items():
+        assert 0 < lv["r"] < 0.7 * lv["d"]
+        sv = lv["sv"]
+        assert np.all(np.diff(sv) <= 0)
+    assert _rel(c1_compressed.evaluate(x, s), c1_direct) < 1e-6
+
+
+def test_compression_error_decreases(oracle_lib, c1_inputs, c1_plan):
+    x, s, w = c1_inputs
+    f0 = c1_plan.evaluate(x, s)
+    errs = []
+    for eps in (1e-3, 1e-5, 1e-7):
+        P = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
+                            compress_tol=eps)
+        errs.append(_rel(P.evaluate(x, s), f0))
+    assert errs[0] > errs[1] > errs[2], errs
+
+
+def test_compressed_operators_symmetry(oracle_lib, c1_compressed):
+    """For a symmetric kernel K^{-delta} = (K^delta)^T, hence C^{-delta} = (C^delta)^T."""
+    k = 2
+    lv = c1_compressed.levels[k]
+    Kd = oracle_lib.m2l_matrices("laplace", 0, lv["Y"], k)
+    t = oracle_lib.offset_table()
+    idx = {tuple(v): i for i, v in enumerate(t)}
+    U = lv["U"]
+    for o in (0, 17, 150):
+        m = idx[tuple(-t[o])]
+        C, Cm = U.T @ Kd[o] @ U, U.T @ Kd[m] @ U
+        np.testing.assert_allclose(C, Cm.T, rtol=0, atol=1e-12 * np.abs(C).max())
+
+
+def test_compression_finite_rank_exact(oracle_lib):
+    x = W.uniform_points(1500, 21)
+    s = W.potentials(1500, 24)
+    P = oracle_lib.Plan("sqdist", 0, [0, 0, 0], 1.0, 3, 1e-8, compress_tol=1e-12)
+    fd = oracle_lib.direct("sqdist", 0, x, x, s)
+    assert _rel(P.evaluate(x, s), fd) < 1e-11
