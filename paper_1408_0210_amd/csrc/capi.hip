@@ -197,6 +197,12 @@ int device_setup(eifmm_plan h) {
     else
       TRY(dalloc(&D.l, m, tr));
   }
+  {
+    int cus = 0;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
+    P.sk_groups = std::max(8, 2 * cus);
+    TRY(dalloc(&P.sk_ws, (size_t)2 * P.sk_groups * 6 * 16 * 128, tr));
+  }
   if (depth >= 2)
     TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dp, tr));
 #undef TRY

@@ -500,21 +500,205 @@ __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
   return (const T *)J.A + idx * J.a_stride;
 }
 
+// Stream-K schedule: the units of a launch are (tile, term) pairs, numbered job
+// by job, tile by tile, term by term; persistent workgroup g processes the
+// contiguous range [B_g, B_{g+1}) with B_g = floor(g U / G).  A tile covered by
+// one workgroup is written directly; the pieces of a tile split between
+// workgroups go to a workspace (slot 2g for the first tile of g, 2g + 1 for its
+// last) and k_gemm_fixup adds them in workgroup order, so the result does not
+// depend on timing.
+__device__ inline int64_t sk_bound(int64_t g, int64_t units, int G) { return g * units / G; }
+
+__device__ inline int find_job_units(const GemmJob *__restrict__ jobs, int njobs, int64_t u) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].units_start <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename T, int MODE, bool FOLD, int RBT>
 __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
-                                                 int ntiles, const int8_t *__restrict__ dvec) {
+                                                 int64_t units, int G, double *__restrict__ ws,
+                                                 const int8_t *__restrict__ dvec) {
   typedef typename Mfma<T>::v4 V4;
   typedef typename Mfma<T>::p2 P2;
   typedef double D4 __attribute__((ext_vector_type(4)));
   constexpr int NA = RBT * 128;         // A chunk, in pairs
   constexpr int QA = (NA + 255) / 256;  // pairs per thread
-  __shared__ T As[RBT * 4 * 64];
-  __shared__ T Bs[4 * GT_CB * 64];
+  constexpr int TILE = RBT * 16 * GT_COLS;
+  __shared__ T As[2][RBT * 4 * 64];
+  __shared__ T Bs[2][4 * GT_CB * 64];
+  const int g = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int jl = t >> 1, hh = t & 1;
+  const int64_t ua = sk_bound(g, units, G), ub = sk_bound(g + 1, units, G);
 
-  // tiles of one job are contiguous and land on one XCD (blocks go round-robin
-  // over the 8 XCDs)
-  const int per = (ntiles + 7) / 8;
-  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  for (int64_t u = ua; u < ub;) {
+    const GemmJob J = jobs[find_job_units(jobs, njobs, u)];
+    const int64_t local = u - J.units_start;
+    const int tile_local = (int)(local / J.nterms);
+    const int term0 = (int)(local - (int64_t)tile_local * J.nterms);
+    const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms;
+    const int term1 = (int)(min(ts + J.nterms, ub) - ts);
+    u = ts + term1;
+    const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
+    const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
+    const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
+    const int ncols = J.ntgt * J.nrhs;
+
+    // the column this thread loads
+    const int jc = col0 + jl;
+    const bool cvalid = jc < ncols;
+    int r = 0, tsl = 0;
+    uint32_t tkey = 0;
+    if (cvalid) {
+      const int tt = jc / J.nrhs;
+      r = jc - tt * J.nrhs;
+      tsl = J.tgt ? J.tgt[tt] : tt;
+      if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
+    }
+    V4 acc[RBT][2];
+    D4 sum[RBT][2];
+    bool rowok[RBT];
+#pragma unroll
+    for (int i = 0; i < RBT; ++i) {
+      rowok[i] = rb0 + i < nrb;
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        acc[i][jj] = V4{0, 0, 0, 0};
+        if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
+      }
+    }
+    P2 ra[QA], rbv[4];
+    const T *srcp = nullptr;
+    const T *Ap = nullptr;
+    auto fetch = [&](int it) {
+      const int term = it / nkc, kc = it - term * nkc;
+      if (kc == 0) {
+        srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec);
+        Ap = gemm_operand<T, MODE>(J, term);
+      }
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int e = t + 256 * q;  // pair index in the chunk
+        const int rb = rb0 + (e >> 7);
+        if (e < NA && rb < nrb)
+          ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
+        else
+          ra[q] = P2{0, 0};
+      }
+      if (srcp) {
+        const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
+      }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int e = t + 256 * q;
+        if (e < NA) *(P2 *)(&As[buf][2 * e]) = ra[q];
+      }
+      const int cb = jl >> 4, c16 = jl & 15;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int kl = 8 * hh + 2 * q + e;
+          Bs[buf][((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = e ? rbv[q].y : rbv[q].x;
+        }
+      }
+    };
+
+    const int it0 = term0 * nkc, it1 = term1 * nkc;
+    if (it0 < it1) {
+      fetch(it0);
+      stash(0);
+      __syncthreads();
+    }
+    for (int it = it0; it < it1; ++it) {
+      const int cur = (it - it0) & 1;
+      if (it + 1 < it1) fetch(it + 1);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        T a[RBT], b[2];
+#pragma unroll
+        for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[cur][(ks * GT_CB + 2 * w + jj) * 64 + lane];
+#pragma unroll
+        for (int i = 0; i < RBT; ++i)
+          if (rowok[i]) {
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
+          }
+      }
+      if constexpr (FOLD) {
+        if ((it + 1) % nkc == 0) {  // a term is complete
+#pragma unroll
+          for (int i = 0; i < RBT; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
+              acc[i][jj] = V4{0, 0, 0, 0};
+            }
+        }
+      }
+      if (it + 1 < it1) stash(cur ^ 1);
+      __syncthreads();
+    }
+
+    const bool whole = term0 == 0 && term1 == J.nterms;
+    double *part = whole ? nullptr : ws + (size_t)(2 * g + (ua >= ts ? 0 : 1)) * TILE;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int jt = 16 * (2 * w + jj) + (lane & 15);
+      const int jo = col0 + jt;
+      if (jo >= ncols) continue;
+      const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
+      const int tso = J.tgt ? J.tgt[tt] : tt;
+      const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
+#pragma unroll
+      for (int i = 0; i < RBT; ++i) {
+        if (!rowok[i]) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rt = 16 * i + Mfma<T>::row(lane, q);
+          double v;
+          if constexpr (FOLD)
+            v = sum[i][jj][q];
+          else
+            v = (double)acc[i][jj][q];
+          if (part) {
+            part[(size_t)rt * GT_COLS + jt] = v;
+          } else {
+            const int64_t o = cbase + 16 * rb0 + rt;
+            if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
+            J.C[o] = v;
+            if (J.C32) J.C32[o] = (float)v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Adds the pieces of the tiles split between workgroups (one block per tile).
+template <int RBT>
+__global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
+                                                    int ntiles, int64_t units, int G,
+                                                    const double *__restrict__ ws) {
+  constexpr int TILE = RBT * 16 * GT_COLS;
+  const int tile = blockIdx.x;
   if (tile >= ntiles) return;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
@@ -525,143 +709,34 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
       hi = mid - 1;
   }
   const GemmJob J = jobs[lo];
-  const int local = tile - J.tiles_start;
-  const int rowtile = local % J.nrowtiles, coltile = local / J.nrowtiles;
+  const int tile_local = tile - J.tiles_start;
+  const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms, te = ts + J.nterms;
+  // workgroups covering [ts, te)
+  int64_t glo = ts * G / units;
+  while (glo + 1 < G && sk_bound(glo + 1, units, G) <= ts) ++glo;
+  while (glo > 0 && sk_bound(glo, units, G) > ts) --glo;
+  int64_t ghi = glo;
+  while (ghi + 1 < G && sk_bound(ghi + 1, units, G) < te) ++ghi;
+  if (ghi == glo) return;  // written directly
+  const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
-  const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
+  const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
   const int ncols = J.ntgt * J.nrhs;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-
-  // the column this thread loads
-  const int jl = t >> 1, hh = t & 1;
-  const int jc = col0 + jl;
-  const bool cvalid = jc < ncols;
-  int r = 0, ts = 0;
-  uint32_t tkey = 0;
-  if (cvalid) {
-    const int tt = jc / J.nrhs;
-    r = jc - tt * J.nrhs;
-    ts = J.tgt ? J.tgt[tt] : tt;
-    if (MODE != MODE_PROJ) tkey = J.tgt_keys[ts];
-  }
-
-  V4 acc[RBT][2];
-  D4 sum[RBT][2];
-  bool rowok[RBT];
-#pragma unroll
-  for (int i = 0; i < RBT; ++i) {
-    rowok[i] = rb0 + i < nrb;
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      acc[i][jj] = V4{0, 0, 0, 0};
-      if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
+  for (int e = threadIdx.x; e < RBT * 16 * GT_COLS; e += 256) {
+    const int rt = e / GT_COLS, jt = e - rt * GT_COLS;
+    const int jo = col0 + jt;
+    if (rt >= nrows || jo >= ncols) continue;
+    double v = 0.0;
+    for (int64_t g = glo; g <= ghi; ++g) {
+      const int slot = (int)(2 * g + (sk_bound(g, units, G) >= ts ? 0 : 1));
+      v += ws[(size_t)slot * TILE + e];
     }
-  }
-
-  const int total = J.nterms * nkc;
-  P2 ra[QA], rbv[4];
-  const T *srcp = nullptr;
-  const T *Ap = nullptr;
-  auto fetch = [&](int it) {
-    const int term = it / nkc, kc = it - term * nkc;
-    if (kc == 0) {
-      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, ts, r, dvec);
-      Ap = gemm_operand<T, MODE>(J, term);
-    }
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = t + 256 * q;  // pair index in the chunk
-      const int rb = rb0 + (e >> 7);
-      if (e < NA && rb < nrb)
-        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
-      else
-        ra[q] = P2{0, 0};
-    }
-    if (srcp) {
-      const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
-    }
-  };
-
-  if (total > 0) fetch(0);
-  for (int it = 0; it < total; ++it) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = t + 256 * q;
-      if (e < NA) *(P2 *)(As + 2 * e) = ra[q];
-    }
-    {
-      const int cb = jl >> 4, c16 = jl & 15;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int kl = 8 * hh + 2 * q + e;
-          const T v = e ? rbv[q].y : rbv[q].x;
-          Bs[((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (it + 1 < total) fetch(it + 1);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      T a[RBT], b[2];
-#pragma unroll
-      for (int i = 0; i < RBT; ++i) a[i] = As[(i * 4 + ks) * 64 + lane];
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[(ks * GT_CB + 2 * w + jj) * 64 + lane];
-#pragma unroll
-      for (int i = 0; i < RBT; ++i)
-        if (rowok[i]) {
-#pragma unroll
-          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
-        }
-    }
-    if constexpr (FOLD) {
-      if ((it + 1) % nkc == 0) {  // a term is complete
-#pragma unroll
-        for (int i = 0; i < RBT; ++i)
-#pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
-            acc[i][jj] = V4{0, 0, 0, 0};
-          }
-      }
-    }
-  }
-
-  // write the tile (result layout per Mfma<T>::row)
-#pragma unroll
-  for (int jj = 0; jj < 2; ++jj) {
-    const int jo = col0 + 16 * (2 * w + jj) + (lane & 15);
-    if (jo >= ncols) continue;
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
     const int tso = J.tgt ? J.tgt[tt] : tt;
-    const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
-#pragma unroll
-    for (int i = 0; i < RBT; ++i) {
-      if (!rowok[i]) continue;
-      const int rbase = 16 * (rb0 + i);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t o = cbase + rbase + Mfma<T>::row(lane, q);
-        double v;
-        if constexpr (FOLD)
-          v = sum[i][jj][q];
-        else
-          v = (double)acc[i][jj][q];
-        if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
-        J.C[o] = v;
-        if (J.C32) J.C32[o] = (float)v;
-      }
-    }
+    const int64_t o = ((int64_t)tso * J.nrhs + ro) * J.dpm + 16 * rb0 + rt;
+    if (J.mode == MODE_L2L) v += J.Cadd[o];
+    J.C[o] = v;
+    if (J.C32) J.C32[o] = (float)v;
   }
 }
 
@@ -704,6 +779,16 @@ void finish_job(GemmJob &J, int &tiles, int rbt) {
   tiles += tiles_of(J);
 }
 
+// unit offsets (tile x term) of the jobs of one launch group
+int64_t finish_units(std::vector<GemmJob> &h, int first) {
+  int64_t u = 0;
+  for (size_t j = first; j < h.size(); ++j) {
+    h[j].units_start = u;
+    u += (int64_t)tiles_of(h[j]) * h[j].nterms;
+  }
+  return u;
+}
+
 }  // namespace
 
 // Job tables of a (points, nrhs) pair, uploaded once and reused.
@@ -737,6 +822,7 @@ int build_jobs(Plan &P, int nrhs) {
     jt.m2m_n[k] = 1;
     jt.m2m_tiles[k] = tiles;
     h.push_back(J);
+    jt.m2m_units[k] = finish_units(h, jt.m2m_first[k]);
   }
   // compression projections What' = U^T What, one job per compressed level
   {
@@ -764,6 +850,7 @@ int build_jobs(Plan &P, int nrhs) {
     }
     jt.pre_n = (int)h.size() - jt.pre_first;
     jt.pre_tiles = tiles;
+    jt.pre_units = finish_units(h, jt.pre_first);
     P.proj_flops = pf;
   }
   // M2L, every level in one launch, finest level first
@@ -806,6 +893,7 @@ int build_jobs(Plan &P, int nrhs) {
     }
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
+    jt.m2l_units = finish_units(h, jt.m2l_first);
     P.m2l_flops = flops;
   }
   // g = U g' on compressed levels
@@ -831,6 +919,7 @@ int build_jobs(Plan &P, int nrhs) {
     }
     jt.post_n = (int)h.size() - jt.post_first;
     jt.post_tiles = tiles;
+    jt.post_units = finish_units(h, jt.post_first);
   }
   // L2L, per child level k = 3 .. depth, one job per child class
   for (int k = 3; k <= depth; ++k) {
@@ -862,6 +951,7 @@ int build_jobs(Plan &P, int nrhs) {
     }
     jt.l2l_n[k] = (int)h.size() - jt.l2l_first[k];
     jt.l2l_tiles[k] = tiles;
+    jt.l2l_units[k] = finish_units(h, jt.l2l_first[k]);
   }
   if (P.job_dev) hipFree(P.job_dev);
   P.job_dev = nullptr;
@@ -878,21 +968,24 @@ int build_jobs(Plan &P, int nrhs) {
 namespace {
 
 template <typename T, int MODE, int RBT>
-void launch_gemm_rbt(Plan &P, int first, int n, int tiles, hipStream_t s) {
-  const int grid = ((tiles + 7) / 8) * 8;
+void launch_gemm_rbt(Plan &P, int first, int n, int tiles, int64_t units, hipStream_t s) {
+  const int G = (int)std::min<int64_t>(units, P.sk_groups);
   constexpr bool fold = sizeof(T) == 4;
-  hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(grid), dim3(256), 0, s,
-                     P.job_dev + first, n, tiles, P.dvec);
+  hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, P.job_dev + first,
+                     n, units, G, P.sk_ws, P.dvec);
+  if (G > 1)
+    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(tiles), dim3(256), 0, s, P.job_dev + first, n,
+                       tiles, units, G, P.sk_ws);
 }
 
 template <typename T, int MODE>
-void launch_gemm(Plan &P, int first, int n, int tiles, hipStream_t s, int rbt = 6) {
-  if (n == 0 || tiles == 0) return;
+void launch_gemm(Plan &P, int first, int n, int tiles, int64_t units, hipStream_t s,
+                 int rbt = 6) {
+  if (n == 0 || tiles == 0 || units == 0) return;
   switch (rbt) {
-    case 4: launch_gemm_rbt<T, MODE, 4>(P, first, n, tiles, s); break;
-    case 5: launch_gemm_rbt<T, MODE, 5>(P, first, n, tiles, s); break;
-    case 7: launch_gemm_rbt<T, MODE, 7>(P, first, n, tiles, s); break;
-    default: launch_gemm_rbt<T, MODE, 6>(P, first, n, tiles, s); break;
+    case 4: launch_gemm_rbt<T, MODE, 4>(P, first, n, tiles, units, s); break;
+    case 5: launch_gemm_rbt<T, MODE, 5>(P, first, n, tiles, units, s); break;
+    default: launch_gemm_rbt<T, MODE, 6>(P, first, n, tiles, units, s); break;
   }
 }
 
@@ -951,7 +1044,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_M2M);
     for (int k = depth - 1; k >= 2; --k)
       launch_gemm<double, MODE_M2M>(P, P.jobs.m2m_first[k], P.jobs.m2m_n[k], P.jobs.m2m_tiles[k],
-                                    s, P.jobs.m2m_rbt[k]);
+                                    P.jobs.m2m_units[k], s, P.jobs.m2m_rbt[k]);
   }
   // step 3: What = Delta W on every level
   {
@@ -980,30 +1073,30 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
   // step 4: M2L (with the compression projections around it when enabled)
   if (P.jobs.pre_n) {
     Timer tm(P, s, EIFMM_PH_PROJ);
-    launch_gemm<double, MODE_PROJ>(P, P.jobs.pre_first, P.jobs.pre_n, P.jobs.pre_tiles, s,
-                                   P.jobs.pre_rbt);
+    launch_gemm<double, MODE_PROJ>(P, P.jobs.pre_first, P.jobs.pre_n, P.jobs.pre_tiles,
+                                   P.jobs.pre_units, s, P.jobs.pre_rbt);
   }
   {
     Timer tm(P, s, EIFMM_PH_M2L);
     if (mixed)
-      launch_gemm<float, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s,
-                                   P.jobs.m2l_rbt);
+      launch_gemm<float, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles,
+                                   P.jobs.m2l_units, s, P.jobs.m2l_rbt);
     else
-      launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles, s,
-                                    P.jobs.m2l_rbt);
+      launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles,
+                                    P.jobs.m2l_units, s, P.jobs.m2l_rbt);
 
   }
   if (P.jobs.post_n) {
     Timer tm(P, s, EIFMM_PH_PROJ);
-    launch_gemm<double, MODE_PROJ>(P, P.jobs.post_first, P.jobs.post_n, P.jobs.post_tiles, s,
-                                   P.jobs.post_rbt);
+    launch_gemm<double, MODE_PROJ>(P, P.jobs.post_first, P.jobs.post_n, P.jobs.post_tiles,
+                                   P.jobs.post_units, s, P.jobs.post_rbt);
   }
   // step 5: l^2 = g^2, then L2L downwards
   {
     Timer tm(P, s, EIFMM_PH_L2L);
     for (int k = 3; k <= depth; ++k)
       launch_gemm<double, MODE_L2L>(P, P.jobs.l2l_first[k], P.jobs.l2l_n[k], P.jobs.l2l_tiles[k],
-                                    s, P.jobs.l2l_rbt[k]);
+                                    P.jobs.l2l_units[k], s, P.jobs.l2l_rbt[k]);
   }
   // step 6: lhat = Delta^T l on the leaf level
   {

@@ -69,6 +69,7 @@ struct GemmJob {
   int ntgt, nterms, dpm, dpk;
   int level, cls, mode, nrhs;
   int tiles_start, ncoltiles, nrowtiles, src_level;
+  int64_t units_start;  // first (tile, term) unit of the job within its launch
 };
 
 // Index ranges of the gathered-GEMM jobs of one (points, nrhs) pair.
@@ -77,6 +78,8 @@ struct JobTables {
   int m2m_first[kMaxLevels] = {}, m2m_n[kMaxLevels] = {}, m2m_tiles[kMaxLevels] = {};
   int l2l_first[kMaxLevels] = {}, l2l_n[kMaxLevels] = {}, l2l_tiles[kMaxLevels] = {};
   int m2m_rbt[kMaxLevels] = {}, l2l_rbt[kMaxLevels] = {};
+  int64_t m2m_units[kMaxLevels] = {}, l2l_units[kMaxLevels] = {};
+  int64_t m2l_units = 0, pre_units = 0, post_units = 0;
   int m2l_first = 0, m2l_n = 0, m2l_tiles = 0, m2l_rbt = 6;
   int pre_first = 0, pre_n = 0, pre_tiles = 0, pre_rbt = 6;     // What' = U^T What
   int post_first = 0, post_n = 0, post_tiles = 0, post_rbt = 6; // g = U g'
@@ -131,6 +134,8 @@ struct Plan {
   // gathered-GEMM job tables (rebuilt when the points or nrhs change)
   JobTables jobs;
   GemmJob *job_dev = nullptr;
+  int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
+  double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
   double m2l_flops = 0, proj_flops = 0;
 
   // stats

@@ -443,7 +443,6 @@ int pick_rbt(int nrb) {
   if (nrb % 6 == 0) return 6;
   if (nrb % 5 == 0) return 5;
   if (nrb % 4 == 0) return 4;
-  if (nrb % 7 == 0) return 7;
   return 6;
 }
 
@@ -509,7 +508,7 @@ int build_tables(Plan &P) {
       // rank from the filters, rounded up to whole 16-row blocks that split evenly
       // into GEMM tiles (extra singular vectors only improve the approximation)
       int nrb = (filter_rank(lv.sv, c.compress_tol) + 15) / 16;
-      while (nrb * 16 < d && nrb % 6 && nrb % 5 && nrb % 4 && nrb % 7) ++nrb;
+      while (nrb * 16 < d && nrb % 6 && nrb % 5 && nrb % 4) ++nrb;
       lv.r = std::min(d, nrb * 16);
       lv.rp = ((lv.r + 15) / 16) * 16;
       lv.U.assign((size_t)d * lv.r, 0.0);
