@@ -61,10 +61,11 @@ extern "C" {
 
 /* precision of the pass */
 #define EIFMM_PREC_FP64 0  /* every step in FP64                                   */
-#define EIFMM_PREC_MIXED 1 /* M2L on FP32 MFMA with FP32 accumulation, P2P in FP32
-                              with leaf-local coordinates and compensated sums;
-                              EIM, triangular solves, M2M, L2L, P2M, L2P and the
-                              final f in FP64                                     */
+#define EIFMM_PREC_MIXED 1 /* M2L on FP32 MFMA (FP32 products, each offset's
+                              contribution added in FP64); P2P with FP64
+                              coordinate differences, FP32 kernel values and
+                              compensated FP32 sums; EIM, triangular solves, M2M,
+                              L2L, P2M, L2P and the final f in FP64              */
 
 /* flags */
 #define EIFMM_FLAG_HOST_ONLY 1 /* plan_create runs the host setup only (no device

@@ -149,7 +149,6 @@ int device_setup(eifmm_plan h) {
   const int64_t nn = std::max<int64_t>(n, 1);
   P.ntiles_sort = (int)((nn + 1023) / 1024);
   TRY(dalloc(&P.xyz, 3 * nn, tr));
-  TRY(dalloc(&P.xloc, 3 * nn, tr));
   TRY(dalloc(&P.keys, nn, tr));
   TRY(dalloc(&P.keys_tmp, nn, tr));
   TRY(dalloc(&P.idx, nn, tr));
@@ -176,6 +175,7 @@ int device_setup(eifmm_plan h) {
   P.near_cap = (size_t)27 * P.ld[depth].cap;
   TRY(dalloc(&P.near_ptr, P.ld[depth].cap + 2, tr));
   TRY(dalloc(&P.near_src, P.near_cap, tr));
+  TRY(dalloc(&P.chunk_ptr, P.ld[depth].cap + 2, tr));
   TRY(dalloc(&P.sig, (size_t)nn * R, tr));
   TRY(dalloc(&P.fnear, (size_t)nn * R, tr));
   for (int k = 2; k <= depth; ++k) {

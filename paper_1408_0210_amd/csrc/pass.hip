@@ -3,14 +3,14 @@
 // Expansions of level k live in slot-major arrays [slot][rhs][dp_k] (slot =
 // rank of a non-empty box in key order; dp_k = d_k padded to 16 with zeros).
 // Steps and kernels:
-//   near field, eq. (13)        k_p2p64 / k_p2p32   one wave per target leaf
+//   near field, eq. (13)        k_p2p64 / k_p2p32   one wave per 64 targets of a leaf
 //   1  P2M                      k_p2m               one workgroup per leaf
 //   2  M2M (Sec. 4.1 operators) k_gemm<MODE_M2M>    MFMA, 8 children per parent
-//   3  What = Delta W           k_solve             blocked triangular solves
+//   3  What = Delta W           k_trsm              blocked triangular solves (MFMA)
 //   4  M2L (Sec. 4.2 matrices)  k_gemm<MODE_M2L>    MFMA, 189 offsets per class
 //   5  L2L                      k_gemm<MODE_L2L>    MFMA, adds g
-//   6  lhat = Delta^T l         k_solve
-//   7  L2P and f = f_far + f_near in input order    k_l2p
+//   6  lhat = Delta^T l         k_trsm
+//   7  L2P and f = f_far + f_near, input order  k_l2p  one wave per 64 targets
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -68,20 +68,37 @@ __global__ void k_gather_sigma(int64_t n, int nrhs, const double *__restrict__ s
 // ------------------------------------------------------------------ near field
 // One 64-lane workgroup per non-empty target leaf; lanes own targets; sources of
 // the neighbour leaves (ascending key) are staged through LDS 64 at a time.
+// Near field and L2P run one workgroup per chunk of up to 64 consecutive targets
+// of a leaf (chunk_ptr: exclusive prefix sum of ceil(count / 64) over the active
+// leaves), so a crowded leaf of a clustered cloud spreads over many workgroups.
+__device__ inline int chunk_leaf(const int *__restrict__ chunk_ptr, int nleaf, int c) {
+  int lo = 0, hi = nleaf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (chunk_ptr[mid] <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int KIND, int RB>
 __global__ __launch_bounds__(64) void k_p2p64(const uint32_t *__restrict__ act,
-                                              const int *__restrict__ ls,
+                                              const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
                                               const int *__restrict__ near_ptr,
                                               const int *__restrict__ near_src,
                                               const double *__restrict__ xyz, int64_t n,
                                               const double *__restrict__ sig, int nrhs,
                                               double *__restrict__ fnear, double p) {
   __shared__ double sx[64], sy[64], sz[64], ss[64 * RB];
-  const int j = blockIdx.x, lane = threadIdx.x;
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int j = chunk_leaf(chunk_ptr, nleaf, c);
   const uint32_t key = act[j];
   const int a = ls[key], b = ls[key + 1];
   const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
-  for (int t0 = a; t0 < b; t0 += 64) {
+  {  // the 64 targets of chunk c
+    const int t0 = a + 64 * (c - chunk_ptr[j]);
     const int i = t0 + lane;
     const bool tv = i < b;
     const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0,
@@ -125,28 +142,31 @@ __global__ __launch_bounds__(64) void k_p2p64(const uint32_t *__restrict__ act,
   }
 }
 
-// FP32 near field: coordinates relative to the target leaf centre (source
-// leaf-local coordinates plus the exact offset between the two centres), FP32
-// kernel values, Neumaier-compensated FP32 sums returned as hi + lo in FP64.
+// Mixed-precision near field: the coordinate differences are taken in FP64 and
+// rounded once to FP32 (so a close pair keeps its relative accuracy however
+// crowded the leaf), kernel values and products in FP32, Neumaier-compensated
+// FP32 sums returned as hi + lo in FP64.
 template <int KIND, int RB>
 __global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
-                                              const int *__restrict__ ls,
+                                              const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
                                               const int *__restrict__ near_ptr,
                                               const int *__restrict__ near_src,
-                                              const float *__restrict__ xl, int64_t n,
+                                              const double *__restrict__ xyz, int64_t n,
                                               const double *__restrict__ sig, int nrhs,
-                                              double *__restrict__ fnear, float h, float p) {
-  __shared__ float sx[64], sy[64], sz[64], ss[64 * RB];
-  const int j = blockIdx.x, lane = threadIdx.x;
+                                              double *__restrict__ fnear, float p) {
+  __shared__ double sx[64], sy[64], sz[64];
+  __shared__ float ss[64 * RB];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int j = chunk_leaf(chunk_ptr, nleaf, c);
   const uint32_t key = act[j];
   const int a = ls[key], b = ls[key + 1];
   const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
-  const int tn0 = (int)morton_axis(key, 0), tn1 = (int)morton_axis(key, 1),
-            tn2 = (int)morton_axis(key, 2);
-  for (int t0 = a; t0 < b; t0 += 64) {
+  {  // the 64 targets of chunk c
+    const int t0 = a + 64 * (c - chunk_ptr[j]);
     const int i = t0 + lane;
     const bool tv = i < b;
-    const float xi = tv ? xl[i] : 0.f, yi = tv ? xl[n + i] : 0.f, zi = tv ? xl[2 * n + i] : 0.f;
+    const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0,
+                 zi = tv ? xyz[2 * n + i] : 0.0;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
       float sum[RB], cmp[RB];
 #pragma unroll
@@ -154,17 +174,14 @@ __global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
       for (int q = q0; q < q1; ++q) {
         const uint32_t skey = act[near_src[q]];
         const int c0 = ls[skey], c1 = ls[skey + 1];
-        const float ox = (float)((int)morton_axis(skey, 0) - tn0) * h;
-        const float oy = (float)((int)morton_axis(skey, 1) - tn1) * h;
-        const float oz = (float)((int)morton_axis(skey, 2) - tn2) * h;
         for (int s0 = c0; s0 < c1; s0 += 64) {
           const int cnt = min(64, c1 - s0);
           __syncthreads();
           if (lane < cnt) {
             const int sidx = s0 + lane;
-            sx[lane] = xl[sidx] + ox;
-            sy[lane] = xl[n + sidx] + oy;
-            sz[lane] = xl[2 * n + sidx] + oz;
+            sx[lane] = xyz[sidx];
+            sy[lane] = xyz[n + sidx];
+            sz[lane] = xyz[2 * n + sidx];
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr)
               ss[lane * RB + rr] =
@@ -172,7 +189,8 @@ __global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
           }
           __syncthreads();
           for (int u = 0; u < cnt; ++u) {
-            const float dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+            const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]),
+                        dz = (float)(zi - sz[u]);
             const float r2 = dx * dx + dy * dy + dz * dz;
             float kv = KF<KIND>::evalf(r2, p);
             if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
 // the input position of x_i (Algorithm 3, step 7).
 template <int KIND, int RB>
 __global__ __launch_bounds__(64) void k_l2p(const uint32_t *__restrict__ act,
-                                            const int *__restrict__ ls,
+                                            const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
                                             const double *__restrict__ X, int d, int dp,
                                             const double *__restrict__ lhat,
                                             const double *__restrict__ xyz, int64_t n,
@@ -283,14 +301,16 @@ __global__ __launch_bounds__(64) void k_l2p(const uint32_t *__restrict__ act,
                                             double lo2, double h, double p) {
   extern __shared__ double sm[];
   double *sX = sm, *sl = sm + 3 * dp;
-  const int j = blockIdx.x, lane = threadIdx.x;
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int j = chunk_leaf(chunk_ptr, nleaf, c);
   const uint32_t key = act[j];
   const int a = ls[key], b = ls[key + 1];
   const double cx = lo0 + ((double)morton_axis(key, 0) + 0.5) * h;
   const double cy = lo1 + ((double)morton_axis(key, 1) + 0.5) * h;
   const double cz = lo2 + ((double)morton_axis(key, 2) + 0.5) * h;
   for (int e = lane; e < 3 * d; e += 64) sX[e] = X[e];
-  for (int t0 = a; t0 < b; t0 += 64) {
+  {  // the 64 targets of chunk c
+    const int t0 = a + 64 * (c - chunk_ptr[j]);
     const int i = t0 + lane;
     const bool tv = i < b;
     const double xc = tv ? xyz[i] - cx : 0.0, yc = tv ? xyz[n + i] - cy : 0.0,
@@ -500,13 +520,16 @@ __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
   return (const T *)J.A + idx * J.a_stride;
 }
 
-// Stream-K schedule: the units of a launch are (tile, term) pairs, numbered job
-// by job, tile by tile, term by term; persistent workgroup g processes the
-// contiguous range [B_g, B_{g+1}) with B_g = floor(g U / G).  A tile covered by
-// one workgroup is written directly; the pieces of a tile split between
-// workgroups go to a workspace (slot 2g for the first tile of g, 2g + 1 for its
-// last) and k_gemm_fixup adds them in workgroup order, so the result does not
-// depend on timing.
+// Schedule (data-parallel + Stream-K): the units of a launch are (tile, term)
+// pairs numbered job by job, tile by tile, term by term.  With G persistent
+// workgroups, the first F = floor(T / G) G tiles run whole, G at a time, all
+// workgroups walking the terms in the same order (so the operators they read are
+// shared in L2); within a round the tiles of one XCD are contiguous in space.
+// The R units of the remaining tiles are split evenly: workgroup g takes
+// [S + B_g, S + B_{g+1}) with B_g = floor(g R / G) and S the first remaining
+// unit.  A tile split between workgroups is stored in pieces (slot 2g for the
+// first remaining tile of g, 2g + 1 for its last) that k_gemm_fixup adds in
+// workgroup order, so results do not depend on timing.
 __device__ inline int64_t sk_bound(int64_t g, int64_t units, int G) { return g * units / G; }
 
 __device__ inline int find_job_units(const GemmJob *__restrict__ jobs, int njobs, int64_t u) {
@@ -521,23 +544,197 @@ __device__ inline int find_job_units(const GemmJob *__restrict__ jobs, int njobs
   return lo;
 }
 
+__device__ inline int find_job_tiles(const GemmJob *__restrict__ jobs, int njobs, int tile) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tiles_start <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// terms [term0, term1) of one tile; writes the result (part == nullptr) or a piece
 template <typename T, int MODE, bool FOLD, int RBT>
-__global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
-                                                 int64_t units, int G, double *__restrict__ ws,
-                                                 const int8_t *__restrict__ dvec) {
+__device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, int term1,
+                                 double *__restrict__ part, const int8_t *__restrict__ dvec,
+                                 T (*As)[RBT * 4 * 64], T (*Bs)[4 * GT_CB * 64]) {
   typedef typename Mfma<T>::v4 V4;
   typedef typename Mfma<T>::p2 P2;
   typedef double D4 __attribute__((ext_vector_type(4)));
   constexpr int NA = RBT * 128;         // A chunk, in pairs
   constexpr int QA = (NA + 255) / 256;  // pairs per thread
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int jl = t >> 1, hh = t & 1;
+  const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
+  const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
+  const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
+  const int ncols = J.ntgt * J.nrhs;
+
+  // the column this thread loads
+  const int jc = col0 + jl;
+  const bool cvalid = jc < ncols;
+  int r = 0, tsl = 0;
+  uint32_t tkey = 0;
+  if (cvalid) {
+    const int tt = jc / J.nrhs;
+    r = jc - tt * J.nrhs;
+    tsl = J.tgt ? J.tgt[tt] : tt;
+    if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
+  }
+  V4 acc[RBT][2];
+  D4 sum[RBT][2];
+  bool rowok[RBT];
+#pragma unroll
+  for (int i = 0; i < RBT; ++i) {
+    rowok[i] = rb0 + i < nrb;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      acc[i][jj] = V4{0, 0, 0, 0};
+      if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
+    }
+  }
+  P2 ra[QA], rbv[4];
+  const T *srcp = nullptr;
+  const T *Ap = nullptr;
+  auto fetch = [&](int it) {
+    const int term = it / nkc, kc = it - term * nkc;
+    if (kc == 0) {
+      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec);
+      Ap = gemm_operand<T, MODE>(J, term);
+    }
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = t + 256 * q;  // pair index in the chunk
+      const int rb = rb0 + (e >> 7);
+      if (e < NA && rb < nrb)
+        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
+      else
+        ra[q] = P2{0, 0};
+    }
+    if (srcp) {
+      const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = t + 256 * q;
+      if (e < NA) *(P2 *)(&As[buf][2 * e]) = ra[q];
+    }
+    const int cb = jl >> 4, c16 = jl & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int kl = 8 * hh + 2 * q + e;
+        Bs[buf][((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = e ? rbv[q].y : rbv[q].x;
+      }
+    }
+  };
+
+  const int it0 = term0 * nkc, it1 = term1 * nkc;
+  if (it0 < it1) {
+    fetch(it0);
+    stash(0);
+    __syncthreads();
+  }
+  for (int it = it0; it < it1; ++it) {
+    const int cur = (it - it0) & 1;
+    if (it + 1 < it1) fetch(it + 1);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      T a[RBT], b[2];
+#pragma unroll
+      for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[cur][(ks * GT_CB + 2 * w + jj) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < RBT; ++i)
+        if (rowok[i]) {
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
+        }
+    }
+    if constexpr (FOLD) {
+      if ((it + 1) % nkc == 0) {  // a term is complete
+#pragma unroll
+        for (int i = 0; i < RBT; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
+            acc[i][jj] = V4{0, 0, 0, 0};
+          }
+      }
+    }
+    if (it + 1 < it1) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int jt = 16 * (2 * w + jj) + (lane & 15);
+    const int jo = col0 + jt;
+    if (jo >= ncols) continue;
+    const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
+    const int tso = J.tgt ? J.tgt[tt] : tt;
+    const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
+#pragma unroll
+    for (int i = 0; i < RBT; ++i) {
+      if (!rowok[i]) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rt = 16 * i + Mfma<T>::row(lane, q);
+        double v;
+        if constexpr (FOLD)
+          v = sum[i][jj][q];
+        else
+          v = (double)acc[i][jj][q];
+        if (part) {
+          part[(size_t)rt * GT_COLS + jt] = v;
+        } else {
+          const int64_t o = cbase + 16 * rb0 + rt;
+          if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
+          J.C[o] = v;
+          if (J.C32) J.C32[o] = (float)v;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int MODE, bool FOLD, int RBT>
+__global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
+                                                 int ntiles, int64_t units, int G,
+                                                 double *__restrict__ ws,
+                                                 const int8_t *__restrict__ dvec) {
   constexpr int TILE = RBT * 16 * GT_COLS;
   __shared__ T As[2][RBT * 4 * 64];
   __shared__ T Bs[2][4 * GT_CB * 64];
   const int g = blockIdx.x;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int jl = t >> 1, hh = t & 1;
-  const int64_t ua = sk_bound(g, units, G), ub = sk_bound(g + 1, units, G);
-
+  // whole tiles, G at a time; the tiles of one XCD (g mod 8) are contiguous
+  const int full = (ntiles / G) * G;
+  const int per = G / 8;
+  const int gx = (G % 8 == 0) ? (g % 8) * per + g / 8 : g;
+  for (int t0 = 0; t0 < full; t0 += G) {
+    const int tile = t0 + gx;
+    const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
+    gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, 0, J.nterms, nullptr, dvec, As, Bs);
+  }
+  if (full == ntiles) return;
+  // the remaining units, split evenly
+  const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
+  const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
+  const int64_t R = units - S;
+  const int64_t ua = S + sk_bound(g, R, G), ub = S + sk_bound(g + 1, R, G);
   for (int64_t u = ua; u < ub;) {
     const GemmJob J = jobs[find_job_units(jobs, njobs, u)];
     const int64_t local = u - J.units_start;
@@ -546,149 +743,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
     const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms;
     const int term1 = (int)(min(ts + J.nterms, ub) - ts);
     u = ts + term1;
-    const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
-    const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
-    const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
-    const int ncols = J.ntgt * J.nrhs;
-
-    // the column this thread loads
-    const int jc = col0 + jl;
-    const bool cvalid = jc < ncols;
-    int r = 0, tsl = 0;
-    uint32_t tkey = 0;
-    if (cvalid) {
-      const int tt = jc / J.nrhs;
-      r = jc - tt * J.nrhs;
-      tsl = J.tgt ? J.tgt[tt] : tt;
-      if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
-    }
-    V4 acc[RBT][2];
-    D4 sum[RBT][2];
-    bool rowok[RBT];
-#pragma unroll
-    for (int i = 0; i < RBT; ++i) {
-      rowok[i] = rb0 + i < nrb;
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        acc[i][jj] = V4{0, 0, 0, 0};
-        if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
-      }
-    }
-    P2 ra[QA], rbv[4];
-    const T *srcp = nullptr;
-    const T *Ap = nullptr;
-    auto fetch = [&](int it) {
-      const int term = it / nkc, kc = it - term * nkc;
-      if (kc == 0) {
-        srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec);
-        Ap = gemm_operand<T, MODE>(J, term);
-      }
-#pragma unroll
-      for (int q = 0; q < QA; ++q) {
-        const int e = t + 256 * q;  // pair index in the chunk
-        const int rb = rb0 + (e >> 7);
-        if (e < NA && rb < nrb)
-          ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
-        else
-          ra[q] = P2{0, 0};
-      }
-      if (srcp) {
-        const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
-      }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-      for (int q = 0; q < QA; ++q) {
-        const int e = t + 256 * q;
-        if (e < NA) *(P2 *)(&As[buf][2 * e]) = ra[q];
-      }
-      const int cb = jl >> 4, c16 = jl & 15;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int kl = 8 * hh + 2 * q + e;
-          Bs[buf][((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = e ? rbv[q].y : rbv[q].x;
-        }
-      }
-    };
-
-    const int it0 = term0 * nkc, it1 = term1 * nkc;
-    if (it0 < it1) {
-      fetch(it0);
-      stash(0);
-      __syncthreads();
-    }
-    for (int it = it0; it < it1; ++it) {
-      const int cur = (it - it0) & 1;
-      if (it + 1 < it1) fetch(it + 1);
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        T a[RBT], b[2];
-#pragma unroll
-        for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[cur][(ks * GT_CB + 2 * w + jj) * 64 + lane];
-#pragma unroll
-        for (int i = 0; i < RBT; ++i)
-          if (rowok[i]) {
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
-          }
-      }
-      if constexpr (FOLD) {
-        if ((it + 1) % nkc == 0) {  // a term is complete
-#pragma unroll
-          for (int i = 0; i < RBT; ++i)
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-#pragma unroll
-              for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
-              acc[i][jj] = V4{0, 0, 0, 0};
-            }
-        }
-      }
-      if (it + 1 < it1) stash(cur ^ 1);
-      __syncthreads();
-    }
-
     const bool whole = term0 == 0 && term1 == J.nterms;
     double *part = whole ? nullptr : ws + (size_t)(2 * g + (ua >= ts ? 0 : 1)) * TILE;
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int jt = 16 * (2 * w + jj) + (lane & 15);
-      const int jo = col0 + jt;
-      if (jo >= ncols) continue;
-      const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
-      const int tso = J.tgt ? J.tgt[tt] : tt;
-      const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
-#pragma unroll
-      for (int i = 0; i < RBT; ++i) {
-        if (!rowok[i]) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int rt = 16 * i + Mfma<T>::row(lane, q);
-          double v;
-          if constexpr (FOLD)
-            v = sum[i][jj][q];
-          else
-            v = (double)acc[i][jj][q];
-          if (part) {
-            part[(size_t)rt * GT_COLS + jt] = v;
-          } else {
-            const int64_t o = cbase + 16 * rb0 + rt;
-            if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
-            J.C[o] = v;
-            if (J.C32) J.C32[o] = (float)v;
-          }
-        }
-      }
-    }
+    gemm_tile<T, MODE, FOLD, RBT>(J, tile_local, term0, term1, part, dvec, As, Bs);
   }
 }
 
@@ -698,37 +755,33 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
                                                     int ntiles, int64_t units, int G,
                                                     const double *__restrict__ ws) {
   constexpr int TILE = RBT * 16 * GT_COLS;
-  const int tile = blockIdx.x;
+  const int full = (ntiles / G) * G;
+  const int tile = full + blockIdx.x;
   if (tile >= ntiles) return;
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].tiles_start <= tile)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const GemmJob J = jobs[lo];
+  const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
+  const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
+  const int64_t R = units - S;
+  const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
   const int tile_local = tile - J.tiles_start;
-  const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms, te = ts + J.nterms;
-  // workgroups covering [ts, te)
-  int64_t glo = ts * G / units;
-  while (glo + 1 < G && sk_bound(glo + 1, units, G) <= ts) ++glo;
-  while (glo > 0 && sk_bound(glo, units, G) > ts) --glo;
+  // unit range of the tile relative to S
+  const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms - S, te = ts + J.nterms;
+  int64_t glo = ts * G / R;
+  while (glo + 1 < G && sk_bound(glo + 1, R, G) <= ts) ++glo;
+  while (glo > 0 && sk_bound(glo, R, G) > ts) --glo;
   int64_t ghi = glo;
-  while (ghi + 1 < G && sk_bound(ghi + 1, units, G) < te) ++ghi;
+  while (ghi + 1 < G && sk_bound(ghi + 1, R, G) < te) ++ghi;
   if (ghi == glo) return;  // written directly
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
   const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
   const int ncols = J.ntgt * J.nrhs;
-  for (int e = threadIdx.x; e < RBT * 16 * GT_COLS; e += 256) {
+  for (int e = threadIdx.x; e < TILE; e += 256) {
     const int rt = e / GT_COLS, jt = e - rt * GT_COLS;
     const int jo = col0 + jt;
     if (rt >= nrows || jo >= ncols) continue;
     double v = 0.0;
     for (int64_t g = glo; g <= ghi; ++g) {
-      const int slot = (int)(2 * g + (sk_bound(g, units, G) >= ts ? 0 : 1));
+      const int slot = (int)(2 * g + (sk_bound(g, R, G) >= ts ? 0 : 1));
       v += ws[(size_t)slot * TILE + e];
     }
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
@@ -972,9 +1025,10 @@ void launch_gemm_rbt(Plan &P, int first, int n, int tiles, int64_t units, hipStr
   const int G = (int)std::min<int64_t>(units, P.sk_groups);
   constexpr bool fold = sizeof(T) == 4;
   hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, P.job_dev + first,
-                     n, units, G, P.sk_ws, P.dvec);
-  if (G > 1)
-    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(tiles), dim3(256), 0, s, P.job_dev + first, n,
+                     n, tiles, units, G, P.sk_ws, P.dvec);
+  const int rest = tiles - (tiles / G) * G;
+  if (G > 1 && rest > 0)
+    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest), dim3(256), 0, s, P.job_dev + first, n,
                        tiles, units, G, P.sk_ws);
 }
 
@@ -996,6 +1050,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
   const double kp = dev_param(KIND, P.cfg.kernel_param);
   const int64_t n = P.n;
   const int nleafa = (int)P.nact[depth];
+  const unsigned nchunk = (unsigned)P.nchunk;
   const double hleaf = std::ldexp(P.cfg.L, -depth);
   LevelDev &LL = P.ld[depth];
   // near field
@@ -1003,19 +1058,19 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_P2P);
     if (mixed) {
       if (nrhs == 1)
-        hipLaunchKernelGGL((k_p2p32<KIND, 1>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
-                           P.near_ptr, P.near_src, P.xloc, n, P.sig, nrhs, P.fnear, (float)hleaf,
-                           (float)kp);
+        hipLaunchKernelGGL((k_p2p32<KIND, 1>), dim3(nchunk), dim3(64), 0, s, LL.act,
+                           P.leaf_start, P.chunk_ptr, nleafa, P.near_ptr, P.near_src, P.xyz, n,
+                           P.sig, nrhs, P.fnear, (float)kp);
       else
-        hipLaunchKernelGGL((k_p2p32<KIND, 8>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
-                           P.near_ptr, P.near_src, P.xloc, n, P.sig, nrhs, P.fnear, (float)hleaf,
-                           (float)kp);
+        hipLaunchKernelGGL((k_p2p32<KIND, 8>), dim3(nchunk), dim3(64), 0, s, LL.act,
+                           P.leaf_start, P.chunk_ptr, nleafa, P.near_ptr, P.near_src, P.xyz, n,
+                           P.sig, nrhs, P.fnear, (float)kp);
     } else {
       if (nrhs == 1)
-        hipLaunchKernelGGL((k_p2p64<KIND, 1>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+        hipLaunchKernelGGL((k_p2p64<KIND, 1>), dim3(nchunk), dim3(64), 0, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
                            P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
       else
-        hipLaunchKernelGGL((k_p2p64<KIND, 8>), dim3(nleafa), dim3(64), 0, s, LL.act, P.leaf_start,
+        hipLaunchKernelGGL((k_p2p64<KIND, 8>), dim3(nchunk), dim3(64), 0, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
                            P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
     }
   }
@@ -1122,11 +1177,11 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     const int rb = nrhs == 1 ? 1 : 8;
     const size_t shm = sizeof(double) * (3 * (size_t)HL.dp + (size_t)rb * HL.dp);
     if (nrhs == 1)
-      hipLaunchKernelGGL((k_l2p<KIND, 1>), dim3(nleafa), dim3(64), shm, s, LL.act, P.leaf_start,
+      hipLaunchKernelGGL((k_l2p<KIND, 1>), dim3(nchunk), dim3(64), shm, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
                          LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
                          P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
     else
-      hipLaunchKernelGGL((k_l2p<KIND, 8>), dim3(nleafa), dim3(64), shm, s, LL.act, P.leaf_start,
+      hipLaunchKernelGGL((k_l2p<KIND, 8>), dim3(nchunk), dim3(64), shm, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
                          LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
                          P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
   }

@@ -103,7 +103,6 @@ struct Plan {
   int64_t n = 0;
   int ntiles_sort = 0;
   double *xyz = nullptr;        // sorted points, SoA 3 x n
-  float *xloc = nullptr;        // leaf-local FP32 coordinates, SoA 3 x n
   uint32_t *keys = nullptr, *keys_tmp = nullptr;
   int *idx = nullptr, *idx_tmp = nullptr;  // idx = perm after the sort
   unsigned *hist = nullptr;
@@ -116,6 +115,8 @@ struct Plan {
   int *near_ptr = nullptr;      // leaf level near lists (CSR over active slots)
   int *near_src = nullptr;      // source leaf slots
   size_t near_cap = 0;
+  int *chunk_ptr = nullptr;     // per active leaf: first 64-target chunk (prefix sum)
+  int64_t nchunk = 0;           // number of 64-target chunks over all leaves
   bool points_set = false;
   int64_t nact[kMaxLevels] = {0};
   int64_t cls_off[kMaxLevels][9] = {{0}};

@@ -115,20 +115,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *__restrict
 
 // ---------------------------------------------------------------- gather
 __global__ void k_gather_points(int64_t n, const double *__restrict__ xin,
-                                const int *__restrict__ perm, const uint32_t *__restrict__ keys,
-                                double *__restrict__ xs, float *__restrict__ xl, double lo0,
-                                double lo1, double lo2, double h) {
+                                const int *__restrict__ perm, double *__restrict__ xs) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
-  const uint32_t key = keys[s];
-  const double lo[3] = {lo0, lo1, lo2};
-  for (int a = 0; a < 3; ++a) {
-    double x = xin[a * n + i];
-    xs[a * n + s] = x;
-    double c = lo[a] + ((double)morton_axis(key, a) + 0.5) * h;
-    xl[a * n + s] = (float)(x - c);
-  }
+  for (int a = 0; a < 3; ++a) xs[a * n + s] = xin[a * n + i];
 }
 
 // leaf_start[k] = first sorted position with key >= k, k = 0..nleaf
@@ -153,6 +144,20 @@ __device__ inline bool box_active(const int *__restrict__ ls, int shift, int64_t
 }
 
 // per block of 256 boxes: active count per child class and in total
+// number of 64-target chunks of each active leaf; 0 past the active count
+__global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict__ act,
+                                                     const int *__restrict__ ls, int nact,
+                                                     int64_t len, int *__restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  int c = 0;
+  if (j < nact) {
+    const uint32_t key = act[j];
+    c = (ls[key + 1] - ls[key] + 63) >> 6;
+  }
+  cnt[j] = c;
+}
+
 __global__ __launch_bounds__(256) void k_act_count(const int *__restrict__ ls, int shift,
                                                    int64_t nb, int *__restrict__ blkcnt) {
   __shared__ int c[9];
@@ -422,8 +427,7 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
                        P.errflag);
     sort_points(P, s);
     hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       xyz_in, P.idx, P.keys, P.xyz, P.xloc, P.cfg.lo[0], P.cfg.lo[1],
-                       P.cfg.lo[2], std::ldexp(P.cfg.L, -depth));
+                       xyz_in, P.idx, P.xyz);
   }
   const int64_t nleaf = (int64_t)1 << (3 * depth);
   hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s, n,
@@ -455,11 +459,21 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   int64_t tot = build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, s);
   if (tot < 0) return EIFMM_ENOMEM;
   P.near_total = tot;
+  // 64-target chunks of the leaves (the grid of the near-field and L2P kernels)
+  {
+    const int64_t cap = P.ld[depth].cap;
+    hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, s,
+                       P.ld[depth].act, P.leaf_start, (int)P.nact[depth], cap + 1, P.list_cnt);
+    scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
+  }
+  int nchunk = 0;
+  hipMemcpyAsync(&nchunk, P.chunk_ptr + P.nact[depth], sizeof(int), hipMemcpyDeviceToHost, s);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     P.last_hip_error = (int)e;
     return EIFMM_EHIP;
   }
+  P.nchunk = nchunk;
   return EIFMM_OK;
 }
 

@@ -56,6 +56,7 @@ TREE_CASES = {
     "uniform500_d0": lambda: (W.uniform_points(500, 33), 0),
     "uniform500_d1": lambda: (W.uniform_points(500, 34), 1),
     "uniform100k_d5": lambda: (W.uniform_points(100_000, 35), 5),
+    "cluster1m_d5": lambda: (W.make_points(W.WORKLOADS["cluster1m_yukawa"]), 5),
 }
 
 
@@ -115,6 +116,22 @@ def test_near_field_only(E, torch_dev, oracle_lib):
         plan, f = _gpu_eval(E, torch_dev, "laplace", 0, x, s, depth, 1e-6)
         assert _rel(f, oracle_lib.direct("laplace", 0, x, x, s)) < 1e-13
         plan.close()
+
+
+def test_crowded_leaves_vs_oracle(E, torch_dev, oracle_lib):
+    """One tight cluster at depth 2: leaves of thousands of points, split into many
+    64-target chunks (ragged last chunk) by the near-field and L2P kernels."""
+    x = W.cluster_points(20000, 1, 0.05, 91, 92)
+    s = W.potentials(20000, 93)
+    plan, f = _gpu_eval(E, torch_dev, "laplace", 0, x, s, 2, 1e-6)
+    O = oracle_lib.Plan("laplace", 0, [0, 0, 0], 1.0, 2, 1e-6)
+    assert _rel(f, O.evaluate(x, s)) < 1e-10
+    fd = oracle_lib.direct("laplace", 0, x, x, s)
+    assert _rel(f, fd) < 1e-6
+    plan.close()
+    plan, f = _gpu_eval(E, torch_dev, "laplace", 0, x, s, 2, 1e-6, precision="mixed")
+    assert _rel(f, fd) < 1e-6
+    plan.close()
 
 
 def test_c1_fp64_vs_oracle(E, torch_dev, c1_inputs, c1_plan, c1_direct):
