@@ -15,7 +15,9 @@ Also reported on the same line:
                 sample of targets (all N sources), whose values also give the
                 sampled rel-L2 error of the GPU result;
   batched_mixed the many-query variant: 2^20 points, 64 sigma vectors, M2L on
-                FP32 MFMA (mixed precision), tree built once, per-RHS rate.
+                FP32 MFMA (mixed precision), tree built once, per-RHS rate;
+  clustered     1e6 points in 16 Gaussian clusters with exp(-r)/r, FP64 and
+                mixed passes, rate and sampled error of each.
 """
 import argparse
 import json
@@ -65,23 +67,26 @@ def cpu_baseline(kernel, param, x, s, gpu_f, target_seconds=10.0):
                        f"({dt:.1f} s), rate scaled to N^2/t"), err, idx, ref
 
 
-def run_plain(args):
+def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data=None):
     import torch
     from paper_1408_0210_amd import eifmm as E
     from paper_1408_0210_amd import workloads as W
-    w = dict(W.WORKLOADS[args.workload])
+    w = dict(W.WORKLOADS[workload or args.workload])
+    precision = precision or args.precision
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
     tau = args.tau if args.tau else w["tau"]
-    x, s = W.make_points(w), W.make_sigma(w)
+    x, s = data if data is not None else (W.make_points(w), W.make_sigma(w))
     n = w["n"]
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], tau,
-                  precision=args.precision, compress_tol=args.compress_tol)
+                  precision=precision, compress_tol=args.compress_tol)
     setup_s = time.perf_counter() - t0
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(s).to(dev)
     f = torch.empty_like(sd)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.set_points(xd)
         plan.evaluate(sd, out=f)
     _sync()
@@ -89,16 +94,43 @@ def run_plain(args):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     _sync()
     ev0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.set_points(xd)
         plan.evaluate(sd, out=f)
     ev1.record()
     _sync()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = ev0.elapsed_time(ev1) / steps
     st = plan.stats()
     plan.set_timing(False)
     fh = f.cpu().numpy()
     return dict(w=w, tau=tau, n=n, ms=ms, stats=st, setup_s=setup_s, f=fh, x=x, s=s, plan=plan)
+
+
+def run_clustered(args):
+    """1e6 points in 16 Gaussian clusters, exp(-r)/r, depth 5: FP64 pass and mixed
+    pass, each timed like the main run, with the sampled error of both."""
+    import oracle
+    from paper_1408_0210_amd import workloads as W
+    name = "cluster1m_yukawa"
+    w = W.WORKLOADS[name]
+    data = (W.make_points(w), W.make_sigma(w))
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(w["n"], 1000, replace=False))
+    ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
+                        threads=min(os.cpu_count() or 1, 16))
+    out = {"workload": name, "n": w["n"], "depth": w["depth"], "kernel": w["kernel"],
+           "param": w["param"], "tau": w["tau"], "compress_tol": args.compress_tol}
+    for prec in ("fp64", "mixed"):
+        r = run_plain(args, workload=name, precision=prec, steps=3, warmup=1, data=data)
+        st = r["stats"]
+        out[prec] = {"value": float(w["n"]) ** 2 / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                     "rel_l2_sampled": _rel_sample(r["f"], idx, ref),
+                     "phase_ms": {k: st["phase_ms"][k] / max(1, st["phase_calls"][k])
+                                  for k in ("tree", "p2p", "m2l", "l2p")},
+                     "near_pairs_leaf_lists": st["near_pairs"]}
+        r["plan"].close()
+    out["note"] = "step = set_points + evaluate; errors on 1000 sampled targets"
+    return out
 
 
 def run_batched(args):
@@ -159,6 +191,8 @@ def main():
     ap.add_argument("--tau", type=float, default=0.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS mixed run")
+    ap.add_argument("--no-clustered", action="store_true",
+                    help="skip the clustered exp(-r)/r run (FP64 and mixed)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--compress-tol", type=float, default=1e-6,
@@ -193,10 +227,14 @@ def main():
         import hashlib
         tr = json.load(open(PROFILE_TRAFFIC))
         key = f"{args.workload}:{args.precision}"
-        src = os.path.join(ROOT, "paper_1408_0210_amd", "csrc", "pass.hip")
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        # counters taken on another version of the kernels do not describe this one
-        if key in tr and tr[key].get("valid", False) and tr[key].get("source_sha256") == cur:
+        src = open(os.path.join(ROOT, "paper_1408_0210_amd", "csrc", "pass.hip")).read()
+        # the gathered-GEMM kernel source (M2L runs in it): counters taken on another
+        # version of this kernel do not describe it
+        a = src.index("// ------------------------------------------------------------------ gathered GEMM")
+        b = src.index("// ------------------------------------------------------------------ host side")
+        cur = hashlib.sha256(src[a:b].encode()).hexdigest()
+        if (key in tr and tr[key].get("valid", False) and tr[key].get("gemm_source_sha256") == cur
+                and abs(args.compress_tol - 1e-6) < 1e-18 and not args.tau):
             traffic = tr[key]["bytes_per_launch"]
     phases = {k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]}
     out = {
@@ -221,6 +259,8 @@ def main():
     r["plan"].close()
     if not args.no_batched:
         out["batched_mixed"] = run_batched(args)
+    if not args.no_clustered:
+        out["clustered"] = run_clustered(args)
     print(json.dumps(out), flush=True)
 
 
