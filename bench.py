@@ -17,7 +17,10 @@ Also reported on the same line:
   batched_mixed the many-query variant: 2^20 points, 64 sigma vectors, M2L on
                 FP32 MFMA (mixed precision), tree built once, per-RHS rate;
   clustered     1e6 points in 16 Gaussian clusters with exp(-r)/r, FP64 and
-                mixed passes, rate and sampled error of each.
+                mixed passes, rate and sampled error of each;
+  uneven_batch  256 independent problems of uneven size in one fused,
+                graph-replayed batch: sum N_p^2 / t, against the same problems
+                evaluated one after another.
 """
 import argparse
 import json
@@ -181,6 +184,71 @@ def run_batched(args):
                 note="tree built once; t covers evaluate of 64 RHS; value = 64 N^2 / t")
 
 
+def run_uneven(args):
+    """256 independent problems of uneven size (N log-uniform in [1e3, 2e5], uniform
+    or clustered, 1/r or exp(-r^2/0.01)) as one batch: depths autotuned, fused
+    launches replayed from a HIP graph; value = sum N_p^2 / t, t = one evaluation
+    of every problem (trees built once).  Also the same work unfused (each
+    problem's own pass, one after another)."""
+    import torch
+    import oracle
+    from paper_1408_0210_amd import eifmm as E
+    from paper_1408_0210_amd import workloads as W
+    dev = torch.device("cuda:0")
+    probs = W.uneven_batch()
+    for q in probs:
+        q.update(W.BATCH_TOLERANCES[q["kernel"]], depth=None)
+    t0 = time.perf_counter()
+    B = E.Batch(probs, precision=args.batch_precision)
+    xs = [torch.from_numpy(q["points"]).to(dev) for q in probs]
+    B.set_points(xs)
+    prep_s = time.perf_counter() - t0
+    ss = [torch.from_numpy(q["sigma"]).to(dev) for q in probs]
+    out = [torch.empty_like(t) for t in ss]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        B.evaluate(ss, out)
+    _sync()
+    reps = 5
+    ev0.record()
+    for _ in range(reps):
+        B.evaluate(ss, out)
+    ev1.record()
+    _sync()
+    ms = ev0.elapsed_time(ev1) / reps
+    F = [f.cpu().numpy() for f in out]
+    uo = [torch.empty_like(t) for t in ss]
+    B.evaluate_unfused(ss, uo)
+    _sync()
+    ev0.record()
+    for _ in range(2):
+        B.evaluate_unfused(ss, uo)
+    ev1.record()
+    _sync()
+    ms_unfused = ev0.elapsed_time(ev1) / 2
+    info = B.info()
+    depths = [B.stats(p)["depth"] for p in range(len(probs))]
+    B.close()
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for p, q in enumerate(probs):
+        idx = np.sort(rng.choice(q["n"], min(50, q["n"]), replace=False))
+        fd = oracle.direct(q["kernel"], q["param"], q["points"][:, idx].copy(), q["points"],
+                           q["sigma"], threads=min(os.cpu_count() or 1, 16))
+        worst = max(worst, _rel_sample(F[p], idx, fd))
+    sn2 = float(sum(float(q["n"]) ** 2 for q in probs))
+    return dict(value=sn2 / (ms * 1e-3), unit="interactions/s", nprob=len(probs),
+                sum_n=int(sum(q["n"] for q in probs)), sum_n2=sn2, ms_per_step=ms,
+                ms_unfused=ms_unfused, unfused_value=sn2 / (ms_unfused * 1e-3),
+                precision=args.batch_precision, graph_nodes=info["graph_nodes"],
+                m2l_rbt=info["m2l_rbt"], ntables=info["ntables"],
+                setup_s=info["setup_ms"] / 1e3, tune_s=info["tune_ms"] / 1e3,
+                prepare_s=prep_s, depth_hist={str(k): depths.count(k) for k in sorted(set(depths))},
+                rel_l2_sampled_max=worst, tolerances=W.BATCH_TOLERANCES,
+                note="value = sum N_p^2 / t; t = one graph replay of the fused pass over all "
+                     "256 problems (trees built once); errors on 50 sampled targets per problem")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +261,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS mixed run")
     ap.add_argument("--no-clustered", action="store_true",
                     help="skip the clustered exp(-r)/r run (FP64 and mixed)")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the batch of 256 uneven problems")
+    ap.add_argument("--batch-precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--compress-tol", type=float, default=1e-6,
@@ -261,6 +332,8 @@ def main():
         out["batched_mixed"] = run_batched(args)
     if not args.no_clustered:
         out["clustered"] = run_clustered(args)
+    if not args.no_uneven:
+        out["uneven_batch"] = run_uneven(args)
     print(json.dumps(out), flush=True)
 
 

@@ -192,6 +192,81 @@ int eifmm_export_expansion(eifmm_plan plan, int32_t which, int32_t k, int32_t rh
 /* Releases the plan and all its device memory. */
 int eifmm_plan_destroy(eifmm_plan plan);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems, each the paper's problem (Sec. 1: its own points,
+ * sigma, N, kernel and depth), evaluated together.  Every step of Algorithm 3
+ * and the near field runs as one launch over all problems (once per kernel
+ * kind for the leaf-level steps); the resulting fixed launch sequence is
+ * captured once into a HIP graph and replayed by eifmm_batch_evaluate.
+ *
+ * Problems whose configurations agree on kernel, kernel_param, lo, L, eim_tol,
+ * tol_mode, dmax, compress_tol and precision share one set of level tables
+ * (Algorithm 1 and the operators of Sec. 3 and 4 depend on nothing else),
+ * built down to the deepest level any of them may use; with tol_mode 1 the
+ * absolute scale is that deepest level's.  All problems of a batch use one
+ * precision; max_rhs must be 1; depth is 2..EIFMM_MAX_DEPTH, or -1 to let the
+ * autotuner of eifmm_batch_set_points choose it.  A batch is not thread-safe. */
+typedef struct eifmm_batch_s *eifmm_batch;
+
+typedef struct {
+  int32_t struct_size;  /* sizeof(eifmm_batch_info)                          */
+  int32_t nprob;        /* problems                                          */
+  int32_t ntables;      /* distinct level-table sets                         */
+  int32_t graph_nodes;  /* nodes of the captured graph (0 before the first
+                           evaluation after set_points)                      */
+  int32_t m2l_rbt;      /* chosen M2L tile height, in 16-row MFMA blocks     */
+  int32_t reserved0;
+  double m2l_flops;     /* 2 r_k^2 per interaction pair, summed over problems */
+  double tune_ms;       /* host time spent autotuning (depths, M2L tiles)    */
+  double setup_ms;      /* host time of eifmm_batch_create (tables)          */
+  double reserved[4];
+} eifmm_batch_info;
+
+/* cfgs: nprob configurations (host memory, copied; n may be 0).  Builds and
+ * uploads the shared level tables.  Errors as eifmm_plan_create, and
+ * EIFMM_EINVAL for nprob < 1, differing precisions, max_rhs != 1, the host-only
+ * flag, or depth outside {-1, 2..EIFMM_MAX_DEPTH}.  On error *out is NULL. */
+int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out);
+
+/* xyz[p]: device pointer to problem p's 3 x n_p SoA points (may be NULL when
+ * n_p = 0).  Builds every tree (synchronises the host with `stream`, like
+ * eifmm_set_points).  At the first call, a problem with depth -1 gets, among
+ * the depths around log8(n_p / 32) (at most 4 of them, within 2..8), the one
+ * whose evaluation runs fastest here; later calls keep it.  The first call also
+ * times the fused M2L launch with tiles of 4, 5 and 6 MFMA row blocks and keeps
+ * the fastest.  Drops the captured graph.  Errors as eifmm_set_points; after
+ * an error the batch must get points again before evaluating. */
+int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream);
+
+/* sigma[p], f[p]: device pointers to n_p doubles each, input order (f is
+ * overwritten).  Copies the pointer table to the device on `stream` and
+ * replays the graph of the fused pass there (capturing it at the first call
+ * after set_points).  Asynchronous.  EIFMM_ESTATE before set_points, EIFMM_EHIP
+ * if capture or launch fails. */
+int eifmm_batch_evaluate(eifmm_batch b, const double *const *sigma, double *const *f,
+                         void *stream);
+
+/* The same results without fusion or graph: each problem's own pass, one
+ * after another on `stream` (the launches eifmm_evaluate makes).  For
+ * measuring what the fused launches and the graph save, and for debugging. */
+int eifmm_batch_evaluate_unfused(eifmm_batch b, const double *const *sigma, double *const *f,
+                                 void *stream);
+
+/* eifmm_export_expansion for problem p of the batch (right-hand side 0) after
+ * an evaluation, fused or not. */
+int eifmm_batch_export_expansion(eifmm_batch b, int32_t p, int32_t which, int32_t k,
+                                 double *out);
+
+/* Statistics of problem p (depth in use, d_k, ranks, counts, setup time of
+ * its table set); EIFMM_EINVAL before its first set_points. */
+int eifmm_batch_get_stats(eifmm_batch b, int32_t p, eifmm_stats *out);
+
+/* Batch-wide information (out->struct_size must be set). */
+int eifmm_batch_get_info(eifmm_batch b, eifmm_batch_info *out);
+
+/* Releases the batch, its plans, tables, graph and device memory. */
+int eifmm_batch_destroy(eifmm_batch b);
+
 /* Static description of a status code. */
 const char *eifmm_status_str(int status);
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -81,18 +82,26 @@ void release(eifmm_plan h) {
   delete h;
 }
 
-int device_setup(eifmm_plan h) {
-  Plan &P = h->P;
-  auto &tr = owned(h);
-  const int depth = P.depth;
-  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
-  const int64_t n = P.n;
-  const int R = P.cfg.max_rhs;
-  int st;
+int stream_k_groups(int device) {
+  int cus = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  return std::max(8, 2 * cus);
+}
+
+size_t stream_k_ws_len(int groups) { return (size_t)2 * groups * 6 * 16 * 128; }
+
 #define TRY(x)            \
   do {                    \
     if ((st = (x)) != 0) return st; \
   } while (0)
+
+// device copies of the plan's tables (offset lists, per-level operators)
+int setup_tables(eifmm_plan h) {
+  Plan &P = h->P;
+  auto &tr = owned(h);
+  const int depth = P.depth;
+  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
+  int st;
   // offset tables: 316 offsets, per-class lists of 189 (Sec. 3.3.2), code -> id
   {
     std::vector<int8_t> dvec(3 * kNumOffsets);
@@ -145,6 +154,19 @@ int device_setup(eifmm_plan h) {
       TRY(upload(&D.utfrag, H.utfrag.data(), H.utfrag.size(), tr));
     }
   }
+  return EIFMM_OK;
+}
+
+// per-query workspaces of a plan: points, tree, lists, expansions; sk_ws, when
+// given, is a Stream-K workspace shared with other plans of a batch
+int setup_workspaces(eifmm_plan h, double *shared_ws) {
+  Plan &P = h->P;
+  auto &tr = owned(h);
+  const int depth = P.depth;
+  const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
+  const int64_t n = P.n;
+  const int R = P.cfg.max_rhs;
+  int st;
   // point workspaces
   const int64_t nn = std::max<int64_t>(n, 1);
   P.ntiles_sort = (int)((nn + 1023) / 1024);
@@ -197,16 +219,156 @@ int device_setup(eifmm_plan h) {
     else
       TRY(dalloc(&D.l, m, tr));
   }
-  {
-    int cus = 0;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
-    P.sk_groups = std::max(8, 2 * cus);
-    TRY(dalloc(&P.sk_ws, (size_t)2 * P.sk_groups * 6 * 16 * 128, tr));
-  }
+  P.sk_groups = stream_k_groups(P.device);
+  if (shared_ws)
+    P.sk_ws = shared_ws;
+  else
+    TRY(dalloc(&P.sk_ws, stream_k_ws_len(P.sk_groups), tr));
   if (depth >= 2)
     TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dp, tr));
 #undef TRY
   return EIFMM_OK;
+}
+
+}  // namespace
+
+struct eifmm_batch_s {
+  std::vector<eifmm_config> cfg;     // as given (depth -1: autotuned)
+  std::vector<int> depth;            // depth in use per problem (-1 until chosen)
+  std::vector<eifmm_plan> plans;     // one per problem, sharing the level tables
+  std::vector<eifmm_plan> tables;    // one per distinct table key
+  std::vector<int> table_of;         // problem -> tables index
+  BatchExec ex;
+  bool ready = false;
+  int m2l_rbt = 0;                   // 0 until tuned
+  int device = 0;
+  int sk_groups = 0;
+  double *sk_ws = nullptr;           // Stream-K workspace shared by every launch
+  double *scratch = nullptr;         // zero sigma and f for the autotuning runs
+  int64_t scratch_n = 0;
+  IoDesc *staging = nullptr;         // pinned host copy of the pointer table
+  hipEvent_t staged = nullptr;
+  hipStream_t cap = nullptr;         // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_nodes = 0;
+  double tune_ms = 0, setup_ms = 0;
+};
+
+namespace {
+
+bool same_tables(const eifmm_config &a, const eifmm_config &b) {
+  return a.kernel == b.kernel && a.kernel_param == b.kernel_param && a.lo[0] == b.lo[0] &&
+         a.lo[1] == b.lo[1] && a.lo[2] == b.lo[2] && a.L == b.L && a.eim_tol == b.eim_tol &&
+         a.tol_mode == b.tol_mode && a.dmax == b.dmax && a.compress_tol == b.compress_tol &&
+         a.precision == b.precision;
+}
+
+// depths the autotuner tries for n points: around log8(n / 32), within 2..8
+void depth_candidates(int64_t n, int &lo, int &hi) {
+  const double c = std::log(std::max<double>((double)n, 1.0) / 32.0) / std::log(8.0);
+  const int k0 = (int)std::lround(c);
+  lo = std::max(2, std::min(EIFMM_MAX_DEPTH, k0 - 1));
+  hi = std::max(lo, std::min(EIFMM_MAX_DEPTH, k0 + 2));
+}
+
+// a plan of problem p at `depth` that uses the batch's level tables
+int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
+  const Plan &T = b->tables[b->table_of[p]]->P;
+  eifmm_plan h = new (std::nothrow) eifmm_plan_s();
+  if (!h) return EIFMM_ENOMEM;
+  Plan &P = h->P;
+  P.cfg = b->cfg[p];
+  P.cfg.depth = depth;
+  P.depth = depth;
+  P.n = P.cfg.n;
+  P.max_rhs = 1;
+  P.device = T.device;
+  P.setup_ms = 0;
+  for (int k = 2; k <= depth; ++k) {
+    LevelHost &H = P.lh[k];
+    const LevelHost &TH = T.lh[k];
+    H.d = TH.d;
+    H.dp = TH.dp;
+    H.scale = TH.scale;
+    H.err = TH.err;
+    H.r = TH.r;
+    H.rp = TH.rp;
+    LevelDev &D = P.ld[k];
+    const LevelDev &TD = T.ld[k];
+    D.kfrag = TD.kfrag;
+    D.kfrag32 = TD.kfrag32;
+    D.m2m = TD.m2m;
+    D.l2l = TD.l2l;
+    for (int q = 0; q < 4; ++q) D.tri[q] = TD.tri[q];
+    D.X = TD.X;
+    D.ufrag = TD.ufrag;
+    D.utfrag = TD.utfrag;
+  }
+  P.dvec = T.dvec;
+  P.code2id = T.code2id;
+  P.dlist = T.dlist;
+  int st = setup_workspaces(h, b->sk_ws);
+  if (st) {
+    release(h);
+    return st;
+  }
+  *out = h;
+  return EIFMM_OK;
+}
+
+void drop_graph(eifmm_batch b) {
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_nodes = 0;
+}
+
+// copy the pointer table (descriptor order) to the device, on stream s
+int stage_io(eifmm_batch b, const double *const *sigma, double *const *f, hipStream_t s) {
+  if (hipEventSynchronize(b->staged) != hipSuccess) return EIFMM_EHIP;
+  const BatchExec &B = b->ex;
+  for (int q = 0; q < B.nprob; ++q) {
+    const int p = B.order[q];
+    const int64_t n = b->cfg[p].n;
+    b->staging[q] = IoDesc{sigma ? sigma[p] : b->scratch, n, f ? f[p] : b->scratch + b->scratch_n, n};
+  }
+  if (hipMemcpyAsync(B.io_dev, b->staging, sizeof(IoDesc) * B.nprob, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return EIFMM_EHIP;
+  hipEventRecord(b->staged, s);
+  return EIFMM_OK;
+}
+
+int prepare(eifmm_batch b, int rbt) {
+  std::vector<Plan *> pl;
+  for (auto h : b->plans) pl.push_back(&h->P);
+  return batch_prepare(b->ex, pl, rbt, b->sk_groups, b->sk_ws);
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t c) {
+  float ms = 0;
+  hipEventSynchronize(c);
+  hipEventElapsedTime(&ms, a, c);
+  return ms;
+}
+
+void batch_free(eifmm_batch b) {
+  if (!b) return;
+  hipDeviceSynchronize();
+  drop_graph(b);
+  for (auto h : b->plans)
+    if (h) release(h);
+  for (auto h : b->tables)
+    if (h) release(h);
+  batch_release(b->ex);
+  if (b->sk_ws) hipFree(b->sk_ws);
+  if (b->scratch) hipFree(b->scratch);
+  if (b->staging) hipHostFree(b->staging);
+  if (b->staged) hipEventDestroy(b->staged);
+  if (b->cap) hipStreamDestroy(b->cap);
+  delete b;
 }
 
 }  // namespace
@@ -228,7 +390,8 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   st = build_tables(P);
   if (st == EIFMM_OK && !P.host_only) {
     hipGetDevice(&P.device);
-    st = device_setup(h);
+    st = setup_tables(h);
+    if (st == EIFMM_OK) st = setup_workspaces(h, nullptr);
     if (st == EIFMM_OK) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) st = EIFMM_EHIP;
@@ -433,6 +596,269 @@ int eifmm_plan_destroy(eifmm_plan h) {
     hipDeviceSynchronize();
   }
   release(h);
+  return EIFMM_OK;
+}
+
+int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out) {
+  if (!out || !cfgs || nprob < 1) return EIFMM_EINVAL;
+  *out = nullptr;
+  for (int p = 0; p < nprob; ++p) {
+    eifmm_config c = cfgs[p];
+    if (c.depth == -1) c.depth = 2;
+    int st = validate(&c);
+    if (st) return st;
+    if (c.depth < 2 || c.max_rhs != 1 || (c.flags & EIFMM_FLAG_HOST_ONLY) ||
+        c.precision != cfgs[0].precision)
+      return EIFMM_EINVAL;
+  }
+  eifmm_batch b = new (std::nothrow) eifmm_batch_s();
+  if (!b) return EIFMM_ENOMEM;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipGetDevice(&b->device);
+  b->cfg.assign(cfgs, cfgs + nprob);
+  b->depth.assign(nprob, -1);
+  b->plans.assign(nprob, nullptr);
+  b->table_of.assign(nprob, -1);
+  int st = EIFMM_OK;
+  // one table set per key, down to the deepest level any of its problems may use
+  std::vector<int> kmax, rep;  // per table set: deepest level, a problem that uses it
+  int64_t nmax = 1;
+  for (int p = 0; p < nprob; ++p) {
+    const eifmm_config &c = b->cfg[p];
+    nmax = std::max<int64_t>(nmax, c.n);
+    int lo = c.depth, hi = c.depth;
+    if (c.depth < 0) depth_candidates(c.n, lo, hi);
+    int t = -1;
+    for (size_t q = 0; q < rep.size() && t < 0; ++q)
+      if (same_tables(b->cfg[rep[q]], c)) t = (int)q;
+    if (t < 0) {
+      t = (int)rep.size();
+      rep.push_back(p);
+      kmax.push_back(hi);
+    }
+    kmax[t] = std::max(kmax[t], hi);
+    b->table_of[p] = t;
+  }
+  for (size_t t = 0; t < rep.size() && !st; ++t) {
+    const int p = rep[t];
+    eifmm_plan h = new (std::nothrow) eifmm_plan_s();
+    if (!h) {
+      st = EIFMM_ENOMEM;
+      break;
+    }
+    b->tables.push_back(h);
+    Plan &P = h->P;
+    P.cfg = b->cfg[p];
+    P.cfg.depth = kmax[t];
+    P.cfg.n = 0;
+    P.depth = kmax[t];
+    P.n = 0;
+    P.max_rhs = 1;
+    P.device = b->device;
+    st = build_tables(P);
+    if (!st) st = setup_tables(h);
+  }
+  if (!st) {
+    b->sk_groups = stream_k_groups(b->device);
+    if (hipMalloc(&b->sk_ws, sizeof(double) * stream_k_ws_len(b->sk_groups)) != hipSuccess)
+      st = EIFMM_ENOMEM;
+  }
+  if (!st) {
+    b->scratch_n = nmax;
+    if (hipMalloc(&b->scratch, sizeof(double) * 2 * nmax) != hipSuccess ||
+        hipMemset(b->scratch, 0, sizeof(double) * 2 * nmax) != hipSuccess)
+      st = EIFMM_ENOMEM;
+  }
+  if (!st && (hipHostMalloc((void **)&b->staging, sizeof(IoDesc) * nprob) != hipSuccess ||
+              hipEventCreate(&b->staged) != hipSuccess || hipStreamCreate(&b->cap) != hipSuccess))
+    st = EIFMM_EHIP;
+  if (!st && hipDeviceSynchronize() != hipSuccess) st = EIFMM_EHIP;
+  if (st) {
+    hipGetLastError();
+    batch_free(b);
+    return st;
+  }
+  b->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                    .count();
+  *out = b;
+  return EIFMM_OK;
+}
+
+int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream) {
+  if (!b || !xyz) return EIFMM_EINVAL;
+  const int np = (int)b->cfg.size();
+  for (int p = 0; p < np; ++p)
+    if (b->cfg[p].n > 0 && !xyz[p]) return EIFMM_EINVAL;
+  hipSetDevice(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  b->ready = false;
+  drop_graph(b);
+  const auto t0 = std::chrono::steady_clock::now();
+  bool tuned = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  int st = EIFMM_OK;
+  for (int p = 0; p < np && !st; ++p) {
+    const eifmm_config &c = b->cfg[p];
+    if (b->plans[p]) {
+      st = eifmm_set_points(b->plans[p], xyz[p], s);
+      continue;
+    }
+    if (c.depth >= 0) {
+      if (!(st = shared_plan(b, p, c.depth, &b->plans[p])))
+        st = eifmm_set_points(b->plans[p], xyz[p], s);
+      b->depth[p] = c.depth;
+      continue;
+    }
+    // autotune the depth: time the evaluation (tree fixed) at every candidate
+    tuned = true;
+    int lo, hi;
+    depth_candidates(c.n, lo, hi);
+    double best = 0;
+    for (int k = lo; k <= hi && !st; ++k) {
+      eifmm_plan h = nullptr;
+      if ((st = shared_plan(b, p, k, &h))) break;
+      st = eifmm_set_points(h, xyz[p], s);
+      double *sg = b->scratch, *fo = b->scratch + b->scratch_n;
+      const int64_t ld = std::max<int64_t>(c.n, 1);
+      if (!st) st = eifmm_evaluate(h, sg, 1, ld, fo, ld, s);
+      hipEventRecord(e0, s);
+      for (int rep = 0; rep < 2 && !st; ++rep) st = eifmm_evaluate(h, sg, 1, ld, fo, ld, s);
+      hipEventRecord(e1, s);
+      const double ms = st ? 0 : elapsed_ms(e0, e1);
+      if (!st && (!b->plans[p] || ms < best)) {
+        if (b->plans[p]) release(b->plans[p]);
+        b->plans[p] = h;
+        b->depth[p] = k;
+        best = ms;
+      } else {
+        release(h);
+      }
+    }
+  }
+  if (!st) st = prepare(b, b->m2l_rbt);
+  if (!st && b->m2l_rbt == 0) {
+    // tile height of the fused M2L launch: one full pass to fill the expansions,
+    // then the M2L launch alone for 4, 5 and 6 row blocks
+    tuned = true;
+    st = stage_io(b, nullptr, nullptr, s);
+    if (!st) batch_run(b->ex, s);
+    double best = 0;
+    int pick = 6;
+    for (int rbt = 4; rbt <= 6 && !st; ++rbt) {
+      if ((st = prepare(b, rbt))) break;
+      batch_run_m2l(b->ex, s);
+      hipEventRecord(e0, s);
+      for (int rep = 0; rep < 3; ++rep) batch_run_m2l(b->ex, s);
+      hipEventRecord(e1, s);
+      const double ms = elapsed_ms(e0, e1);
+      if (rbt == 4 || ms < best) {
+        best = ms;
+        pick = rbt;
+      }
+    }
+    b->m2l_rbt = pick;
+    if (!st) st = prepare(b, pick);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!st) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = EIFMM_EHIP;
+  }
+  if (tuned)
+    b->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                      .count();
+  if (st) return st;
+  b->ready = true;
+  return EIFMM_OK;
+}
+
+int eifmm_batch_evaluate(eifmm_batch b, const double *const *sigma, double *const *f,
+                         void *stream) {
+  if (!b || !sigma || !f) return EIFMM_EINVAL;
+  if (!b->ready) return EIFMM_ESTATE;
+  const int np = (int)b->cfg.size();
+  for (int p = 0; p < np; ++p)
+    if (b->cfg[p].n > 0 && (!sigma[p] || !f[p])) return EIFMM_EINVAL;
+  hipSetDevice(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  int st = stage_io(b, sigma, f, s);
+  if (st) return st;
+  if (!b->gexec) {
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return EIFMM_EHIP;
+    batch_run(b->ex, b->cap);
+    if (hipStreamEndCapture(b->cap, &b->graph) != hipSuccess) {
+      hipGetLastError();
+      b->graph = nullptr;
+      return EIFMM_EHIP;
+    }
+    if (hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGetLastError();
+      drop_graph(b);
+      return EIFMM_EHIP;
+    }
+    size_t nodes = 0;
+    hipGraphGetNodes(b->graph, nullptr, &nodes);
+    b->graph_nodes = (int)nodes;
+  }
+  if (hipGraphLaunch(b->gexec, s) != hipSuccess) return EIFMM_EHIP;
+  for (auto h : b->plans) h->P.last_rhs = 1;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? EIFMM_OK : EIFMM_EHIP;
+}
+
+int eifmm_batch_evaluate_unfused(eifmm_batch b, const double *const *sigma, double *const *f,
+                                 void *stream) {
+  if (!b || !sigma || !f) return EIFMM_EINVAL;
+  if (!b->ready) return EIFMM_ESTATE;
+  const int np = (int)b->cfg.size();
+  for (int p = 0; p < np; ++p)
+    if (b->cfg[p].n > 0 && (!sigma[p] || !f[p])) return EIFMM_EINVAL;
+  for (int p = 0; p < np; ++p) {
+    const int64_t n = b->cfg[p].n;
+    if (n == 0) continue;
+    int st = eifmm_evaluate(b->plans[p], sigma[p], 1, n, f[p], n, stream);
+    if (st) return st;
+  }
+  return EIFMM_OK;
+}
+
+int eifmm_batch_export_expansion(eifmm_batch b, int32_t p, int32_t which, int32_t k,
+                                 double *out) {
+  if (!b || p < 0 || p >= (int)b->cfg.size() || !b->plans[p]) return EIFMM_EINVAL;
+  return eifmm_export_expansion(b->plans[p], which, k, 0, out);
+}
+
+int eifmm_batch_get_stats(eifmm_batch b, int32_t p, eifmm_stats *out) {
+  if (!b || p < 0 || p >= (int)b->cfg.size() || !b->plans[p]) return EIFMM_EINVAL;
+  int st = eifmm_get_stats(b->plans[p], out);
+  if (!st) out->setup_ms = b->tables[b->table_of[p]]->P.setup_ms;
+  return st;
+}
+
+int eifmm_batch_get_info(eifmm_batch b, eifmm_batch_info *out) {
+  if (!b || !out || out->struct_size != (int32_t)sizeof(eifmm_batch_info)) return EIFMM_EINVAL;
+  eifmm_batch_info i;
+  std::memset(&i, 0, sizeof(i));
+  i.struct_size = sizeof(i);
+  i.nprob = (int32_t)b->cfg.size();
+  i.ntables = (int32_t)b->tables.size();
+  i.graph_nodes = b->graph_nodes;
+  i.m2l_rbt = b->m2l_rbt;
+  i.m2l_flops = b->ex.m2l_flops;
+  i.tune_ms = b->tune_ms;
+  i.setup_ms = b->setup_ms;
+  *out = i;
+  return EIFMM_OK;
+}
+
+int eifmm_batch_destroy(eifmm_batch b) {
+  if (!b) return EIFMM_EINVAL;
+  hipSetDevice(b->device);
+  batch_free(b);
   return EIFMM_OK;
 }
 

@@ -55,27 +55,24 @@ __host__ __device__ inline double dev_param(int kind, double p) {
   return kind == EIFMM_K_GAUSS ? 1.0 / p : p;
 }
 
-// ------------------------------------------------------------------ sigma
-__global__ void k_gather_sigma(int64_t n, int nrhs, const double *__restrict__ sigma, int64_t ld,
-                               const int *__restrict__ perm, double *__restrict__ sig) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * nrhs) return;
-  int64_t s = e / nrhs;
-  int r = (int)(e - s * nrhs);
-  sig[e] = sigma[(int64_t)perm[s] + (int64_t)r * ld];
-}
-
-// ------------------------------------------------------------------ near field
-// One 64-lane workgroup per non-empty target leaf; lanes own targets; sources of
-// the neighbour leaves (ascending key) are staged through LDS 64 at a time.
+// ------------------------------------------------------------------ leaf level
+// The kernels of the leaf level (sigma gather, near field, P2M, L2P) read one
+// problem's arrays from a LeafDesc.  A plan launches them with its descriptor by
+// value (BATCH = false); a batch of problems launches each kernel once over the
+// chunks / leaves / points of all its problems with an array of descriptors in
+// device memory (BATCH = true): each workgroup finds its problem by a binary
+// search over the first chunk (leaf, point) of every problem.
+//
 // Near field and L2P run one workgroup per chunk of up to 64 consecutive targets
 // of a leaf (chunk_ptr: exclusive prefix sum of ceil(count / 64) over the active
 // leaves), so a crowded leaf of a clustered cloud spreads over many workgroups.
-__device__ inline int chunk_leaf(const int *__restrict__ chunk_ptr, int nleaf, int c) {
-  int lo = 0, hi = nleaf - 1;
+
+template <typename F>
+__device__ inline int find_last_le(int n, int64_t v, F key) {
+  int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (chunk_ptr[mid] <= c)
+    if (key(mid) <= v)
       lo = mid;
     else
       hi = mid - 1;
@@ -83,61 +80,109 @@ __device__ inline int chunk_leaf(const int *__restrict__ chunk_ptr, int nleaf, i
   return lo;
 }
 
-template <int KIND, int RB>
-__global__ __launch_bounds__(64) void k_p2p64(const uint32_t *__restrict__ act,
-                                              const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
-                                              const int *__restrict__ near_ptr,
-                                              const int *__restrict__ near_src,
-                                              const double *__restrict__ xyz, int64_t n,
-                                              const double *__restrict__ sig, int nrhs,
-                                              double *__restrict__ fnear, double p) {
+__device__ inline int chunk_leaf(const int *__restrict__ chunk_ptr, int nleaf, int c) {
+  return find_last_le(nleaf, c, [&](int m) { return (int64_t)chunk_ptr[m]; });
+}
+
+// the descriptor of block b and b's index within its problem
+template <bool BATCH, int WHICH>  // WHICH: 0 chunk, 1 leaf
+__device__ inline void pick_desc(const LeafDesc &one, const LeafDesc *__restrict__ many,
+                                 int nmany, LeafDesc &D, int &local, int &prob) {
+  const int b = blockIdx.x;
+  if constexpr (BATCH) {
+    prob = find_last_le(nmany, b, [&](int m) {
+      return WHICH == 0 ? many[m].chunk_base : many[m].leaf_base;
+    });
+    D = many[prob];
+    local = b - (int)(WHICH == 0 ? D.chunk_base : D.leaf_base);
+  } else {
+    prob = 0;
+    D = one;
+    local = b;
+  }
+}
+
+// ------------------------------------------------------------------ sigma
+// sig[s][r] = sigma[perm[s] + r ld] (sorted order)
+template <bool BATCH>
+__global__ void k_gather_sigma(LeafDesc one, IoDesc ione, const LeafDesc *__restrict__ many,
+                               const IoDesc *__restrict__ io, int nmany, int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  LeafDesc D;
+  IoDesc O;
+  int64_t el = e;
+  if constexpr (BATCH) {
+    const int pr = find_last_le(nmany, e, [&](int m) { return many[m].pt_base; });
+    D = many[pr];
+    O = io[pr];
+    el = e - D.pt_base;
+  } else {
+    D = one;
+    O = ione;
+  }
+  const int64_t s = el / D.nrhs;
+  const int r = (int)(el - s * D.nrhs);
+  D.sig[el] = O.sigma[(int64_t)D.perm[s] + (int64_t)r * O.ld];
+}
+
+// ------------------------------------------------------------------ near field
+// Lanes own targets; sources of the neighbour leaves (ascending key) are staged
+// through LDS 64 at a time.
+template <int KIND, int RB, bool BATCH>
+__global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__restrict__ many,
+                                              int nmany) {
   __shared__ double sx[64], sy[64], sz[64], ss[64 * RB];
-  const int c = blockIdx.x, lane = threadIdx.x;
-  const int j = chunk_leaf(chunk_ptr, nleaf, c);
-  const uint32_t key = act[j];
-  const int a = ls[key], b = ls[key + 1];
-  const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
-  {  // the 64 targets of chunk c
-    const int t0 = a + 64 * (c - chunk_ptr[j]);
-    const int i = t0 + lane;
-    const bool tv = i < b;
-    const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0,
-                 zi = tv ? xyz[2 * n + i] : 0.0;
-    for (int r0 = 0; r0 < nrhs; r0 += RB) {
-      double acc[RB];
+  LeafDesc D;
+  int c, prob;
+  pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  const int lane = threadIdx.x;
+  const int64_t n = D.n;
+  const int nrhs = D.nrhs;
+  const double *__restrict__ xyz = D.xyz;
+  const double *__restrict__ sig = D.sig;
+  const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
+  const uint32_t key = D.act[j];
+  const int a = D.ls[key], b = D.ls[key + 1];
+  const int q0 = D.near_ptr[j], q1 = D.near_ptr[j + 1];
+  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
+  const int i = t0 + lane;
+  const bool tv = i < b;
+  const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    double acc[RB];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
-      for (int q = q0; q < q1; ++q) {
-        const uint32_t skey = act[near_src[q]];
-        const int c0 = ls[skey], c1 = ls[skey + 1];
-        for (int s0 = c0; s0 < c1; s0 += 64) {
-          const int cnt = min(64, c1 - s0);
-          __syncthreads();
-          if (lane < cnt) {
-            const int sidx = s0 + lane;
-            sx[lane] = xyz[sidx];
-            sy[lane] = xyz[n + sidx];
-            sz[lane] = xyz[2 * n + sidx];
+    for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const uint32_t skey = D.act[D.near_src[q]];
+      const int c0 = D.ls[skey], c1 = D.ls[skey + 1];
+      for (int s0 = c0; s0 < c1; s0 += 64) {
+        const int cnt = min(64, c1 - s0);
+        __syncthreads();
+        if (lane < cnt) {
+          const int sidx = s0 + lane;
+          sx[lane] = xyz[sidx];
+          sy[lane] = xyz[n + sidx];
+          sz[lane] = xyz[2 * n + sidx];
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr)
-              ss[lane * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
-          }
-          __syncthreads();
-          for (int u = 0; u < cnt; ++u) {
-            const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            double kv = KF<KIND>::eval(r2, p);
-            if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
+          for (int rr = 0; rr < RB; ++rr)
+            ss[lane * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
+        }
+        __syncthreads();
+        for (int u = 0; u < cnt; ++u) {
+          const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          double kv = KF<KIND>::eval(r2, D.p);
+          if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
-          }
+          for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
         }
       }
-      if (tv) {
+    }
+    if (tv) {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < nrhs) fnear[(int64_t)i * nrhs + r0 + rr] = acc[rr];
-      }
+      for (int rr = 0; rr < RB; ++rr)
+        if (r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = acc[rr];
     }
   }
 }
@@ -146,71 +191,67 @@ __global__ __launch_bounds__(64) void k_p2p64(const uint32_t *__restrict__ act,
 // rounded once to FP32 (so a close pair keeps its relative accuracy however
 // crowded the leaf), kernel values and products in FP32, Neumaier-compensated
 // FP32 sums returned as hi + lo in FP64.
-template <int KIND, int RB>
-__global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
-                                              const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
-                                              const int *__restrict__ near_ptr,
-                                              const int *__restrict__ near_src,
-                                              const double *__restrict__ xyz, int64_t n,
-                                              const double *__restrict__ sig, int nrhs,
-                                              double *__restrict__ fnear, float p) {
+template <int KIND, int RB, bool BATCH>
+__global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__restrict__ many,
+                                              int nmany) {
   __shared__ double sx[64], sy[64], sz[64];
   __shared__ float ss[64 * RB];
-  const int c = blockIdx.x, lane = threadIdx.x;
-  const int j = chunk_leaf(chunk_ptr, nleaf, c);
-  const uint32_t key = act[j];
-  const int a = ls[key], b = ls[key + 1];
-  const int q0 = near_ptr[j], q1 = near_ptr[j + 1];
-  {  // the 64 targets of chunk c
-    const int t0 = a + 64 * (c - chunk_ptr[j]);
-    const int i = t0 + lane;
-    const bool tv = i < b;
-    const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0,
-                 zi = tv ? xyz[2 * n + i] : 0.0;
-    for (int r0 = 0; r0 < nrhs; r0 += RB) {
-      float sum[RB], cmp[RB];
+  LeafDesc D;
+  int c, prob;
+  pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  const int lane = threadIdx.x;
+  const int64_t n = D.n;
+  const int nrhs = D.nrhs;
+  const float p = (float)D.p;
+  const double *__restrict__ xyz = D.xyz;
+  const double *__restrict__ sig = D.sig;
+  const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
+  const uint32_t key = D.act[j];
+  const int a = D.ls[key], b = D.ls[key + 1];
+  const int q0 = D.near_ptr[j], q1 = D.near_ptr[j + 1];
+  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
+  const int i = t0 + lane;
+  const bool tv = i < b;
+  const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    float sum[RB], cmp[RB];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) sum[rr] = cmp[rr] = 0.f;
-      for (int q = q0; q < q1; ++q) {
-        const uint32_t skey = act[near_src[q]];
-        const int c0 = ls[skey], c1 = ls[skey + 1];
-        for (int s0 = c0; s0 < c1; s0 += 64) {
-          const int cnt = min(64, c1 - s0);
-          __syncthreads();
-          if (lane < cnt) {
-            const int sidx = s0 + lane;
-            sx[lane] = xyz[sidx];
-            sy[lane] = xyz[n + sidx];
-            sz[lane] = xyz[2 * n + sidx];
+    for (int rr = 0; rr < RB; ++rr) sum[rr] = cmp[rr] = 0.f;
+    for (int q = q0; q < q1; ++q) {
+      const uint32_t skey = D.act[D.near_src[q]];
+      const int c0 = D.ls[skey], c1 = D.ls[skey + 1];
+      for (int s0 = c0; s0 < c1; s0 += 64) {
+        const int cnt = min(64, c1 - s0);
+        __syncthreads();
+        if (lane < cnt) {
+          const int sidx = s0 + lane;
+          sx[lane] = xyz[sidx];
+          sy[lane] = xyz[n + sidx];
+          sz[lane] = xyz[2 * n + sidx];
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr)
-              ss[lane * RB + rr] =
-                  (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
-          }
-          __syncthreads();
-          for (int u = 0; u < cnt; ++u) {
-            const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]),
-                        dz = (float)(zi - sz[u]);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            float kv = KF<KIND>::evalf(r2, p);
-            if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
+          for (int rr = 0; rr < RB; ++rr)
+            ss[lane * RB + rr] = (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
+        }
+        __syncthreads();
+        for (int u = 0; u < cnt; ++u) {
+          const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          float kv = KF<KIND>::evalf(r2, p);
+          if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) {
-              const float v = ss[u * RB + rr] * kv;
-              const float tsum = sum[rr] + v;
-              cmp[rr] += (fabsf(sum[rr]) >= fabsf(v)) ? ((sum[rr] - tsum) + v)
-                                                      : ((v - tsum) + sum[rr]);
-              sum[rr] = tsum;
-            }
+          for (int rr = 0; rr < RB; ++rr) {
+            const float v = ss[u * RB + rr] * kv;
+            const float tsum = sum[rr] + v;
+            cmp[rr] += (fabsf(sum[rr]) >= fabsf(v)) ? ((sum[rr] - tsum) + v) : ((v - tsum) + sum[rr]);
+            sum[rr] = tsum;
           }
         }
       }
-      if (tv) {
+    }
+    if (tv) {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < nrhs)
-            fnear[(int64_t)i * nrhs + r0 + rr] = (double)sum[rr] + (double)cmp[rr];
-      }
+      for (int rr = 0; rr < RB; ++rr)
+        if (r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = (double)sum[rr] + (double)cmp[rr];
     }
   }
 }
@@ -218,30 +259,32 @@ __global__ __launch_bounds__(64) void k_p2p32(const uint32_t *__restrict__ act,
 // ------------------------------------------------------------------ P2M
 // W^I_m = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I)  (Algorithm 3, step 1)
 // One 256-thread workgroup per leaf; thread t owns rows m = t + 256 u.
-template <int KIND, int RB>
-__global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
-                                             const int *__restrict__ ls,
-                                             const double *__restrict__ X, int d, int dp,
-                                             const double *__restrict__ xyz, int64_t n,
-                                             const double *__restrict__ sig, int nrhs,
-                                             double *__restrict__ W, double lo0, double lo1,
-                                             double lo2, double h, double p) {
+template <int KIND, int RB, bool BATCH>
+__global__ __launch_bounds__(256) void k_p2m(LeafDesc one, const LeafDesc *__restrict__ many,
+                                             int nmany) {
   __shared__ double px[64], py[64], pz[64], ps[64 * RB];
-  const int j = blockIdx.x, t = threadIdx.x;
-  const uint32_t key = act[j];
-  const int a = ls[key], b = ls[key + 1];
-  const double cx = lo0 + ((double)morton_axis(key, 0) + 0.5) * h;
-  const double cy = lo1 + ((double)morton_axis(key, 1) + 0.5) * h;
-  const double cz = lo2 + ((double)morton_axis(key, 2) + 0.5) * h;
+  LeafDesc D;
+  int j, prob;
+  pick_desc<BATCH, 1>(one, many, nmany, D, j, prob);
+  const int t = threadIdx.x;
+  const int64_t n = D.n;
+  const int nrhs = D.nrhs, d = D.d, dp = D.dp;
+  const double *__restrict__ xyz = D.xyz;
+  const double *__restrict__ sig = D.sig;
+  const uint32_t key = D.act[j];
+  const int a = D.ls[key], b = D.ls[key + 1];
+  const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
+  const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
+  const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
   const int nu = (dp + 255) / 256;
   double xm[4], ym[4], zm[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int m = t + 256 * u;
     const bool ok = u < nu && m < d;
-    xm[u] = ok ? X[3 * m] : 0.0;
-    ym[u] = ok ? X[3 * m + 1] : 0.0;
-    zm[u] = ok ? X[3 * m + 2] : 0.0;
+    xm[u] = ok ? D.X[3 * m] : 0.0;
+    ym[u] = ok ? D.X[3 * m + 1] : 0.0;
+    zm[u] = ok ? D.X[3 * m + 2] : 0.0;
   }
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     double acc[4][RB];
@@ -267,7 +310,7 @@ __global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
         for (int u = 0; u < 4; ++u) {
           if (u < nu) {
             const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
-            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, p);
+            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, D.p);
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) acc[u][rr] += ps[q * RB + rr] * kv;
           }
@@ -280,7 +323,7 @@ __global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
       if (u < nu && m < dp) {
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < nrhs) W[((int64_t)j * nrhs + r0 + rr) * dp + m] = m < d ? acc[u][rr] : 0.0;
+          if (r0 + rr < nrhs) D.W[((int64_t)j * nrhs + r0 + rr) * dp + m] = m < d ? acc[u][rr] : 0.0;
       }
     }
   }
@@ -289,55 +332,57 @@ __global__ __launch_bounds__(256) void k_p2m(const uint32_t *__restrict__ act,
 // ------------------------------------------------------------------ L2P + combine
 // f(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I + f_near(x_i), written to
 // the input position of x_i (Algorithm 3, step 7).
-template <int KIND, int RB>
-__global__ __launch_bounds__(64) void k_l2p(const uint32_t *__restrict__ act,
-                                            const int *__restrict__ ls, const int *__restrict__ chunk_ptr, int nleaf,
-                                            const double *__restrict__ X, int d, int dp,
-                                            const double *__restrict__ lhat,
-                                            const double *__restrict__ xyz, int64_t n,
-                                            const double *__restrict__ fnear,
-                                            const int *__restrict__ perm, double *__restrict__ f,
-                                            int64_t ldf, int nrhs, double lo0, double lo1,
-                                            double lo2, double h, double p) {
+template <int KIND, int RB, bool BATCH>
+__global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
+                                            const LeafDesc *__restrict__ many,
+                                            const IoDesc *__restrict__ io, int nmany) {
   extern __shared__ double sm[];
+  LeafDesc D;
+  int c, prob;
+  pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  IoDesc O;
+  if constexpr (BATCH)
+    O = io[prob];
+  else
+    O = ione;
+  const int dp = D.dp, d = D.d, nrhs = D.nrhs;
+  const int64_t n = D.n;
   double *sX = sm, *sl = sm + 3 * dp;
-  const int c = blockIdx.x, lane = threadIdx.x;
-  const int j = chunk_leaf(chunk_ptr, nleaf, c);
-  const uint32_t key = act[j];
-  const int a = ls[key], b = ls[key + 1];
-  const double cx = lo0 + ((double)morton_axis(key, 0) + 0.5) * h;
-  const double cy = lo1 + ((double)morton_axis(key, 1) + 0.5) * h;
-  const double cz = lo2 + ((double)morton_axis(key, 2) + 0.5) * h;
-  for (int e = lane; e < 3 * d; e += 64) sX[e] = X[e];
-  {  // the 64 targets of chunk c
-    const int t0 = a + 64 * (c - chunk_ptr[j]);
-    const int i = t0 + lane;
-    const bool tv = i < b;
-    const double xc = tv ? xyz[i] - cx : 0.0, yc = tv ? xyz[n + i] - cy : 0.0,
-                 zc = tv ? xyz[2 * n + i] - cz : 0.0;
-    for (int r0 = 0; r0 < nrhs; r0 += RB) {
-      __syncthreads();
-      for (int e = lane; e < RB * d; e += 64) {
-        const int rr = e / d, l = e - rr * d;
-        sl[rr * dp + l] = (r0 + rr < nrhs) ? lhat[((int64_t)j * nrhs + r0 + rr) * dp + l] : 0.0;
-      }
-      __syncthreads();
-      double acc[RB];
+  const int lane = threadIdx.x;
+  const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
+  const uint32_t key = D.act[j];
+  const int a = D.ls[key], b = D.ls[key + 1];
+  const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
+  const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
+  const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
+  for (int e = lane; e < 3 * d; e += 64) sX[e] = D.X[e];
+  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
+  const int i = t0 + lane;
+  const bool tv = i < b;
+  const double xc = tv ? D.xyz[i] - cx : 0.0, yc = tv ? D.xyz[n + i] - cy : 0.0,
+               zc = tv ? D.xyz[2 * n + i] - cz : 0.0;
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    __syncthreads();
+    for (int e = lane; e < RB * d; e += 64) {
+      const int rr = e / d, l = e - rr * d;
+      sl[rr * dp + l] = (r0 + rr < nrhs) ? D.lhat[((int64_t)j * nrhs + r0 + rr) * dp + l] : 0.0;
+    }
+    __syncthreads();
+    double acc[RB];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
-      for (int l = 0; l < d; ++l) {
-        const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
-        const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, p);
+    for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
+    for (int l = 0; l < d; ++l) {
+      const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
+      const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, D.p);
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
-      }
-      if (tv) {
-        const int64_t o = perm[i];
+      for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
+    }
+    if (tv) {
+      const int64_t o = D.perm[i];
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < nrhs)
-            f[o + (int64_t)(r0 + rr) * ldf] = acc[rr] + fnear[(int64_t)i * nrhs + r0 + rr];
-      }
+      for (int rr = 0; rr < RB; ++rr)
+        if (r0 + rr < nrhs)
+          O.f[o + (int64_t)(r0 + rr) * O.ldf] = acc[rr] + D.fnear[(int64_t)i * nrhs + r0 + rr];
     }
   }
 }
@@ -363,25 +408,13 @@ __global__ void k_combine_near(int64_t n, int nrhs, const double *__restrict__ f
 // next product without data movement.
 //   Delta   v: Gamma z = v, then B^T w = z
 //   Delta^T v: B z = v,     then Gamma^T w = z
-struct SolveDesc {
-  const double *in;
-  double *out;
-  float *out32;
-  const double *Tf, *Tb;  // fragment tables (setup.cpp)
-  int ncols, dp, blk_start, pad;
-};
 struct SolveArgs {
   SolveDesc lv[kMaxLevels];
   int nlev;
 };
 
-__global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
+__device__ inline void trsm_body(const SolveDesc &D, double *zs) {
   typedef double v4 __attribute__((ext_vector_type(4)));
-  extern __shared__ double zs[];  // [nb][4][64]
-  int li = 0;
-  for (int q = 1; q < A.nlev; ++q)
-    if ((int)blockIdx.x >= A.lv[q].blk_start) li = q;
-  const SolveDesc &D = A.lv[li];
   const int lane = threadIdx.x;
   const int c = ((int)blockIdx.x - D.blk_start) * 16 + (lane & 15);
   const bool cv = c < D.ncols;
@@ -437,6 +470,23 @@ __global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
       }
     }
   }
+}
+
+// one plan: up to one descriptor per level, passed by value
+__global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
+  extern __shared__ double zs[];  // [nb][4][64]
+  int li = 0;
+  for (int q = 1; q < A.nlev; ++q)
+    if ((int)blockIdx.x >= A.lv[q].blk_start) li = q;
+  trsm_body(A.lv[li], zs);
+}
+
+// a batch: every (problem, level) of the launch, descriptors in device memory
+__global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ L, int n) {
+  extern __shared__ double zs[];
+  const int li = find_last_le(n, blockIdx.x, [&](int m) { return (int64_t)L[m].blk_start; });
+  const SolveDesc D = L[li];
+  trsm_body(D, zs);
 }
 
 // ------------------------------------------------------------------ gathered GEMM
@@ -781,7 +831,9 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
     if (rt >= nrows || jo >= ncols) continue;
     double v = 0.0;
     for (int64_t g = glo; g <= ghi; ++g) {
-      const int slot = (int)(2 * g + (sk_bound(g, R, G) >= ts ? 0 : 1));
+      const int64_t b0 = sk_bound(g, R, G);
+      if (sk_bound(g + 1, R, G) == b0) continue;  // no units (R < G): wrote no piece
+      const int slot = (int)(2 * g + (b0 >= ts ? 0 : 1));
       v += ws[(size_t)slot * TILE + e];
     }
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
@@ -1006,6 +1058,7 @@ int build_jobs(Plan &P, int nrhs) {
     jt.l2l_tiles[k] = tiles;
     jt.l2l_units[k] = finish_units(h, jt.l2l_first[k]);
   }
+  P.jobs_host = h;
   if (P.job_dev) hipFree(P.job_dev);
   P.job_dev = nullptr;
   if (!h.empty()) {
@@ -1021,78 +1074,155 @@ int build_jobs(Plan &P, int nrhs) {
 namespace {
 
 template <typename T, int MODE, int RBT>
-void launch_gemm_rbt(Plan &P, int first, int n, int tiles, int64_t units, hipStream_t s) {
-  const int G = (int)std::min<int64_t>(units, P.sk_groups);
+void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int gmax,
+                     double *ws, const int8_t *dvec, hipStream_t s) {
+  const int G = (int)std::min<int64_t>(units, gmax);
   constexpr bool fold = sizeof(T) == 4;
-  hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, P.job_dev + first,
-                     n, tiles, units, G, P.sk_ws, P.dvec);
+  hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, jobs, n, tiles,
+                     units, G, ws, dvec);
   const int rest = tiles - (tiles / G) * G;
   if (G > 1 && rest > 0)
-    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest), dim3(256), 0, s, P.job_dev + first, n,
-                       tiles, units, G, P.sk_ws);
+    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest), dim3(256), 0, s, jobs, n, tiles, units,
+                       G, ws);
+}
+
+template <typename T, int MODE>
+void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int rbt, int gmax,
+                     double *ws, const int8_t *dvec, hipStream_t s) {
+  if (n == 0 || tiles == 0 || units == 0) return;
+  switch (rbt) {
+    case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
+    case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
+    default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
+  }
 }
 
 template <typename T, int MODE>
 void launch_gemm(Plan &P, int first, int n, int tiles, int64_t units, hipStream_t s,
                  int rbt = 6) {
-  if (n == 0 || tiles == 0 || units == 0) return;
-  switch (rbt) {
-    case 4: launch_gemm_rbt<T, MODE, 4>(P, first, n, tiles, units, s); break;
-    case 5: launch_gemm_rbt<T, MODE, 5>(P, first, n, tiles, units, s); break;
-    default: launch_gemm_rbt<T, MODE, 6>(P, first, n, tiles, units, s); break;
+  launch_gemm_tab<T, MODE>(P.job_dev + first, n, tiles, units, rbt, P.sk_groups, P.sk_ws, P.dvec,
+                           s);
+}
+
+void launch_gemm_fused(const FusedGemm &F, int mode, bool fp32, int gmax, double *ws,
+                       const int8_t *dvec, hipStream_t s) {
+  switch (mode) {
+    case MODE_M2M:
+      launch_gemm_tab<double, MODE_M2M>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      break;
+    case MODE_L2L:
+      launch_gemm_tab<double, MODE_L2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      break;
+    case MODE_PROJ:
+      launch_gemm_tab<double, MODE_PROJ>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      break;
+    default:
+      if (fp32)
+        launch_gemm_tab<float, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      else
+        launch_gemm_tab<double, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
   }
 }
 
+// ---- leaf-level launches (one plan: BATCH = false; a batch group: BATCH = true)
+template <int KIND, bool BATCH>
+void launch_p2p(bool mixed, int nrhs, unsigned grid, const LeafDesc &one, const LeafDesc *many,
+                int nmany, hipStream_t s) {
+  if (grid == 0) return;
+  if (mixed) {
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_p2p32<KIND, 1, BATCH>), dim3(grid), dim3(64), 0, s, one, many, nmany);
+    else
+      hipLaunchKernelGGL((k_p2p32<KIND, 8, BATCH>), dim3(grid), dim3(64), 0, s, one, many, nmany);
+  } else {
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_p2p64<KIND, 1, BATCH>), dim3(grid), dim3(64), 0, s, one, many, nmany);
+    else
+      hipLaunchKernelGGL((k_p2p64<KIND, 8, BATCH>), dim3(grid), dim3(64), 0, s, one, many, nmany);
+  }
+}
+
+template <int KIND, bool BATCH>
+void launch_p2m(int nrhs, unsigned grid, const LeafDesc &one, const LeafDesc *many, int nmany,
+                hipStream_t s) {
+  if (grid == 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH>), dim3(grid), dim3(256), 0, s, one, many, nmany);
+  else
+    hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH>), dim3(grid), dim3(256), 0, s, one, many, nmany);
+}
+
+size_t l2p_shm(int nrhs, int dpmax) {
+  const int rb = nrhs == 1 ? 1 : 8;
+  return sizeof(double) * (3 * (size_t)dpmax + (size_t)rb * dpmax);
+}
+
+template <int KIND, bool BATCH>
+void launch_l2p(int nrhs, unsigned grid, size_t shm, const LeafDesc &one, const IoDesc &ione,
+                const LeafDesc *many, const IoDesc *io, int nmany, hipStream_t s) {
+  if (grid == 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_l2p<KIND, 1, BATCH>), dim3(grid), dim3(64), shm, s, one, ione, many, io,
+                       nmany);
+  else
+    hipLaunchKernelGGL((k_l2p<KIND, 8, BATCH>), dim3(grid), dim3(64), shm, s, one, ione, many, io,
+                       nmany);
+}
+
+LeafDesc leaf_desc(const Plan &P, int nrhs) {
+  const int depth = P.depth;
+  LeafDesc D{};
+  D.act = P.ld[depth].act;
+  D.ls = P.leaf_start;
+  D.chunk_ptr = P.chunk_ptr;
+  D.near_ptr = P.near_ptr;
+  D.near_src = P.near_src;
+  D.perm = P.idx;
+  D.xyz = P.xyz;
+  D.X = P.ld[depth].X;
+  D.lhat = P.lhat;
+  D.sig = P.sig;
+  D.fnear = P.fnear;
+  D.W = P.ld[depth].W;
+  D.n = P.n;
+  D.nleaf = (int)P.nact[depth];
+  D.nrhs = nrhs;
+  D.d = depth >= 2 ? P.lh[depth].d : 0;
+  D.dp = depth >= 2 ? P.lh[depth].dp : 0;
+  D.lo0 = P.cfg.lo[0];
+  D.lo1 = P.cfg.lo[1];
+  D.lo2 = P.cfg.lo[2];
+  D.h = std::ldexp(P.cfg.L, -depth);
+  D.p = dev_param(P.cfg.kernel, P.cfg.kernel_param);
+  return D;
+}
+
 template <int KIND>
-void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
+void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   const int depth = P.depth;
   const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
-  const double kp = dev_param(KIND, P.cfg.kernel_param);
   const int64_t n = P.n;
   const int nleafa = (int)P.nact[depth];
   const unsigned nchunk = (unsigned)P.nchunk;
-  const double hleaf = std::ldexp(P.cfg.L, -depth);
+  const LeafDesc LD = leaf_desc(P, nrhs);
   LevelDev &LL = P.ld[depth];
   // near field
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_P2P);
-    if (mixed) {
-      if (nrhs == 1)
-        hipLaunchKernelGGL((k_p2p32<KIND, 1>), dim3(nchunk), dim3(64), 0, s, LL.act,
-                           P.leaf_start, P.chunk_ptr, nleafa, P.near_ptr, P.near_src, P.xyz, n,
-                           P.sig, nrhs, P.fnear, (float)kp);
-      else
-        hipLaunchKernelGGL((k_p2p32<KIND, 8>), dim3(nchunk), dim3(64), 0, s, LL.act,
-                           P.leaf_start, P.chunk_ptr, nleafa, P.near_ptr, P.near_src, P.xyz, n,
-                           P.sig, nrhs, P.fnear, (float)kp);
-    } else {
-      if (nrhs == 1)
-        hipLaunchKernelGGL((k_p2p64<KIND, 1>), dim3(nchunk), dim3(64), 0, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
-                           P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
-      else
-        hipLaunchKernelGGL((k_p2p64<KIND, 8>), dim3(nchunk), dim3(64), 0, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
-                           P.near_ptr, P.near_src, P.xyz, n, P.sig, nrhs, P.fnear, kp);
-    }
+    launch_p2p<KIND, false>(mixed, nrhs, nchunk, LD, nullptr, 0, s);
   }
   if (depth < 2) {
     const int64_t m = n * nrhs;
     if (m > 0)
       hipLaunchKernelGGL(k_combine_near, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n,
-                         nrhs, P.fnear, P.idx, f, ldf);
+                         nrhs, P.fnear, P.idx, io.f, io.ldf);
     return;
   }
   const LevelHost &HL = P.lh[depth];
   // step 1: P2M
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_P2M);
-    if (nrhs == 1)
-      hipLaunchKernelGGL((k_p2m<KIND, 1>), dim3(nleafa), dim3(256), 0, s, LL.act, P.leaf_start,
-                         LL.X, HL.d, HL.dp, P.xyz, n, P.sig, nrhs, LL.W, P.cfg.lo[0], P.cfg.lo[1],
-                         P.cfg.lo[2], hleaf, kp);
-    else
-      hipLaunchKernelGGL((k_p2m<KIND, 8>), dim3(nleafa), dim3(256), 0, s, LL.act, P.leaf_start,
-                         LL.X, HL.d, HL.dp, P.xyz, n, P.sig, nrhs, LL.W, P.cfg.lo[0], P.cfg.lo[1],
-                         P.cfg.lo[2], hleaf, kp);
+    launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, LD, nullptr, 0, s);
   }
   // step 2: M2M
   {
@@ -1139,7 +1269,6 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
     else
       launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles,
                                     P.jobs.m2l_units, s, P.jobs.m2l_rbt);
-
   }
   if (P.jobs.post_n) {
     Timer tm(P, s, EIFMM_PH_PROJ);
@@ -1174,16 +1303,7 @@ void run_kind(Plan &P, int nrhs, double *f, int64_t ldf, hipStream_t s) {
   // step 7: L2P and the final sum
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_L2P);
-    const int rb = nrhs == 1 ? 1 : 8;
-    const size_t shm = sizeof(double) * (3 * (size_t)HL.dp + (size_t)rb * HL.dp);
-    if (nrhs == 1)
-      hipLaunchKernelGGL((k_l2p<KIND, 1>), dim3(nchunk), dim3(64), shm, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
-                         LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
-                         P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
-    else
-      hipLaunchKernelGGL((k_l2p<KIND, 8>), dim3(nchunk), dim3(64), shm, s, LL.act, P.leaf_start, P.chunk_ptr, nleafa,
-                         LL.X, HL.d, HL.dp, P.lhat, P.xyz, n, P.fnear, P.idx, f, ldf, nrhs,
-                         P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], hleaf, kp);
+    launch_l2p<KIND, false>(nrhs, nchunk, l2p_shm(nrhs, HL.dp), LD, io, nullptr, nullptr, 0, s);
   }
 }
 
@@ -1208,21 +1328,22 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
     if (st != EIFMM_OK) return st;
   }
   const int64_t m = P.n * nrhs;
+  const IoDesc io{sigma, ld, f, ldf};
   if (m > 0)
-    hipLaunchKernelGGL(k_gather_sigma, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, P.n,
-                       nrhs, sigma, ld, P.idx, P.sig);
+    hipLaunchKernelGGL((k_gather_sigma<false>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
+                       s, leaf_desc(P, nrhs), io, nullptr, nullptr, 0, m);
   switch (P.cfg.kernel) {
     case EIFMM_K_LAPLACE:
-      run_kind<EIFMM_K_LAPLACE>(P, nrhs, f, ldf, s);
+      run_kind<EIFMM_K_LAPLACE>(P, nrhs, io, s);
       break;
     case EIFMM_K_YUKAWA:
-      run_kind<EIFMM_K_YUKAWA>(P, nrhs, f, ldf, s);
+      run_kind<EIFMM_K_YUKAWA>(P, nrhs, io, s);
       break;
     case EIFMM_K_GAUSS:
-      run_kind<EIFMM_K_GAUSS>(P, nrhs, f, ldf, s);
+      run_kind<EIFMM_K_GAUSS>(P, nrhs, io, s);
       break;
     default:
-      run_kind<EIFMM_K_SQDIST>(P, nrhs, f, ldf, s);
+      run_kind<EIFMM_K_SQDIST>(P, nrhs, io, s);
       break;
   }
   hipError_t e = hipGetLastError();
@@ -1232,6 +1353,242 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
   }
   P.last_rhs = nrhs;
   return EIFMM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+// A batch runs the pass of many independent problems (one plan each) as a fixed,
+// short sequence of launches, each covering every problem: the leaf-level
+// kernels once per kernel kind with an array of LeafDesc, the triangular solves
+// once per step with a list of SolveDesc, and each gathered-GEMM step once with
+// the concatenated jobs of all plans (re-tiled for the fused launch).  The
+// sequence contains no host synchronisation and no allocation, so it can be
+// captured once into a HIP graph and replayed.
+
+namespace {
+
+template <typename T>
+int bupload(T **p, const std::vector<T> &v, std::vector<void *> &track) {
+  *p = nullptr;
+  if (v.empty()) return EIFMM_OK;
+  if (hipMalloc((void **)p, sizeof(T) * v.size()) != hipSuccess) {
+    hipGetLastError();
+    return EIFMM_ENOMEM;
+  }
+  track.push_back((void *)*p);
+  if (hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return EIFMM_EHIP;
+  return EIFMM_OK;
+}
+
+// concatenate the job ranges [first, first + n) of every plan into one launch
+int fuse_jobs(FusedGemm &F, const std::vector<Plan *> &plans,
+              const std::vector<std::pair<int, int>> &ranges, int rbt,
+              std::vector<void *> &track) {
+  std::vector<GemmJob> h;
+  int dmax = 16;
+  for (size_t q = 0; q < plans.size(); ++q)
+    for (int j = ranges[q].first; j < ranges[q].first + ranges[q].second; ++j) {
+      const GemmJob &J = plans[q]->jobs_host[j];
+      if (J.ntgt == 0) continue;
+      h.push_back(J);
+      dmax = std::max(dmax, J.dpm);
+    }
+  F = FusedGemm{};
+  F.rbt = rbt > 0 ? rbt : pick_rbt(dmax / 16);
+  int tiles = 0;
+  for (auto &J : h) finish_job(J, tiles, F.rbt);
+  F.units = finish_units(h, 0);
+  F.tiles = tiles;
+  F.n = (int)h.size();
+  return bupload(&F.dev, h, track);
+}
+
+template <int KIND>
+void run_group(const BatchExec &B, const BatchGroup &g, int phase, hipStream_t s) {
+  const LeafDesc *many = B.leaf_dev + g.first;
+  const LeafDesc none{};
+  const IoDesc inone{};
+  if (phase == 0)
+    launch_p2p<KIND, true>(B.mixed, 1, (unsigned)g.nchunk, none, many, g.count, s);
+  else if (phase == 1)
+    launch_p2m<KIND, true>(1, (unsigned)g.nleaf, none, many, g.count, s);
+  else
+    launch_l2p<KIND, true>(1, (unsigned)g.nchunk, l2p_shm(1, g.dpmax), none, inone, many,
+                           B.io_dev + g.first, g.count, s);
+}
+
+void run_groups(const BatchExec &B, int phase, hipStream_t s) {
+  for (const BatchGroup &g : B.groups) {
+    switch (g.kind) {
+      case EIFMM_K_LAPLACE: run_group<EIFMM_K_LAPLACE>(B, g, phase, s); break;
+      case EIFMM_K_YUKAWA: run_group<EIFMM_K_YUKAWA>(B, g, phase, s); break;
+      case EIFMM_K_GAUSS: run_group<EIFMM_K_GAUSS>(B, g, phase, s); break;
+      default: run_group<EIFMM_K_SQDIST>(B, g, phase, s); break;
+    }
+  }
+}
+
+}  // namespace
+
+void batch_release(BatchExec &B) {
+  if (!B.track.empty()) hipDeviceSynchronize();  // launches may still read the tables
+  for (void *p : B.track) hipFree(p);
+  B = BatchExec{};
+}
+
+int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt, int sk_groups,
+                  double *sk_ws) {
+  batch_release(B);
+  const int np = (int)plans_in.size();
+  if (np == 0) return EIFMM_EINVAL;
+  B.nprob = np;
+  B.mixed = plans_in[0]->cfg.precision == EIFMM_PREC_MIXED;
+  for (Plan *P : plans_in) {
+    if (!P->points_set || P->depth < 2) return EIFMM_ESTATE;
+    if ((P->cfg.precision == EIFMM_PREC_MIXED) != B.mixed) return EIFMM_EINVAL;
+    if (P->jobs.nrhs != 1) {
+      int st = build_jobs(*P, 1);
+      if (st) return st;
+    }
+    B.maxdepth = std::max(B.maxdepth, P->depth);
+  }
+  // descriptor order: problems grouped by kernel kind, batch order inside a group
+  std::vector<Plan *> plans;
+  for (int kind = EIFMM_K_LAPLACE; kind <= EIFMM_K_SQDIST; ++kind) {
+    BatchGroup g;
+    g.kind = kind;
+    g.first = (int)plans.size();
+    for (int q = 0; q < np; ++q)
+      if (plans_in[q]->cfg.kernel == kind) {
+        B.order.push_back(q);
+        plans.push_back(plans_in[q]);
+      }
+    g.count = (int)plans.size() - g.first;
+    if (g.count) B.groups.push_back(g);
+  }
+  std::vector<LeafDesc> leaf(np);
+  int64_t pts = 0;
+  for (BatchGroup &g : B.groups) {
+    int64_t ch = 0, lf = 0;
+    for (int q = g.first; q < g.first + g.count; ++q) {
+      const Plan &P = *plans[q];
+      LeafDesc D = leaf_desc(P, 1);
+      D.chunk_base = ch;
+      D.leaf_base = lf;
+      D.pt_base = pts;
+      ch += P.nchunk;
+      lf += P.nact[P.depth];
+      pts += P.n;
+      g.dpmax = std::max(g.dpmax, P.lh[P.depth].dp);
+      leaf[q] = D;
+    }
+    g.nchunk = ch;
+    g.nleaf = lf;
+  }
+  B.total_pts = pts;
+  int st = bupload(&B.leaf_dev, leaf, B.track);
+  if (st) return st;
+  {
+    std::vector<IoDesc> io(np, IoDesc{nullptr, 0, nullptr, 0});
+    if ((st = bupload(&B.io_dev, io, B.track))) return st;
+  }
+  // triangular solves: What on every level, lhat on the leaf level
+  {
+    std::vector<SolveDesc> w, l;
+    int bw = 0, bl = 0;
+    for (Plan *Pp : plans) {
+      const Plan &P = *Pp;
+      for (int k = 2; k <= P.depth; ++k) {
+        const int nc = (int)P.nact[k];
+        if (nc == 0) continue;
+        SolveDesc D{};
+        D.in = P.ld[k].W;
+        D.out = P.ld[k].Wh;
+        D.out32 = (B.mixed && P.lh[k].r == 0) ? P.ld[k].Wh32 : nullptr;
+        D.Tf = P.ld[k].tri[0];
+        D.Tb = P.ld[k].tri[1];
+        D.ncols = nc;
+        D.dp = P.lh[k].dp;
+        D.blk_start = bw;
+        bw += (nc + 15) / 16;
+        B.what_shm = std::max(B.what_shm, sizeof(double) * 4 * 64 * (size_t)(D.dp / 16));
+        w.push_back(D);
+      }
+      const int k = P.depth, nc = (int)P.nact[k];
+      if (nc == 0) continue;
+      SolveDesc D{};
+      D.in = P.ld[k].l;
+      D.out = P.lhat;
+      D.out32 = nullptr;
+      D.Tf = P.ld[k].tri[2];
+      D.Tb = P.ld[k].tri[3];
+      D.ncols = nc;
+      D.dp = P.lh[k].dp;
+      D.blk_start = bl;
+      bl += (nc + 15) / 16;
+      B.lhat_shm = std::max(B.lhat_shm, sizeof(double) * 4 * 64 * (size_t)(D.dp / 16));
+      l.push_back(D);
+    }
+    B.what_n = (int)w.size();
+    B.what_blk = bw;
+    B.lhat_n = (int)l.size();
+    B.lhat_blk = bl;
+    if ((st = bupload(&B.what_dev, w, B.track))) return st;
+    if ((st = bupload(&B.lhat_dev, l, B.track))) return st;
+  }
+  // gathered GEMMs
+  const int nq = (int)plans.size();
+  std::vector<std::pair<int, int>> r(nq);
+  for (int k = B.maxdepth - 1; k >= 2; --k) {
+    for (int q = 0; q < nq; ++q)
+      r[q] = {plans[q]->jobs.m2m_first[k], k < plans[q]->depth ? plans[q]->jobs.m2m_n[k] : 0};
+    if ((st = fuse_jobs(B.m2m[k], plans, r, 0, B.track))) return st;
+  }
+  for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.pre_first, plans[q]->jobs.pre_n};
+  if ((st = fuse_jobs(B.pre, plans, r, 0, B.track))) return st;
+  for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.m2l_first, plans[q]->jobs.m2l_n};
+  if ((st = fuse_jobs(B.m2l, plans, r, m2l_rbt, B.track))) return st;
+  for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.post_first, plans[q]->jobs.post_n};
+  if ((st = fuse_jobs(B.post, plans, r, 0, B.track))) return st;
+  for (int k = 3; k <= B.maxdepth; ++k) {
+    for (int q = 0; q < nq; ++q)
+      r[q] = {plans[q]->jobs.l2l_first[k], k <= plans[q]->depth ? plans[q]->jobs.l2l_n[k] : 0};
+    if ((st = fuse_jobs(B.l2l[k], plans, r, 0, B.track))) return st;
+  }
+  B.m2l_flops = 0;
+  for (Plan *P : plans) B.m2l_flops += P->m2l_flops;
+  B.sk_groups = sk_groups;
+  B.sk_ws = sk_ws;
+  B.dvec = plans[0]->dvec;
+  hipError_t e = hipDeviceSynchronize();
+  return e == hipSuccess ? EIFMM_OK : EIFMM_EHIP;
+}
+
+void batch_run_m2l(const BatchExec &B, hipStream_t s) {
+  launch_gemm_fused(B.m2l, MODE_M2L, B.mixed, B.sk_groups, B.sk_ws, B.dvec, s);
+}
+
+void batch_run(const BatchExec &B, hipStream_t s) {
+  if (B.total_pts > 0)
+    hipLaunchKernelGGL((k_gather_sigma<true>), dim3((unsigned)((B.total_pts + 255) / 256)),
+                       dim3(256), 0, s, LeafDesc{}, IoDesc{}, B.leaf_dev, B.io_dev, B.nprob,
+                       B.total_pts);
+  run_groups(B, 0, s);  // near field
+  run_groups(B, 1, s);  // P2M
+  for (int k = B.maxdepth - 1; k >= 2; --k)
+    launch_gemm_fused(B.m2m[k], MODE_M2M, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  if (B.what_blk > 0)
+    hipLaunchKernelGGL(k_trsm_list, dim3(B.what_blk), dim3(64), B.what_shm, s, B.what_dev,
+                       B.what_n);
+  launch_gemm_fused(B.pre, MODE_PROJ, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  batch_run_m2l(B, s);
+  launch_gemm_fused(B.post, MODE_PROJ, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  for (int k = 3; k <= B.maxdepth; ++k)
+    launch_gemm_fused(B.l2l[k], MODE_L2L, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  if (B.lhat_blk > 0)
+    hipLaunchKernelGGL(k_trsm_list, dim3(B.lhat_blk), dim3(64), B.lhat_shm, s, B.lhat_dev,
+                       B.lhat_n);
+  run_groups(B, 2, s);  // L2P and the final sum
 }
 
 }  // namespace eifmm

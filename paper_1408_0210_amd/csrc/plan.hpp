@@ -72,6 +72,79 @@ struct GemmJob {
   int64_t units_start;  // first (tile, term) unit of the job within its launch
 };
 
+// One problem's leaf level as the near-field, P2M and L2P kernels read it.
+struct LeafDesc {
+  const uint32_t *act;      // active leaf keys
+  const int *ls;            // leaf_start
+  const int *chunk_ptr;     // first 64-target chunk of each active leaf
+  const int *near_ptr, *near_src;
+  const int *perm;          // sorted position -> input index
+  const double *xyz;        // sorted points
+  const double *X;          // leaf-level EIM points X (d x 3)
+  const double *lhat;
+  double *sig, *fnear, *W;  // sorted sigma, near field, leaf W
+  int64_t n;
+  int nleaf, nrhs, d, dp;
+  double lo0, lo1, lo2, h, p;  // domain corner, leaf width, device kernel parameter
+  int64_t chunk_base, leaf_base, pt_base;  // batch launches: first chunk / leaf / element
+};
+
+// Caller buffers of one evaluation: sigma (input order, column stride ld) and f.
+struct IoDesc {
+  const double *sigma;
+  int64_t ld;
+  double *f;
+  int64_t ldf;
+};
+
+// A gathered-GEMM launch assembled from the jobs of several plans.
+struct FusedGemm {
+  GemmJob *dev = nullptr;
+  int n = 0, tiles = 0, rbt = 6;
+  int64_t units = 0;
+};
+
+// One (problem, level) of a blocked triangular-solve launch: columns of `in`
+// (dp doubles each) solved into `out` (and an optional FP32 copy) with the
+// fragment tables Tf (forward) and Tb (backward); blk_start = first workgroup.
+struct SolveDesc {
+  const double *in;
+  double *out;
+  float *out32;
+  const double *Tf, *Tb;
+  int ncols, dp, blk_start, pad;
+};
+
+// Problems of one kernel kind inside a batch (contiguous descriptor range).
+struct BatchGroup {
+  int kind = 0;
+  int first = 0, count = 0;
+  int64_t nchunk = 0, nleaf = 0;
+  int dpmax = 0;
+};
+
+// The fused pass of a batch of plans: one launch per phase over all problems
+// (per kernel kind for the leaf-level kernels).  Built by batch_prepare once the
+// trees are known, replayed by batch_run.
+struct BatchExec {
+  int nprob = 0, maxdepth = 0;
+  bool mixed = false;
+  int64_t total_pts = 0;
+  std::vector<int> order;          // descriptor slot -> problem index
+  std::vector<BatchGroup> groups;
+  LeafDesc *leaf_dev = nullptr;    // [nprob] in descriptor order
+  IoDesc *io_dev = nullptr;        // [nprob] in descriptor order, written per evaluation
+  SolveDesc *what_dev = nullptr, *lhat_dev = nullptr;
+  int what_n = 0, what_blk = 0, lhat_n = 0, lhat_blk = 0;
+  size_t what_shm = 0, lhat_shm = 0;
+  FusedGemm m2m[kMaxLevels], l2l[kMaxLevels], pre, m2l, post;
+  int sk_groups = 0;
+  double *sk_ws = nullptr;
+  const int8_t *dvec = nullptr;
+  double m2l_flops = 0;
+  std::vector<void *> track;       // device allocations of the tables above
+};
+
 // Index ranges of the gathered-GEMM jobs of one (points, nrhs) pair.
 struct JobTables {
   int nrhs = -1;
@@ -135,6 +208,7 @@ struct Plan {
   // gathered-GEMM job tables (rebuilt when the points or nrhs change)
   JobTables jobs;
   GemmJob *job_dev = nullptr;
+  std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
   double m2l_flops = 0, proj_flops = 0;
@@ -160,5 +234,11 @@ int build_jobs(Plan &P, int nrhs);
 void timing_drain(Plan &P);
 int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
              hipStream_t s);
+// batches (pass.hip): m2l_rbt <= 0 picks the M2L tile height from the operators
+int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans, int m2l_rbt, int sk_groups,
+                  double *sk_ws);
+void batch_release(BatchExec &B);
+void batch_run(const BatchExec &B, hipStream_t s);
+void batch_run_m2l(const BatchExec &B, hipStream_t s);
 
 }  // namespace eifmm

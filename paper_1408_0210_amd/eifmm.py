@@ -51,6 +51,14 @@ class Stats(ctypes.Structure):
                 ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("nprob", ctypes.c_int32),
+                ("ntables", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
+                ("m2l_rbt", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("m2l_flops", ctypes.c_double), ("tune_ms", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("reserved", ctypes.c_double * 4)]
+
+
 _lib = None
 
 
@@ -77,12 +85,24 @@ def lib():
         L.eifmm_export_lists.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp]
         L.eifmm_export_expansion.argtypes = [vp, i32, i32, i32, vp]
         L.eifmm_plan_destroy.argtypes = [vp]
+        L.eifmm_batch_create.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(vp)]
+        L.eifmm_batch_set_points.argtypes = [vp, vp, vp]
+        L.eifmm_batch_evaluate.argtypes = [vp, vp, vp, vp]
+        L.eifmm_batch_evaluate_unfused.argtypes = [vp, vp, vp, vp]
+        L.eifmm_batch_export_expansion.argtypes = [vp, i32, i32, i32, vp]
+        L.eifmm_batch_get_stats.argtypes = [vp, i32, ctypes.POINTER(Stats)]
+        L.eifmm_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+        L.eifmm_batch_destroy.argtypes = [vp]
         L.eifmm_status_str.argtypes = [ctypes.c_int]
         L.eifmm_status_str.restype = ctypes.c_char_p
         for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_evaluate", "eifmm_set_timing",
                   "eifmm_get_stats", "eifmm_get_level", "eifmm_get_compression",
                   "eifmm_export_tree", "eifmm_export_lists",
-                  "eifmm_export_expansion", "eifmm_plan_destroy"):
+                  "eifmm_export_expansion", "eifmm_plan_destroy", "eifmm_batch_create",
+                  "eifmm_batch_set_points", "eifmm_batch_evaluate",
+                  "eifmm_batch_evaluate_unfused", "eifmm_batch_export_expansion",
+                  "eifmm_batch_get_stats",
+                  "eifmm_batch_get_info", "eifmm_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -109,27 +129,47 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
+                dmax=0, host_only=False, compress_tol=0.0):
+    c = Config()
+    c.struct_size = ctypes.sizeof(Config)
+    c.kernel = KERNELS[kernel]
+    c.kernel_param = float(param)
+    for a in range(3):
+        c.lo[a] = float(lo[a])
+    c.L = float(L)
+    c.n = int(n)
+    c.depth = int(depth)
+    c.max_rhs = int(max_rhs)
+    c.eim_tol = float(tau)
+    c.tol_mode = int(tol_mode)
+    c.precision = PRECISIONS[precision]
+    c.dmax = int(dmax)
+    c.flags = FLAG_HOST_ONLY if host_only else 0
+    c.compress_tol = float(compress_tol)
+    return c
+
+
+def _stats_dict(s, depth):
+    lv = range(2, depth + 1)
+    return dict(depth=s.depth, d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
+                rank={k: s.rank[k] for k in lv}, proj_flops=s.proj_flops,
+                eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
+                phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},
+                phase_calls={PHASES[q]: s.phase_calls[q] for q in range(NPHASE)},
+                m2l_flops=s.m2l_flops,
+                active_boxes={k: s.active_boxes[k] for k in range(depth + 1)},
+                il_pairs={k: s.il_pairs[k] for k in lv}, near_pairs=s.near_pairs,
+                hip_error=s.hip_error)
+
+
 class Plan:
     """One fixed (kernel, domain, N, depth, tau) setting; points and potentials vary."""
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
                  tol_mode=0, dmax=0, host_only=False, compress_tol=0.0):
-        c = Config()
-        c.struct_size = ctypes.sizeof(Config)
-        c.kernel = KERNELS[kernel]
-        c.kernel_param = float(param)
-        for a in range(3):
-            c.lo[a] = float(lo[a])
-        c.L = float(L)
-        c.n = int(n)
-        c.depth = int(depth)
-        c.max_rhs = int(max_rhs)
-        c.eim_tol = float(tau)
-        c.tol_mode = int(tol_mode)
-        c.precision = PRECISIONS[precision]
-        c.dmax = int(dmax)
-        c.flags = FLAG_HOST_ONLY if host_only else 0
-        c.compress_tol = float(compress_tol)
+        c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
+                        host_only, compress_tol)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.kernel, self.precision = kernel, precision
@@ -171,16 +211,7 @@ class Plan:
         s = Stats()
         s.struct_size = ctypes.sizeof(Stats)
         _check(lib().eifmm_get_stats(self._h, ctypes.byref(s)), "eifmm_get_stats")
-        lv = range(2, self.depth + 1)
-        return dict(d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
-                    rank={k: s.rank[k] for k in lv}, proj_flops=s.proj_flops,
-                    eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
-                    phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},
-                    phase_calls={PHASES[q]: s.phase_calls[q] for q in range(NPHASE)},
-                    m2l_flops=s.m2l_flops,
-                    active_boxes={k: s.active_boxes[k] for k in range(self.depth + 1)},
-                    il_pairs={k: s.il_pairs[k] for k in lv}, near_pairs=s.near_pairs,
-                    hip_error=s.hip_error)
+        return _stats_dict(s, self.depth)
 
     def level(self, k):
         d = ctypes.c_int32()
@@ -244,6 +275,98 @@ class Plan:
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.eifmm_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Independent problems evaluated together (eifmm_batch_*).
+
+    problems: list of dicts with keys kernel, param, n, tau and optionally depth
+    (None or -1: autotuned), tol_mode, compress_tol, lo, L, dmax; precision is
+    one for the whole batch."""
+
+    def __init__(self, problems, precision="fp64"):
+        n = len(problems)
+        arr = (Config * n)()
+        for i, q in enumerate(problems):
+            depth = q.get("depth")
+            arr[i] = make_config(q["kernel"], q.get("param", 0.0), q.get("lo", (0, 0, 0)),
+                                 q.get("L", 1.0), q["n"], -1 if depth is None else depth,
+                                 q["tau"], 1, precision, q.get("tol_mode", 0), q.get("dmax", 0),
+                                 False, q.get("compress_tol", 0.0))
+        self.ns = [int(q["n"]) for q in problems]
+        self.nprob = n
+        h = ctypes.c_void_p()
+        _check(lib().eifmm_batch_create(arr, n, ctypes.byref(h)), "eifmm_batch_create")
+        self._h = h
+
+    @staticmethod
+    def _ptrs(tensors, ns, shape):
+        assert len(tensors) == len(ns)
+        a = (ctypes.c_void_p * len(ns))()
+        for i, (t, n) in enumerate(zip(tensors, ns)):
+            assert t.is_cuda and t.element_size() == 8 and t.is_contiguous()
+            assert tuple(t.shape) == shape(n)
+            a[i] = t.data_ptr() if n > 0 else None
+        return a
+
+    def set_points(self, xyz):
+        """xyz: list of CUDA float64 tensors of shape (3, n_p)."""
+        self._xyz = list(xyz)  # the library reads them during the call only
+        p = self._ptrs(self._xyz, self.ns, lambda n: (3, n))
+        _check(lib().eifmm_batch_set_points(self._h, p, _stream()), "eifmm_batch_set_points")
+
+    def evaluate(self, sigma, out=None):
+        """sigma: list of CUDA float64 tensors (n_p,); returns the list of f."""
+        import torch
+        if out is None:
+            out = [torch.empty_like(t) for t in sigma]
+        ps = self._ptrs(sigma, self.ns, lambda n: (n,))
+        pf = self._ptrs(out, self.ns, lambda n: (n,))
+        _check(lib().eifmm_batch_evaluate(self._h, ps, pf, _stream()), "eifmm_batch_evaluate")
+        return out
+
+    def evaluate_unfused(self, sigma, out=None):
+        """Each problem's own pass in sequence (no fusion, no graph)."""
+        import torch
+        if out is None:
+            out = [torch.empty_like(t) for t in sigma]
+        ps = self._ptrs(sigma, self.ns, lambda n: (n,))
+        pf = self._ptrs(out, self.ns, lambda n: (n,))
+        _check(lib().eifmm_batch_evaluate_unfused(self._h, ps, pf, _stream()),
+               "eifmm_batch_evaluate_unfused")
+        return out
+
+    def export_expansion(self, p, which, k):
+        """Expansion of problem p after an evaluation, as Plan.export_expansion."""
+        w = ["W", "What", "g", "l", "lhat"].index(which)
+        d = self.stats(p)["d"][k]
+        out = np.empty((1 << (3 * k), d))
+        _check(lib().eifmm_batch_export_expansion(self._h, p, w, k, _np_ptr(out)),
+               "eifmm_batch_export_expansion")
+        return out
+
+    def stats(self, p):
+        s = Stats()
+        s.struct_size = ctypes.sizeof(Stats)
+        _check(lib().eifmm_batch_get_stats(self._h, p, ctypes.byref(s)), "eifmm_batch_get_stats")
+        return _stats_dict(s, s.depth)
+
+    def info(self):
+        i = BatchInfo()
+        i.struct_size = ctypes.sizeof(BatchInfo)
+        _check(lib().eifmm_batch_get_info(self._h, ctypes.byref(i)), "eifmm_batch_get_info")
+        return dict(nprob=i.nprob, ntables=i.ntables, graph_nodes=i.graph_nodes,
+                    m2l_rbt=i.m2l_rbt, m2l_flops=i.m2l_flops, tune_ms=i.tune_ms,
+                    setup_ms=i.setup_ms)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.eifmm_batch_destroy(h)
         self._h = None
 
     def __del__(self):

@@ -76,6 +76,13 @@ def make_sigma(w):
     return potentials(w["n"], s)
 
 
+# EIM and compression tolerances per kernel for the uneven batch: exp(-r^2/0.01)
+# uses the absolute stopping rule (tol_mode 1) and a tolerance of 5e-7, which
+# keeps its rel-L2 error below 1e-6; 1/r meets 1e-6 with tau = 1e-6.
+BATCH_TOLERANCES = {"laplace": dict(tau=1e-6, tol_mode=0, compress_tol=1e-6),
+                    "gauss": dict(tau=5e-7, tol_mode=1, compress_tol=5e-7)}
+
+
 def uneven_batch(nprob=256, seed=9, nmin=1e3, nmax=2e5):
     """Uneven batch recipe: N log-uniform in [nmin, nmax]; exactly half the problems
     uniform and half from 4 Gaussian clusters (width 0.03), assigned by a seeded
