@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the batch of 256 uneven problems")
     ap.add_argument("--batch-precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--only-leg", choices=["batched", "clustered", "uneven"],
+                    help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--compress-tol", type=float, default=1e-6,
@@ -283,6 +285,11 @@ def main():
         print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
               "(the path has no multi-GPU mode)", file=sys.stderr)
         sys.exit(2)
+
+    if args.only_leg:
+        leg = {"batched": run_batched, "clustered": run_clustered, "uneven": run_uneven}
+        print(json.dumps({args.only_leg: leg[args.only_leg](args)}), flush=True)
+        return
 
     r = run_plain(args)
     st, n, ms = r["stats"], r["n"], r["ms"]

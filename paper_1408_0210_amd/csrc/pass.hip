@@ -530,7 +530,8 @@ struct Mfma<float> {
 
 template <typename T, int MODE>
 __device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
-                                       int ts, int r, const int8_t *__restrict__ dvec) {
+                                       int ts, int r, const int8_t *__restrict__ dvec,
+                                       const int *__restrict__ src_slot, const T *Bsrc) {
   if (!cvalid) return nullptr;
   int s;
   if constexpr (MODE == MODE_PROJ) {
@@ -550,10 +551,10 @@ __device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, 
     } else {
       skey = tkey >> 3;
     }
-    s = J.src_slot[skey];
+    s = src_slot[skey];
     if (s < 0) return nullptr;
   }
-  return (const T *)J.Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
+  return Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
 }
 
 template <typename T, int MODE>
@@ -628,11 +629,22 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   const bool cvalid = jc < ncols;
   int r = 0, tsl = 0;
   uint32_t tkey = 0;
+  const int *cslot = J.src_slot;
+  const T *cB = (const T *)J.Bsrc;
   if (cvalid) {
     const int tt = jc / J.nrhs;
     r = jc - tt * J.nrhs;
-    tsl = J.tgt ? J.tgt[tt] : tt;
-    if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
+    if (MODE == MODE_M2L && J.colref) {
+      const ColRef cr = J.colref[tt];
+      const ColSrc &cs = J.colsrc[cr.rec];
+      tsl = cr.slot;
+      tkey = cs.keys[tsl];
+      cslot = cs.slot;
+      cB = (const T *)cs.B;
+    } else {
+      tsl = J.tgt ? J.tgt[tt] : tt;
+      if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
+    }
   }
   V4 acc[RBT][2];
   D4 sum[RBT][2];
@@ -652,7 +664,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   auto fetch = [&](int it) {
     const int term = it / nkc, kc = it - term * nkc;
     if (kc == 0) {
-      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec);
+      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec, cslot, cB);
       Ap = gemm_operand<T, MODE>(J, term);
     }
 #pragma unroll
@@ -735,7 +747,15 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     const int jo = col0 + jt;
     if (jo >= ncols) continue;
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
-    const int tso = J.tgt ? J.tgt[tt] : tt;
+    int tso;
+    double *Cout = J.C;
+    if (MODE == MODE_M2L && J.colref) {
+      const ColRef cr = J.colref[tt];
+      tso = cr.slot;
+      Cout = J.colsrc[cr.rec].C;
+    } else {
+      tso = J.tgt ? J.tgt[tt] : tt;
+    }
     const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
 #pragma unroll
     for (int i = 0; i < RBT; ++i) {
@@ -753,7 +773,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
         } else {
           const int64_t o = cbase + 16 * rb0 + rt;
           if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
-          J.C[o] = v;
+          Cout[o] = v;
           if (J.C32) J.C32[o] = (float)v;
         }
       }
@@ -837,10 +857,18 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
       v += ws[(size_t)slot * TILE + e];
     }
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
-    const int tso = J.tgt ? J.tgt[tt] : tt;
+    int tso;
+    double *Cout = J.C;
+    if (J.colref) {
+      const ColRef cr = J.colref[tt];
+      tso = cr.slot;
+      Cout = J.colsrc[cr.rec].C;
+    } else {
+      tso = J.tgt ? J.tgt[tt] : tt;
+    }
     const int64_t o = ((int64_t)tso * J.nrhs + ro) * J.dpm + 16 * rb0 + rt;
     if (J.mode == MODE_L2L) v += J.Cadd[o];
-    J.C[o] = v;
+    Cout[o] = v;
     if (J.C32) J.C32[o] = (float)v;
   }
 }
@@ -1403,6 +1431,103 @@ int fuse_jobs(FusedGemm &F, const std::vector<Plan *> &plans,
   return bupload(&F.dev, h, track);
 }
 
+// Packed M2L: one job per (operator set, level, child class) whose columns are
+// the targets of that class in every problem using the set, so the coarse
+// levels of small problems (a few boxes per class each) fill whole tiles.
+int pack_m2l(FusedGemm &F, const std::vector<Plan *> &plans, int rbt, bool mixed,
+             std::vector<void *> &track) {
+  struct Key {
+    const void *A;
+    int k, c;
+  };
+  std::vector<Key> keys;
+  std::vector<GemmJob> jobs;
+  std::vector<std::vector<ColRef>> refs;
+  std::vector<ColSrc> srcs;
+  std::vector<int> cls;
+  int dmax = 16;
+  for (Plan *Pp : plans) {
+    const Plan &P = *Pp;
+    for (int k = P.depth; k >= 2; --k) {
+      const int64_t na = P.nact[k];
+      if (na == 0) continue;
+      cls.resize(na);
+      if (hipMemcpy(cls.data(), P.ld[k].cls, sizeof(int) * na, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+        return EIFMM_EHIP;
+      const bool cz = P.lh[k].r > 0;
+      const int dm = cz ? P.lh[k].rp : P.lh[k].dp;
+      dmax = std::max(dmax, dm);
+      const void *A = mixed ? (const void *)P.ld[k].kfrag32 : (const void *)P.ld[k].kfrag;
+      ColSrc cs;
+      cs.keys = P.ld[k].act;
+      cs.slot = P.ld[k].slot;
+      if (cz)
+        cs.B = mixed ? (const void *)P.ld[k].Whp32 : (const void *)P.ld[k].Whp;
+      else
+        cs.B = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
+      cs.C = cz ? P.ld[k].gp : P.ld[k].g;
+      const int rec = (int)srcs.size();
+      srcs.push_back(cs);
+      for (int c = 0; c < 8; ++c) {
+        const int64_t c0 = P.cls_off[k][c], c1 = P.cls_off[k][c + 1];
+        if (c1 == c0) continue;
+        size_t j = 0;
+        while (j < keys.size() && !(keys[j].A == A && keys[j].k == k && keys[j].c == c)) ++j;
+        if (j == keys.size()) {
+          keys.push_back(Key{A, k, c});
+          GemmJob J{};
+          J.A = A;
+          J.terms = P.dlist + 189 * c;
+          J.a_stride = (int64_t)dm * dm;
+          J.nterms = 189;
+          J.dpm = J.dpk = dm;
+          J.level = k;
+          J.cls = c;
+          J.mode = MODE_M2L;
+          J.nrhs = 1;
+          jobs.push_back(J);
+          refs.emplace_back();
+        }
+        for (int64_t i = c0; i < c1; ++i) refs[j].push_back(ColRef{rec, cls[i]});
+      }
+    }
+  }
+  F = FusedGemm{};
+  F.rbt = rbt > 0 ? rbt : pick_rbt(dmax / 16);
+  if (jobs.empty()) return EIFMM_OK;
+  // finest level first (as in a plan's own launch), then operator set and class
+  std::vector<int> order(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return jobs[a].level > jobs[b].level; });
+  std::vector<ColRef> all;
+  std::vector<GemmJob> h;
+  std::vector<size_t> off;
+  for (int j : order) {
+    off.push_back(all.size());
+    all.insert(all.end(), refs[j].begin(), refs[j].end());
+    GemmJob J = jobs[j];
+    J.ntgt = (int)refs[j].size();
+    h.push_back(J);
+  }
+  ColSrc *srcs_dev = nullptr;
+  ColRef *refs_dev = nullptr;
+  int st = bupload(&srcs_dev, srcs, track);
+  if (!st) st = bupload(&refs_dev, all, track);
+  if (st) return st;
+  int tiles = 0;
+  for (size_t j = 0; j < h.size(); ++j) {
+    h[j].colsrc = srcs_dev;
+    h[j].colref = refs_dev + off[j];
+    finish_job(h[j], tiles, F.rbt);
+  }
+  F.units = finish_units(h, 0);
+  F.tiles = tiles;
+  F.n = (int)h.size();
+  return bupload(&F.dev, h, track);
+}
+
 template <int KIND>
 void run_group(const BatchExec &B, const BatchGroup &g, int phase, hipStream_t s) {
   const LeafDesc *many = B.leaf_dev + g.first;
@@ -1546,8 +1671,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
   }
   for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.pre_first, plans[q]->jobs.pre_n};
   if ((st = fuse_jobs(B.pre, plans, r, 0, B.track))) return st;
-  for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.m2l_first, plans[q]->jobs.m2l_n};
-  if ((st = fuse_jobs(B.m2l, plans, r, m2l_rbt, B.track))) return st;
+  if ((st = pack_m2l(B.m2l, plans, m2l_rbt, B.mixed, B.track))) return st;
   for (int q = 0; q < nq; ++q) r[q] = {plans[q]->jobs.post_first, plans[q]->jobs.post_n};
   if ((st = fuse_jobs(B.post, plans, r, 0, B.track))) return st;
   for (int k = 3; k <= B.maxdepth; ++k) {

@@ -54,6 +54,19 @@ struct LevelDev {
   float *Whp32 = nullptr;
 };
 
+// Packed M2L jobs of a batch: the columns of one job belong to several problems
+// that share the level's operators; each column names its problem's arrays.
+struct ColSrc {
+  const uint32_t *keys;  // active keys of the level
+  const int *slot;       // slot map of the level
+  const void *B;         // source expansions (What or What')
+  double *C;             // output (g or g')
+};
+struct ColRef {
+  int rec;   // ColSrc record
+  int slot;  // target slot
+};
+
 // One target group of a gathered GEMM launch (see pass.hip).
 struct GemmJob {
   const void *A;        // fragment-ordered operand(s)
@@ -70,6 +83,8 @@ struct GemmJob {
   int level, cls, mode, nrhs;
   int tiles_start, ncoltiles, nrowtiles, src_level;
   int64_t units_start;  // first (tile, term) unit of the job within its launch
+  const ColRef *colref;  // packed M2L: per target column (tgt, tgt_keys, src_slot,
+  const ColSrc *colsrc;  // Bsrc and C unused); null otherwise
 };
 
 // One problem's leaf level as the near-field, P2M and L2P kernels read it.
