@@ -131,6 +131,8 @@ typedef struct {
   int64_t near_pairs;                /* ordered leaf pairs in the near lists      */
   int32_t hip_error;                 /* last hipError_t seen (0 = none)           */
   int32_t reserved;
+  int64_t near_point_pairs;          /* ordered point pairs (targets x sources) of
+                                        the near field, self pairs included      */
 } eifmm_stats;
 
 /* Per-level EIM plan: runs Algorithm 1 for k = 2..depth on the training sets,

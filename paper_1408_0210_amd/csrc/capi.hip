@@ -1,5 +1,6 @@
 // capi.hip -- the extern "C" entry points of libeifmm.so (declared in include/eifmm.h).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -198,6 +199,7 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
   TRY(dalloc(&P.near_ptr, P.ld[depth].cap + 2, tr));
   TRY(dalloc(&P.near_src, P.near_cap, tr));
   TRY(dalloc(&P.chunk_ptr, P.ld[depth].cap + 2, tr));
+  TRY(dalloc(&P.npairs_dev, 2, tr));
   TRY(dalloc(&P.sig, (size_t)nn * R, tr));
   TRY(dalloc(&P.fnear, (size_t)nn * R, tr));
   for (int k = 2; k <= depth; ++k) {
@@ -253,6 +255,15 @@ struct eifmm_batch_s {
   hipGraphExec_t gexec = nullptr;
   int graph_nodes = 0;
   double tune_ms = 0, setup_ms = 0;
+  // depth autotuning: per problem, the work of each candidate depth
+  // (cand_lo + i), and the rates of the fused pass that turn work into time
+  bool tuned = false;
+  std::vector<int> cand_lo;
+  std::vector<std::vector<std::array<double, 4>>> cand;
+  double rate_near[4] = {0, 0, 0, 0};  // near-field lane pairs / ms, per kernel kind
+  double rate_m2l = 0;                 // M2L flops / ms
+  double rate_leaf = 0;                // P2M + L2P kernel evaluations / ms
+  double rate_box = 0;                 // box-level d^2 units / ms (M2M, L2L, solves)
 };
 
 namespace {
@@ -315,6 +326,90 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
   }
   *out = h;
   return EIFMM_OK;
+}
+
+// work of one problem's pass at its current depth, in the units of the rates:
+// near-field lane pairs, M2L flops (2 r_k^2 per interaction pair), P2M + L2P
+// kernel evaluations, and sum over levels of active boxes x d_k^2
+std::array<double, 4> work_of(const Plan &P) {
+  std::array<double, 4> w{};
+  w[0] = (double)P.near_lane_pairs;
+  if (P.depth >= 2) {
+    for (int k = 2; k <= P.depth; ++k) {
+      const double rk = P.lh[k].r > 0 ? P.lh[k].r : P.lh[k].d;
+      w[1] += 2.0 * rk * rk * (double)P.il_pairs[k];
+      w[3] += (double)P.nact[k] * P.lh[k].d * P.lh[k].d;
+    }
+    w[2] = 2.0 * (double)P.n * P.lh[P.depth].d;
+  }
+  return w;
+}
+
+// the candidate depth with the smallest modelled time, as an offset from cand_lo
+int pick_depth(eifmm_batch b, int p) {
+  const int kind = b->cfg[p].kernel;
+  int best = 0;
+  double tbest = 0;
+  for (size_t i = 0; i < b->cand[p].size(); ++i) {
+    const auto &w = b->cand[p][i];
+    const double t = w[0] / b->rate_near[kind] + w[1] / b->rate_m2l + w[2] / b->rate_leaf +
+                     w[3] / b->rate_box;
+    if (i == 0 || t < tbest) {
+      best = (int)i;
+      tbest = t;
+    }
+  }
+  return best;
+}
+
+int stage_io(eifmm_batch b, const double *const *sigma, double *const *f, hipStream_t s);
+
+// one fused pass with zero sigma and phase marks; rates = work / time, summed over
+// the problems of the batch (keeps the previous rate where a phase had no work)
+int calibrate(eifmm_batch b, hipStream_t s) {
+  const BatchExec &B = b->ex;
+  const int nm = batch_marks(B);
+  std::vector<hipEvent_t> ev(nm, nullptr);
+  for (auto &e : ev) hipEventCreate(&e);
+  int st = stage_io(b, nullptr, nullptr, s);
+  if (!st) {
+    batch_run(B, s);  // warm-up
+    batch_run(B, s, ev.data());
+    if (hipEventSynchronize(ev.back()) != hipSuccess) st = EIFMM_EHIP;
+  }
+  if (!st) {
+    const int G = (int)B.groups.size();
+    auto dt = [&](int a) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, ev[a], ev[a + 1]);
+      return (double)ms;
+    };
+    // marks: 0 start, 1 gather, 2..G+1 near, G+2..2G+1 P2M, 2G+2 M2M, 2G+3 What,
+    // 2G+4 pre, 2G+5 M2L, 2G+6 post, 2G+7 L2L, 2G+8 lhat, 2G+9.. L2P
+    std::array<double, 4> wk[4] = {};
+    double leaf = 0, box = 0, m2l = 0;
+    for (int p = 0; p < (int)b->plans.size(); ++p) {
+      const auto w = work_of(b->plans[p]->P);
+      wk[b->cfg[p].kernel][0] += w[0];
+      m2l += w[1];
+      leaf += w[2];
+      box += w[3];
+    }
+    double t_leaf = 0;
+    for (int g = 0; g < G; ++g) {
+      const double t = dt(1 + g);
+      if (t > 0 && wk[B.groups[g].kind][0] > 0) b->rate_near[B.groups[g].kind] = wk[B.groups[g].kind][0] / t;
+      t_leaf += dt(1 + G + g) + dt(2 * G + 8 + g);
+    }
+    const double t_box = dt(2 * G + 1) + dt(2 * G + 2) + dt(2 * G + 3) + dt(2 * G + 5) +
+                         dt(2 * G + 6) + dt(2 * G + 7);
+    const double t_m2l = dt(2 * G + 4);
+    if (t_m2l > 0 && m2l > 0) b->rate_m2l = m2l / t_m2l;
+    if (t_leaf > 0 && leaf > 0) b->rate_leaf = leaf / t_leaf;
+    if (t_box > 0 && box > 0) b->rate_box = box / t_box;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
+  return st;
 }
 
 void drop_graph(eifmm_batch b) {
@@ -487,6 +582,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
     s.il_pairs[k] = P.il_pairs[k];
   }
   s.near_pairs = P.near_total;
+  s.near_point_pairs = P.near_point_pairs;
   s.hip_error = P.last_hip_error;
   *out = s;
   return EIFMM_OK;
@@ -619,6 +715,14 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
   b->depth.assign(nprob, -1);
   b->plans.assign(nprob, nullptr);
   b->table_of.assign(nprob, -1);
+  b->cand_lo.assign(nprob, 2);
+  b->cand.assign(nprob, {});
+  // starting rates, per millisecond, of the phases of a fused pass on MI355X
+  // (FP64, one right-hand side); the first set_points measures the batch's own
+  for (int k = 0; k < 4; ++k) b->rate_near[k] = 4.0e8;
+  b->rate_m2l = 3.0e10;
+  b->rate_leaf = 6.0e8;
+  b->rate_box = 1.5e9;
   int st = EIFMM_OK;
   // one table set per key, down to the deepest level any of its problems may use
   std::vector<int> kmax, rep;  // per table set: deepest level, a problem that uses it
@@ -694,56 +798,61 @@ int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream
   b->ready = false;
   drop_graph(b);
   const auto t0 = std::chrono::steady_clock::now();
-  bool tuned = false;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  const bool first = !b->tuned;
   int st = EIFMM_OK;
+  // trees; at the first call, the work of every candidate depth of the autotuned
+  // problems (their trees are built once per candidate, then dropped)
   for (int p = 0; p < np && !st; ++p) {
     const eifmm_config &c = b->cfg[p];
     if (b->plans[p]) {
       st = eifmm_set_points(b->plans[p], xyz[p], s);
       continue;
     }
-    if (c.depth >= 0) {
-      if (!(st = shared_plan(b, p, c.depth, &b->plans[p])))
-        st = eifmm_set_points(b->plans[p], xyz[p], s);
-      b->depth[p] = c.depth;
-      continue;
-    }
-    // autotune the depth: time the evaluation (tree fixed) at every candidate
-    tuned = true;
-    int lo, hi;
-    depth_candidates(c.n, lo, hi);
-    double best = 0;
-    for (int k = lo; k <= hi && !st; ++k) {
-      eifmm_plan h = nullptr;
-      if ((st = shared_plan(b, p, k, &h))) break;
-      st = eifmm_set_points(h, xyz[p], s);
-      double *sg = b->scratch, *fo = b->scratch + b->scratch_n;
-      const int64_t ld = std::max<int64_t>(c.n, 1);
-      if (!st) st = eifmm_evaluate(h, sg, 1, ld, fo, ld, s);
-      hipEventRecord(e0, s);
-      for (int rep = 0; rep < 2 && !st; ++rep) st = eifmm_evaluate(h, sg, 1, ld, fo, ld, s);
-      hipEventRecord(e1, s);
-      const double ms = st ? 0 : elapsed_ms(e0, e1);
-      if (!st && (!b->plans[p] || ms < best)) {
-        if (b->plans[p]) release(b->plans[p]);
-        b->plans[p] = h;
-        b->depth[p] = k;
-        best = ms;
-      } else {
+    if (c.depth < 0) {
+      int lo, hi;
+      depth_candidates(c.n, lo, hi);
+      b->cand_lo[p] = lo;
+      b->cand[p].clear();
+      for (int k = lo; k <= hi && !st; ++k) {
+        eifmm_plan h = nullptr;
+        if ((st = shared_plan(b, p, k, &h))) break;
+        st = eifmm_set_points(h, xyz[p], s);
+        if (!st) b->cand[p].push_back(work_of(h->P));
         release(h);
       }
+      if (st) break;
+      b->depth[p] = b->cand_lo[p] + pick_depth(b, p);
+    } else {
+      b->depth[p] = c.depth;
     }
+    if (!(st = shared_plan(b, p, b->depth[p], &b->plans[p])))
+      st = eifmm_set_points(b->plans[p], xyz[p], s);
   }
-  if (!st) st = prepare(b, b->m2l_rbt);
-  if (!st && b->m2l_rbt == 0) {
-    // tile height of the fused M2L launch: one full pass to fill the expansions,
-    // then the M2L launch alone for 4, 5 and 6 row blocks
-    tuned = true;
-    st = stage_io(b, nullptr, nullptr, s);
+  if (!st) st = prepare(b, b->m2l_rbt > 0 ? b->m2l_rbt : 0);
+  if (!st && first) {
+    // measure the fused pass once (zero sigma), turn the phase times into rates,
+    // choose the depths again with them and rebuild the problems that change
+    st = calibrate(b, s);
+    bool changed = false;
+    for (int p = 0; p < np && !st; ++p) {
+      if (b->cfg[p].depth >= 0 || b->cand[p].empty()) continue;
+      const int k = b->cand_lo[p] + pick_depth(b, p);
+      if (k == b->depth[p]) continue;
+      changed = true;
+      release(b->plans[p]);
+      b->plans[p] = nullptr;
+      b->depth[p] = k;
+      if (!(st = shared_plan(b, p, k, &b->plans[p])))
+        st = eifmm_set_points(b->plans[p], xyz[p], s);
+    }
+    if (!st && changed) st = prepare(b, 0);
+    // tile height of the fused M2L launch: the M2L launch alone for 4, 5 and 6
+    // row blocks, after one full pass that fills the expansions
+    if (!st) st = stage_io(b, nullptr, nullptr, s);
     if (!st) batch_run(b->ex, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
     double best = 0;
     int pick = 6;
     for (int rbt = 4; rbt <= 6 && !st; ++rbt) {
@@ -758,16 +867,17 @@ int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream
         pick = rbt;
       }
     }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
     b->m2l_rbt = pick;
     if (!st) st = prepare(b, pick);
+    if (!st) b->tuned = true;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (!st) {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = EIFMM_EHIP;
   }
-  if (tuned)
+  if (first)
     b->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
                       .count();
   if (st) return st;

@@ -1542,7 +1542,8 @@ void run_group(const BatchExec &B, const BatchGroup &g, int phase, hipStream_t s
                            B.io_dev + g.first, g.count, s);
 }
 
-void run_groups(const BatchExec &B, int phase, hipStream_t s) {
+void run_groups(const BatchExec &B, int phase, hipStream_t s, const hipEvent_t *mark,
+                int &m) {
   for (const BatchGroup &g : B.groups) {
     switch (g.kind) {
       case EIFMM_K_LAPLACE: run_group<EIFMM_K_LAPLACE>(B, g, phase, s); break;
@@ -1550,6 +1551,7 @@ void run_groups(const BatchExec &B, int phase, hipStream_t s) {
       case EIFMM_K_GAUSS: run_group<EIFMM_K_GAUSS>(B, g, phase, s); break;
       default: run_group<EIFMM_K_SQDIST>(B, g, phase, s); break;
     }
+    if (mark) hipEventRecord(mark[m++], s);
   }
 }
 
@@ -1692,27 +1694,42 @@ void batch_run_m2l(const BatchExec &B, hipStream_t s) {
   launch_gemm_fused(B.m2l, MODE_M2L, B.mixed, B.sk_groups, B.sk_ws, B.dvec, s);
 }
 
-void batch_run(const BatchExec &B, hipStream_t s) {
+int batch_marks(const BatchExec &B) { return 9 + 3 * (int)B.groups.size(); }
+
+void batch_run(const BatchExec &B, hipStream_t s, const hipEvent_t *mark) {
+  int m = 0;
+  auto tick = [&]() {
+    if (mark) hipEventRecord(mark[m++], s);
+  };
+  tick();
   if (B.total_pts > 0)
     hipLaunchKernelGGL((k_gather_sigma<true>), dim3((unsigned)((B.total_pts + 255) / 256)),
                        dim3(256), 0, s, LeafDesc{}, IoDesc{}, B.leaf_dev, B.io_dev, B.nprob,
                        B.total_pts);
-  run_groups(B, 0, s);  // near field
-  run_groups(B, 1, s);  // P2M
+  tick();
+  run_groups(B, 0, s, mark, m);  // near field, one mark per kernel kind
+  run_groups(B, 1, s, mark, m);  // P2M
   for (int k = B.maxdepth - 1; k >= 2; --k)
     launch_gemm_fused(B.m2m[k], MODE_M2M, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  tick();
   if (B.what_blk > 0)
     hipLaunchKernelGGL(k_trsm_list, dim3(B.what_blk), dim3(64), B.what_shm, s, B.what_dev,
                        B.what_n);
+  tick();
   launch_gemm_fused(B.pre, MODE_PROJ, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  tick();
   batch_run_m2l(B, s);
+  tick();
   launch_gemm_fused(B.post, MODE_PROJ, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  tick();
   for (int k = 3; k <= B.maxdepth; ++k)
     launch_gemm_fused(B.l2l[k], MODE_L2L, false, B.sk_groups, B.sk_ws, B.dvec, s);
+  tick();
   if (B.lhat_blk > 0)
     hipLaunchKernelGGL(k_trsm_list, dim3(B.lhat_blk), dim3(64), B.lhat_shm, s, B.lhat_dev,
                        B.lhat_n);
-  run_groups(B, 2, s);  // L2P and the final sum
+  tick();
+  run_groups(B, 2, s, mark, m);  // L2P and the final sum
 }
 
 }  // namespace eifmm

@@ -205,6 +205,9 @@ struct Plan {
   size_t near_cap = 0;
   int *chunk_ptr = nullptr;     // per active leaf: first 64-target chunk (prefix sum)
   int64_t nchunk = 0;           // number of 64-target chunks over all leaves
+  unsigned long long *npairs_dev = nullptr;  // near-field work counters (2)
+  int64_t near_point_pairs = 0;  // target x source point pairs of the near field
+  int64_t near_lane_pairs = 0;   // the same with targets rounded up to 64-lane chunks
   bool points_set = false;
   int64_t nact[kMaxLevels] = {0};
   int64_t cls_off[kMaxLevels][9] = {{0}};
@@ -253,7 +256,12 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
 int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans, int m2l_rbt, int sk_groups,
                   double *sk_ws);
 void batch_release(BatchExec &B);
-void batch_run(const BatchExec &B, hipStream_t s);
+// mark: null, or batch_marks(B) events recorded at the phase boundaries: start,
+// after the sigma gather, after the near field of each kernel kind, after P2M of
+// each kind, after M2M, What, the first projection, M2L, the second projection,
+// L2L, lhat, and after L2P of each kind
+void batch_run(const BatchExec &B, hipStream_t s, const hipEvent_t *mark = nullptr);
+int batch_marks(const BatchExec &B);
 void batch_run_m2l(const BatchExec &B, hipStream_t s);
 
 }  // namespace eifmm

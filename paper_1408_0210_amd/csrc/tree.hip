@@ -144,6 +144,28 @@ __device__ inline bool box_active(const int *__restrict__ ls, int shift, int64_t
 }
 
 // per block of 256 boxes: active count per child class and in total
+// near-field work: out[0] = point pairs (count(leaf) x the point count of its
+// near list, summed over active leaves), out[1] = the same with count(leaf)
+// rounded up to 64-target chunks (the sweeps the near-field kernels make);
+// integer atomics, so the totals are exact
+__global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__ act,
+                                                    const int *__restrict__ ls,
+                                                    const int *__restrict__ near_ptr,
+                                                    const int *__restrict__ near_src, int nact,
+                                                    unsigned long long *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nact) return;
+  const uint32_t key = act[j];
+  long long src = 0;
+  for (int q = near_ptr[j]; q < near_ptr[j + 1]; ++q) {
+    const uint32_t sk = act[near_src[q]];
+    src += ls[sk + 1] - ls[sk];
+  }
+  const long long cnt = ls[key + 1] - ls[key];
+  atomicAdd(out, (unsigned long long)(cnt * src));
+  atomicAdd(out + 1, (unsigned long long)(((cnt + 63) / 64) * 64 * src));
+}
+
 // number of 64-target chunks of each active leaf; 0 past the active count
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict__ act,
                                                      const int *__restrict__ ls, int nact,
@@ -466,14 +488,23 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
                        P.ld[depth].act, P.leaf_start, (int)P.nact[depth], cap + 1, P.list_cnt);
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
+  hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), s);
+  if (P.nact[depth] > 0)
+    hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
+                       s, P.ld[depth].act, P.leaf_start, P.near_ptr, P.near_src,
+                       (int)P.nact[depth], P.npairs_dev);
   int nchunk = 0;
+  unsigned long long npairs[2] = {0, 0};
   hipMemcpyAsync(&nchunk, P.chunk_ptr + P.nact[depth], sizeof(int), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(npairs, P.npairs_dev, sizeof(npairs), hipMemcpyDeviceToHost, s);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     P.last_hip_error = (int)e;
     return EIFMM_EHIP;
   }
   P.nchunk = nchunk;
+  P.near_point_pairs = (int64_t)npairs[0];
+  P.near_lane_pairs = (int64_t)npairs[1];
   return EIFMM_OK;
 }
 

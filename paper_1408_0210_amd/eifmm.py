@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("m2l_flops", ctypes.c_double), ("proj_flops", ctypes.c_double),
                 ("active_boxes", ctypes.c_int64 * (MAX_DEPTH + 1)),
                 ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
-                ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("near_point_pairs", ctypes.c_int64)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -160,7 +161,7 @@ def _stats_dict(s, depth):
                 m2l_flops=s.m2l_flops,
                 active_boxes={k: s.active_boxes[k] for k in range(depth + 1)},
                 il_pairs={k: s.il_pairs[k] for k in lv}, near_pairs=s.near_pairs,
-                hip_error=s.hip_error)
+                near_point_pairs=s.near_point_pairs, hip_error=s.hip_error)
 
 
 class Plan:

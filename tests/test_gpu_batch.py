@@ -47,9 +47,8 @@ def _small_problems():
     for i, (n, kern, dist, depth) in enumerate(spec):
         x = (W.uniform_points(n, 500 + i) if dist == "uniform"
              else W.cluster_points(n, 4, 0.03, 600 + i, 700 + i))
-        out.append(dict(n=n, kernel=kern, param=0.01 if kern == "gauss" else 0.0, tau=1e-6,
-                        tol_mode=1 if kern == "gauss" else 0, compress_tol=1e-6, depth=depth,
-                        points=x, sigma=W.potentials(n, 800 + i)))
+        out.append(dict(n=n, kernel=kern, param=0.01 if kern == "gauss" else 0.0, depth=depth,
+                        points=x, sigma=W.potentials(n, 800 + i), **W.BATCH_TOLERANCES[kern]))
     return out
 
 
