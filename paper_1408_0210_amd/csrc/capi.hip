@@ -79,7 +79,12 @@ void release(eifmm_plan h) {
     hipEventDestroy(e.b);
   }
   for (void *p : owned(h)) hipFree(p);
+  if (P.job_evt) {
+    hipEventSynchronize(P.job_evt);
+    hipEventDestroy(P.job_evt);
+  }
   if (P.job_dev) hipFree(P.job_dev);
+  if (P.job_pin) hipHostFree(P.job_pin);
   delete h;
 }
 
@@ -331,7 +336,8 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
 // work of one problem's pass at its current depth, in the units of the rates:
 // near-field lane pairs, M2L flops (2 r_k^2 per interaction pair), P2M + L2P
 // kernel evaluations, and sum over levels of active boxes x d_k^2
-std::array<double, 4> work_of(const Plan &P) {
+std::array<double, 4> work_of(Plan &P) {
+  tree_counts(P);
   std::array<double, 4> w{};
   w[0] = (double)P.near_lane_pairs;
   if (P.depth >= 2) {
@@ -560,6 +566,10 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
   if (!h || !out || out->struct_size != (int32_t)sizeof(eifmm_stats)) return EIFMM_EINVAL;
   Plan &P = h->P;
   timing_drain(P);
+  if (!P.host_only && P.points_set) {
+    hipSetDevice(P.device);
+    if (tree_counts(P) != EIFMM_OK) return EIFMM_EHIP;
+  }
   eifmm_stats s;
   std::memset(&s, 0, sizeof(s));
   s.struct_size = sizeof(eifmm_stats);

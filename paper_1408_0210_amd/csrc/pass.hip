@@ -136,6 +136,7 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
   const int lane = threadIdx.x;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
   const int lane = threadIdx.x;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
@@ -340,6 +342,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
+  if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
   IoDesc O;
   if constexpr (BATCH)
     O = io[prob];
@@ -503,6 +506,7 @@ __global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ 
 // the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
 constexpr int GT_CB = 8, GT_COLS = 16 * GT_CB;
+constexpr int kMaxPieces = 512;  // pieces of one split tile: at most its terms + 1
 
 // Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result layouts differ: FP64 keeps rows (l / 16) + 4 q of column l % 16 in
@@ -576,11 +580,12 @@ __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
 // workgroups, the first F = floor(T / G) G tiles run whole, G at a time, all
 // workgroups walking the terms in the same order (so the operators they read are
 // shared in L2); within a round the tiles of one XCD are contiguous in space.
-// The R units of the remaining tiles are split evenly: workgroup g takes
-// [S + B_g, S + B_{g+1}) with B_g = floor(g R / G) and S the first remaining
-// unit.  A tile split between workgroups is stored in pieces (slot 2g for the
-// first remaining tile of g, 2g + 1 for its last) that k_gemm_fixup adds in
-// workgroup order, so results do not depend on timing.
+// The R units of the remaining tiles are split evenly over G_t = min(G, R)
+// workgroups: workgroup g < G_t takes [S + B_g, S + B_{g+1}) with
+// B_g = floor(g R / G_t) and S the first remaining unit.  A tile split between
+// workgroups is stored in pieces (slot 2g for the first remaining tile of g,
+// 2g + 1 for its last) that k_gemm_fixup adds in workgroup order, so results do
+// not depend on timing.
 __device__ inline int64_t sk_bound(int64_t g, int64_t units, int G) { return g * units / G; }
 
 __device__ inline int find_job_units(const GemmJob *__restrict__ jobs, int njobs, int64_t u) {
@@ -804,7 +809,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
   const int64_t R = units - S;
-  const int64_t ua = S + sk_bound(g, R, G), ub = S + sk_bound(g + 1, R, G);
+  const int Gt = (int)min((int64_t)G, R);  // workgroups sharing the tail: each owns >= 1 unit
+  if (g >= Gt) return;
+  const int64_t ua = S + sk_bound(g, R, Gt), ub = S + sk_bound(g + 1, R, Gt);
   for (int64_t u = ua; u < ub;) {
     const GemmJob J = jobs[find_job_units(jobs, njobs, u)];
     const int64_t local = u - J.units_start;
@@ -831,16 +838,29 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
   const int64_t R = units - S;
+  const int Gt = (int)min((int64_t)G, R);
   const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
   const int tile_local = tile - J.tiles_start;
   // unit range of the tile relative to S
   const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms - S, te = ts + J.nterms;
-  int64_t glo = ts * G / R;
-  while (glo + 1 < G && sk_bound(glo + 1, R, G) <= ts) ++glo;
-  while (glo > 0 && sk_bound(glo, R, G) > ts) --glo;
+  int64_t glo = ts * Gt / R;
+  while (glo + 1 < Gt && sk_bound(glo + 1, R, Gt) <= ts) ++glo;
+  while (glo > 0 && sk_bound(glo, R, Gt) > ts) --glo;
   int64_t ghi = glo;
-  while (ghi + 1 < G && sk_bound(ghi + 1, R, G) < te) ++ghi;
+  while (ghi + 1 < Gt && sk_bound(ghi + 1, R, Gt) < te) ++ghi;
   if (ghi == glo) return;  // written directly
+  // workspace slots of the pieces, in workgroup order (every workgroup of the
+  // tail owns at least one unit, so each one in [glo, ghi] wrote a piece)
+  __shared__ int slot[kMaxPieces];
+  __shared__ int npieces;
+  if (threadIdx.x == 0) {
+    int np = 0;
+    for (int64_t g = glo; g <= ghi && np < kMaxPieces; ++g)
+      slot[np++] = (int)(2 * g + (sk_bound(g, R, Gt) >= ts ? 0 : 1));
+    npieces = np;
+  }
+  __syncthreads();
+  const int np = npieces;
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
   const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
@@ -850,12 +870,7 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
     const int jo = col0 + jt;
     if (rt >= nrows || jo >= ncols) continue;
     double v = 0.0;
-    for (int64_t g = glo; g <= ghi; ++g) {
-      const int64_t b0 = sk_bound(g, R, G);
-      if (sk_bound(g + 1, R, G) == b0) continue;  // no units (R < G): wrote no piece
-      const int slot = (int)(2 * g + (b0 >= ts ? 0 : 1));
-      v += ws[(size_t)slot * TILE + e];
-    }
+    for (int i = 0; i < np; ++i) v += ws[(size_t)slot[i] * TILE + e];
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
     int tso;
     double *Cout = J.C;
@@ -925,7 +940,7 @@ int64_t finish_units(std::vector<GemmJob> &h, int first) {
 }  // namespace
 
 // Job tables of a (points, nrhs) pair, uploaded once and reused.
-int build_jobs(Plan &P, int nrhs) {
+int build_jobs(Plan &P, int nrhs, hipStream_t s) {
   const int depth = P.depth;
   const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
   std::vector<GemmJob> h;
@@ -1087,12 +1102,31 @@ int build_jobs(Plan &P, int nrhs) {
     jt.l2l_units[k] = finish_units(h, jt.l2l_first[k]);
   }
   P.jobs_host = h;
-  if (P.job_dev) hipFree(P.job_dev);
-  P.job_dev = nullptr;
   if (!h.empty()) {
-    if (hipMalloc(&P.job_dev, sizeof(GemmJob) * h.size()) != hipSuccess) return EIFMM_ENOMEM;
-    if (hipMemcpy(P.job_dev, h.data(), sizeof(GemmJob) * h.size(), hipMemcpyHostToDevice) !=
-        hipSuccess)
+    // the table goes to the device from pinned memory, asynchronously on the
+    // stream of the evaluation; buffers grow only when the job count does
+    if (h.size() > P.job_cap) {
+      if (P.job_evt) hipEventSynchronize(P.job_evt);
+      if (P.job_dev) hipFree(P.job_dev);
+      if (P.job_pin) hipHostFree(P.job_pin);
+      P.job_dev = nullptr;
+      P.job_pin = nullptr;
+      P.job_cap = 0;
+      const size_t cap = h.size() + h.size() / 2 + 16;
+      if (hipMalloc(&P.job_dev, sizeof(GemmJob) * cap) != hipSuccess ||
+          hipHostMalloc((void **)&P.job_pin, sizeof(GemmJob) * cap) != hipSuccess) {
+        hipGetLastError();
+        return EIFMM_ENOMEM;
+      }
+      P.job_cap = cap;
+      if (!P.job_evt && hipEventCreateWithFlags(&P.job_evt, hipEventDisableTiming) != hipSuccess)
+        return EIFMM_EHIP;
+    }
+    if (hipEventSynchronize(P.job_evt) != hipSuccess) return EIFMM_EHIP;
+    std::memcpy(P.job_pin, h.data(), sizeof(GemmJob) * h.size());
+    if (hipMemcpyAsync(P.job_dev, P.job_pin, sizeof(GemmJob) * h.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipEventRecord(P.job_evt, s) != hipSuccess)
       return EIFMM_EHIP;
   }
   jt.nrhs = nrhs;
@@ -1352,7 +1386,7 @@ void timing_drain(Plan &P) {
 int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
              hipStream_t s) {
   if (P.jobs.nrhs != nrhs) {
-    int st = build_jobs(P, nrhs);
+    int st = build_jobs(P, nrhs, s);
     if (st != EIFMM_OK) return st;
   }
   const int64_t m = P.n * nrhs;
@@ -1574,7 +1608,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
     if (!P->points_set || P->depth < 2) return EIFMM_ESTATE;
     if ((P->cfg.precision == EIFMM_PREC_MIXED) != B.mixed) return EIFMM_EINVAL;
     if (P->jobs.nrhs != 1) {
-      int st = build_jobs(*P, 1);
+      int st = build_jobs(*P, 1, nullptr);
       if (st) return st;
     }
     B.maxdepth = std::max(B.maxdepth, P->depth);

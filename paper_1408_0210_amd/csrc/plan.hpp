@@ -204,10 +204,11 @@ struct Plan {
   int *near_src = nullptr;      // source leaf slots
   size_t near_cap = 0;
   int *chunk_ptr = nullptr;     // per active leaf: first 64-target chunk (prefix sum)
-  int64_t nchunk = 0;           // number of 64-target chunks over all leaves
+  int64_t nchunk = 0;           // bound on the 64-target chunks over all leaves (grid size)
   unsigned long long *npairs_dev = nullptr;  // near-field work counters (2)
   int64_t near_point_pairs = 0;  // target x source point pairs of the near field
   int64_t near_lane_pairs = 0;   // the same with targets rounded up to 64-lane chunks
+  bool counts_pending = false;   // the three counts above are still on the device
   bool points_set = false;
   int64_t nact[kMaxLevels] = {0};
   int64_t cls_off[kMaxLevels][9] = {{0}};
@@ -226,6 +227,9 @@ struct Plan {
   // gathered-GEMM job tables (rebuilt when the points or nrhs change)
   JobTables jobs;
   GemmJob *job_dev = nullptr;
+  size_t job_cap = 0;             // jobs job_dev and job_pin hold
+  GemmJob *job_pin = nullptr;     // pinned staging copy of the job table
+  hipEvent_t job_evt = nullptr;   // recorded after the last copy from job_pin
   std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
@@ -246,9 +250,10 @@ int pick_rbt(int nrb);
 
 // device-side entry points (tree.hip, pass.hip)
 int tree_build(Plan &P, const double *xyz_in, hipStream_t s);
+int tree_counts(Plan &P);
 int lists_export(Plan &P, int level, int64_t *nactive, uint32_t *active, int64_t *near_ptr,
                  uint32_t *near_src, int64_t *il_ptr, uint32_t *il_src, int16_t *il_off);
-int build_jobs(Plan &P, int nrhs);
+int build_jobs(Plan &P, int nrhs, hipStream_t s);
 void timing_drain(Plan &P);
 int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
              hipStream_t s);

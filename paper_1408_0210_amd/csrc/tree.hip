@@ -407,9 +407,11 @@ void build_active(Plan &P, int k, hipStream_t s) {
                      counts, P.ld[k].act, P.ld[k].slot, P.ld[k].cls);
 }
 
-// CSR list for level k into (ptr, src, off); returns the entry count.
+// CSR list for level k into (ptr, src, off).  bounded: the entry count cannot
+// exceed cap (27 near entries per box), so it is not read back and 0 is
+// returned; otherwise returns the entry count, or -1 if it exceeds cap.
 int64_t build_list(Plan &P, int k, int mode, int *ptr, int *src, int16_t *off, size_t cap,
-                   hipStream_t s) {
+                   bool bounded, hipStream_t s) {
   LevelDev &L = P.ld[k];
   const int *nact = P.counts_dev + 16 * k + 8;
   const int grid = (int)((L.cap + 1 + 127) / 128);
@@ -422,9 +424,11 @@ int64_t build_list(Plan &P, int k, int mode, int *ptr, int *src, int16_t *off, s
                        cnt, nullptr, nullptr, P.code2id);
   scan_exclusive_i32(cnt, ptr, (int64_t)L.cap + 1, P.scan_tmp, s);
   int total = 0;
-  hipMemcpyAsync(&total, ptr + P.nact[k], sizeof(int), hipMemcpyDeviceToHost, s);
-  hipStreamSynchronize(s);
-  if ((size_t)total > cap) return -1;
+  if (!bounded) {
+    hipMemcpyAsync(&total, ptr + P.nact[k], sizeof(int), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    if ((size_t)total > cap) return -1;
+  }
   if (mode == 0)
     hipLaunchKernelGGL(k_list<0>, dim3(grid), dim3(128), 0, s, k, L.act, nact, L.slot, ptr,
                        nullptr, src, nullptr, nullptr);
@@ -477,34 +481,49 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     P.cls_off[k][8] = P.nact[k];
     P.il_pairs[k] = k >= 2 ? host_counts[16 * k + 9] : 0;
   }
-  // near lists of the leaf level (used by the near-field pass)
-  int64_t tot = build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, s);
-  if (tot < 0) return EIFMM_ENOMEM;
-  P.near_total = tot;
-  // 64-target chunks of the leaves (the grid of the near-field and L2P kernels)
+  // near lists of the leaf level (used by the near-field pass); at most 27
+  // entries per box, within near_cap = 27 cap
+  build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, true, s);
+  // 64-target chunks of the leaves (the grid of the near-field and L2P kernels).
+  // The grid is launched with the bound nact + ceil(n / 64) on the chunk count,
+  // and workgroups past chunk_ptr[nact] exit, so the count is not read back.
   {
     const int64_t cap = P.ld[depth].cap;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, s,
                        P.ld[depth].act, P.leaf_start, (int)P.nact[depth], cap + 1, P.list_cnt);
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
+  P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 63) / 64 : 0;
   hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), s);
   if (P.nact[depth] > 0)
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
                        s, P.ld[depth].act, P.leaf_start, P.near_ptr, P.near_src,
                        (int)P.nact[depth], P.npairs_dev);
-  int nchunk = 0;
-  unsigned long long npairs[2] = {0, 0};
-  hipMemcpyAsync(&nchunk, P.chunk_ptr + P.nact[depth], sizeof(int), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(npairs, P.npairs_dev, sizeof(npairs), hipMemcpyDeviceToHost, s);
-  e = hipStreamSynchronize(s);
+  P.counts_pending = true;
+  e = hipGetLastError();
   if (e != hipSuccess) {
     P.last_hip_error = (int)e;
     return EIFMM_EHIP;
   }
-  P.nchunk = nchunk;
+  return EIFMM_OK;
+}
+
+// Copies the counts the tree build leaves on the device (near-list entries,
+// near-field point pairs) to the plan; synchronises the host with the device.
+int tree_counts(Plan &P) {
+  if (!P.counts_pending) return EIFMM_OK;
+  const int depth = P.depth;
+  int total = 0;
+  unsigned long long npairs[2] = {0, 0};
+  if (P.nact[depth] > 0 &&
+      (hipMemcpy(&total, P.near_ptr + P.nact[depth], sizeof(int), hipMemcpyDeviceToHost) !=
+           hipSuccess ||
+       hipMemcpy(npairs, P.npairs_dev, sizeof(npairs), hipMemcpyDeviceToHost) != hipSuccess))
+    return EIFMM_EHIP;
+  P.near_total = total;
   P.near_point_pairs = (int64_t)npairs[0];
   P.near_lane_pairs = (int64_t)npairs[1];
+  P.counts_pending = false;
   return EIFMM_OK;
 }
 
@@ -545,7 +564,8 @@ int lists_export(Plan &P, int level, int64_t *nactive, uint32_t *active, int64_t
       for (int64_t j = 0; j <= na; ++j) optr[j] = 0;
       continue;
     }
-    int64_t tot = build_list(P, level, mode, dptr, dsrc, doff, mode == 0 ? cap_near : cap_il, s);
+    int64_t tot =
+        build_list(P, level, mode, dptr, dsrc, doff, mode == 0 ? cap_near : cap_il, false, s);
     if (tot < 0) {
       rc = EIFMM_ENOMEM;
       break;
