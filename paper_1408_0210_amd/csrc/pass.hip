@@ -612,44 +612,64 @@ __device__ inline int find_job_tiles(const GemmJob *__restrict__ jobs, int njobs
   return lo;
 }
 
-// terms [term0, term1) of one tile; writes the result (part == nullptr) or a piece
+// Source metadata of one target column of a gathered-GEMM tile.
+struct ColState {
+  const int *slot_map;  // slot map of the source level
+  const void *B;        // source expansions
+  uint32_t tkey;        // target key
+  int tsl, r;           // target slot, right-hand side
+  int valid;
+};
+
+// terms [term0, term1) of one tile; writes the result (part == nullptr) or a piece.
+// A (the operators) is shared by the 4 waves and staged through LDS; each wave
+// multiplies its own 32 columns, so B (the gathered source expansions) goes
+// straight from memory to registers: within each 16-k chunk lane l supplies
+// k = 4 (l / 16) + ks at k-step ks, four consecutive elements of its column, and
+// the operator tables use the same k order (setup.cpp).
 template <typename T, int MODE, bool FOLD, int RBT>
 __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, int term1,
                                  double *__restrict__ part, const int8_t *__restrict__ dvec,
-                                 T (*As)[RBT * 4 * 64], T (*Bs)[4 * GT_CB * 64]) {
+                                 T (*As)[RBT * 4 * 64], ColState *cst) {
   typedef typename Mfma<T>::v4 V4;
   typedef typename Mfma<T>::p2 P2;
   typedef double D4 __attribute__((ext_vector_type(4)));
   constexpr int NA = RBT * 128;         // A chunk, in pairs
   constexpr int QA = (NA + 255) / 256;  // pairs per thread
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int jl = t >> 1, hh = t & 1;
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
   const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
   const int ncols = J.ntgt * J.nrhs;
+  const int koff = 4 * (lane >> 4);
 
-  // the column this thread loads
-  const int jc = col0 + jl;
-  const bool cvalid = jc < ncols;
-  int r = 0, tsl = 0;
-  uint32_t tkey = 0;
-  const int *cslot = J.src_slot;
-  const T *cB = (const T *)J.Bsrc;
-  if (cvalid) {
-    const int tt = jc / J.nrhs;
-    r = jc - tt * J.nrhs;
-    if (MODE == MODE_M2L && J.colref) {
-      const ColRef cr = J.colref[tt];
-      const ColSrc &cs = J.colsrc[cr.rec];
-      tsl = cr.slot;
-      tkey = cs.keys[tsl];
-      cslot = cs.slot;
-      cB = (const T *)cs.B;
-    } else {
-      tsl = J.tgt ? J.tgt[tt] : tt;
-      if (MODE != MODE_PROJ) tkey = J.tgt_keys[tsl];
+  // the two columns of this lane (one per 16-column block of the wave); their
+  // source metadata waits in LDS (this thread's own slots) until each term
+  // starts, which keeps it out of the registers the accumulators need
+  ColState *my = cst + 2 * t;
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int jc = col0 + 16 * (2 * w + jj) + (lane & 15);
+    ColState c{};
+    c.valid = jc < ncols;
+    c.slot_map = J.src_slot;
+    c.B = J.Bsrc;
+    if (c.valid) {
+      const int tt = jc / J.nrhs;
+      c.r = jc - tt * J.nrhs;
+      if (MODE == MODE_M2L && J.colref) {
+        const ColRef cr = J.colref[tt];
+        const ColSrc &cs = J.colsrc[cr.rec];
+        c.tsl = cr.slot;
+        c.tkey = cs.keys[cr.slot];
+        c.slot_map = cs.slot;
+        c.B = cs.B;
+      } else {
+        c.tsl = J.tgt ? J.tgt[tt] : tt;
+        if (MODE != MODE_PROJ) c.tkey = J.tgt_keys[c.tsl];
+      }
     }
+    my[jj] = c;
   }
   V4 acc[RBT][2];
   D4 sum[RBT][2];
@@ -663,13 +683,19 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
     }
   }
-  P2 ra[QA], rbv[4];
-  const T *srcp = nullptr;
+  P2 ra[QA];
+  P2 bn[2][2], bc[2][2];  // B of the next and the current chunk: [column][pair]
+  const T *srcp[2] = {nullptr, nullptr};
   const T *Ap = nullptr;
   auto fetch = [&](int it) {
     const int term = it / nkc, kc = it - term * nkc;
     if (kc == 0) {
-      srcp = gemm_source<T, MODE>(J, term, cvalid, tkey, tsl, r, dvec, cslot, cB);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const ColState c = my[jj];
+        srcp[jj] = gemm_source<T, MODE>(J, term, c.valid, c.tkey, c.tsl, c.r, dvec, c.slot_map,
+                                        (const T *)c.B);
+      }
       Ap = gemm_operand<T, MODE>(J, term);
     }
 #pragma unroll
@@ -681,13 +707,16 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       else
         ra[q] = P2{0, 0};
     }
-    if (srcp) {
-      const P2 *s2 = (const P2 *)(srcp + kc * 16 + 8 * hh);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rbv[q] = s2[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rbv[q] = P2{0, 0};
+    for (int jj = 0; jj < 2; ++jj) {
+      if (srcp[jj]) {
+        const P2 *s2 = (const P2 *)(srcp[jj] + kc * 16 + koff);
+        bn[jj][0] = s2[0];
+        bn[jj][1] = s2[1];
+      } else {
+        bn[jj][0] = P2{0, 0};
+        bn[jj][1] = P2{0, 0};
+      }
     }
   };
   auto stash = [&](int buf) {
@@ -695,15 +724,6 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     for (int q = 0; q < QA; ++q) {
       const int e = t + 256 * q;
       if (e < NA) *(P2 *)(&As[buf][2 * e]) = ra[q];
-    }
-    const int cb = jl >> 4, c16 = jl & 15;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int kl = 8 * hh + 2 * q + e;
-        Bs[buf][((kl >> 2) * GT_CB + cb) * 64 + c16 + 16 * (kl & 3)] = e ? rbv[q].y : rbv[q].x;
-      }
     }
   };
 
@@ -715,6 +735,11 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   }
   for (int it = it0; it < it1; ++it) {
     const int cur = (it - it0) & 1;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      bc[jj][0] = bn[jj][0];
+      bc[jj][1] = bn[jj][1];
+    }
     if (it + 1 < it1) fetch(it + 1);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
@@ -722,7 +747,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
 #pragma unroll
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) b[jj] = Bs[cur][(ks * GT_CB + 2 * w + jj) * 64 + lane];
+      for (int jj = 0; jj < 2; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
 #pragma unroll
       for (int i = 0; i < RBT; ++i)
         if (rowok[i]) {
@@ -793,7 +818,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
                                                  const int8_t *__restrict__ dvec) {
   constexpr int TILE = RBT * 16 * GT_COLS;
   __shared__ T As[2][RBT * 4 * 64];
-  __shared__ T Bs[2][4 * GT_CB * 64];
+  __shared__ ColState cst[2 * 256];
   const int g = blockIdx.x;
   // whole tiles, G at a time; the tiles of one XCD (g mod 8) are contiguous
   const int full = (ntiles / G) * G;
@@ -802,7 +827,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   for (int t0 = 0; t0 < full; t0 += G) {
     const int tile = t0 + gx;
     const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
-    gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, 0, J.nterms, nullptr, dvec, As, Bs);
+    gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, 0, J.nterms, nullptr, dvec, As,
+                                  cst);
   }
   if (full == ntiles) return;
   // the remaining units, split evenly
@@ -822,7 +848,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
     u = ts + term1;
     const bool whole = term0 == 0 && term1 == J.nterms;
     double *part = whole ? nullptr : ws + (size_t)(2 * g + (ua >= ts ? 0 : 1)) * TILE;
-    gemm_tile<T, MODE, FOLD, RBT>(J, tile_local, term0, term1, part, dvec, As, Bs);
+    gemm_tile<T, MODE, FOLD, RBT>(J, tile_local, term0, term1, part, dvec, As, cst);
   }
 }
 

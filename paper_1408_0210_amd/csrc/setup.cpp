@@ -280,14 +280,15 @@ void solve_mtinv(const LevelHost &lv, double *x) {
 }
 
 // Dense rows x cols (row-major) -> MFMA fragment order for a 16x16x4 A operand:
-// [rb = rows/16][ks = cols/4][lane 64], lane l holding (16 rb + l % 16, 4 ks + l / 16);
-// padded rows / columns are zero.
+// [rb = rows/16][ks = cols/4][lane 64], lane l holding row 16 rb + l % 16 and, within
+// the 16-column chunk ks / 4, column 4 (l / 16) + ks % 4 (the gathered GEMM feeds B
+// in the same k order); padded rows / columns are zero.
 void to_fragments(const double *A, int rows, int cols, int rpad, int cpad, double *out) {
   const int nrb = rpad / 16, nks = cpad / 4;
   for (int rb = 0; rb < nrb; ++rb)
     for (int ks = 0; ks < nks; ++ks)
       for (int l = 0; l < 64; ++l) {
-        int r = 16 * rb + (l & 15), c = 4 * ks + (l >> 4);
+        int r = 16 * rb + (l & 15), c = 16 * (ks >> 2) + 4 * (l >> 4) + (ks & 3);
         out[((size_t)rb * nks + ks) * 64 + l] =
             (r < rows && c < cols) ? A[(size_t)r * cols + c] : 0.0;
       }
