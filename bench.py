@@ -209,6 +209,7 @@ def run_batched(args):
                 rel_l2_sampled_max=max(errs),
                 m2l_frac=st["m2l_flops"] / (m2l_ms * 1e-3) / (PEAK_TFLOPS["mixed"] * 1e12),
                 sequential_ms=ms_seq, sequential_value=R * float(n) ** 2 / (ms_seq * 1e-3),
+                phase_ms={k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]},
                 note="tree built once; t covers evaluate of 64 RHS; value = 64 N^2 / t; "
                      "sequential = the same 64 RHS as 64 single-RHS evaluations (mixed)")
 

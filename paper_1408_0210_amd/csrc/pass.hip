@@ -63,9 +63,11 @@ __host__ __device__ inline double dev_param(int kind, double p) {
 // device memory (BATCH = true): each workgroup finds its problem by a binary
 // search over the first chunk (leaf, point) of every problem.
 //
-// Near field and L2P run one workgroup per chunk of up to 64 consecutive targets
-// of a leaf (chunk_ptr: exclusive prefix sum of ceil(count / 64) over the active
-// leaves), so a crowded leaf of a clustered cloud spreads over many workgroups.
+// Near field and L2P work on chunks of up to 32 consecutive targets of a leaf
+// (chunk_ptr: exclusive prefix sum of ceil(count / 32) over the active leaves),
+// one chunk per 64-lane workgroup whose two halves share the chunk's work, so
+// a crowded leaf of a clustered cloud spreads over many workgroups and a sparse
+// one (~30 points) does not idle half a wave.
 
 template <typename F>
 __device__ inline int find_last_le(int n, int64_t v, F key) {
@@ -84,11 +86,11 @@ __device__ inline int chunk_leaf(const int *__restrict__ chunk_ptr, int nleaf, i
   return find_last_le(nleaf, c, [&](int m) { return (int64_t)chunk_ptr[m]; });
 }
 
-// the descriptor of block b and b's index within its problem
+// the descriptor of work item b (a chunk or a leaf of the launch) and b's index
+// within its problem
 template <bool BATCH, int WHICH>  // WHICH: 0 chunk, 1 leaf
-__device__ inline void pick_desc(const LeafDesc &one, const LeafDesc *__restrict__ many,
-                                 int nmany, LeafDesc &D, int &local, int &prob) {
-  const int b = blockIdx.x;
+__device__ inline void pick_desc_at(const LeafDesc &one, const LeafDesc *__restrict__ many,
+                                    int nmany, int b, LeafDesc &D, int &local, int &prob) {
   if constexpr (BATCH) {
     prob = find_last_le(nmany, b, [&](int m) {
       return WHICH == 0 ? many[m].chunk_base : many[m].leaf_base;
@@ -100,6 +102,12 @@ __device__ inline void pick_desc(const LeafDesc &one, const LeafDesc *__restrict
     D = one;
     local = b;
   }
+}
+
+template <bool BATCH, int WHICH>
+__device__ inline void pick_desc(const LeafDesc &one, const LeafDesc *__restrict__ many,
+                                 int nmany, LeafDesc &D, int &local, int &prob) {
+  pick_desc_at<BATCH, WHICH>(one, many, nmany, (int)blockIdx.x, D, local, prob);
 }
 
 // ------------------------------------------------------------------ sigma
@@ -127,60 +135,108 @@ __global__ void k_gather_sigma(LeafDesc one, IoDesc ione, const LeafDesc *__rest
 }
 
 // ------------------------------------------------------------------ near field
-// Lanes own targets; sources of the neighbour leaves (ascending key) are staged
-// through LDS 64 at a time.
+// One 64-lane workgroup per chunk of up to 32 targets.  The sources of the
+// chunk's neighbour leaves are numbered consecutively (a prefix sum over the
+// near list, in LDS) and staged 64 at a time, so every batch is full whatever
+// the leaf sizes; lane l and lane l + 32 hold the same target and take the
+// first and the second half of each batch, and their sums are added at the end.
+// The next batch is loaded into registers while the current one is used.
+struct NearSrc {
+  int nq;        // neighbour leaves
+  int total;     // sources over all of them
+};
+
+// pre[e] = first source number of neighbour e, start[e] = its first point
+__device__ inline NearSrc near_sources(const LeafDesc &D, int j, int *pre, int *start) {
+  const int lane = threadIdx.x;
+  const int q0 = D.near_ptr[j], nq = D.near_ptr[j + 1] - q0;
+  int cnt = 0;
+  if (lane < nq) {
+    const uint32_t sk = D.act[D.near_src[q0 + lane]];
+    start[lane] = D.ls[sk];
+    cnt = D.ls[sk + 1] - D.ls[sk];
+  }
+  // inclusive scan of cnt over the (at most 27) lanes
+  int v = cnt;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if ((lane & 31) >= o) v += u;
+  }
+  if (lane < nq) pre[lane + 1] = v;
+  if (lane == 0) pre[0] = 0;
+  __syncthreads();
+  return NearSrc{nq, pre[nq]};
+}
+
+// point index of source number v (0 <= v < total)
+__device__ inline int near_point(int v, int nq, const int *pre, const int *start) {
+  int e = 0;
+  while (e + 1 < nq && pre[e + 1] <= v) ++e;
+  return start[e] + (v - pre[e]);
+}
+
 template <int KIND, int RB, bool BATCH>
 __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__restrict__ many,
                                               int nmany) {
   __shared__ double sx[64], sy[64], sz[64], ss[64 * RB];
+  __shared__ int pre[28], start[27];
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
   if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, half = lane >> 5;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
   const double *__restrict__ xyz = D.xyz;
   const double *__restrict__ sig = D.sig;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
-  const int a = D.ls[key], b = D.ls[key + 1];
-  const int q0 = D.near_ptr[j], q1 = D.near_ptr[j + 1];
-  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
-  const int i = t0 + lane;
+  const int b = D.ls[key + 1];
+  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const bool tv = i < b;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
+  const NearSrc S = near_sources(D, j, pre, start);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     double acc[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
-    for (int q = q0; q < q1; ++q) {
-      const uint32_t skey = D.act[D.near_src[q]];
-      const int c0 = D.ls[skey], c1 = D.ls[skey + 1];
-      for (int s0 = c0; s0 < c1; s0 += 64) {
-        const int cnt = min(64, c1 - s0);
-        __syncthreads();
-        if (lane < cnt) {
-          const int sidx = s0 + lane;
-          sx[lane] = xyz[sidx];
-          sy[lane] = xyz[n + sidx];
-          sz[lane] = xyz[2 * n + sidx];
+    double px = 0, py = 0, pz = 0, ps[RB];
+    auto load = [&](int base) {
+      const int v = base + lane;
+      if (v < S.total) {
+        const int sidx = near_point(v, S.nq, pre, start);
+        px = xyz[sidx];
+        py = xyz[n + sidx];
+        pz = xyz[2 * n + sidx];
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr)
-            ss[lane * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
-        }
-        __syncthreads();
-        for (int u = 0; u < cnt; ++u) {
-          const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          double kv = KF<KIND>::eval(r2, D.p);
-          if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
+        for (int rr = 0; rr < RB; ++rr)
+          ps[rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
+      }
+    };
+    load(0);
+    for (int base = 0; base < S.total; base += 64) {
+      __syncthreads();
+      sx[lane] = px;
+      sy[lane] = py;
+      sz[lane] = pz;
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
-        }
+      for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
+      __syncthreads();
+      if (base + 64 < S.total) load(base + 64);
+      const int u0 = 32 * half, u1 = min(u0 + 32, S.total - base);
+      for (int u = u0; u < u1; ++u) {
+        const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double kv = KF<KIND>::eval(r2, D.p);
+        if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
       }
     }
-    if (tv) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
+    if (tv && half == 0) {
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = acc[rr];
@@ -191,17 +247,18 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
 // Mixed-precision near field: the coordinate differences are taken in FP64 and
 // rounded once to FP32 (so a close pair keeps its relative accuracy however
 // crowded the leaf), kernel values and products in FP32, Neumaier-compensated
-// FP32 sums returned as hi + lo in FP64.
+// FP32 sums per half, the two halves and their compensations added in FP64.
 template <int KIND, int RB, bool BATCH>
 __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__restrict__ many,
                                               int nmany) {
   __shared__ double sx[64], sy[64], sz[64];
   __shared__ float ss[64 * RB];
+  __shared__ int pre[28], start[27];
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
   if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, half = lane >> 5;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
   const float p = (float)D.p;
@@ -209,51 +266,59 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
   const double *__restrict__ sig = D.sig;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
-  const int a = D.ls[key], b = D.ls[key + 1];
-  const int q0 = D.near_ptr[j], q1 = D.near_ptr[j + 1];
-  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
-  const int i = t0 + lane;
+  const int b = D.ls[key + 1];
+  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const bool tv = i < b;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
+  const NearSrc S = near_sources(D, j, pre, start);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     float sum[RB], cmp[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) sum[rr] = cmp[rr] = 0.f;
-    for (int q = q0; q < q1; ++q) {
-      const uint32_t skey = D.act[D.near_src[q]];
-      const int c0 = D.ls[skey], c1 = D.ls[skey + 1];
-      for (int s0 = c0; s0 < c1; s0 += 64) {
-        const int cnt = min(64, c1 - s0);
-        __syncthreads();
-        if (lane < cnt) {
-          const int sidx = s0 + lane;
-          sx[lane] = xyz[sidx];
-          sy[lane] = xyz[n + sidx];
-          sz[lane] = xyz[2 * n + sidx];
+    double px = 0, py = 0, pz = 0;
+    float ps[RB];
+    auto load = [&](int base) {
+      const int v = base + lane;
+      if (v < S.total) {
+        const int sidx = near_point(v, S.nq, pre, start);
+        px = xyz[sidx];
+        py = xyz[n + sidx];
+        pz = xyz[2 * n + sidx];
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr)
-            ss[lane * RB + rr] = (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
-        }
-        __syncthreads();
-        for (int u = 0; u < cnt; ++u) {
-          const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          float kv = KF<KIND>::evalf(r2, p);
-          if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
+        for (int rr = 0; rr < RB; ++rr)
+          ps[rr] = (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
+      }
+    };
+    load(0);
+    for (int base = 0; base < S.total; base += 64) {
+      __syncthreads();
+      sx[lane] = px;
+      sy[lane] = py;
+      sz[lane] = pz;
 #pragma unroll
-          for (int rr = 0; rr < RB; ++rr) {
-            const float v = ss[u * RB + rr] * kv;
-            const float tsum = sum[rr] + v;
-            cmp[rr] += (fabsf(sum[rr]) >= fabsf(v)) ? ((sum[rr] - tsum) + v) : ((v - tsum) + sum[rr]);
-            sum[rr] = tsum;
-          }
+      for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
+      __syncthreads();
+      if (base + 64 < S.total) load(base + 64);
+      const int u0 = 32 * half, u1 = min(u0 + 32, S.total - base);
+      for (int u = u0; u < u1; ++u) {
+        const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float kv = KF<KIND>::evalf(r2, p);
+        if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const float w = ss[u * RB + rr] * kv;
+          const float tsum = sum[rr] + w;
+          cmp[rr] += (fabsf(sum[rr]) >= fabsf(w)) ? ((sum[rr] - tsum) + w) : ((w - tsum) + sum[rr]);
+          sum[rr] = tsum;
         }
       }
     }
-    if (tv) {
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr)
-        if (r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = (double)sum[rr] + (double)cmp[rr];
+    for (int rr = 0; rr < RB; ++rr) {
+      const double mine = (double)sum[rr] + (double)cmp[rr];
+      const double other = __shfl_xor(mine, 32);
+      if (tv && half == 0 && r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = mine + other;
     }
   }
 }
@@ -333,7 +398,9 @@ __global__ __launch_bounds__(256) void k_p2m(LeafDesc one, const LeafDesc *__res
 
 // ------------------------------------------------------------------ L2P + combine
 // f(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I + f_near(x_i), written to
-// the input position of x_i (Algorithm 3, step 7).
+// the input position of x_i (Algorithm 3, step 7).  One 64-lane workgroup per
+// chunk of up to 32 targets: lane l and lane l + 32 hold the same target and sum
+// the first and the second half of the d terms.
 template <int KIND, int RB, bool BATCH>
 __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
                                             const LeafDesc *__restrict__ many,
@@ -351,19 +418,19 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
   const int dp = D.dp, d = D.d, nrhs = D.nrhs;
   const int64_t n = D.n;
   double *sX = sm, *sl = sm + 3 * dp;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, half = lane >> 5;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
-  const int a = D.ls[key], b = D.ls[key + 1];
+  const int b = D.ls[key + 1];
+  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
   for (int e = lane; e < 3 * d; e += 64) sX[e] = D.X[e];
-  const int t0 = a + 64 * (c - D.chunk_ptr[j]);  // the 64 targets of chunk c
-  const int i = t0 + lane;
   const bool tv = i < b;
   const double xc = tv ? D.xyz[i] - cx : 0.0, yc = tv ? D.xyz[n + i] - cy : 0.0,
                zc = tv ? D.xyz[2 * n + i] - cz : 0.0;
+  const int dh = (d + 1) >> 1, l0 = half * dh, l1 = min(d, l0 + dh);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     __syncthreads();
     for (int e = lane; e < RB * d; e += 64) {
@@ -374,13 +441,15 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
     double acc[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
-    for (int l = 0; l < d; ++l) {
+    for (int l = l0; l < l1; ++l) {
       const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
       const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, D.p);
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
     }
-    if (tv) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
+    if (tv && half == 0) {
       const int64_t o = D.perm[i];
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
@@ -532,14 +601,16 @@ struct Mfma<float> {
   __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-template <typename T, int MODE>
-__device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
-                                       int ts, int r, const int8_t *__restrict__ dvec,
-                                       const int *__restrict__ src_slot, const T *Bsrc) {
-  if (!cvalid) return nullptr;
-  int s;
+// Slot of the source box that term `term` pairs with target (tkey, ts): M2L
+// the box at offset delta (-1 outside the domain or empty), M2M child `term`,
+// L2L the parent, PROJ the box itself.
+template <int MODE>
+__device__ inline int gemm_source_slot(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
+                                       int ts, const int8_t *__restrict__ dvec,
+                                       const int *__restrict__ src_slot) {
+  if (!cvalid) return -1;
   if constexpr (MODE == MODE_PROJ) {
-    s = ts;
+    return ts;
   } else {
     uint32_t skey;
     if constexpr (MODE == MODE_M2L) {
@@ -548,17 +619,20 @@ __device__ inline const T *gemm_source(const GemmJob &J, int term, bool cvalid, 
       const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
       const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
       const int m2 = (int)morton_axis(tkey, 2) + dvec[3 * id + 2];
-      if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return nullptr;
+      if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return -1;
       skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
     } else if constexpr (MODE == MODE_M2M) {
       skey = tkey * 8u + (uint32_t)term;
     } else {
       skey = tkey >> 3;
     }
-    s = src_slot[skey];
-    if (s < 0) return nullptr;
+    return src_slot[skey];
   }
-  return Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
+}
+
+template <typename T>
+__device__ inline const T *gemm_source_ptr(const GemmJob &J, int s, int r, const T *Bsrc) {
+  return s < 0 ? nullptr : Bsrc + ((int64_t)s * J.nrhs + r) * J.dpk;
 }
 
 template <typename T, int MODE>
@@ -687,17 +761,31 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   P2 bn[2][2], bc[2][2];  // B of the next and the current chunk: [column][pair]
   const T *srcp[2] = {nullptr, nullptr};
   const T *Ap = nullptr;
+  // the source slots of term + 1 are looked up halfway through term, so the
+  // dependent loads (slot, then data) do not stall the start of the next term
+  int nslot[2] = {-1, -1};
+  int pre_term = -1;
+  const int kmid = nkc >> 1;
+  auto lookup = [&](int term) {
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const ColState c = my[jj];
+      nslot[jj] = gemm_source_slot<MODE>(J, term, c.valid, c.tkey, c.tsl, dvec, c.slot_map);
+    }
+    pre_term = term;
+  };
   auto fetch = [&](int it) {
     const int term = it / nkc, kc = it - term * nkc;
     if (kc == 0) {
+      if (pre_term != term) lookup(term);
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
         const ColState c = my[jj];
-        srcp[jj] = gemm_source<T, MODE>(J, term, c.valid, c.tkey, c.tsl, c.r, dvec, c.slot_map,
-                                        (const T *)c.B);
+        srcp[jj] = gemm_source_ptr<T>(J, nslot[jj], c.r, (const T *)c.B);
       }
       Ap = gemm_operand<T, MODE>(J, term);
     }
+    if (kc == kmid && term + 1 < term1) lookup(term + 1);
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = t + 256 * q;  // pair index in the chunk
@@ -1213,9 +1301,13 @@ void launch_gemm_fused(const FusedGemm &F, int mode, bool fp32, int gmax, double
 }
 
 // ---- leaf-level launches (one plan: BATCH = false; a batch group: BATCH = true)
+// workgroups of a chunk launch: one per 32-target chunk
+unsigned chunk_grid(int64_t nchunk) { return (unsigned)nchunk; }
+
 template <int KIND, bool BATCH>
-void launch_p2p(bool mixed, int nrhs, unsigned grid, const LeafDesc &one, const LeafDesc *many,
+void launch_p2p(bool mixed, int nrhs, int64_t nchunk, const LeafDesc &one, const LeafDesc *many,
                 int nmany, hipStream_t s) {
+  const unsigned grid = chunk_grid(nchunk);
   if (grid == 0) return;
   if (mixed) {
     if (nrhs == 1)
@@ -1246,9 +1338,11 @@ size_t l2p_shm(int nrhs, int dpmax) {
 }
 
 template <int KIND, bool BATCH>
-void launch_l2p(int nrhs, unsigned grid, size_t shm, const LeafDesc &one, const IoDesc &ione,
+void launch_l2p(int nrhs, int64_t nchunk, int dpmax, const LeafDesc &one, const IoDesc &ione,
                 const LeafDesc *many, const IoDesc *io, int nmany, hipStream_t s) {
+  const unsigned grid = chunk_grid(nchunk);
   if (grid == 0) return;
+  const size_t shm = l2p_shm(nrhs, dpmax);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_l2p<KIND, 1, BATCH>), dim3(grid), dim3(64), shm, s, one, ione, many, io,
                        nmany);
@@ -1291,7 +1385,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   const bool mixed = P.cfg.precision == EIFMM_PREC_MIXED;
   const int64_t n = P.n;
   const int nleafa = (int)P.nact[depth];
-  const unsigned nchunk = (unsigned)P.nchunk;
+  const int64_t nchunk = P.nchunk;
   const LeafDesc LD = leaf_desc(P, nrhs);
   LevelDev &LL = P.ld[depth];
   // near field
@@ -1391,7 +1485,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   // step 7: L2P and the final sum
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_L2P);
-    launch_l2p<KIND, false>(nrhs, nchunk, l2p_shm(nrhs, HL.dp), LD, io, nullptr, nullptr, 0, s);
+    launch_l2p<KIND, false>(nrhs, nchunk, HL.dp, LD, io, nullptr, nullptr, 0, s);
   }
 }
 
@@ -1594,12 +1688,12 @@ void run_group(const BatchExec &B, const BatchGroup &g, int phase, hipStream_t s
   const LeafDesc none{};
   const IoDesc inone{};
   if (phase == 0)
-    launch_p2p<KIND, true>(B.mixed, 1, (unsigned)g.nchunk, none, many, g.count, s);
+    launch_p2p<KIND, true>(B.mixed, 1, g.nchunk, none, many, g.count, s);
   else if (phase == 1)
     launch_p2m<KIND, true>(1, (unsigned)g.nleaf, none, many, g.count, s);
   else
-    launch_l2p<KIND, true>(1, (unsigned)g.nchunk, l2p_shm(1, g.dpmax), none, inone, many,
-                           B.io_dev + g.first, g.count, s);
+    launch_l2p<KIND, true>(1, g.nchunk, g.dpmax, none, inone, many, B.io_dev + g.first, g.count,
+                           s);
 }
 
 void run_groups(const BatchExec &B, int phase, hipStream_t s, const hipEvent_t *mark,

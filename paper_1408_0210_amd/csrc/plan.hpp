@@ -91,7 +91,7 @@ struct GemmJob {
 struct LeafDesc {
   const uint32_t *act;      // active leaf keys
   const int *ls;            // leaf_start
-  const int *chunk_ptr;     // first 64-target chunk of each active leaf
+  const int *chunk_ptr;     // first 32-target chunk of each active leaf
   const int *near_ptr, *near_src;
   const int *perm;          // sorted position -> input index
   const double *xyz;        // sorted points
@@ -203,11 +203,11 @@ struct Plan {
   int *near_ptr = nullptr;      // leaf level near lists (CSR over active slots)
   int *near_src = nullptr;      // source leaf slots
   size_t near_cap = 0;
-  int *chunk_ptr = nullptr;     // per active leaf: first 64-target chunk (prefix sum)
-  int64_t nchunk = 0;           // bound on the 64-target chunks over all leaves (grid size)
+  int *chunk_ptr = nullptr;     // per active leaf: first 32-target chunk (prefix sum)
+  int64_t nchunk = 0;           // bound on the 32-target chunks over all leaves
   unsigned long long *npairs_dev = nullptr;  // near-field work counters (2)
   int64_t near_point_pairs = 0;  // target x source point pairs of the near field
-  int64_t near_lane_pairs = 0;   // the same with targets rounded up to 64-lane chunks
+  int64_t near_lane_pairs = 0;   // the same with targets rounded up to 32-target chunks
   bool counts_pending = false;   // the three counts above are still on the device
   bool points_set = false;
   int64_t nact[kMaxLevels] = {0};

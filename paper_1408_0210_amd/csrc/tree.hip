@@ -146,7 +146,7 @@ __device__ inline bool box_active(const int *__restrict__ ls, int shift, int64_t
 // per block of 256 boxes: active count per child class and in total
 // near-field work: out[0] = point pairs (count(leaf) x the point count of its
 // near list, summed over active leaves), out[1] = the same with count(leaf)
-// rounded up to 64-target chunks (the sweeps the near-field kernels make);
+// rounded up to 32-target chunks (the sweeps the near-field kernels make);
 // integer atomics, so the totals are exact
 __global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__ act,
                                                     const int *__restrict__ ls,
@@ -163,10 +163,10 @@ __global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__
   }
   const long long cnt = ls[key + 1] - ls[key];
   atomicAdd(out, (unsigned long long)(cnt * src));
-  atomicAdd(out + 1, (unsigned long long)(((cnt + 63) / 64) * 64 * src));
+  atomicAdd(out + 1, (unsigned long long)(((cnt + 31) / 32) * 32 * src));
 }
 
-// number of 64-target chunks of each active leaf; 0 past the active count
+// number of 32-target chunks of each active leaf; 0 past the active count
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict__ act,
                                                      const int *__restrict__ ls, int nact,
                                                      int64_t len, int *__restrict__ cnt) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict_
   int c = 0;
   if (j < nact) {
     const uint32_t key = act[j];
-    c = (ls[key + 1] - ls[key] + 63) >> 6;
+    c = (ls[key + 1] - ls[key] + 31) >> 5;
   }
   cnt[j] = c;
 }
@@ -484,8 +484,8 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   // near lists of the leaf level (used by the near-field pass); at most 27
   // entries per box, within near_cap = 27 cap
   build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, true, s);
-  // 64-target chunks of the leaves (the grid of the near-field and L2P kernels).
-  // The grid is launched with the bound nact + ceil(n / 64) on the chunk count,
+  // 32-target chunks of the leaves (the work of the near-field and L2P kernels).
+  // The grid is launched with the bound nact + ceil(n / 32) on the chunk count,
   // and workgroups past chunk_ptr[nact] exit, so the count is not read back.
   {
     const int64_t cap = P.ld[depth].cap;
@@ -493,7 +493,7 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
                        P.ld[depth].act, P.leaf_start, (int)P.nact[depth], cap + 1, P.list_cnt);
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
-  P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 63) / 64 : 0;
+  P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 31) / 32 : 0;
   hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), s);
   if (P.nact[depth] > 0)
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
