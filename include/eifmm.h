@@ -58,6 +58,8 @@ extern "C" {
 #define EIFMM_K_YUKAWA 1  /* exp(-a r)/r, a = kernel_param, singular             */
 #define EIFMM_K_GAUSS 2   /* exp(-r^2/h2), h2 = kernel_param                     */
 #define EIFMM_K_SQDIST 3  /* r^2: rank-5 test kernel, the EIM is exact           */
+#define EIFMM_K_COSR 4    /* cos(w r)/r, w = kernel_param, singular (Sec. 5.4)   */
+#define EIFMM_K_MQ 5      /* sqrt(r^2 + c), c = kernel_param > 0 (Sec. 5.4)       */
 
 /* precision of the pass */
 #define EIFMM_PREC_FP64 0  /* every step in FP64                                   */

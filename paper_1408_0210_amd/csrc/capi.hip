@@ -48,8 +48,9 @@ int upload(T **p, const T *src, size_t count, std::vector<void *> &track) {
 
 int validate(const eifmm_config *c) {
   if (!c || c->struct_size != (int32_t)sizeof(eifmm_config)) return EIFMM_EINVAL;
-  if (c->kernel < EIFMM_K_LAPLACE || c->kernel > EIFMM_K_SQDIST) return EIFMM_EINVAL;
+  if (c->kernel < EIFMM_K_LAPLACE || c->kernel > EIFMM_K_MQ) return EIFMM_EINVAL;
   if ((c->kernel == EIFMM_K_GAUSS && !(c->kernel_param > 0)) ||
+      (c->kernel == EIFMM_K_MQ && !(c->kernel_param > 0)) ||
       (c->kernel == EIFMM_K_YUKAWA && !(c->kernel_param >= 0)) || !std::isfinite(c->kernel_param))
     return EIFMM_EINVAL;
   if (!(c->L > 0) || !std::isfinite(c->L)) return EIFMM_EINVAL;
@@ -265,7 +266,7 @@ struct eifmm_batch_s {
   bool tuned = false;
   std::vector<int> cand_lo;
   std::vector<std::vector<std::array<double, 4>>> cand;
-  double rate_near[4] = {0, 0, 0, 0};  // near-field lane pairs / ms, per kernel kind
+  double rate_near[EIFMM_K_MQ + 1] = {};  // near-field lane pairs / ms, per kernel kind
   double rate_m2l = 0;                 // M2L flops / ms
   double rate_leaf = 0;                // P2M + L2P kernel evaluations / ms
   double rate_box = 0;                 // box-level d^2 units / ms (M2M, L2L, solves)
@@ -392,7 +393,7 @@ int calibrate(eifmm_batch b, hipStream_t s) {
     };
     // marks: 0 start, 1 gather, 2..G+1 near, G+2..2G+1 P2M, 2G+2 M2M, 2G+3 What,
     // 2G+4 pre, 2G+5 M2L, 2G+6 post, 2G+7 L2L, 2G+8 lhat, 2G+9.. L2P
-    std::array<double, 4> wk[4] = {};
+    std::array<double, 4> wk[EIFMM_K_MQ + 1] = {};
     double leaf = 0, box = 0, m2l = 0;
     for (int p = 0; p < (int)b->plans.size(); ++p) {
       const auto w = work_of(b->plans[p]->P);
@@ -729,7 +730,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
   b->cand.assign(nprob, {});
   // starting rates, per millisecond, of the phases of a fused pass on MI355X
   // (FP64, one right-hand side); the first set_points measures the batch's own
-  for (int k = 0; k < 4; ++k) b->rate_near[k] = 4.0e8;
+  for (int k = 0; k <= EIFMM_K_MQ; ++k) b->rate_near[k] = 4.0e8;
   b->rate_m2l = 3.0e10;
   b->rate_leaf = 6.0e8;
   b->rate_box = 1.5e9;

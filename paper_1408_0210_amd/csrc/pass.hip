@@ -23,8 +23,9 @@ namespace eifmm {
 // ------------------------------------------------------------------ kernels k
 template <int KIND>
 struct KF {
-  static constexpr bool singular = (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA);
-  // p: Yukawa a, Gauss 1/h2
+  static constexpr bool singular =
+      (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA || KIND == EIFMM_K_COSR);
+  // p: Yukawa a, Gauss 1/h2, cos(w r)/r w, multiquadric c
   __device__ static inline double eval(double r2, double p) {
     if constexpr (KIND == EIFMM_K_LAPLACE) {
       return rsqrt(r2);
@@ -33,6 +34,11 @@ struct KF {
       return exp(-p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_GAUSS) {
       return exp(-r2 * p);
+    } else if constexpr (KIND == EIFMM_K_COSR) {
+      double ri = rsqrt(r2);
+      return cos(p * (r2 * ri)) * ri;
+    } else if constexpr (KIND == EIFMM_K_MQ) {
+      return sqrt(r2 + p);
     } else {
       return r2;
     }
@@ -45,6 +51,11 @@ struct KF {
       return expf(-p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_GAUSS) {
       return expf(-r2 * p);
+    } else if constexpr (KIND == EIFMM_K_COSR) {
+      float ri = rsqrtf(r2);
+      return cosf(p * (r2 * ri)) * ri;
+    } else if constexpr (KIND == EIFMM_K_MQ) {
+      return sqrtf(r2 + p);
     } else {
       return r2;
     }
@@ -1524,6 +1535,12 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
     case EIFMM_K_GAUSS:
       run_kind<EIFMM_K_GAUSS>(P, nrhs, io, s);
       break;
+    case EIFMM_K_COSR:
+      run_kind<EIFMM_K_COSR>(P, nrhs, io, s);
+      break;
+    case EIFMM_K_MQ:
+      run_kind<EIFMM_K_MQ>(P, nrhs, io, s);
+      break;
     default:
       run_kind<EIFMM_K_SQDIST>(P, nrhs, io, s);
       break;
@@ -1703,6 +1720,8 @@ void run_groups(const BatchExec &B, int phase, hipStream_t s, const hipEvent_t *
       case EIFMM_K_LAPLACE: run_group<EIFMM_K_LAPLACE>(B, g, phase, s); break;
       case EIFMM_K_YUKAWA: run_group<EIFMM_K_YUKAWA>(B, g, phase, s); break;
       case EIFMM_K_GAUSS: run_group<EIFMM_K_GAUSS>(B, g, phase, s); break;
+      case EIFMM_K_COSR: run_group<EIFMM_K_COSR>(B, g, phase, s); break;
+      case EIFMM_K_MQ: run_group<EIFMM_K_MQ>(B, g, phase, s); break;
       default: run_group<EIFMM_K_SQDIST>(B, g, phase, s); break;
     }
     if (mark) hipEventRecord(mark[m++], s);
@@ -1735,7 +1754,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
   }
   // descriptor order: problems grouped by kernel kind, batch order inside a group
   std::vector<Plan *> plans;
-  for (int kind = EIFMM_K_LAPLACE; kind <= EIFMM_K_SQDIST; ++kind) {
+  for (int kind = EIFMM_K_LAPLACE; kind <= EIFMM_K_MQ; ++kind) {
     BatchGroup g;
     g.kind = kind;
     g.first = (int)plans.size();

@@ -42,6 +42,12 @@ inline double kern_host(int kind, double p, double zx, double zy, double zz) {
       return std::exp(-r2 / p);
     case EIFMM_K_SQDIST:
       return r2;
+    case EIFMM_K_COSR: {
+      double r = std::sqrt(r2);
+      return std::cos(p * r) / r;
+    }
+    case EIFMM_K_MQ:
+      return std::sqrt(r2 + p);
   }
   return NAN;
 }
@@ -104,7 +110,11 @@ void add_volume(int m, std::vector<double> &out) {
       }
 }
 
-bool volume_kernel(int kind) { return kind == EIFMM_K_GAUSS; }
+// kernels without a maximum principle (no decay, oscillation or growth) are
+// trained on a volume grid of J_0 rather than on its surface
+bool volume_kernel(int kind) {
+  return kind == EIFMM_K_GAUSS || kind == EIFMM_K_COSR || kind == EIFMM_K_MQ;
+}
 
 // Shell radii in units of l_k; level k keeps those below 2^(k+1) - 1 and then
 // adds the outer boundary 2^(k+1) - 1 of I_0^k itself.

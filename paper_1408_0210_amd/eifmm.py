@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeifmm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "eifmm.h")
 
-KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3}
+KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3, "cosr": 4, "mq": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_HOST_ONLY = 1
 MAX_DEPTH = 8

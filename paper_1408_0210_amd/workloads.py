@@ -62,6 +62,14 @@ WORKLOADS = {
                                        param=0.0, depth=5, tau=1e-6),
 }
 
+# The paper's inhomogeneous-kernel test cases (Sec. 5.4, Table 3): 1e6 points
+# uniform in the cube, a 6-level tree (depth 5), kernels cos(20 r)/r, exp(-r^2)
+# and sqrt(r^2 + 1); here with tau = 1e-6 for the 1e-6 accuracy target.
+for _name, _k, _p in (("cosr", "cosr", 20.0), ("gauss1", "gauss", 1.0), ("mq", "mq", 1.0)):
+    WORKLOADS[f"uniform1m_{_name}_d5"] = dict(n=1_000_000, dist="uniform", seed_pts=3,
+                                               seed_sigma=4, kernel=_k, param=_p, depth=5,
+                                               tau=1e-6)
+
 
 def make_points(w):
     if w["dist"] == "uniform":

@@ -59,7 +59,8 @@ def test_eim_dmax_error(E):
 
 
 @pytest.mark.parametrize("kernel,param,depth,tau", [("laplace", 0, 3, 1e-6), ("yukawa", 1.0, 3, 1e-5),
-                                                    ("gauss", 1.0, 3, 1e-6), ("sqdist", 0, 3, 1e-8)])
+                                                    ("gauss", 1.0, 3, 1e-6), ("sqdist", 0, 3, 1e-8),
+                                                    ("cosr", 20.0, 2, 1e-4), ("mq", 1.0, 3, 1e-6)])
 def test_host_setup_matches_oracle(E, oracle_lib, kernel, param, depth, tau):
     """The library's greedy (complete-pivot cross approximation and a Crout
     factorisation of K(X, Y)) and the oracle's Algorithm 1 with the Gamma

@@ -191,3 +191,20 @@ def test_rhs64_batched_mixed(E, torch_dev, oracle_lib):
         f1 = _eval(torch_dev, single, S[:, r])
         assert _rel(F[r], f1) <= 1e-6, r
     single.close()
+
+
+@pytest.mark.parametrize("name", ["uniform1m_cosr_d5", "uniform1m_gauss1_d5", "uniform1m_mq_d5"])
+def test_paper_kernels_1m(name, E, torch_dev, oracle_lib):
+    """The paper's inhomogeneous kernels on its 1e6-point cube (Sec. 5.4), depth 5,
+    tau = 1e-6 with compression at the same tolerance: sampled rel-L2 <= 1e-6; for
+    exp(-r^2) and sqrt(r^2+1) the number of interpolation points falls with depth."""
+    case = Case(name, torch_dev, oracle_lib)
+    plan = _plan(E, case, compress_tol=case.w["tau"])
+    f = _eval(torch_dev, plan, case.s)
+    err = _rel(f[case.idx], case.ref())
+    d = plan.stats()["d"]
+    print(f"{name}: d={d} sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-6
+    if case.w["kernel"] in ("gauss", "mq"):
+        assert d[5] < d[4] < d[3] < d[2]
+    plan.close()

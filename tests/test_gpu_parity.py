@@ -180,14 +180,15 @@ def test_multi_rhs_matches_single(E, torch_dev, oracle_lib):
     plan.close()
 
 
-@pytest.mark.parametrize("kernel,param,tau", [("yukawa", 1.0, 1e-6), ("gauss", 0.1, 1e-6)])
+@pytest.mark.parametrize("kernel,param,tau", [("yukawa", 1.0, 1e-6), ("gauss", 0.1, 1e-6),
+                                              ("cosr", 20.0, 1e-4), ("mq", 1.0, 1e-6)])
 def test_other_kernels_vs_oracle(kernel, param, tau, E, torch_dev, oracle_lib):
     x = W.cluster_points(2000, 4, 0.1, 71, 72)
     s = W.potentials(2000, 73)
     plan, f = _gpu_eval(E, torch_dev, kernel, param, x, s, 3, tau)
     O = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, 3, tau)
     assert _rel(f, O.evaluate(x, s)) < 1e-10
-    assert _rel(f, oracle_lib.direct(kernel, param, x, x, s)) < 1e-5
+    assert _rel(f, oracle_lib.direct(kernel, param, x, x, s)) < max(1e-5, 10 * tau)
     plan.close()
 
 
