@@ -22,7 +22,8 @@ Also reported on the same line:
                 graph-replayed batch: sum N_p^2 / t, against the same problems
                 evaluated one after another;
   paper_kernels the paper's cos(20r)/r, exp(-r^2), sqrt(r^2+1) on its 1e6-point
-                cube, with d per level and its own one-core timings as context.
+                cube, with d per level and its own one-core timings as context;
+  uniform100m   the paper's 1e8-point exp(-r^2) cube (Table 4), FP64 and mixed.
 """
 import argparse
 import json
@@ -190,6 +191,33 @@ def run_paper_kernels(args):
     return out
 
 
+def run_100m(args):
+    """The paper's 1e8-point cube with exp(-r^2) (Table 4) on one GPU: FP64 and mixed
+    passes at depth 7 (~48 points per leaf), tau = 1e-6, error on 100 sampled
+    targets; the paper's own run took 2636 s on one core at rel. acc. 7e-5."""
+    import oracle
+    from paper_1408_0210_amd import workloads as W
+    w = W.WORKLOADS["uniform100m_gauss1_d7"]
+    data = (W.make_points(w), W.make_sigma(w))
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(w["n"], 100, replace=False))
+    ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
+                        threads=min(os.cpu_count() or 1, 16))
+    out = {"workload": "uniform100m_gauss1_d7", "n": w["n"], "depth": w["depth"],
+           "tau": w["tau"], "paper_seconds_1core_total": 2636, "paper_rel_acc": 7e-5}
+    for prec in ("fp64", "mixed"):
+        a = argparse.Namespace(**vars(args))
+        r = run_plain(a, precision=prec, steps=3, warmup=1, data=data, wdict=w)
+        st = r["stats"]
+        out[prec] = {"ms_per_step": r["ms"], "value": float(w["n"]) ** 2 / (r["ms"] * 1e-3),
+                     "rel_l2_sampled": _rel_sample(r["f"], idx, ref), "d": st["d"],
+                     "phase_ms": {k: st["phase_ms"][k] / max(1, st["phase_calls"][k])
+                                  for k in st["phase_ms"]}}
+        r["plan"].close()
+        del r
+    return out
+
+
 def run_batched(args):
     """Many right-hand sides on one fixed point set, mixed precision."""
     import torch
@@ -334,8 +362,11 @@ def main():
                     help="skip the batch of 256 uneven problems")
     ap.add_argument("--no-paper-kernels", action="store_true",
                     help="skip the paper's cos(20r)/r, exp(-r^2), sqrt(r^2+1) cube runs")
+    ap.add_argument("--no-100m", action="store_true",
+                    help="skip the 1e8-point exp(-r^2) run")
     ap.add_argument("--batch-precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--only-leg", choices=["batched", "clustered", "uneven", "paper_kernels"],
+    ap.add_argument("--only-leg",
+                    choices=["batched", "clustered", "uneven", "paper_kernels", "100m"],
                     help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
@@ -359,7 +390,7 @@ def main():
 
     if args.only_leg:
         leg = {"batched": run_batched, "clustered": run_clustered, "uneven": run_uneven,
-               "paper_kernels": run_paper_kernels}
+               "paper_kernels": run_paper_kernels, "100m": run_100m}
         print(json.dumps({args.only_leg: leg[args.only_leg](args)}), flush=True)
         return
 
@@ -416,6 +447,8 @@ def main():
         out["uneven_batch"] = run_uneven(args)
     if not args.no_paper_kernels:
         out["paper_kernels"] = run_paper_kernels(args)
+    if not args.no_100m:
+        out["uniform100m"] = run_100m(args)
     print(json.dumps(out), flush=True)
 
 

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_act_scatter(const int *__restrict__ ls,
 __global__ __launch_bounds__(256) void k_il_count(int level, const uint32_t *__restrict__ act,
                                                   const int *__restrict__ nact,
                                                   const int *__restrict__ slot,
-                                                  int *__restrict__ out) {
+                                                  unsigned long long *__restrict__ out) {
   __shared__ int tot;
   if (threadIdx.x == 0) tot = 0;
   __syncthreads();
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_il_count(int level, const uint32_t *__r
   }
   if (c) atomicAdd(&tot, c);
   __syncthreads();
-  if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
+  if (threadIdx.x == 0 && tot) atomicAdd(out, (unsigned long long)tot);
 }
 
 // ---------------------------------------------------------------- lists
@@ -461,8 +461,10 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   for (int k = std::min(2, depth); k <= depth; ++k) build_active(P, k, s);
   for (int k = 2; k <= depth; ++k) {
     const int grid = (int)((P.ld[k].cap + 255) / 256);
+    // 64-bit pair count in ints 10-11 of the level's block (8-byte aligned)
     hipLaunchKernelGGL(k_il_count, dim3(grid), dim3(256), 0, s, k, P.ld[k].act,
-                       P.counts_dev + 16 * k + 8, P.ld[k].slot, P.counts_dev + 16 * k + 9);
+                       P.counts_dev + 16 * k + 8, P.ld[k].slot,
+                       (unsigned long long *)(P.counts_dev + 16 * k + 10));
   }
   int host_counts[16 * kMaxLevels + 1];
   hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
@@ -479,7 +481,9 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     P.nact[k] = host_counts[16 * k + 8];
     for (int c = 0; c < 8; ++c) P.cls_off[k][c] = host_counts[16 * k + c];
     P.cls_off[k][8] = P.nact[k];
-    P.il_pairs[k] = k >= 2 ? host_counts[16 * k + 9] : 0;
+    unsigned long long ilp = 0;
+    std::memcpy(&ilp, &host_counts[16 * k + 10], sizeof(ilp));
+    P.il_pairs[k] = k >= 2 ? (int64_t)ilp : 0;
   }
   // near lists of the leaf level (used by the near-field pass); at most 27
   // entries per box, within near_cap = 27 cap

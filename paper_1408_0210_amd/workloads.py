@@ -70,6 +70,11 @@ for _name, _k, _p in (("cosr", "cosr", 20.0), ("gauss1", "gauss", 1.0), ("mq", "
                                                seed_sigma=4, kernel=_k, param=_p, depth=5,
                                                tau=1e-6)
 
+# The paper's largest case (Sec. 5.4.2, Table 4): 1e8 points in the cube, exp(-r^2).
+WORKLOADS["uniform100m_gauss1_d7"] = dict(n=100_000_000, dist="uniform", seed_pts=21,
+                                          seed_sigma=22, kernel="gauss", param=1.0, depth=7,
+                                          tau=1e-6)
+
 
 def make_points(w):
     if w["dist"] == "uniform":

@@ -208,3 +208,23 @@ def test_paper_kernels_1m(name, E, torch_dev, oracle_lib):
     if case.w["kernel"] in ("gauss", "mq"):
         assert d[5] < d[4] < d[3] < d[2]
     plan.close()
+
+
+def test_uniform100m_gauss(E, torch_dev, oracle_lib):
+    """The paper's largest case (Table 4): 1e8 points in the cube, exp(-r^2), depth 7,
+    tau 1e-6, mixed precision: 100 sampled targets against the direct sum."""
+    torch, dev = torch_dev
+    w = W.WORKLOADS["uniform100m_gauss1_d7"]
+    x, s = W.make_points(w), W.make_sigma(w)
+    idx = np.sort(np.random.default_rng(5).choice(w["n"], 100, replace=False))
+    ref = oracle_lib.direct(w["kernel"], w["param"], x[:, idx].copy(), x, s, threads=THREADS)
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  precision="mixed", compress_tol=1e-6)
+    xd = torch.from_numpy(x).to(dev)
+    plan.set_points(xd)
+    f = plan.evaluate(torch.from_numpy(s).to(dev))
+    torch.cuda.synchronize()
+    err = _rel(f.cpu().numpy()[idx], ref)
+    print(f"uniform100m gauss: d={plan.stats()['d']} sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-6
+    plan.close()
