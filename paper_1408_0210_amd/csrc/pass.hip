@@ -336,9 +336,10 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
 
 // ------------------------------------------------------------------ P2M
 // W^I_m = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I)  (Algorithm 3, step 1)
-// One 256-thread workgroup per leaf; thread t owns rows m = t + 256 u.
-template <int KIND, int RB, bool BATCH>
-__global__ __launch_bounds__(256) void k_p2m(LeafDesc one, const LeafDesc *__restrict__ many,
+// One NT-thread workgroup per leaf (NT = 64 when d <= 64, else 256); thread t
+// owns rows m = t + NT u, u < 4.
+template <int KIND, int RB, bool BATCH, int NT>
+__global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__restrict__ many,
                                              int nmany) {
   __shared__ double px[64], py[64], pz[64], ps[64 * RB];
   LeafDesc D;
@@ -354,11 +355,11 @@ __global__ __launch_bounds__(256) void k_p2m(LeafDesc one, const LeafDesc *__res
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
-  const int nu = (dp + 255) / 256;
+  const int nu = (dp + NT - 1) / NT;
   double xm[4], ym[4], zm[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int m = t + 256 * u;
+    const int m = t + NT * u;
     const bool ok = u < nu && m < d;
     xm[u] = ok ? D.X[3 * m] : 0.0;
     ym[u] = ok ? D.X[3 * m + 1] : 0.0;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_p2m(LeafDesc one, const LeafDesc *__res
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int m = t + 256 * u;
+      const int m = t + NT * u;
       if (u < nu && m < dp) {
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr)
@@ -1334,13 +1335,24 @@ void launch_p2p(bool mixed, int nrhs, int64_t nchunk, const LeafDesc &one, const
 }
 
 template <int KIND, bool BATCH>
-void launch_p2m(int nrhs, unsigned grid, const LeafDesc &one, const LeafDesc *many, int nmany,
-                hipStream_t s) {
+void launch_p2m(int nrhs, unsigned grid, int dpmax, const LeafDesc &one, const LeafDesc *many,
+                int nmany, hipStream_t s) {
   if (grid == 0) return;
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH>), dim3(grid), dim3(256), 0, s, one, many, nmany);
-  else
-    hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH>), dim3(grid), dim3(256), 0, s, one, many, nmany);
+  if (dpmax <= 64) {  // one row per thread: a 64-lane workgroup wastes no lanes on small d
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH, 64>), dim3(grid), dim3(64), 0, s, one, many,
+                         nmany);
+    else
+      hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH, 64>), dim3(grid), dim3(64), 0, s, one, many,
+                         nmany);
+  } else {
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH, 256>), dim3(grid), dim3(256), 0, s, one, many,
+                         nmany);
+    else
+      hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH, 256>), dim3(grid), dim3(256), 0, s, one, many,
+                         nmany);
+  }
 }
 
 size_t l2p_shm(int nrhs, int dpmax) {
@@ -1415,7 +1427,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   // step 1: P2M
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_P2M);
-    launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, LD, nullptr, 0, s);
+    launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, HL.dp, LD, nullptr, 0, s);
   }
   // step 2: M2M
   {
@@ -1707,7 +1719,7 @@ void run_group(const BatchExec &B, const BatchGroup &g, int phase, hipStream_t s
   if (phase == 0)
     launch_p2p<KIND, true>(B.mixed, 1, g.nchunk, none, many, g.count, s);
   else if (phase == 1)
-    launch_p2m<KIND, true>(1, (unsigned)g.nleaf, none, many, g.count, s);
+    launch_p2m<KIND, true>(1, (unsigned)g.nleaf, g.dpmax, none, many, g.count, s);
   else
     launch_l2p<KIND, true>(1, g.nchunk, g.dpmax, none, inone, many, B.io_dev + g.first, g.count,
                            s);
