@@ -89,8 +89,9 @@ def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data
     n = w["n"]
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
+    ctol = args.compress_tol if args.compress_tol is not None else w.get("compress_tol", 1e-6)
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], tau,
-                  precision=precision, compress_tol=args.compress_tol)
+                  precision=precision, compress_tol=ctol)
     setup_s = time.perf_counter() - t0
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(s).to(dev)
@@ -112,7 +113,8 @@ def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data
     st = plan.stats()
     plan.set_timing(False)
     fh = f.cpu().numpy()
-    return dict(w=w, tau=tau, n=n, ms=ms, stats=st, setup_s=setup_s, f=fh, x=x, s=s, plan=plan)
+    return dict(w=w, tau=tau, n=n, ms=ms, stats=st, setup_s=setup_s, f=fh, x=x, s=s, plan=plan,
+                compress_tol=ctol)
 
 
 def run_clustered(args):
@@ -131,13 +133,14 @@ def run_clustered(args):
     idx = np.sort(rng.choice(w["n"], 1000, replace=False))
     ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
                         threads=min(os.cpu_count() or 1, 16))
+    ctol = args.compress_tol if args.compress_tol is not None else w["compress_tol"]
     B = E.Batch([dict(kernel=w["kernel"], param=w["param"], n=w["n"], tau=w["tau"],
-                      compress_tol=args.compress_tol, depth=None)], precision="mixed")
+                      compress_tol=ctol, depth=None)], precision="mixed")
     B.set_points([torch.from_numpy(data[0]).to("cuda:0")])
     tuned = B.stats(0)["depth"]
     B.close()
     out = {"workload": name, "n": w["n"], "kernel": w["kernel"], "param": w["param"],
-           "tau": w["tau"], "compress_tol": args.compress_tol, "autotuned_depth": tuned}
+           "tau": w["tau"], "compress_tol": ctol, "autotuned_depth": tuned}
     for depth in sorted({w["depth"], tuned}):
         for prec in ("fp64", "mixed"):
             r = run_plain(args, precision=prec, steps=3, warmup=1, data=data,
@@ -227,8 +230,9 @@ def run_batched(args):
     x, S = W.make_points(w), W.make_sigma(w)  # S: (n, 64) column-major
     n, R = w["n"], S.shape[1]
     dev = torch.device("cuda:0")
+    ctol = args.compress_tol if args.compress_tol is not None else w["compress_tol"]
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], args.batched_tau,
-                  max_rhs=R, precision="mixed", compress_tol=args.compress_tol)
+                  max_rhs=R, precision="mixed", compress_tol=ctol)
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(np.ascontiguousarray(S.T)).to(dev)  # (64, n)
     f = torch.empty_like(sd)
@@ -271,7 +275,7 @@ def run_batched(args):
     plan.close()
     return dict(value=R * float(n) ** 2 / (ms * 1e-3), unit="interactions/s", nrhs=R, n=n,
                 ms_per_step=ms, precision="mixed", tau=args.batched_tau,
-                compress_tol=args.compress_tol, rank=st["rank"],
+                compress_tol=ctol, rank=st["rank"],
                 rel_l2_sampled_max=max(errs),
                 m2l_frac=st["m2l_flops"] / (m2l_ms * 1e-3) / (PEAK_TFLOPS["mixed"] * 1e12),
                 sequential_ms=ms_seq, sequential_value=R * float(n) ** 2 / (ms_seq * 1e-3),
@@ -370,8 +374,8 @@ def main():
                     help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
-    ap.add_argument("--compress-tol", type=float, default=1e-6,
-                    help="M2L compression tolerance (Sec. 4.2); 0 disables it")
+    ap.add_argument("--compress-tol", type=float, default=None,
+                    help="M2L compression tolerance (Sec. 4.2); default: the workload's; 0 disables it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -415,7 +419,7 @@ def main():
         b = src.index("// ------------------------------------------------------------------ host side")
         cur = hashlib.sha256(src[a:b].encode()).hexdigest()
         if (key in tr and tr[key].get("valid", False) and tr[key].get("gemm_source_sha256") == cur
-                and abs(args.compress_tol - 1e-6) < 1e-18 and not args.tau
+                and tr[key].get("compress_tol") == r["compress_tol"] and not args.tau
                 and not args.depth):
             traffic = tr[key]["bytes_per_launch"]
     phases = {k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]}
@@ -427,7 +431,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "depth": r["w"]["depth"],
                    "kernel": r["w"]["kernel"], "tau": r["tau"], "nrhs": 1,
                    "precision": args.precision, "d": st["d"],
-                   "compress_tol": args.compress_tol, "rank": st["rank"],
+                   "compress_tol": r["compress_tol"], "rank": st["rank"],
                    "step": "set_points + evaluate", "phase_ms": phases},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,

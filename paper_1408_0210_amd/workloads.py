@@ -45,21 +45,25 @@ def potentials_multi(n, seeds):
 
 
 # Workload recipes (sizes, seeds, kernels) used by the tests and the benchmark.
+# compress_tol is the M2L compression tolerance (Sec. 4.2): 5e-6 keeps rank 160
+# of d = 287 for 1/r at tau = 1e-6, with rel-L2 errors of 1.2-4.7e-7 on these
+# workloads (1e-5 would give rank 128 and 4.8e-7 on the uniform one).
 WORKLOADS = {
     # FP64, single right-hand side, oracle-sized: 2000 points, depth 3.
     "uniform2k_laplace_d3": dict(n=2000, dist="uniform", seed_pts=1, seed_sigma=2,
                                  kernel="laplace", param=0.0, depth=3, tau=1e-6),
     # FP64 single RHS, 1e6 uniform points, depth 5 (~30 points per leaf).
     "uniform1m_laplace_d5": dict(n=1_000_000, dist="uniform", seed_pts=3, seed_sigma=4,
-                                 kernel="laplace", param=0.0, depth=5, tau=1e-6),
+                                 kernel="laplace", param=0.0, depth=5, tau=1e-6,
+                                 compress_tol=5e-6),
     # Mixed precision, 16 Gaussian clusters (width 0.03), exp(-r)/r.
     "cluster1m_yukawa": dict(n=1_000_000, dist="cluster", ncl=16, width=0.03, seed_centres=5,
                              seed_pts=6, seed_sigma=7, kernel="yukawa", param=1.0, depth=5,
-                             tau=1e-6),
+                             tau=1e-6, compress_tol=5e-6),
     # Many right-hand sides: 2^20 uniform points, 64 sigma vectors, depth 5.
     "uniform1m_laplace_d5_rhs64": dict(n=1 << 20, dist="uniform", seed_pts=8,
                                        seed_sigma=list(range(100, 164)), kernel="laplace",
-                                       param=0.0, depth=5, tau=1e-6),
+                                       param=0.0, depth=5, tau=1e-6, compress_tol=5e-6),
 }
 
 # The paper's inhomogeneous-kernel test cases (Sec. 5.4, Table 3): 1e6 points
