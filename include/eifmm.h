@@ -190,7 +190,10 @@ int eifmm_export_lists(eifmm_plan plan, int32_t level, int64_t *nactive, uint32_
 
 /* Host copy of one expansion of the last evaluate, right-hand side `rhs`, as a
  * dense 8^k x d_k array in key order (zeros for empty boxes).  which: 0 = W,
- * 1 = What (= Delta W), 2 = g (M2L output), 3 = l, 4 = lhat (level depth only). */
+ * 1 = What (= Delta W), 2 = g (M2L output), 3 = l, 4 = lhat (level depth only).
+ * With M2L compression the pass applies the factor B^{-T} of Delta = B^{-T}
+ * Gamma^{-1} inside the projection (What' = U^T B^{-T} (Gamma^{-1} W)), so What
+ * of a compressed level is computed by this call, on the device, from W. */
 int eifmm_export_expansion(eifmm_plan plan, int32_t which, int32_t k, int32_t rhs, double *out);
 
 /* Releases the plan and all its device memory. */

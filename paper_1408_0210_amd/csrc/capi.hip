@@ -158,7 +158,7 @@ int setup_tables(eifmm_plan h) {
     TRY(upload(&D.X, H.X.data(), H.X.size(), tr));
     if (H.r > 0) {
       TRY(upload(&D.ufrag, H.ufrag.data(), H.ufrag.size(), tr));
-      TRY(upload(&D.utfrag, H.utfrag.data(), H.utfrag.size(), tr));
+      TRY(upload(&D.pfrag, H.pfrag.data(), H.pfrag.size(), tr));
     }
   }
   return EIFMM_OK;
@@ -320,7 +320,7 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
     for (int q = 0; q < 4; ++q) D.tri[q] = TD.tri[q];
     D.X = TD.X;
     D.ufrag = TD.ufrag;
-    D.utfrag = TD.utfrag;
+    D.pfrag = TD.pfrag;
   }
   P.dvec = T.dvec;
   P.code2id = T.code2id;
@@ -668,6 +668,8 @@ int eifmm_export_expansion(eifmm_plan h, int32_t which, int32_t k, int32_t rhs, 
   if (rhs < 0 || rhs >= P.last_rhs) return EIFMM_EINVAL;
   hipSetDevice(P.device);
   if (hipDeviceSynchronize() != hipSuccess) return EIFMM_EHIP;
+  int st = materialize_expansion(P, which, k);
+  if (st) return st;
   const LevelDev &D = P.ld[k];
   const int d = P.lh[k].d, dp = P.lh[k].dp, R = P.last_rhs;
   const int64_t na = P.nact[k];

@@ -524,7 +524,12 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
       z = __builtin_amdgcn_mfma_f64_16x16x4f64(Ad[ks * 64], acc[ks], z, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = z[q];
+    if (!D.Tb && cv) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[16 * bi + rs + 4 * q] = z[q];
+    }
   }
+  if (!D.Tb) return;  // forward solve only
   for (int bi = nb - 1; bi >= 0; --bi) {
     v4 acc;
 #pragma unroll
@@ -555,6 +560,9 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
     }
   }
 }
+
+// LDS bytes of a solve launch: the solved tiles of the 16 columns
+inline size_t trsm_shm(int dp) { return sizeof(double) * 4 * 64 * (size_t)(dp / 16); }
 
 // one plan: up to one descriptor per level, passed by value
 __global__ __launch_bounds__(64) void k_trsm(SolveArgs A) {
@@ -1098,7 +1106,8 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     h.push_back(J);
     jt.m2m_units[k] = finish_units(h, jt.m2m_first[k]);
   }
-  // compression projections What' = U^T What, one job per compressed level
+  // compression projections What' = U^T B^{-T} z with z = Gamma^{-1} W from the
+  // forward solve, one job per compressed level
   {
     int tiles = 0;
     jt.pre_first = (int)h.size();
@@ -1107,7 +1116,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     for (int k = depth; k >= 2; --k) {
       if (P.lh[k].r == 0 || P.nact[k] == 0) continue;
       GemmJob J{};
-      J.A = P.ld[k].utfrag;
+      J.A = P.ld[k].pfrag;
       J.Bsrc = P.ld[k].Wh;
       J.C = P.ld[k].Whp;
       J.C32 = mixed ? P.ld[k].Whp32 : nullptr;
@@ -1436,7 +1445,8 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
       launch_gemm<double, MODE_M2M>(P, P.jobs.m2m_first[k], P.jobs.m2m_n[k], P.jobs.m2m_tiles[k],
                                     P.jobs.m2m_units[k], s, P.jobs.m2m_rbt[k]);
   }
-  // step 3: What = Delta W on every level
+  // step 3: What = Delta W = B^{-T} Gamma^{-1} W on uncompressed levels; on
+  // compressed ones z = Gamma^{-1} W (the projection applies U^T B^{-T})
   {
     Timer tm(P, s, EIFMM_PH_WHAT);
     SolveArgs A{};
@@ -1450,12 +1460,12 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
       D.out = P.ld[k].Wh;
       D.out32 = (mixed && P.lh[k].r == 0) ? P.ld[k].Wh32 : nullptr;
       D.Tf = P.ld[k].tri[0];
-      D.Tb = P.ld[k].tri[1];
+      D.Tb = solves_what(P, k) ? P.ld[k].tri[1] : nullptr;
       D.ncols = nc;
       D.dp = P.lh[k].dp;
       D.blk_start = blk;
       blk += (nc + 15) / 16;
-      shm = std::max(shm, sizeof(double) * 4 * 64 * (size_t)(P.lh[k].dp / 16));
+      shm = std::max(shm, trsm_shm(P.lh[k].dp));
     }
     A.nlev = q;
     if (blk > 0) hipLaunchKernelGGL(k_trsm, dim3(blk), dim3(64), shm, s, A);
@@ -1502,8 +1512,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     A.lv[0].blk_start = 0;
     A.nlev = 1;
     if (nc > 0)
-      hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64),
-                         sizeof(double) * 4 * 64 * (size_t)(HL.dp / 16), s, A);
+      hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64), trsm_shm(HL.dp), s, A);
   }
   // step 7: L2P and the final sum
   if (nleafa > 0) {
@@ -1563,6 +1572,36 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
     return EIFMM_EHIP;
   }
   P.last_rhs = nrhs;
+  return EIFMM_OK;
+}
+
+int materialize_expansion(Plan &P, int which, int k) {
+  const int nrhs = P.jobs.nrhs;
+  if (nrhs < 1 || k < 2 || k > P.depth || P.nact[k] == 0) return EIFMM_OK;
+  hipStream_t s = nullptr;
+  if (which == 1 && !solves_what(P, k)) {
+    // What = Delta W, as the pass computes it on uncompressed levels
+    SolveArgs A{};
+    SolveDesc &D = A.lv[0];
+    D.in = P.ld[k].W;
+    D.out = P.ld[k].Wh;
+    D.out32 = nullptr;
+    D.Tf = P.ld[k].tri[0];
+    D.Tb = P.ld[k].tri[1];
+    D.ncols = (int)(P.nact[k] * nrhs);
+    D.dp = P.lh[k].dp;
+    D.blk_start = 0;
+    A.nlev = 1;
+    hipLaunchKernelGGL(k_trsm, dim3((D.ncols + 15) / 16), dim3(64), trsm_shm(D.dp), s, A);
+  } else {
+    return EIFMM_OK;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
   return EIFMM_OK;
 }
 
@@ -1804,7 +1843,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
     std::vector<IoDesc> io(np, IoDesc{nullptr, 0, nullptr, 0});
     if ((st = bupload(&B.io_dev, io, B.track))) return st;
   }
-  // triangular solves: What on every level, lhat on the leaf level
+  // triangular solves: What (z on compressed levels) on every level, lhat on the leaf level
   {
     std::vector<SolveDesc> w, l;
     int bw = 0, bl = 0;
@@ -1818,12 +1857,12 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
         D.out = P.ld[k].Wh;
         D.out32 = (B.mixed && P.lh[k].r == 0) ? P.ld[k].Wh32 : nullptr;
         D.Tf = P.ld[k].tri[0];
-        D.Tb = P.ld[k].tri[1];
+        D.Tb = solves_what(P, k) ? P.ld[k].tri[1] : nullptr;
         D.ncols = nc;
         D.dp = P.lh[k].dp;
         D.blk_start = bw;
         bw += (nc + 15) / 16;
-        B.what_shm = std::max(B.what_shm, sizeof(double) * 4 * 64 * (size_t)(D.dp / 16));
+        B.what_shm = std::max(B.what_shm, trsm_shm(D.dp));
         w.push_back(D);
       }
       const int k = P.depth, nc = (int)P.nact[k];
@@ -1838,7 +1877,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
       D.dp = P.lh[k].dp;
       D.blk_start = bl;
       bl += (nc + 15) / 16;
-      B.lhat_shm = std::max(B.lhat_shm, sizeof(double) * 4 * 64 * (size_t)(D.dp / 16));
+      B.lhat_shm = std::max(B.lhat_shm, trsm_shm(D.dp));
       l.push_back(D);
     }
     B.what_n = (int)w.size();

@@ -30,8 +30,8 @@ struct LevelHost {
   int r = 0, rp = 0;
   std::vector<double> sv;       // singular values of [K^delta_1 .. K^delta_316]
   std::vector<double> U;        // d x r, row-major
-  std::vector<double> ufrag;    // U   (dp x rp), fragment order: g = U g'
-  std::vector<double> utfrag;   // U^T (rp x dp), fragment order: What' = U^T What
+  std::vector<double> ufrag;    // U          (dp x rp), fragment order: g = U g'
+  std::vector<double> pfrag;    // U^T B^{-T} (rp x dp), fragment order: What' = U^T B^{-T} Gamma^{-1} W
 };
 
 // Device copy of one level's tables.
@@ -49,7 +49,7 @@ struct LevelDev {
   double *W = nullptr, *Wh = nullptr, *g = nullptr, *l = nullptr;
   float *Wh32 = nullptr;  // FP32 copy of What (mixed precision M2L)
   // compressed M2L
-  double *ufrag = nullptr, *utfrag = nullptr;
+  double *ufrag = nullptr, *pfrag = nullptr;
   double *Whp = nullptr, *gp = nullptr;  // What' = U^T What and g' (rp per box and RHS)
   float *Whp32 = nullptr;
 };
@@ -169,7 +169,7 @@ struct JobTables {
   int64_t m2m_units[kMaxLevels] = {}, l2l_units[kMaxLevels] = {};
   int64_t m2l_units = 0, pre_units = 0, post_units = 0;
   int m2l_first = 0, m2l_n = 0, m2l_tiles = 0, m2l_rbt = 6;
-  int pre_first = 0, pre_n = 0, pre_tiles = 0, pre_rbt = 6;     // What' = U^T What
+  int pre_first = 0, pre_n = 0, pre_tiles = 0, pre_rbt = 6;     // What' = U^T B^{-T} z
   int post_first = 0, post_n = 0, post_tiles = 0, post_rbt = 6; // g = U g'
 };
 
@@ -257,6 +257,12 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s);
 void timing_drain(Plan &P);
 int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int64_t ldf,
              hipStream_t s);
+// Writes an expansion of the last pass that the pass itself skipped (What of a
+// compressed level), on the null stream.
+int materialize_expansion(Plan &P, int which, int k);
+// On a compressed level the solve for What stops at z = Gamma^{-1} W: the
+// projection applies U^T B^{-T} (pass.hip)
+inline bool solves_what(const Plan &P, int k) { return P.lh[k].r == 0; }
 // batches (pass.hip): m2l_rbt <= 0 picks the M2L tile height from the operators
 int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans, int m2l_rbt, int sk_groups,
                   double *sk_ws);

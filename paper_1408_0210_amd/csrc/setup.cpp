@@ -16,7 +16,9 @@
 //    asked for, their compression (Sec. 4.2, first stage): the leading left
 //    singular vectors U of [K^delta_1 .. K^delta_316] (Householder QR of the
 //    transpose, then a one-sided Jacobi SVD of R^T -- an exact SVD in place of the
-//    paper's bivariate ACA) and C^delta = U^T K^delta U.
+//    paper's bivariate ACA) and C^delta = U^T K^delta U; the factor B^{-T} of
+//    Delta = M^{-1} is folded into the projection before the M2L step, U^T B^{-T}
+//    (the Gamma solve stays on the device).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -525,13 +527,23 @@ int build_tables(Plan &P) {
       lv.U.assign((size_t)d * lv.r, 0.0);
       for (int i = 0; i < d; ++i)
         for (int a = 0; a < lv.r; ++a) lv.U[(size_t)i * lv.r + a] = Ufull[(size_t)i * d + a];
-      std::vector<double> Ut((size_t)lv.r * d);
-      for (int a = 0; a < lv.r; ++a)
-        for (int i = 0; i < d; ++i) Ut[(size_t)a * d + i] = lv.U[(size_t)i * lv.r + a];
+      // What' = U^T What = (U^T B^{-T}) (Gamma^{-1} W): the well-conditioned factor
+      // B^T is folded into the projection (row a is (B^{-1} u_a)^T), the solve with
+      // the ill-conditioned Gamma stays a solve
+      std::vector<double> Pm((size_t)lv.r * d);
+      for (int a = 0; a < lv.r; ++a) {
+        double *row = &Pm[(size_t)a * d];
+        for (int i = 0; i < d; ++i) row[i] = lv.U[(size_t)i * lv.r + a];
+        for (int i = 0; i < d; ++i) {  // B row = u_a, B unit lower
+          double t = row[i];
+          for (int j = 0; j < i; ++j) t -= lv.B[(size_t)i * d + j] * row[j];
+          row[i] = t;
+        }
+      }
       lv.ufrag.assign((size_t)dp * lv.rp, 0.0);
-      lv.utfrag.assign((size_t)lv.rp * dp, 0.0);
+      lv.pfrag.assign((size_t)lv.rp * dp, 0.0);
       to_fragments(lv.U.data(), d, lv.r, dp, lv.rp, lv.ufrag.data());
-      to_fragments(Ut.data(), lv.r, d, lv.rp, dp, lv.utfrag.data());
+      to_fragments(Pm.data(), lv.r, d, lv.rp, dp, lv.pfrag.data());
     }
     const int r = lv.r, rp = lv.rp;
     const int dm = r > 0 ? rp : dp;  // size of the transferred expansions

@@ -262,6 +262,37 @@ def test_compressed_fp64_vs_oracle(E, torch_dev, oracle_lib, c1_inputs, c1_direc
     plan.close()
 
 
+@pytest.mark.parametrize("depth", [2, 3])
+def test_compressed_stages_vs_oracle(depth, E, torch_dev, oracle_lib, c1_inputs):
+    """With compression the pass folds the factor B^{-T} of Delta = B^{-T} Gamma^{-1}
+    into the projection (What' = U^T B^{-T} (Gamma^{-1} W)).  The result and every
+    expansion, including What, which the export computes on demand on compressed
+    levels, against the oracle's compressed pass, which solves for What."""
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], depth, w["tau"],
+                  compress_tol=1e-6)
+    ranks = plan.stats()["rank"]
+    assert all(0 < r < plan.stats()["d"][k] for k, r in ranks.items())
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
+    O = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, depth, w["tau"],
+                        compress_tol=1e-6, compress_rank=ranks)
+    fo, D = O.evaluate(x, s, dumps=True)
+    assert _rel(f, fo) < 1e-10
+    tol = {"W": 1e-12, "What": 1e-5, "g": 1e-10, "l": 1e-10}
+    for k in range(2, depth + 1):
+        for name in ("W", "What", "g", "l"):
+            e = _rel(plan.export_expansion(name, k), D[name][k])
+            assert e < tol[name], (name, k, e)
+    e = _rel(plan.export_expansion("lhat", depth), D["lhat"])
+    assert e < 1e-5, e
+    # the on-demand exports leave the pass intact
+    f2 = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
+    np.testing.assert_array_equal(f2, f)
+    plan.close()
+
+
 def test_compressed_mixed_and_multi_rhs(E, torch_dev, oracle_lib, c1_inputs, c1_direct):
     torch, dev = torch_dev
     x, s, w = c1_inputs
