@@ -23,7 +23,8 @@ Also reported on the same line:
                 evaluated one after another;
   paper_kernels the paper's cos(20r)/r, exp(-r^2), sqrt(r^2+1) on its 1e6-point
                 cube, with d per level and its own one-core timings as context;
-  uniform100m   the paper's 1e8-point exp(-r^2) cube (Table 4), FP64 and mixed.
+  uniform100m   the paper's 1e8-point exp(-r^2) cube (Table 4), FP64 and mixed;
+  targets       1e6 sources and 1e6 separate targets (1/r, depth 5): N_s N_t / t.
 """
 import argparse
 import json
@@ -191,6 +192,47 @@ def run_paper_kernels(args):
                      "paper_seconds_1core": paper["seconds"],
                      "paper_rel_acc": paper["rel_acc"]}
         r["plan"].close()
+    return out
+
+
+def run_targets(args):
+    """1e6 sources and 1e6 separate targets, uniform in the cube, 1/r, depth 5,
+    tau 1e-6: one octree over both point sets (set_points_targets) plus the pass,
+    FP64 and mixed; value = N_s N_t / t; error on 2000 sampled targets."""
+    import torch
+    import oracle
+    from paper_1408_0210_amd import eifmm as E
+    from paper_1408_0210_amd import workloads as W
+    name = "uniform1m_targets1m_laplace_d5"
+    w = W.WORKLOADS[name]
+    xs, xt, s = W.make_points(w), W.make_targets(w), W.make_sigma(w)
+    idx = np.sort(np.random.default_rng(17).choice(w["n_targets"], 2000, replace=False))
+    ref = oracle.direct(w["kernel"], w["param"], xt[:, idx].copy(), xs, s,
+                        threads=min(os.cpu_count() or 1, 16))
+    dev = torch.device("cuda:0")
+    xsd, xtd, sd = (torch.from_numpy(a).to(dev) for a in (xs, xt, s))
+    out = {"workload": name, "n_sources": w["n"], "n_targets": w["n_targets"],
+           "depth": w["depth"], "tau": w["tau"], "compress_tol": w["compress_tol"]}
+    for prec in ("fp64", "mixed"):
+        plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                      precision=prec, compress_tol=w["compress_tol"], n_targets=w["n_targets"])
+        f = torch.empty(w["n_targets"], dtype=torch.float64, device=dev)
+        plan.set_points(xsd, targets=xtd)
+        plan.evaluate(sd, out=f)
+        _sync()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = 3
+        ev0.record()
+        for _ in range(steps):
+            plan.set_points(xsd, targets=xtd)
+            plan.evaluate(sd, out=f)
+        ev1.record()
+        _sync()
+        ms = ev0.elapsed_time(ev1) / steps
+        out[prec] = {"ms_per_step": ms,
+                     "value": float(w["n"]) * w["n_targets"] / (ms * 1e-3),
+                     "rel_l2_sampled": _rel_sample(f.cpu().numpy(), idx, ref)}
+        plan.close()
     return out
 
 
@@ -368,9 +410,12 @@ def main():
                     help="skip the paper's cos(20r)/r, exp(-r^2), sqrt(r^2+1) cube runs")
     ap.add_argument("--no-100m", action="store_true",
                     help="skip the 1e8-point exp(-r^2) run")
+    ap.add_argument("--no-targets", action="store_true",
+                    help="skip the separate-targets run (1e6 sources, 1e6 targets)")
     ap.add_argument("--batch-precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--only-leg",
-                    choices=["batched", "clustered", "uneven", "paper_kernels", "100m"],
+                    choices=["batched", "clustered", "uneven", "paper_kernels", "100m",
+                             "targets"],
                     help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
@@ -394,7 +439,7 @@ def main():
 
     if args.only_leg:
         leg = {"batched": run_batched, "clustered": run_clustered, "uneven": run_uneven,
-               "paper_kernels": run_paper_kernels, "100m": run_100m}
+               "paper_kernels": run_paper_kernels, "100m": run_100m, "targets": run_targets}
         print(json.dumps({args.only_leg: leg[args.only_leg](args)}), flush=True)
         return
 
@@ -453,6 +498,8 @@ def main():
         out["paper_kernels"] = run_paper_kernels(args)
     if not args.no_100m:
         out["uniform100m"] = run_100m(args)
+    if not args.no_targets:
+        out["targets"] = run_targets(args)
     print(json.dumps(out), flush=True)
 
 

@@ -7,9 +7,13 @@
  *     f(x_i) = sum_{j=1..N} sigma_j K(x_i, x_j),   i = 1..N,
  *
  * for translation-invariant 3D kernels K(x, y) = k(x - y), with targets equal
- * to sources (the N-body setting of Sec. 1).  Following the problem statement
- * of Sec. 1, the domain Omega and N are fixed per plan while the points and the
- * potentials change from query to query:
+ * to sources (the N-body setting of Sec. 1) or, when the plan says so, at
+ * n_targets separate target points x_i and N source points y_j:
+ *
+ *     f(x_i) = sum_{j=1..N} sigma_j K(x_i, y_j),   i = 1..n_targets.
+ *
+ * Following the problem statement of Sec. 1, the domain Omega and N are fixed
+ * per plan while the points and the potentials change from query to query:
  *
  *     eifmm_plan_create   per-level EIM (Algorithm 1) and operator tables,
  *                         host FP64, uploaded once                (Sec. 2, 4.1, 4.2)
@@ -98,6 +102,9 @@ typedef struct {
                            is the larger of the two filters (s_j/s_0 > eps, and the
                            prefix holding 1 - eps of the sum of singular values),
                            rounded up to the MFMA tile granularity; 0 = off      */
+  int64_t n_targets;    /* 0: the targets are the n sources; > 0: that many separate
+                           target points (eifmm_set_points_targets), fixed per
+                           plan; n + n_targets <= 2^30 - 1                       */
 } eifmm_config;
 
 /* evaluation phases timed when timing is enabled (eifmm_set_timing) */
@@ -152,9 +159,22 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out);
  * has no points).  Waits for the build. */
 int eifmm_set_points(eifmm_plan plan, const double *xyz_dev, void *hip_stream);
 
+/* For a plan with n_targets > 0: builds one octree over the n sources
+ * src_xyz_dev and the n_targets targets tgt_xyz_dev (both device, SoA FP64),
+ * sorted by (leaf key, source before target, input index), so that every leaf
+ * holds its sources, then its targets.  Boxes are those with any point; P2M and
+ * the near field read the sources of a leaf, L2P and the near field write its
+ * targets (eq. (13) with x_i a target).  A target that coincides with a source
+ * skips that pair for singular kernels, as a source does with itself.  Errors
+ * as eifmm_set_points; EIFMM_EINVAL on a plan with n_targets == 0 (and
+ * eifmm_set_points is EIFMM_EINVAL on a plan with n_targets > 0). */
+int eifmm_set_points_targets(eifmm_plan plan, const double *src_xyz_dev, const double *tgt_xyz_dev,
+                             void *hip_stream);
+
 /* f = K sigma for nrhs right-hand sides: sigma_dev (n x nrhs, column-major,
- * leading dimension ld) in input order; f_dev (n x nrhs, leading dimension ldf)
- * is overwritten in input order.  Requires set_points; nrhs <= max_rhs. */
+ * leading dimension ld >= n) in input order; f_dev (m x nrhs, leading dimension
+ * ldf >= m, m = n_targets if > 0, else n) is overwritten in input order.
+ * Requires set_points (set_points_targets); nrhs <= max_rhs. */
 int eifmm_evaluate(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
                    double *f_dev, int64_t ldf, void *hip_stream);
 
@@ -176,7 +196,9 @@ int eifmm_get_level(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y
 int eifmm_get_compression(eifmm_plan plan, int32_t k, int32_t *r, double *sv, double *U);
 
 /* Host copies of the current tree: perm[n] (input index of each Morton-ordered
- * point), leaf_start[8^depth + 1], keys[n] (leaf key of each sorted point). */
+ * point), leaf_start[8^depth + 1], keys[n] (leaf key of each sorted point).
+ * With separate targets the arrays cover n + n_targets points; perm holds n + t
+ * for target t. */
 int eifmm_export_tree(eifmm_plan plan, int32_t *perm, int64_t *leaf_start, uint32_t *keys);
 
 /* Builds (on the device) and copies the lists of `level`: active boxes in key
@@ -232,7 +254,8 @@ typedef struct {
 /* cfgs: nprob configurations (host memory, copied; n may be 0).  Builds and
  * uploads the shared level tables.  Errors as eifmm_plan_create, and
  * EIFMM_EINVAL for nprob < 1, differing precisions, max_rhs != 1, the host-only
- * flag, or depth outside {-1, 2..EIFMM_MAX_DEPTH}.  On error *out is NULL. */
+ * flag, n_targets != 0, or depth outside {-1, 2..EIFMM_MAX_DEPTH}.  On error
+ * *out is NULL. */
 int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out);
 
 /* xyz[p]: device pointer to problem p's 3 x n_p SoA points (may be NULL when

@@ -56,7 +56,9 @@ int validate(const eifmm_config *c) {
   if (!(c->L > 0) || !std::isfinite(c->L)) return EIFMM_EINVAL;
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(c->lo[a])) return EIFMM_EINVAL;
-  if (c->n < 0 || c->n > (int64_t)INT32_MAX / 2) return EIFMM_EINVAL;
+  if (c->n < 0 || c->n_targets < 0 || c->n > (int64_t)INT32_MAX / 2 ||
+      c->n_targets > (int64_t)INT32_MAX / 2 - c->n)
+    return EIFMM_EINVAL;
   if (c->depth < 0 || c->depth > EIFMM_MAX_DEPTH) return EIFMM_EINVAL;
   if (c->max_rhs < 1 || c->max_rhs > 4096) return EIFMM_EINVAL;
   if (!(c->eim_tol > 0) || !std::isfinite(c->eim_tol)) return EIFMM_EINVAL;
@@ -185,6 +187,10 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
   TRY(dalloc(&P.hist, (size_t)256 * P.ntiles_sort, tr));
   const int64_t nleaf = (int64_t)1 << (3 * depth);
   TRY(dalloc(&P.leaf_start, nleaf + 1, tr));
+  if (P.nt) {
+    TRY(dalloc(&P.tgt_begin, nleaf + 1, tr));
+    TRY(dalloc(&P.xin, 3 * nn, tr));
+  }
   size_t maxcap = 1;
   for (int k = 0; k <= depth; ++k) {
     LevelDev &D = P.ld[k];
@@ -298,7 +304,7 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
   P.cfg = b->cfg[p];
   P.cfg.depth = depth;
   P.depth = depth;
-  P.n = P.cfg.n;
+  P.n = P.ns = P.cfg.n;
   P.max_rhs = 1;
   P.device = T.device;
   P.setup_ms = 0;
@@ -486,7 +492,9 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   Plan &P = h->P;
   P.cfg = *cfg;
   P.depth = cfg->depth;
-  P.n = cfg->n;
+  P.ns = cfg->n;
+  P.nt = cfg->n_targets;
+  P.n = P.ns + P.nt;
   P.max_rhs = cfg->max_rhs;
   P.host_only = (cfg->flags & EIFMM_FLAG_HOST_ONLY) != 0;
   st = build_tables(P);
@@ -507,15 +515,27 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   return EIFMM_OK;
 }
 
-int eifmm_set_points(eifmm_plan h, const double *xyz, void *stream) {
-  if (!h) return EIFMM_EINVAL;
+namespace {
+// tree build over xyz (n points, SoA); with separate targets the sources and
+// the targets are first copied into one array (sources first)
+int set_points_impl(eifmm_plan h, const double *xyz, const double *tgt, void *stream) {
   Plan &P = h->P;
-  if (P.host_only) return EIFMM_ESTATE;
-  if (P.n > 0 && !xyz) return EIFMM_EINVAL;
   hipSetDevice(P.device);
   P.points_set = false;
   P.jobs.nrhs = -1;
   hipStream_t s = (hipStream_t)stream;
+  if (P.nt) {
+    for (int a = 0; a < 3; ++a) {
+      if (P.ns > 0 &&
+          hipMemcpyAsync(P.xin + a * P.n, xyz + a * P.ns, sizeof(double) * P.ns,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return EIFMM_EHIP;
+      if (hipMemcpyAsync(P.xin + a * P.n + P.ns, tgt + a * P.nt, sizeof(double) * P.nt,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return EIFMM_EHIP;
+    }
+    xyz = P.xin;
+  }
   if (P.timing) {
     // tree time is recorded as one phase
     EventPair e;
@@ -539,6 +559,24 @@ int eifmm_set_points(eifmm_plan h, const double *xyz, void *stream) {
   P.points_set = true;
   return EIFMM_OK;
 }
+}  // namespace
+
+int eifmm_set_points(eifmm_plan h, const double *xyz, void *stream) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (P.host_only) return EIFMM_ESTATE;
+  if (P.nt || (P.n > 0 && !xyz)) return EIFMM_EINVAL;
+  return set_points_impl(h, xyz, nullptr, stream);
+}
+
+int eifmm_set_points_targets(eifmm_plan h, const double *src_xyz, const double *tgt_xyz,
+                             void *stream) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (P.host_only) return EIFMM_ESTATE;
+  if (!P.nt || !tgt_xyz || (P.ns > 0 && !src_xyz)) return EIFMM_EINVAL;
+  return set_points_impl(h, src_xyz, tgt_xyz, stream);
+}
 
 int eifmm_evaluate(eifmm_plan h, const double *sigma, int32_t nrhs, int64_t ld, double *f,
                    int64_t ldf, void *stream) {
@@ -546,7 +584,9 @@ int eifmm_evaluate(eifmm_plan h, const double *sigma, int32_t nrhs, int64_t ld, 
   Plan &P = h->P;
   if (P.host_only || !P.points_set) return EIFMM_ESTATE;
   if (nrhs < 1 || nrhs > P.max_rhs) return EIFMM_EINVAL;
-  if (P.n > 0 && (!sigma || !f || ld < P.n || ldf < P.n)) return EIFMM_EINVAL;
+  const int64_t nout = P.nt ? P.nt : P.ns;
+  if ((P.ns > 0 && (!sigma || ld < P.ns)) || (nout > 0 && (!f || ldf < nout)))
+    return EIFMM_EINVAL;
   hipSetDevice(P.device);
   return pass_run(P, sigma, nrhs, ld, f, ldf, (hipStream_t)stream);
 }
@@ -633,7 +673,11 @@ int eifmm_export_tree(eifmm_plan h, int32_t *perm, int64_t *leaf_start, uint32_t
   hipSetDevice(P.device);
   if (hipDeviceSynchronize() != hipSuccess) return EIFMM_EHIP;
   if (perm && P.n) hipMemcpy(perm, P.idx, sizeof(int) * P.n, hipMemcpyDeviceToHost);
-  if (keys && P.n) hipMemcpy(keys, P.keys, sizeof(uint32_t) * P.n, hipMemcpyDeviceToHost);
+  if (keys && P.n) {
+    hipMemcpy(keys, P.keys, sizeof(uint32_t) * P.n, hipMemcpyDeviceToHost);
+    if (P.nt)  // drop the source/target bit of the sort key
+      for (int64_t q = 0; q < P.n; ++q) keys[q] >>= 1;
+  }
   if (leaf_start) {
     const int64_t nl = ((int64_t)1 << (3 * P.depth)) + 1;
     std::vector<int> tmp(nl);
@@ -717,7 +761,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
     int st = validate(&c);
     if (st) return st;
     if (c.depth < 2 || c.max_rhs != 1 || (c.flags & EIFMM_FLAG_HOST_ONLY) ||
-        c.precision != cfgs[0].precision)
+        c.precision != cfgs[0].precision || c.n_targets != 0)
       return EIFMM_EINVAL;
   }
   eifmm_batch b = new (std::nothrow) eifmm_batch_s();

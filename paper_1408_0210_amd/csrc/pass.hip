@@ -122,7 +122,7 @@ __device__ inline void pick_desc(const LeafDesc &one, const LeafDesc *__restrict
 }
 
 // ------------------------------------------------------------------ sigma
-// sig[s][r] = sigma[perm[s] + r ld] (sorted order)
+// sig[s][r] = sigma[perm[s] + r ld] (sorted order; 0 at targets)
 template <bool BATCH>
 __global__ void k_gather_sigma(LeafDesc one, IoDesc ione, const LeafDesc *__restrict__ many,
                                const IoDesc *__restrict__ io, int nmany, int64_t total) {
@@ -142,7 +142,8 @@ __global__ void k_gather_sigma(LeafDesc one, IoDesc ione, const LeafDesc *__rest
   }
   const int64_t s = el / D.nrhs;
   const int r = (int)(el - s * D.nrhs);
-  D.sig[el] = O.sigma[(int64_t)D.perm[s] + (int64_t)r * O.ld];
+  const int64_t src = D.perm[s];  // a target (src >= nsrc) carries no potential
+  D.sig[el] = src < D.nsrc ? O.sigma[src + (int64_t)r * O.ld] : 0.0;
 }
 
 // ------------------------------------------------------------------ near field
@@ -165,7 +166,7 @@ __device__ inline NearSrc near_sources(const LeafDesc &D, int j, int *pre, int *
   if (lane < nq) {
     const uint32_t sk = D.act[D.near_src[q0 + lane]];
     start[lane] = D.ls[sk];
-    cnt = D.ls[sk + 1] - D.ls[sk];
+    cnt = D.se[sk] - D.ls[sk];
   }
   // inclusive scan of cnt over the (at most 27) lanes
   int v = cnt;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
   const int b = D.ls[key + 1];
-  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
+  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const bool tv = i < b;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
   const NearSrc S = near_sources(D, j, pre, start);
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
   const int b = D.ls[key + 1];
-  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
+  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const bool tv = i < b;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
   const NearSrc S = near_sources(D, j, pre, start);
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
   const double *__restrict__ xyz = D.xyz;
   const double *__restrict__ sig = D.sig;
   const uint32_t key = D.act[j];
-  const int a = D.ls[key], b = D.ls[key + 1];
+  const int a = D.ls[key], b = D.se[key];
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
   const int b = D.ls[key + 1];
-  const int i = D.ls[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
+  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
     if (tv && half == 0) {
-      const int64_t o = D.perm[i];
+      const int64_t o = D.perm[i] - D.toff;
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < nrhs)
@@ -472,13 +473,16 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
 }
 
 // depth < 2: no far field, f = f_near in input order
+// (targets only: input indices from toff on)
 __global__ void k_combine_near(int64_t n, int nrhs, const double *__restrict__ fnear,
-                               const int *__restrict__ perm, double *__restrict__ f, int64_t ldf) {
+                               const int *__restrict__ perm, int64_t toff, double *__restrict__ f,
+                               int64_t ldf) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * nrhs) return;
   int64_t s = e / nrhs;
   int r = (int)(e - s * nrhs);
-  f[(int64_t)perm[s] + (int64_t)r * ldf] = fnear[e];
+  const int64_t o = (int64_t)perm[s] - toff;
+  if (o >= 0) f[o + (int64_t)r * ldf] = fnear[e];
 }
 
 // ------------------------------------------------------------------ triangular solves
@@ -1388,6 +1392,10 @@ LeafDesc leaf_desc(const Plan &P, int nrhs) {
   LeafDesc D{};
   D.act = P.ld[depth].act;
   D.ls = P.leaf_start;
+  // targets = sources: every point of a leaf is both; otherwise each leaf holds
+  // its sources, then its targets
+  D.se = P.nt ? P.tgt_begin : P.leaf_start + 1;
+  D.tb = P.nt ? P.tgt_begin : P.leaf_start;
   D.chunk_ptr = P.chunk_ptr;
   D.near_ptr = P.near_ptr;
   D.near_src = P.near_src;
@@ -1399,6 +1407,8 @@ LeafDesc leaf_desc(const Plan &P, int nrhs) {
   D.fnear = P.fnear;
   D.W = P.ld[depth].W;
   D.n = P.n;
+  D.nsrc = P.nt ? P.ns : P.n;
+  D.toff = P.nt ? P.ns : 0;
   D.nleaf = (int)P.nact[depth];
   D.nrhs = nrhs;
   D.d = depth >= 2 ? P.lh[depth].d : 0;
@@ -1429,7 +1439,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     const int64_t m = n * nrhs;
     if (m > 0)
       hipLaunchKernelGGL(k_combine_near, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n,
-                         nrhs, P.fnear, P.idx, io.f, io.ldf);
+                         nrhs, P.fnear, P.idx, LD.toff, io.f, io.ldf);
     return;
   }
   const LevelHost &HL = P.lh[depth];

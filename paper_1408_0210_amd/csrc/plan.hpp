@@ -90,7 +90,9 @@ struct GemmJob {
 // One problem's leaf level as the near-field, P2M and L2P kernels read it.
 struct LeafDesc {
   const uint32_t *act;      // active leaf keys
-  const int *ls;            // leaf_start
+  const int *ls;            // leaf_start: points of leaf `key` are [ls[key], ls[key + 1])
+  const int *se;            // sources of leaf key: [ls[key], se[key])
+  const int *tb;            // targets of leaf key: [tb[key], ls[key + 1])
   const int *chunk_ptr;     // first 32-target chunk of each active leaf
   const int *near_ptr, *near_src;
   const int *perm;          // sorted position -> input index
@@ -99,6 +101,8 @@ struct LeafDesc {
   const double *lhat;
   double *sig, *fnear, *W;  // sorted sigma, near field, leaf W
   int64_t n;
+  int64_t nsrc;             // input indices below nsrc are sources (sigma rows)
+  int64_t toff;             // target t has input index toff + t (f row t)
   int nleaf, nrhs, d, dp;
   double lo0, lo1, lo2, h, p;  // domain corner, leaf width, device kernel parameter
   int64_t chunk_base, leaf_base, pt_base;  // batch launches: first chunk / leaf / element
@@ -187,8 +191,12 @@ struct Plan {
   LevelDev ld[kMaxLevels];
   double setup_ms = 0;
 
-  // tree / points (device)
+  // tree / points (device).  With separate targets the tree holds n = ns + nt
+  // points: input index i < ns is source i, ns + t is target t.
   int64_t n = 0;
+  int64_t ns = 0, nt = 0;       // sources; separate targets (0: targets = sources)
+  double *xin = nullptr;        // separate targets: sources then targets, SoA 3 x n
+  int *tgt_begin = nullptr;     // separate targets: first target of each leaf [8^depth + 1]
   int ntiles_sort = 0;
   double *xyz = nullptr;        // sorted points, SoA 3 x n
   uint32_t *keys = nullptr, *keys_tmp = nullptr;

@@ -21,9 +21,12 @@
 namespace eifmm {
 
 // ---------------------------------------------------------------- keys
+// With separate targets (tbit = 1) the sort key is 2 * leaf key + (i >= tsplit),
+// so each leaf's sources precede its targets.
 __global__ void k_keys(int64_t n, const double *__restrict__ xyz, double lo0, double lo1,
-                       double lo2, double L, double scale, int side, uint32_t *__restrict__ keys,
-                       int *__restrict__ idx, int *__restrict__ err) {
+                       double lo2, double L, double scale, int side, int64_t tsplit, int tbit,
+                       uint32_t *__restrict__ keys, int *__restrict__ idx,
+                       int *__restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double lo[3] = {lo0, lo1, lo2};
@@ -44,7 +47,7 @@ __global__ void k_keys(int64_t n, const double *__restrict__ xyz, double lo0, do
     c[a] = (uint32_t)q;
   }
   if (bad) atomicOr(err, 1);
-  keys[i] = morton_encode(c[0], c[1], c[2]);
+  keys[i] = (morton_encode(c[0], c[1], c[2]) << tbit) | (uint32_t)(tbit && i >= tsplit);
   idx[i] = (int)i;
 }
 
@@ -122,15 +125,17 @@ __global__ void k_gather_points(int64_t n, const double *__restrict__ xin,
   for (int a = 0; a < 3; ++a) xs[a * n + s] = xin[a * n + i];
 }
 
-// leaf_start[k] = first sorted position with key >= k, k = 0..nleaf
+// ls[k] = first sorted position with key >= (k << shift) + add, k = 0..nleaf
+// (leaf_start: shift = tbit, add = 0; first target of a leaf: shift 1, add 1)
 __global__ void k_leaf_start(int64_t n, const uint32_t *__restrict__ keys, int64_t nleaf,
-                             int *__restrict__ ls) {
+                             int shift, int add, int *__restrict__ ls) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nleaf) return;
+  const int64_t v = (k << shift) + add;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < k)
+    if ((int64_t)keys[mid] < v)
       lo = mid + 1;
     else
       hi = mid;
@@ -148,8 +153,11 @@ __device__ inline bool box_active(const int *__restrict__ ls, int shift, int64_t
 // near list, summed over active leaves), out[1] = the same with count(leaf)
 // rounded up to 32-target chunks (the sweeps the near-field kernels make);
 // integer atomics, so the totals are exact
+// (targets of the leaf [tb[key], ls[key + 1]), sources of a neighbour [ls, se))
 __global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__ act,
                                                     const int *__restrict__ ls,
+                                                    const int *__restrict__ se,
+                                                    const int *__restrict__ tb,
                                                     const int *__restrict__ near_ptr,
                                                     const int *__restrict__ near_src, int nact,
                                                     unsigned long long *__restrict__ out) {
@@ -159,23 +167,25 @@ __global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__
   long long src = 0;
   for (int q = near_ptr[j]; q < near_ptr[j + 1]; ++q) {
     const uint32_t sk = act[near_src[q]];
-    src += ls[sk + 1] - ls[sk];
+    src += se[sk] - ls[sk];
   }
-  const long long cnt = ls[key + 1] - ls[key];
+  const long long cnt = ls[key + 1] - tb[key];
   atomicAdd(out, (unsigned long long)(cnt * src));
   atomicAdd(out + 1, (unsigned long long)(((cnt + 31) / 32) * 32 * src));
 }
 
-// number of 32-target chunks of each active leaf; 0 past the active count
+// number of 32-target chunks of each active leaf (targets [tb[key], ls[key + 1]));
+// 0 past the active count
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict__ act,
-                                                     const int *__restrict__ ls, int nact,
+                                                     const int *__restrict__ ls,
+                                                     const int *__restrict__ tb, int nact,
                                                      int64_t len, int *__restrict__ cnt) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= len) return;
   int c = 0;
   if (j < nact) {
     const uint32_t key = act[j];
-    c = (ls[key + 1] - ls[key] + 31) >> 5;
+    c = (ls[key + 1] - tb[key] + 31) >> 5;
   }
   cnt[j] = c;
 }
@@ -376,7 +386,7 @@ namespace {
 
 int sort_points(Plan &P, hipStream_t s) {
   const int64_t n = P.n;
-  const int bits = 3 * P.depth;
+  const int bits = 3 * P.depth + (P.nt ? 1 : 0);
   const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
   uint32_t *ka = P.keys, *kb = P.keys_tmp;
   int *ia = P.idx, *ib = P.idx_tmp;
@@ -445,19 +455,25 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   const int depth = P.depth;
   const int side = 1 << depth;
   const double scale = std::ldexp(1.0, depth) / P.cfg.L;
+  const int tbit = P.nt ? 1 : 0;
+  const int *se = tbit ? P.tgt_begin : P.leaf_start + 1;
+  const int *tb = tbit ? P.tgt_begin : P.leaf_start;
   hipMemsetAsync(P.errflag, 0, sizeof(int), s);
   hipMemsetAsync(P.counts_dev, 0, sizeof(int) * 16 * kMaxLevels, s);
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz_in,
-                       P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], P.cfg.L, scale, side, P.keys, P.idx,
-                       P.errflag);
+                       P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], P.cfg.L, scale, side, P.ns, tbit,
+                       P.keys, P.idx, P.errflag);
     sort_points(P, s);
     hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        xyz_in, P.idx, P.xyz);
   }
   const int64_t nleaf = (int64_t)1 << (3 * depth);
   hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s, n,
-                     P.keys, nleaf, P.leaf_start);
+                     P.keys, nleaf, tbit, 0, P.leaf_start);
+  if (tbit)
+    hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s,
+                       n, P.keys, nleaf, 1, 1, P.tgt_begin);
   for (int k = std::min(2, depth); k <= depth; ++k) build_active(P, k, s);
   for (int k = 2; k <= depth; ++k) {
     const int grid = (int)((P.ld[k].cap + 255) / 256);
@@ -494,14 +510,15 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   {
     const int64_t cap = P.ld[depth].cap;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, s,
-                       P.ld[depth].act, P.leaf_start, (int)P.nact[depth], cap + 1, P.list_cnt);
+                       P.ld[depth].act, P.leaf_start, tb, (int)P.nact[depth], cap + 1,
+                       P.list_cnt);
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
   P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 31) / 32 : 0;
   hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), s);
   if (P.nact[depth] > 0)
     hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
-                       s, P.ld[depth].act, P.leaf_start, P.near_ptr, P.near_src,
+                       s, P.ld[depth].act, P.leaf_start, se, tb, P.near_ptr, P.near_src,
                        (int)P.nact[depth], P.npairs_dev);
   P.counts_pending = true;
   e = hipGetLastError();

@@ -36,7 +36,7 @@ class Config(ctypes.Structure):
                 ("max_rhs", ctypes.c_int32), ("eim_tol", ctypes.c_double),
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("compress_tol", ctypes.c_double)]
+                ("compress_tol", ctypes.c_double), ("n_targets", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -77,6 +77,7 @@ def lib():
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.eifmm_plan_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
         L.eifmm_set_points.argtypes = [vp, vp, vp]
+        L.eifmm_set_points_targets.argtypes = [vp, vp, vp, vp]
         L.eifmm_evaluate.argtypes = [vp, vp, i32, i64, vp, i64, vp]
         L.eifmm_set_timing.argtypes = [vp, i32]
         L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -96,7 +97,8 @@ def lib():
         L.eifmm_batch_destroy.argtypes = [vp]
         L.eifmm_status_str.argtypes = [ctypes.c_int]
         L.eifmm_status_str.restype = ctypes.c_char_p
-        for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_evaluate", "eifmm_set_timing",
+        for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_set_points_targets",
+                  "eifmm_evaluate", "eifmm_set_timing",
                   "eifmm_get_stats", "eifmm_get_level", "eifmm_get_compression",
                   "eifmm_export_tree", "eifmm_export_lists",
                   "eifmm_export_expansion", "eifmm_plan_destroy", "eifmm_batch_create",
@@ -131,7 +133,7 @@ def _stream():
 
 
 def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
-                dmax=0, host_only=False, compress_tol=0.0):
+                dmax=0, host_only=False, compress_tol=0.0, n_targets=0):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.kernel = KERNELS[kernel]
@@ -148,6 +150,7 @@ def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64"
     c.dmax = int(dmax)
     c.flags = FLAG_HOST_ONLY if host_only else 0
     c.compress_tol = float(compress_tol)
+    c.n_targets = int(n_targets)
     return c
 
 
@@ -165,38 +168,51 @@ def _stats_dict(s, depth):
 
 
 class Plan:
-    """One fixed (kernel, domain, N, depth, tau) setting; points and potentials vary."""
+    """One fixed (kernel, domain, N, depth, tau) setting; points and potentials vary.
+    n_targets > 0: f is evaluated at that many separate targets (set_points with
+    targets=...)."""
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
-                 tol_mode=0, dmax=0, host_only=False, compress_tol=0.0):
+                 tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0):
         c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
-                        host_only, compress_tol)
+                        host_only, compress_tol, n_targets)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
+        self.n_targets = int(n_targets)
+        self.n_out = self.n_targets if self.n_targets else self.n
         self.kernel, self.precision = kernel, precision
         h = ctypes.c_void_p()
         _check(lib().eifmm_plan_create(ctypes.byref(c), ctypes.byref(h)), "eifmm_plan_create")
         self._h = h
 
     # -- per query -----------------------------------------------------------
-    def set_points(self, xyz):
-        """xyz: CUDA float64 tensor of shape (3, n), contiguous."""
+    def set_points(self, xyz, targets=None):
+        """xyz: CUDA float64 tensor of shape (3, n), contiguous (the sources); targets:
+        (3, n_targets) for a plan with separate targets."""
         assert xyz.is_cuda and xyz.dtype.is_floating_point and xyz.element_size() == 8
         assert tuple(xyz.shape) == (3, self.n) and xyz.is_contiguous()
-        _check(lib().eifmm_set_points(self._h, ctypes.c_void_p(xyz.data_ptr()), _stream()),
-               "eifmm_set_points")
+        if targets is None:
+            _check(lib().eifmm_set_points(self._h, ctypes.c_void_p(xyz.data_ptr()), _stream()),
+                   "eifmm_set_points")
+            return
+        assert targets.is_cuda and targets.element_size() == 8 and targets.is_contiguous()
+        assert tuple(targets.shape) == (3, self.n_targets)
+        _check(lib().eifmm_set_points_targets(self._h, ctypes.c_void_p(xyz.data_ptr()),
+                                              ctypes.c_void_p(targets.data_ptr()), _stream()),
+               "eifmm_set_points_targets")
 
     def evaluate(self, sigma, out=None):
         """sigma: CUDA float64 tensor (n,) or (nrhs, n) (column-major n x nrhs).
-        Returns f with the same shape, in input order."""
+        Returns f, (m,) or (nrhs, m) with m the target count, in input order."""
         import torch
         assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
         nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
         assert sigma.shape[-1] == self.n
         if out is None:
-            out = torch.empty_like(sigma)
+            shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
+            out = torch.empty(shape, dtype=torch.float64, device=sigma.device)
         _check(lib().eifmm_evaluate(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs, self.n,
-                                    ctypes.c_void_p(out.data_ptr()), self.n, _stream()),
+                                    ctypes.c_void_p(out.data_ptr()), self.n_out, _stream()),
                "eifmm_evaluate")
         return out
 
@@ -238,8 +254,9 @@ class Plan:
         return r.value, sv, U
 
     def export_tree(self):
-        perm = np.empty(self.n, dtype=np.int32)
-        keys = np.empty(self.n, dtype=np.uint32)
+        m = self.n + self.n_targets
+        perm = np.empty(m, dtype=np.int32)
+        keys = np.empty(m, dtype=np.uint32)
         ls = np.empty((1 << (3 * self.depth)) + 1, dtype=np.int64)
         _check(lib().eifmm_export_tree(self._h, _np_ptr(perm), _np_ptr(ls), _np_ptr(keys)),
                "eifmm_export_tree")

@@ -80,6 +80,19 @@ WORKLOADS["uniform100m_gauss1_d7"] = dict(n=100_000_000, dist="uniform", seed_pt
                                           tau=1e-6)
 
 
+# Separate targets: 1e6 sources and 1e6 targets, both uniform in the cube
+# (independent seeds), 1/r, depth 5, tau 1e-6, M2L compressed as above.
+WORKLOADS["uniform1m_targets1m_laplace_d5"] = dict(n=1_000_000, n_targets=1_000_000,
+                                                   dist="uniform", seed_pts=91, seed_tgt=93,
+                                                   seed_sigma=92, kernel="laplace", param=0.0,
+                                                   depth=5, tau=1e-6, compress_tol=5e-6)
+
+
+def make_targets(w):
+    """Separate target points of a workload (uniform in the cube)."""
+    return uniform_points(w["n_targets"], w["seed_tgt"])
+
+
 def make_points(w):
     if w["dist"] == "uniform":
         return uniform_points(w["n"], w["seed_pts"])

@@ -28,7 +28,8 @@ def test_status_strings(E):
 
 @pytest.mark.parametrize("field,value", [("depth", 9), ("depth", -1), ("eim_tol", 0.0),
                                          ("L", -1.0), ("max_rhs", 0), ("kernel", 7),
-                                         ("precision", 3), ("n", -5), ("struct_size", 8)])
+                                         ("precision", 3), ("n", -5), ("struct_size", 8),
+                                         ("n_targets", -1), ("n_targets", 1 << 30)])
 def test_invalid_config(E, field, value):
     c = E.Config()
     c.struct_size = ctypes.sizeof(E.Config)
@@ -49,6 +50,17 @@ def test_host_only_plan_refuses_device_calls(E):
     P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-2, host_only=True)
     assert E.lib().eifmm_set_points(P._h, None, None) == -3
     assert P.stats()["d"][2] > 0
+    P.close()
+
+
+def test_host_only_plan_with_targets(E):
+    """A plan with separate targets accepts only set_points_targets; a host-only
+    plan accepts neither."""
+    P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-2, host_only=True, n_targets=7)
+    L = E.lib()
+    assert L.eifmm_set_points(P._h, None, None) == -3
+    assert L.eifmm_set_points_targets(P._h, None, None, None) == -3
+    assert P.n_out == 7
     P.close()
 
 

@@ -230,3 +230,24 @@ def test_uniform100m_gauss(E, torch_dev, oracle_lib):
     print(f"uniform100m gauss: d={plan.stats()['d']} sampled rel-L2 {err:.3e}", flush=True)
     assert err <= 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_targets1m_sampled(precision, E, torch_dev, oracle_lib):
+    """1e6 sources and 1e6 separate targets in the cube (the benchmark's targets
+    run): 2000 sampled targets against the direct sum, and exact linearity."""
+    torch, dev = torch_dev
+    w = W.WORKLOADS["uniform1m_targets1m_laplace_d5"]
+    xs, xt, s = W.make_points(w), W.make_targets(w), W.make_sigma(w)
+    idx = np.sort(np.random.default_rng(17).choice(w["n_targets"], NS, replace=False))
+    ref = oracle_lib.direct(w["kernel"], w["param"], xt[:, idx].copy(), xs, s, threads=THREADS)
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  precision=precision, compress_tol=w["compress_tol"], n_targets=w["n_targets"])
+    plan.set_points(torch.from_numpy(xs).to(dev), targets=torch.from_numpy(xt).to(dev))
+    sd = torch.from_numpy(s).to(dev)
+    f = plan.evaluate(sd).cpu().numpy()
+    err = _rel(f[idx], ref)
+    print(f"targets1m {precision}: sampled rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-6
+    np.testing.assert_array_equal(plan.evaluate(2.0 * sd).cpu().numpy(), 2.0 * f)
+    plan.close()
