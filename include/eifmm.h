@@ -76,6 +76,10 @@ extern "C" {
 /* flags */
 #define EIFMM_FLAG_HOST_ONLY 1 /* plan_create runs the host setup only (no device
                                   tables); only eifmm_get_level/get_stats work   */
+#define EIFMM_FLAG_HOST_SETUP 2 /* run the Algorithm 1 iterations on the host even
+                                   for a device plan (by default a device plan
+                                   runs them on the GPU; both select the same
+                                   points and factors, bit for bit)             */
 
 #define EIFMM_MAX_DEPTH 8
 

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeifmm.so")
-SOURCES = ["capi.hip", "tree.hip", "pass.hip", "scan.hip", "setup.cpp"]
+SOURCES = ["capi.hip", "tree.hip", "pass.hip", "scan.hip", "eim_gpu.hip", "setup.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay disabled for every device code object.

@@ -497,9 +497,10 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   P.n = P.ns + P.nt;
   P.max_rhs = cfg->max_rhs;
   P.host_only = (cfg->flags & EIFMM_FLAG_HOST_ONLY) != 0;
+  P.gpu_setup = !P.host_only && !(cfg->flags & EIFMM_FLAG_HOST_SETUP);
+  if (!P.host_only) hipGetDevice(&P.device);
   st = build_tables(P);
   if (st == EIFMM_OK && !P.host_only) {
-    hipGetDevice(&P.device);
     st = setup_tables(h);
     if (st == EIFMM_OK) st = setup_workspaces(h, nullptr);
     if (st == EIFMM_OK) {
@@ -816,6 +817,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
     P.n = 0;
     P.max_rhs = 1;
     P.device = b->device;
+    P.gpu_setup = !(P.cfg.flags & EIFMM_FLAG_HOST_SETUP);
     st = build_tables(P);
     if (!st) st = setup_tables(h);
   }

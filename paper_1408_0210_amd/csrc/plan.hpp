@@ -186,6 +186,7 @@ struct Plan {
   eifmm_config cfg{};
   int device = 0;
   bool host_only = false;
+  bool gpu_setup = false;  // Algorithm 1 iterations on the device
   int depth = 0;
   LevelHost lh[kMaxLevels];
   LevelDev ld[kMaxLevels];
@@ -254,6 +255,16 @@ struct Plan {
 
 // setup.cpp
 int build_tables(Plan &P);
+// Algorithm 1 iterations on the device (eim_gpu.hip): training matrix R (nx x ny,
+// row-major), stopping rule |pivot| <= tau scale with scale = abs_scale if > 0,
+// else the first pivot's magnitude; at most dmax points (then EIFMM_EEIM)
+struct EimResult {
+  std::vector<int64_t> ia, ib;  // selected rows / columns
+  double scale = 0, emax = 0;   // scale, largest |residual| left
+  int status = EIFMM_OK;
+};
+int eim_iterate_gpu(const std::vector<double> &R, int64_t nx, int64_t ny, double tau,
+                    double abs_scale, int dmax, EimResult &res);
 int pick_rbt(int nrb);
 
 // device-side entry points (tree.hip, pass.hip)

@@ -150,8 +150,24 @@ void training_sets(int kind, int level, double lk, std::vector<double> &tx,
 }
 
 // ---- Algorithm 1 as complete-pivot cross approximation ----------------------
+// d, scale, relative training error and the selected points from ia / ib
+void finish_eim(const std::vector<double> &tx, const std::vector<double> &ty, double scale,
+                double emax, LevelHost &out) {
+  const int d = (int)out.ia.size();
+  out.d = d;
+  out.scale = scale;
+  out.err = scale > 0 ? emax / scale : 0;
+  out.X.resize(3 * (size_t)d);
+  out.Y.resize(3 * (size_t)d);
+  for (int i = 0; i < d; ++i)
+    for (int c = 0; c < 3; ++c) {
+      out.X[3 * i + c] = tx[3 * out.ia[i] + c];
+      out.Y[3 * i + c] = ty[3 * out.ib[i] + c];
+    }
+}
+
 int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, double abs_scale,
-               LevelHost &out) {
+               bool gpu, LevelHost &out) {
   const double lk = std::ldexp(L, -level - 1);
   std::vector<double> tx, ty;
   training_sets(kind, level, lk, tx, ty);
@@ -163,6 +179,16 @@ int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, do
         R[a * ny + b] = kern_host(kind, p, tx[3 * a] - ty[3 * b], tx[3 * a + 1] - ty[3 * b + 1],
                                   tx[3 * a + 2] - ty[3 * b + 2]);
   });
+  if (gpu) {
+    // the same iterations on the device (eim_gpu.hip), bit for bit
+    EimResult res;
+    int st = eim_iterate_gpu(R, nx, ny, tau, abs_scale, dmax, res);
+    if (st != EIFMM_OK) return st;
+    out.ia = res.ia;
+    out.ib = res.ib;
+    finish_eim(tx, ty, res.scale, res.emax, out);
+    return res.status;
+  }
   const int nth = hw_threads();
   struct Best {
     double v;
@@ -218,17 +244,7 @@ int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, do
   // training error left after the last accepted point
   double emax = 0;
   for (double v : R) emax = std::max(emax, std::fabs(v));
-  const int d = (int)out.ia.size();
-  out.d = d;
-  out.scale = scale;
-  out.err = scale > 0 ? emax / scale : 0;
-  out.X.resize(3 * (size_t)d);
-  out.Y.resize(3 * (size_t)d);
-  for (int i = 0; i < d; ++i)
-    for (int c = 0; c < 3; ++c) {
-      out.X[3 * i + c] = tx[3 * out.ia[i] + c];
-      out.Y[3 * i + c] = ty[3 * out.ib[i] + c];
-    }
+  finish_eim(tx, ty, scale, emax, out);
   return status;
 }
 
@@ -468,7 +484,8 @@ int build_tables(Plan &P) {
   double abs_scale = 0;
   for (int k = depth; k >= 2; --k) {
     LevelHost &lv = P.lh[k];
-    int st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale : 0.0, lv);
+    int st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale : 0.0,
+                        P.gpu_setup, lv);
     if (st != EIFMM_OK) return st;
     if (k == depth && c.tol_mode == 1) abs_scale = lv.scale;
     crout(kind, p, lv);

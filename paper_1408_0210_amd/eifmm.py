@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "eifmm.h")
 KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3, "cosr": 4, "mq": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_HOST_ONLY = 1
+FLAG_HOST_SETUP = 2
 MAX_DEPTH = 8
 NPHASE = 10
 PHASES = ["tree", "p2p", "p2m", "m2m", "what", "m2l", "l2l", "lhat", "l2p", "proj"]
@@ -133,7 +134,7 @@ def _stream():
 
 
 def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
-                dmax=0, host_only=False, compress_tol=0.0, n_targets=0):
+                dmax=0, host_only=False, compress_tol=0.0, n_targets=0, host_setup=False):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.kernel = KERNELS[kernel]
@@ -148,7 +149,7 @@ def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64"
     c.tol_mode = int(tol_mode)
     c.precision = PRECISIONS[precision]
     c.dmax = int(dmax)
-    c.flags = FLAG_HOST_ONLY if host_only else 0
+    c.flags = (FLAG_HOST_ONLY if host_only else 0) | (FLAG_HOST_SETUP if host_setup else 0)
     c.compress_tol = float(compress_tol)
     c.n_targets = int(n_targets)
     return c
@@ -173,9 +174,10 @@ class Plan:
     targets=...)."""
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
-                 tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0):
+                 tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0,
+                 host_setup=False):
         c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
-                        host_only, compress_tol, n_targets)
+                        host_only, compress_tol, n_targets, host_setup)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.n_targets = int(n_targets)
