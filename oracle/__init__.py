@@ -23,8 +23,9 @@ SRC = os.path.join(_HERE, "eifmm_oracle.c")
 LIB_PATH = os.environ.get("ORACLE_LIB_OVERRIDE") or os.path.join(_HERE, "liboracle.so")
 
 KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3, "cosr": 4, "mq": 5,
-           "cosdot": 6, "expdot": 7}
-SINGULAR = {"laplace", "yukawa", "cosr"}
+           "cosdot": 6, "expdot": 7, "advdiff": 8}
+SINGULAR = {"laplace", "yukawa", "cosr", "advdiff"}
+NONSYMMETRIC = {"expdot", "advdiff"}  # k(-z) != k(z): two EIMs per level
 
 OK, EINVAL, EDOMAIN, EEIM, ENOMEM = 0, -1, -2, -4, -5
 
@@ -67,11 +68,12 @@ def lib():
         L.orc_training_sets.argtypes = [i32, i32, vp, P(i64), vp, P(i64)]
         L.orc_eim.argtypes = [i32, vp, i32, d, d, i32, d, P(i32), vp, vp, vp, vp, vp, vp, vp,
                               P(d)]
+        L.orc_eim_swapped.argtypes = L.orc_eim.argtypes
         L.orc_apply_delta.argtypes = [i32, i32, vp, vp, vp, vp, i32]
         L.orc_apply_delta.restype = None
-        L.orc_plan_create.argtypes = [i32, vp, vp, d, i32, d, i32, i32, P(i32)]
+        L.orc_plan_create.argtypes = [i32, vp, vp, d, i32, d, i32, i32, i32, P(i32)]
         L.orc_plan_create.restype = vp
-        L.orc_plan_level.argtypes = [vp, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]
+        L.orc_plan_level.argtypes = [vp, i32, i32, P(i32), vp, vp, vp, vp, vp, vp, vp]
         L.orc_plan_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.orc_plan_free.argtypes = [vp]
         L.orc_plan_free.restype = None
@@ -180,8 +182,10 @@ def training_sets(kernel, level):
     return tx, ty
 
 
-def eim(kernel, param, level, L, tau, dmax=1024, abs_scale=0.0):
-    """Algorithm 1 on the level's training sets; returns the interpolation data."""
+def eim(kernel, param, level, L, tau, dmax=1024, abs_scale=0.0, swapped=False):
+    """Algorithm 1 on the level's training sets; returns the interpolation data.
+    swapped: the second EIM of Sec. 3.1, on D_x = J_0 and D_y = I_0 (X then holds
+    J_0 points, Y holds I_0 points)."""
     p = _params(param)
     ia = np.empty(dmax, dtype=np.int64)
     ib = np.empty(dmax, dtype=np.int64)
@@ -192,9 +196,10 @@ def eim(kernel, param, level, L, tau, dmax=1024, abs_scale=0.0):
     eps = np.empty(dmax + 1)
     d = ctypes.c_int()
     sc = ctypes.c_double()
-    st = lib().orc_eim(KERNELS[kernel], _p(p), level, float(L), float(tau), dmax,
-                       float(abs_scale), ctypes.byref(d), _p(ia), _p(ib), _p(X), _p(Y), _p(B),
-                       _p(G), _p(eps), ctypes.byref(sc))
+    fn = lib().orc_eim_swapped if swapped else lib().orc_eim
+    st = fn(KERNELS[kernel], _p(p), level, float(L), float(tau), dmax, float(abs_scale),
+            ctypes.byref(d), _p(ia), _p(ib), _p(X), _p(Y), _p(B), _p(G), _p(eps),
+            ctypes.byref(sc))
     dd = d.value
     res = dict(d=dd, ia=ia[:dd].copy(), ib=ib[:dd].copy(), X=X[:dd].copy(), Y=Y[:dd].copy(),
                B=B[:dd, :dd].copy(), G=G[:dd, :dd].copy(), eps=eps[:dd + 1].copy(),
@@ -246,19 +251,24 @@ def compression_basis(kernel, param, Y, level, eps, L=1.0, rank=None):
 
 
 class Plan:
-    """Per-level EIM data (levels 2..depth) and the Algorithm-3 evaluation."""
+    """Per-level EIM data (levels 2..depth) and the Algorithm-3 evaluation.
+    A kernel that is not symmetric gets the second EIM of Sec. 3.1 on every level
+    (levels2); two_eim=True gives it to a symmetric kernel too."""
 
     def __init__(self, kernel, param, lo, L, depth, tau, dmax=1024, tol_mode=0, compress_tol=0.0,
-                 compress_rank=None):
+                 compress_rank=None, two_eim=False):
         self.kernel, self.param = kernel, _params(param)
         self.lo = np.ascontiguousarray(lo, dtype=np.float64)
         self.L, self.depth, self.tau = float(L), int(depth), float(tau)
+        self.two = bool(two_eim) or kernel in NONSYMMETRIC
         st = ctypes.c_int()
         self._h = lib().orc_plan_create(KERNELS[kernel], _p(self.param), _p(self.lo), self.L,
-                                        self.depth, self.tau, dmax, tol_mode, ctypes.byref(st))
+                                        self.depth, self.tau, dmax, tol_mode,
+                                        1 if two_eim else 0, ctypes.byref(st))
         if not self._h:
             raise OracleError(st.value, "plan_create")
         self.levels = {k: self._level(k) for k in range(2, self.depth + 1)}
+        self.levels2 = {k: self._level(k, 1) for k in range(2, self.depth + 1)} if self.two else {}
         self.compress_tol = float(compress_tol)
         if compress_tol > 0:
             for k in range(2, self.depth + 1):
@@ -270,24 +280,27 @@ class Plan:
                 if st:
                     raise OracleError(st, "set_compression")
 
-    def _level(self, k):
+    def _level(self, k, which=0):
         d = ctypes.c_int()
-        lib().orc_plan_level(self._h, k, ctypes.byref(d), None, None, None, None, None, None,
-                             None)
+        lib().orc_plan_level(self._h, k, which, ctypes.byref(d), None, None, None, None, None,
+                             None, None)
         dd = d.value
         X, Y = np.empty((dd, 3)), np.empty((dd, 3))
         B, G = np.empty((dd, dd)), np.empty((dd, dd))
         ia, ib = np.empty(dd, dtype=np.int64), np.empty(dd, dtype=np.int64)
         eps = np.empty(dd + 1)
-        lib().orc_plan_level(self._h, k, ctypes.byref(d), _p(X), _p(Y), _p(B), _p(G), _p(ia),
-                             _p(ib), _p(eps))
+        lib().orc_plan_level(self._h, k, which, ctypes.byref(d), _p(X), _p(Y), _p(B), _p(G),
+                             _p(ia), _p(ib), _p(eps))
         return dict(d=dd, X=X, Y=Y, B=B, G=G, ia=ia, ib=ib, eps=eps)
 
-    def level_offsets(self):
+    def level_offsets(self, second=False):
+        """Dump layout: (offset, boxes, values per box) per level; second=True for g,
+        l and lhat, which hold the second EIM's d values per box when there is one."""
+        lv = self.levels2 if (second and self.two) else self.levels
         off, out = 0, {}
         for k in range(2, self.depth + 1):
-            out[k] = (off, (1 << (3 * k)), self.levels[k]["d"])
-            off += (1 << (3 * k)) * self.levels[k]["d"]
+            out[k] = (off, (1 << (3 * k)), lv[k]["d"])
+            off += (1 << (3 * k)) * lv[k]["d"]
         return out, off
 
     def evaluate(self, xyz, sigma, dumps=False, threads=0):
@@ -299,9 +312,13 @@ class Plan:
         dd = {}
         if dumps:
             offs, tot = self.level_offsets()
-            dk = self.levels[self.depth]["d"] if self.depth >= 2 else 0
-            for name in ("W", "What", "g", "l"):
+            offs2, tot2 = self.level_offsets(second=True)
+            lvd = self.levels2 if self.two else self.levels
+            dk = lvd[self.depth]["d"] if self.depth >= 2 else 0
+            for name in ("W", "What"):
                 dd[name] = np.zeros(tot)
+            for name in ("g", "l"):
+                dd[name] = np.zeros(tot2)
             dd["lhat"] = np.zeros((1 << (3 * self.depth)) * dk)
             dd["fnear"] = np.zeros(n)
             dd["ffar"] = np.zeros(n)
@@ -313,10 +330,10 @@ class Plan:
             raise OracleError(st, "plan_eval")
         if not dumps:
             return f
-        offs, _ = self.level_offsets()
         out = {"fnear": dd["fnear"], "ffar": dd["ffar"]}
         for name in ("W", "What", "g", "l"):
-            out[name] = {k: dd[name][o:o + nb * d].reshape(nb, d) for k, (o, nb, d) in offs.items()}
+            of = offs if name in ("W", "What") else offs2
+            out[name] = {k: dd[name][o:o + nb * d].reshape(nb, d) for k, (o, nb, d) in of.items()}
         if self.depth >= 2:
             out["lhat"] = dd["lhat"].reshape(1 << (3 * self.depth), -1)
         return f, out

@@ -42,7 +42,9 @@ enum {
   ORC_COSR = 4,    /* cos(w r)/r,       p[0] = w          */
   ORC_MQ = 5,      /* sqrt(r^2 + c),    p[0] = c          */
   ORC_COSDOT = 6,  /* cos(w . z) (finite rank 2)          */
-  ORC_EXPDOT = 7   /* exp(a . z) (rank 1, not symmetric)  */
+  ORC_EXPDOT = 7,  /* exp(a . z) (rank 1, not symmetric)  */
+  ORC_ADVDIFF = 8  /* exp(a (z_x - r))/r, p[0] = a: not symmetric (steady
+                      advection-diffusion along x, up to constants)      */
 };
 
 #define ORC_OK 0
@@ -57,8 +59,11 @@ typedef struct {
 } okern;
 
 static int k_singular(int kind) {
-  return kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_COSR;
+  return kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_COSR || kind == ORC_ADVDIFF;
 }
+
+/* k(-z) = k(z): one EIM per level suffices (Sec. 3.1); otherwise two. */
+static int k_symmetric(int kind) { return kind != ORC_EXPDOT && kind != ORC_ADVDIFF; }
 
 /* k(z); the squared norm is summed x, y, z in that order. */
 static double k_eval(const okern *K, double zx, double zy, double zz) {
@@ -84,6 +89,10 @@ static double k_eval(const okern *K, double zx, double zy, double zz) {
     return cos(K->p[0] * zx + K->p[1] * zy + K->p[2] * zz);
   case ORC_EXPDOT:
     return exp(K->p[0] * zx + K->p[1] * zy + K->p[2] * zz);
+  case ORC_ADVDIFF: {
+    double r = sqrt(r2);
+    return exp(K->p[0] * (zx - r)) / r;
+  }
   }
   return NAN;
 }
@@ -357,7 +366,8 @@ int orc_lists(int depth, const int64_t *leaf_start, int level, int64_t *nactive,
 /* Training sets (Sec. 2 leaves them unspecified).  Reading used here, in    */
 /* units of l_k (the half-width of a level-k box):                           */
 /*   D_y = J_0^k = [-1,1]^3, D_x = I_0^k = {u : 3 <= ||u||_inf <= 2^(k+1)-1}. */
-/*   "surface" kernels (1/r, exp(-ar)/r, r^2): maximum principle, so the      */
+/*   "surface" kernels (1/r, exp(-ar)/r, r^2, exp(a(z_x-r))/r): maximum      */
+/*     principle, so the                                                      */
 /*     residual peaks on boundaries -- T_y is the surface of J_0 with an 11x11 */
 /*     grid per face; T_x is a set of cube shells ||u||_inf = rho.            */
 /*   "volume" kernels: T_y is an 11^3 grid of J_0; T_x adds shells between.   */
@@ -376,7 +386,8 @@ static const double SHELLS_V[] = {3,    3.25, 3.5, 3.75, 4,   4.5, 5,   5.5,  6,
                                   724,  861,  1024, 1218, 1448, 1722, 2048};
 
 static int kernel_is_volume(int kind) {
-  return !(kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_SQDIST);
+  return !(kind == ORC_LAPLACE || kind == ORC_YUKAWA || kind == ORC_SQDIST ||
+           kind == ORC_ADVDIFF);
 }
 
 static int64_t emit_shell(double rho, int m, double *out) {
@@ -465,9 +476,11 @@ int orc_training_sets(int kind, int level, double *tx, int64_t *ntx, double *ty,
 /* physical units (d x 3), B and Gamma (dmax x dmax row-major, leading dim     */
 /* dmax), eps history eps[0..d] (eps[k] = max |delta_k K| over the grid).      */
 /* ------------------------------------------------------------------------ */
-int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax,
-            double abs_scale, int *d_out, int64_t *ia, int64_t *ib, double *X, double *Y,
-            double *Bm, double *Gm, double *eps, double *scale_out) {
+/* swap = 1: the second EIM of Sec. 3.1, with D_x = J_0 and D_y = I_0 (the     */
+/* training sets exchanged); X then holds J_0 points and Y holds I_0 points.   */
+static int eim_run(int kind, const double *p, int level, double L, double tau, int dmax,
+                   double abs_scale, int swap, int *d_out, int64_t *ia, int64_t *ib, double *X,
+                   double *Y, double *Bm, double *Gm, double *eps, double *scale_out) {
   if (!(tau > 0.0) || dmax < 1 || level < 2) return ORC_EINVAL;
   okern K = make_kern(kind, p);
   int64_t ntx, nty;
@@ -475,7 +488,7 @@ int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax
   double *tx = (double *)malloc(sizeof(double) * 3 * (size_t)ntx);
   double *ty = (double *)malloc(sizeof(double) * 3 * (size_t)nty);
   double *R = (double *)malloc(sizeof(double) * (size_t)ntx * (size_t)nty);
-  double *q = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)nty);
+  double *q = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)(ntx > nty ? ntx : nty));
   if (!tx || !ty || !R || !q) {
     free(tx); free(ty); free(R); free(q);
     return ORC_ENOMEM;
@@ -484,6 +497,14 @@ int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax
   double lk = ldexp(L, -level - 1);
   for (int64_t a = 0; a < 3 * ntx; a++) tx[a] *= lk;
   for (int64_t b = 0; b < 3 * nty; b++) ty[b] *= lk;
+  if (swap) {
+    double *t = tx;
+    tx = ty;
+    ty = t;
+    int64_t n = ntx;
+    ntx = nty;
+    nty = n;
+  }
 
   /* delta_0 K = K on the training grid */
   for (int64_t a = 0; a < ntx; a++)
@@ -553,6 +574,20 @@ int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax
   return status;
 }
 
+int orc_eim(int kind, const double *p, int level, double L, double tau, int dmax,
+            double abs_scale, int *d_out, int64_t *ia, int64_t *ib, double *X, double *Y,
+            double *Bm, double *Gm, double *eps, double *scale_out) {
+  return eim_run(kind, p, level, L, tau, dmax, abs_scale, 0, d_out, ia, ib, X, Y, Bm, Gm, eps,
+                 scale_out);
+}
+
+int orc_eim_swapped(int kind, const double *p, int level, double L, double tau, int dmax,
+                    double abs_scale, int *d_out, int64_t *ia, int64_t *ib, double *X, double *Y,
+                    double *Bm, double *Gm, double *eps, double *scale_out) {
+  return eim_run(kind, p, level, L, tau, dmax, abs_scale, 1, d_out, ia, ib, X, Y, Bm, Gm, eps,
+                 scale_out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Triangular solves that apply Delta = B^{-T} Gamma^{-1} and its transpose    */
 /* without forming an inverse (Sec. 4.1).  ld = leading dimension.            */
@@ -598,11 +633,18 @@ void orc_apply_delta(int d, int ld, const double *Bm, const double *Gm, const do
 /* ------------------------------------------------------------------------ */
 /* Plan: per-level EIM results (levels 2..depth).                             */
 /* ------------------------------------------------------------------------ */
+/* One EIM of a level: d points X in D_x, Y in D_y, factors of K(X, Y). */
 typedef struct {
   int d;
   double *X, *Y, *B, *G, *eps;
   int64_t *ia, *ib;
   double scale;
+} oeim;
+
+/* Level k: the EIM on (I_0, J_0) (Delta^{I_0,J_0}, Sec. 3.1) and, for a kernel
+ * that is not symmetric, the second EIM on (J_0, I_0) (Delta^{J_0,I_0}). */
+typedef struct {
+  oeim a, b;
   int r;      /* M2L compression rank (0: uncompressed) */
   double *U;  /* d x r orthonormal basis of the M2L matrices (Sec. 4.2) */
 } olevel;
@@ -611,14 +653,31 @@ typedef struct {
   okern K;
   double lo[3], L, tau;
   int depth, dmax, tol_mode;
+  int two;    /* the second EIM is used (kernels that are not symmetric) */
   olevel lv[16];
 } orc_plan;
+
+static void eim_free(oeim *e) {
+  free(e->X); free(e->Y); free(e->B); free(e->G); free(e->eps); free(e->ia); free(e->ib);
+}
+
+static int eim_alloc(oeim *e, int dmax) {
+  e->X = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
+  e->Y = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
+  e->B = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
+  e->G = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
+  e->eps = (double *)malloc(sizeof(double) * ((size_t)dmax + 1));
+  e->ia = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
+  e->ib = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
+  return (e->X && e->Y && e->B && e->G && e->eps && e->ia && e->ib) ? ORC_OK : ORC_ENOMEM;
+}
 
 void orc_plan_free(orc_plan *P) {
   if (!P) return;
   for (int k = 0; k < 16; k++) {
-    free(P->lv[k].X); free(P->lv[k].Y); free(P->lv[k].B); free(P->lv[k].G);
-    free(P->lv[k].eps); free(P->lv[k].ia); free(P->lv[k].ib); free(P->lv[k].U);
+    eim_free(&P->lv[k].a);
+    eim_free(&P->lv[k].b);
+    free(P->lv[k].U);
   }
   free(P);
 }
@@ -628,23 +687,25 @@ void orc_plan_free(orc_plan *P) {
  * symmetric kernel the compressed matrices are C^delta = U^T K^delta U and the
  * M2L step becomes g = U sum_J C^delta (U^T What^J).  r = 0 removes it. */
 int orc_plan_set_compression(orc_plan *P, int k, int r, const double *U) {
-  if (!P || k < 2 || k > P->depth || r < 0 || r > P->lv[k].d) return ORC_EINVAL;
+  if (!P || P->two || k < 2 || k > P->depth || r < 0 || r > P->lv[k].a.d) return ORC_EINVAL;
   olevel *lv = &P->lv[k];
   free(lv->U);
   lv->U = NULL;
   lv->r = 0;
   if (r == 0) return ORC_OK;
-  lv->U = (double *)malloc(sizeof(double) * (size_t)lv->d * (size_t)r);
+  lv->U = (double *)malloc(sizeof(double) * (size_t)lv->a.d * (size_t)r);
   if (!lv->U) return ORC_ENOMEM;
-  memcpy(lv->U, U, sizeof(double) * (size_t)lv->d * (size_t)r);
+  memcpy(lv->U, U, sizeof(double) * (size_t)lv->a.d * (size_t)r);
   lv->r = r;
   return ORC_OK;
 }
 
 /* tol_mode 0: relative to each level's own max |K| over its training grid;
- * tol_mode 1: relative to the finest level's max |K| (one absolute threshold). */
+ * tol_mode 1: relative to the finest level's max |K| (one absolute threshold,
+ * per EIM).  two_eim = 1 runs the second EIM for a symmetric kernel too (the
+ * general form of Sec. 3.1); a kernel that is not symmetric always gets it. */
 orc_plan *orc_plan_create(int kind, const double *p, const double *lo, double L, int depth,
-                          double tau, int dmax, int tol_mode, int *status) {
+                          double tau, int dmax, int tol_mode, int two_eim, int *status) {
   *status = ORC_EINVAL;
   if (depth < 0 || depth > 10 || !(L > 0.0) || !(tau > 0.0) || dmax < 1) return NULL;
   orc_plan *P = (orc_plan *)calloc(1, sizeof(orc_plan));
@@ -659,38 +720,43 @@ orc_plan *orc_plan_create(int kind, const double *p, const double *lo, double L,
   P->depth = depth;
   P->dmax = dmax;
   P->tol_mode = tol_mode;
-  double abs_scale = 0.0;
+  P->two = two_eim || !k_symmetric(kind);
+  double abs_scale = 0.0, abs_scale2 = 0.0;
   *status = ORC_OK;
   for (int k = depth; k >= 2; k--) {
     olevel *lv = &P->lv[k];
-    lv->X = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
-    lv->Y = (double *)malloc(sizeof(double) * 3 * (size_t)dmax);
-    lv->B = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
-    lv->G = (double *)malloc(sizeof(double) * (size_t)dmax * (size_t)dmax);
-    lv->eps = (double *)malloc(sizeof(double) * ((size_t)dmax + 1));
-    lv->ia = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
-    lv->ib = (int64_t *)malloc(sizeof(int64_t) * (size_t)dmax);
-    if (!lv->X || !lv->Y || !lv->B || !lv->G || !lv->eps || !lv->ia || !lv->ib) {
+    if (eim_alloc(&lv->a, dmax) != ORC_OK || (P->two && eim_alloc(&lv->b, dmax) != ORC_OK)) {
       *status = ORC_ENOMEM;
       orc_plan_free(P);
       return NULL;
     }
-    int st = orc_eim(kind, p, k, L, tau, dmax, tol_mode == 1 ? abs_scale : 0.0, &lv->d, lv->ia,
-                     lv->ib, lv->X, lv->Y, lv->B, lv->G, lv->eps, &lv->scale);
+    oeim *e = &lv->a;
+    int st = eim_run(kind, p, k, L, tau, dmax, tol_mode == 1 ? abs_scale : 0.0, 0, &e->d, e->ia,
+                     e->ib, e->X, e->Y, e->B, e->G, e->eps, &e->scale);
+    if (st == ORC_OK && P->two) {
+      oeim *f = &lv->b;
+      st = eim_run(kind, p, k, L, tau, dmax, tol_mode == 1 ? abs_scale2 : 0.0, 1, &f->d, f->ia,
+                   f->ib, f->X, f->Y, f->B, f->G, f->eps, &f->scale);
+    }
     if (st != ORC_OK) {
       *status = st;
       orc_plan_free(P);
       return NULL;
     }
-    if (k == depth && tol_mode == 1) abs_scale = lv->scale;
+    if (k == depth && tol_mode == 1) {
+      abs_scale = lv->a.scale;
+      if (P->two) abs_scale2 = lv->b.scale;
+    }
   }
   return P;
 }
 
-int orc_plan_level(const orc_plan *P, int k, int *d, double *X, double *Y, double *B,
+/* which = 0: the EIM on (I_0, J_0); 1: the second EIM (EINVAL without it). */
+int orc_plan_level(const orc_plan *P, int k, int which, int *d, double *X, double *Y, double *B,
                    double *G, int64_t *ia, int64_t *ib, double *eps) {
-  if (!P || k < 2 || k > P->depth) return ORC_EINVAL;
-  const olevel *lv = &P->lv[k];
+  if (!P || k < 2 || k > P->depth || which < 0 || which > 1 || (which && !P->two))
+    return ORC_EINVAL;
+  const oeim *lv = which ? &P->lv[k].b : &P->lv[k].a;
   int dd = lv->d, dm = P->dmax;
   *d = dd;
   if (X) memcpy(X, lv->X, sizeof(double) * 3 * (size_t)dd);
@@ -722,13 +788,27 @@ static void child_shift(const orc_plan *P, int k, int i, double *s) {
   for (int a = 0; a < 3; a++) s[a] = ((i >> a) & 1) ? lk : -lk;
 }
 
+/* The second EIM's size, its J_0 points x^{J_0}, its I_0 points y^{I_0} and
+ * Delta^{J_0,I_0}; for a symmetric kernel with one EIM these are d, Y, X and
+ * the transpose of Delta^{I_0,J_0} (Sec. 3.1). */
+static int dB(const orc_plan *P, int k) { return P->two ? P->lv[k].b.d : P->lv[k].a.d; }
+static const double *XB(const orc_plan *P, int k) { return P->two ? P->lv[k].b.X : P->lv[k].a.Y; }
+static const double *YB(const orc_plan *P, int k) { return P->two ? P->lv[k].b.Y : P->lv[k].a.X; }
+static void apply_delta_b(const orc_plan *P, int k, const double *v, double *w) {
+  if (P->two)
+    apply_delta(P->lv[k].b.d, P->dmax, P->lv[k].b.B, P->lv[k].b.G, v, w);
+  else
+    apply_delta_t(P->lv[k].a.d, P->dmax, P->lv[k].a.B, P->lv[k].a.G, v, w);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Algorithm 3 plus the near field (eq. (12)-(13)), one right-hand side.      */
 /* xyz: 3 x n SoA input points (targets = sources); sigma[n]; f[n] output in  */
 /* input order.  Optional dumps (NULL to skip), dense over all boxes of each  */
 /* level in key order, levels 2..depth concatenated, box-major with d_k        */
 /* values per box:  W (step 1-2), What (step 3), g (step 4), l (step 5);      */
-/* lhat (step 6, level depth only); fnear / ffar in input order.              */
+/* lhat (step 6, level depth only); fnear / ffar in input order.  With two    */
+/* EIMs, g, l and lhat hold the second EIM's d_k values per box.              */
 /* ------------------------------------------------------------------------ */
 int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double *sigma,
                   double *f, double *dW, double *dWh, double *dg, double *dl, double *dlh,
@@ -765,16 +845,17 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
   double *W[16] = {0}, *Wh[16] = {0}, *g[16] = {0}, *l[16] = {0};
   int ok = 1;
   for (int k = 2; k <= depth; k++) {
-    size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].d;
+    size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].a.d;
+    size_t szb = (size_t)((int64_t)1 << (3 * k)) * (size_t)dB(P, k);
     W[k] = (double *)calloc(sz, sizeof(double));
     Wh[k] = (double *)calloc(sz, sizeof(double));
-    g[k] = (double *)calloc(sz, sizeof(double));
-    l[k] = (double *)calloc(sz, sizeof(double));
+    g[k] = (double *)calloc(szb, sizeof(double));
+    l[k] = (double *)calloc(szb, sizeof(double));
     if (!W[k] || !Wh[k] || !g[k] || !l[k]) ok = 0;
   }
   double *lh = NULL;
   if (depth >= 2) {
-    lh = (double *)calloc((size_t)nleaf * (size_t)P->lv[depth].d, sizeof(double));
+    lh = (double *)calloc((size_t)nleaf * (size_t)dB(P, depth), sizeof(double));
     if (!lh) ok = 0;
   }
   if (!ok) {
@@ -785,7 +866,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
   if (depth >= 2) {
     /* Step 1 (P2M): W_m^I = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I). */
     {
-      const olevel *lv = &P->lv[depth];
+      const oeim *lv = &P->lv[depth].a;
       int d = lv->d;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8)
@@ -809,11 +890,11 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
      * W_m^{I^k} = sum_{J child} sum_p K(x_m^{I_0^k} + c_I - c_J, y_p^{J_0^{k+1}}) What_p^J
      * with What^J = Delta^{k+1} W^J (the Delta-contraction of eq. (17)). */
     for (int k = depth; k >= 2; k--) {
-      const olevel *lv = &P->lv[k];
+      const oeim *lv = &P->lv[k].a;
       int d = lv->d;
       int64_t nb = (int64_t)1 << (3 * k);
       if (k < depth) {
-        const olevel *lc = &P->lv[k + 1];
+        const oeim *lc = &P->lv[k + 1].a;
         int dc = lc->d;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8)
@@ -846,18 +927,21 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
                     Wh[k] + (size_t)key * (size_t)d);
       }
     }
-    /* Step 4 (M2L): g_{m'}^I = sum_{J in IL(I)} sum_l K(x_{m'}^{J_0}, y_l^{J_0} + c_J - c_I) What_l^J.
-     * For a symmetric kernel x^{J_0} = y^{J_0} = Y.  The 316 matrices
-     * K^delta_{m' l} = K(Y_{m'}, Y_l + 2 l_k delta) are tabulated once per level (Sec. 4.2). */
+    /* Step 4 (M2L): g_{m'}^I = sum_{J in IL(I)} sum_l K(x_{m'}^{J_0}, y_l^{J_0} + c_J - c_I) What_l^J,
+     * x^{J_0} from the second EIM (Y for a symmetric kernel), y^{J_0} from the
+     * first.  The 316 matrices K^delta_{m' l} = K(x_{m'}^{J_0}, y_l^{J_0} + 2 l_k delta)
+     * (d_B x d rows x columns) are tabulated once per level (Sec. 4.2). */
     int dtab[316 * 3];
     orc_offset_table(dtab);
     for (int k = 2; k <= depth; k++) {
-      const olevel *lv = &P->lv[k];
-      int d = lv->d;
+      const olevel *lvl = &P->lv[k];
+      const oeim *lv = &lvl->a;
+      const int d = lv->d, db = dB(P, k);
+      const double *xb = XB(P, k);
       int side = 1 << k;
       int64_t nb = (int64_t)1 << (3 * k);
       double h = ldexp(P->L, -k); /* 2 l_k */
-      double *Kd = (double *)malloc(sizeof(double) * 316 * (size_t)d * (size_t)d);
+      double *Kd = (double *)malloc(sizeof(double) * 316 * (size_t)db * (size_t)d);
       if (!Kd) {
         st = ORC_ENOMEM;
         goto done;
@@ -867,17 +951,18 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
 #endif
       for (int o = 0; o < 316; o++) {
         double dv[3] = {dtab[3 * o] * h, dtab[3 * o + 1] * h, dtab[3 * o + 2] * h};
-        for (int mp = 0; mp < d; mp++)
+        for (int mp = 0; mp < db; mp++)
           for (int ll = 0; ll < d; ll++) {
             double yl[3] = {lv->Y[3 * ll] + dv[0], lv->Y[3 * ll + 1] + dv[1],
                             lv->Y[3 * ll + 2] + dv[2]};
-            Kd[((size_t)o * (size_t)d + (size_t)mp) * (size_t)d + (size_t)ll] =
-                K2(K, lv->Y + 3 * mp, yl);
+            Kd[((size_t)o * (size_t)db + (size_t)mp) * (size_t)d + (size_t)ll] =
+                K2(K, xb + 3 * mp, yl);
           }
       }
-      /* compressed form: C^delta = U^T K^delta U (r x r), What' = U^T What */
-      const int r = lv->r;
-      const int dd = r > 0 ? r : d; /* size of the transferred expansions */
+      /* compressed form (one EIM only, so db = d): C^delta = U^T K^delta U (r x r),
+       * What' = U^T What */
+      const int r = lvl->r;
+      const int dr = r > 0 ? r : db, dc = r > 0 ? r : d; /* rows (g) and columns (What) */
       const double *Ad = Kd;
       double *Cd = NULL, *Whp = NULL, *gp = NULL;
       if (r > 0) {
@@ -898,13 +983,13 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           for (int i = 0; i < d; i++)
             for (int b = 0; b < r; b++) {
               double t = 0.0;
-              for (int j = 0; j < d; j++) t += A[(size_t)i * d + j] * lv->U[(size_t)j * r + b];
+              for (int j = 0; j < d; j++) t += A[(size_t)i * d + j] * lvl->U[(size_t)j * r + b];
               KU[(size_t)i * r + b] = t;
             }
           for (int a = 0; a < r; a++)
             for (int b = 0; b < r; b++) {
               double t = 0.0;
-              for (int i = 0; i < d; i++) t += lv->U[(size_t)i * r + a] * KU[(size_t)i * r + b];
+              for (int i = 0; i < d; i++) t += lvl->U[(size_t)i * r + a] * KU[(size_t)i * r + b];
               Cd[((size_t)o * r + a) * r + b] = t;
             }
           free(KU);
@@ -917,7 +1002,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           for (int a = 0; a < r; a++) {
             double t = 0.0;
             for (int i = 0; i < d; i++)
-              t += lv->U[(size_t)i * r + a] * Wh[k][(size_t)key * (size_t)d + (size_t)i];
+              t += lvl->U[(size_t)i * r + a] * Wh[k][(size_t)key * (size_t)d + (size_t)i];
             Whp[(size_t)key * r + a] = t;
           }
         }
@@ -932,7 +1017,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
         if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
         int nI[3];
         unmorton3((uint32_t)key, k, nI);
-        double *gI = gdst + (size_t)key * (size_t)dd;
+        double *gI = gdst + (size_t)key * (size_t)dr;
         for (int o = 0; o < 316; o++) {
           int nJ[3] = {nI[0] + dtab[3 * o], nI[1] + dtab[3 * o + 1], nI[2] + dtab[3 * o + 2]};
           int inside = 1, pc = 0;
@@ -944,11 +1029,11 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           if (!inside || pc > 1) continue;
           uint32_t kj = morton3((uint32_t)nJ[0], (uint32_t)nJ[1], (uint32_t)nJ[2], k);
           if (box_count(ls, depth, k, kj, NULL) == 0) continue;
-          const double *wj = Wsrc + (size_t)kj * (size_t)dd;
-          const double *A = Ad + (size_t)o * (size_t)dd * (size_t)dd;
-          for (int mp = 0; mp < dd; mp++) {
+          const double *wj = Wsrc + (size_t)kj * (size_t)dc;
+          const double *A = Ad + (size_t)o * (size_t)dr * (size_t)dc;
+          for (int mp = 0; mp < dr; mp++) {
             double s = 0.0;
-            for (int ll = 0; ll < dd; ll++) s += A[(size_t)mp * (size_t)dd + (size_t)ll] * wj[ll];
+            for (int ll = 0; ll < dc; ll++) s += A[(size_t)mp * (size_t)dc + (size_t)ll] * wj[ll];
             gI[mp] += s;
           }
         }
@@ -962,7 +1047,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
           for (int i = 0; i < d; i++) {
             double t = 0.0;
-            for (int a = 0; a < r; a++) t += lv->U[(size_t)i * r + a] * gp[(size_t)key * r + a];
+            for (int a = 0; a < r; a++) t += lvl->U[(size_t)i * r + a] * gp[(size_t)key * r + a];
             g[k][(size_t)key * (size_t)d + (size_t)i] = t;
           }
         }
@@ -972,15 +1057,15 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
     }
     /* Step 5 (L2L): l^{I^2} = g^{I^2}; for k = 3..depth
      * l_{m'}^{I^k} = g_{m'}^{I^k} + sum_{p'} K(x_{m'}^{J_0^k} + c_I - c_P, y_{p'}^{I_0^{k-1}}) lhat_{p'}^P,
-     * lhat^P = Delta^{J_0^{k-1}, I_0^{k-1}} l^P; for a symmetric kernel
-     * x^{J_0} = Y, y^{I_0} = X and Delta^{J_0,I_0} = (Delta^{I_0,J_0})^T. */
+     * lhat^P = Delta^{J_0^{k-1}, I_0^{k-1}} l^P, all from the second EIM; for a
+     * symmetric kernel x^{J_0} = Y, y^{I_0} = X and Delta^{J_0,I_0} = (Delta^{I_0,J_0})^T. */
     {
       int64_t nb2 = (int64_t)1 << 6;
-      memcpy(l[2], g[2], sizeof(double) * (size_t)nb2 * (size_t)P->lv[2].d);
+      memcpy(l[2], g[2], sizeof(double) * (size_t)nb2 * (size_t)dB(P, 2));
     }
     for (int k = 3; k <= depth; k++) {
-      const olevel *lv = &P->lv[k], *lp = &P->lv[k - 1];
-      int d = lv->d, dp = lp->d;
+      const int d = dB(P, k), dp = dB(P, k - 1);
+      const double *xb = XB(P, k), *ybp = YB(P, k - 1);
       int64_t nb = (int64_t)1 << (3 * k);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8)
@@ -989,14 +1074,13 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
         if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
         uint32_t pk = (uint32_t)(key >> 3);
         double *lhp = (double *)malloc(sizeof(double) * (size_t)dp);
-        apply_delta_t(dp, P->dmax, lp->B, lp->G, l[k - 1] + (size_t)pk * (size_t)dp, lhp);
+        apply_delta_b(P, k - 1, l[k - 1] + (size_t)pk * (size_t)dp, lhp);
         double sh[3];
         child_shift(P, k, (int)(key & 7), sh); /* c_I - c_P */
         for (int mp = 0; mp < d; mp++) {
-          double ym[3] = {lv->Y[3 * mp] + sh[0], lv->Y[3 * mp + 1] + sh[1],
-                          lv->Y[3 * mp + 2] + sh[2]};
+          double ym[3] = {xb[3 * mp] + sh[0], xb[3 * mp + 1] + sh[1], xb[3 * mp + 2] + sh[2]};
           double s = 0.0;
-          for (int pp = 0; pp < dp; pp++) s += K2(K, ym, lp->X + 3 * pp) * lhp[pp];
+          for (int pp = 0; pp < dp; pp++) s += K2(K, ym, ybp + 3 * pp) * lhp[pp];
           l[k][(size_t)key * (size_t)d + (size_t)mp] =
               g[k][(size_t)key * (size_t)d + (size_t)mp] + s;
         }
@@ -1006,8 +1090,8 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
     /* Step 6: lhat^I = Delta^{J_0^kappa, I_0^kappa} l^I;
      * Step 7 (L2P): f_F(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I. */
     {
-      const olevel *lv = &P->lv[depth];
-      int d = lv->d;
+      const int d = dB(P, depth);
+      const double *yb = YB(P, depth);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8)
 #endif
@@ -1015,13 +1099,13 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
         int64_t a = ls[key], b = ls[key + 1];
         if (a == b) continue;
         double *lhI = lh + (size_t)key * (size_t)d;
-        apply_delta_t(d, P->dmax, lv->B, lv->G, l[depth] + (size_t)key * (size_t)d, lhI);
+        apply_delta_b(P, depth, l[depth] + (size_t)key * (size_t)d, lhI);
         double c[3];
         box_centre(P, depth, (uint32_t)key, c);
         for (int64_t i = a; i < b; i++) {
           double xc[3] = {ps[3 * i] - c[0], ps[3 * i + 1] - c[1], ps[3 * i + 2] - c[2]};
           double s = 0.0;
-          for (int lp = 0; lp < d; lp++) s += K2(K, xc, lv->X + 3 * lp) * lhI[lp];
+          for (int lp = 0; lp < d; lp++) s += K2(K, xc, yb + 3 * lp) * lhI[lp];
           fs[i] = s;
         }
       }
@@ -1071,15 +1155,18 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
   }
   {
     size_t off = 0;
+    size_t offb = 0;
     for (int k = 2; k <= depth; k++) {
-      size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].d;
+      size_t sz = (size_t)((int64_t)1 << (3 * k)) * (size_t)P->lv[k].a.d;
+      size_t szb = (size_t)((int64_t)1 << (3 * k)) * (size_t)dB(P, k);
       if (dW) memcpy(dW + off, W[k], sz * sizeof(double));
       if (dWh) memcpy(dWh + off, Wh[k], sz * sizeof(double));
-      if (dg) memcpy(dg + off, g[k], sz * sizeof(double));
-      if (dl) memcpy(dl + off, l[k], sz * sizeof(double));
+      if (dg) memcpy(dg + offb, g[k], szb * sizeof(double));
+      if (dl) memcpy(dl + offb, l[k], szb * sizeof(double));
       off += sz;
+      offb += szb;
     }
-    if (dlh && lh) memcpy(dlh, lh, sizeof(double) * (size_t)nleaf * (size_t)P->lv[depth].d);
+    if (dlh && lh) memcpy(dlh, lh, sizeof(double) * (size_t)nleaf * (size_t)dB(P, depth));
   }
   st = ORC_OK;
 done:

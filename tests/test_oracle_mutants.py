@@ -11,8 +11,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "eifmm_oracle.c")
 
 MUTANTS = {
-    "l2l_uses_delta_not_delta_t": ("apply_delta_t(dp, P->dmax, lp->B, lp->G, l[k - 1]",
-                                   "apply_delta(dp, P->dmax, lp->B, lp->G, l[k - 1]"),
+    "lhat_uses_delta_not_delta_t": (
+        "apply_delta_t(P->lv[k].a.d, P->dmax, P->lv[k].a.B, P->lv[k].a.G, v, w);",
+        "apply_delta(P->lv[k].a.d, P->dmax, P->lv[k].a.B, P->lv[k].a.G, v, w);"),
+    "two_eim_lhat_transposed": (
+        "apply_delta(P->lv[k].b.d, P->dmax, P->lv[k].b.B, P->lv[k].b.G, v, w);",
+        "apply_delta_t(P->lv[k].b.d, P->dmax, P->lv[k].b.B, P->lv[k].b.G, v, w);"),
+    "two_eim_m2l_rows_from_first_eim": ("return P->two ? P->lv[k].b.X : P->lv[k].a.Y;",
+                                        "return P->two ? P->lv[k].a.Y : P->lv[k].a.Y;"),
+    "two_eim_l2p_points_from_first_eim": ("return P->two ? P->lv[k].b.Y : P->lv[k].a.X;",
+                                          "return P->two ? P->lv[k].a.X : P->lv[k].a.X;"),
+    "swapped_eim_keeps_roles": ("  if (swap) {\n    double *t = tx;", "  if (0) {\n    double *t = tx;"),
     "m2m_child_shift_sign": ("double xm[3] = {lv->X[3 * m] - sh[0]",
                              "double xm[3] = {lv->X[3 * m] + sh[0]"),
     "m2l_offset_sign": ("double yl[3] = {lv->Y[3 * ll] + dv[0]",
@@ -41,6 +50,8 @@ def test_mutant_is_caught(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pass.py"),
                         os.path.join(ROOT, "tests", "test_oracle_eim.py"),
-                        "-k", "finite_rank or gamma or interpolation or c1_accuracy"],
+                        os.path.join(ROOT, "tests", "test_oracle_nonsym.py"),
+                        "-k", "finite_rank or gamma or interpolation or c1_accuracy or swapped "
+                              "or two_eim or advdiff_two"],
                        env=env, capture_output=True, text=True, cwd=ROOT)
     assert r.returncode != 0, f"mutant {name} survived:\n{r.stdout[-2000:]}"

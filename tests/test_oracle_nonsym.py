@@ -1,0 +1,82 @@
+"""The oracle's general form of Sec. 3.1: two EIMs per level, one on (I_0, J_0)
+giving Delta^{I_0,J_0}, one on (J_0, I_0) giving Delta^{J_0,I_0}, used by a kernel
+that is not symmetric.  Pins, none of which reuses the oracle's own formulas:
+
+  * for a symmetric kernel the second EIM's training matrix is the transpose of
+    the first's, so it selects the same pairs with the roles exchanged, and the
+    two-EIM pass equals the one-EIM pass to rounding;
+  * finite-rank kernels (exp(a.z), rank 1 and not symmetric; cos(w.z), rank 2,
+    forced through the two-EIM pass) are interpolated exactly, so the whole pass
+    equals the direct sum to rounding;
+  * the advection-diffusion kernel exp(a (z_x - r))/r meets the accuracy of the
+    EIM tolerance against the direct sum, and its two EIMs differ.
+"""
+import numpy as np
+import pytest
+
+from paper_1408_0210_amd import workloads as W
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def pts():
+    return W.uniform_points(1200, 101), W.potentials(1200, 102)
+
+
+def test_swapped_eim_is_transposed_for_symmetric_kernel(oracle_lib):
+    A = oracle_lib.eim("laplace", 0.0, 2, 1.0, 1e-4)
+    B = oracle_lib.eim("laplace", 0.0, 2, 1.0, 1e-4, swapped=True)
+    assert A["d"] == B["d"]
+    np.testing.assert_array_equal(A["ia"], B["ib"])
+    np.testing.assert_array_equal(A["ib"], B["ia"])
+    np.testing.assert_array_equal(A["X"], B["Y"])
+    np.testing.assert_array_equal(A["Y"], B["X"])
+
+
+def test_swapped_eim_of_rank_one_kernel(oracle_lib):
+    """exp(a.(x - y)) = exp(a.x) exp(-a.y): one point each way, and zero residual."""
+    for swapped in (False, True):
+        e = oracle_lib.eim("expdot", [1.0, 0.5, -0.3], 3, 1.0, 1e-12, swapped=swapped)
+        assert e["d"] == 1
+        assert e["eps"][1] <= 1e-14 * e["eps"][0]
+
+
+@pytest.mark.parametrize("kernel,param,two", [("expdot", [1.0, 0.5, -0.3], False),
+                                              ("cosdot", [3.0, 1.0, 2.0], True)])
+def test_finite_rank_two_eim_pass_is_exact(kernel, param, two, pts, oracle_lib):
+    x, s = pts
+    P = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, 3, 1e-11, two_eim=two)
+    assert P.two
+    f = P.evaluate(x, s)
+    assert _rel(f, oracle_lib.direct(kernel, param, x, x, s)) < 1e-12
+
+
+def test_two_eim_pass_equals_one_eim_pass_for_laplace(pts, oracle_lib):
+    x, s = pts
+    P1 = oracle_lib.Plan("laplace", 0.0, [0, 0, 0], 1.0, 2, 1e-4)
+    P2 = oracle_lib.Plan("laplace", 0.0, [0, 0, 0], 1.0, 2, 1e-4, two_eim=True)
+    assert _rel(P2.evaluate(x, s), P1.evaluate(x, s)) < 1e-13
+
+
+def test_advdiff_two_eims_meet_the_tolerance(pts, oracle_lib):
+    x, s = pts
+    P = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 2, 1e-4)
+    a, b = P.levels[2], P.levels2[2]
+    assert not np.array_equal(a["Y"], b["X"][:len(a["Y"])]) or a["d"] != b["d"]
+    f = P.evaluate(x, s)
+    assert _rel(f, oracle_lib.direct("advdiff", 1.0, x, x, s)) < 1e-5
+
+
+def test_advdiff_kernel_values(oracle_lib):
+    """exp(a (z_x - r)) / r by its definition at a few vectors (a = 1.5): equal to
+    1/r along +x, decaying like exp(-2 a r)/r along -x."""
+    z = np.array([[0.3, 0.0, 0.0], [-0.3, 0.0, 0.0], [0.0, 0.4, 0.0], [0.1, -0.2, 0.2]])
+    r = np.linalg.norm(z, axis=1)
+    want = np.exp(1.5 * (z[:, 0] - r)) / r
+    got = oracle_lib.kernel_eval("advdiff", 1.5, z)
+    np.testing.assert_allclose(got, want, rtol=1e-15)
+    assert got[0] == pytest.approx(1 / 0.3, rel=1e-15)
+    assert got[1] == pytest.approx(np.exp(-0.9) / 0.3, rel=1e-15)
