@@ -24,7 +24,8 @@ Also reported on the same line:
   paper_kernels the paper's cos(20r)/r, exp(-r^2), sqrt(r^2+1) on its 1e6-point
                 cube, with d per level and its own one-core timings as context;
   uniform100m   the paper's 1e8-point exp(-r^2) cube (Table 4), FP64 and mixed;
-  targets       1e6 sources and 1e6 separate targets (1/r, depth 5): N_s N_t / t.
+  targets       1e6 sources and 1e6 separate targets (1/r, depth 5): N_s N_t / t;
+  nonsymmetric  exp(a (z_x - r))/r (two EIMs per level) on the 1e6-point cube.
 """
 import argparse
 import json
@@ -236,6 +237,34 @@ def run_targets(args):
     return out
 
 
+def run_nonsym(args):
+    """The advection-diffusion kernel exp(z_x - r)/r, which is not symmetric (two EIMs
+    per level, Sec. 3.1), on the 1e6-point cube at depth 5, tau 1e-6: FP64 and mixed
+    passes timed like the main run, error on 500 sampled targets."""
+    import oracle
+    from paper_1408_0210_amd import workloads as W
+    name = "uniform1m_advdiff1_d5"
+    w = W.WORKLOADS[name]
+    data = (W.make_points(w), W.make_sigma(w))
+    idx = np.sort(np.random.default_rng(19).choice(w["n"], 500, replace=False))
+    ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
+                        threads=min(os.cpu_count() or 1, 16))
+    out = {"workload": name, "n": w["n"], "kernel": w["kernel"], "param": w["param"],
+           "depth": w["depth"], "tau": w["tau"]}
+    for prec in ("fp64", "mixed"):
+        a = argparse.Namespace(**vars(args))
+        a.compress_tol = 0.0
+        r = run_plain(a, precision=prec, steps=3, warmup=1, data=data, wdict=w)
+        st = r["stats"]
+        out[prec] = {"ms_per_step": r["ms"], "value": float(w["n"]) ** 2 / (r["ms"] * 1e-3),
+                     "rel_l2_sampled": _rel_sample(r["f"], idx, ref), "d": st["d"],
+                     "d2": st["d2"], "setup_s": r["setup_s"],
+                     "phase_ms": {k: st["phase_ms"][k] / max(1, st["phase_calls"][k])
+                                  for k in st["phase_ms"]}}
+        r["plan"].close()
+    return out
+
+
 def run_100m(args):
     """The paper's 1e8-point cube with exp(-r^2) (Table 4) on one GPU: FP64 and mixed
     passes at depth 7 (~48 points per leaf), tau = 1e-6, error on 100 sampled
@@ -412,10 +441,12 @@ def main():
                     help="skip the 1e8-point exp(-r^2) run")
     ap.add_argument("--no-targets", action="store_true",
                     help="skip the separate-targets run (1e6 sources, 1e6 targets)")
+    ap.add_argument("--no-nonsym", action="store_true",
+                    help="skip the advection-diffusion (not symmetric) run")
     ap.add_argument("--batch-precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--only-leg",
                     choices=["batched", "clustered", "uneven", "paper_kernels", "100m",
-                             "targets"],
+                             "targets", "nonsym"],
                     help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
@@ -439,7 +470,8 @@ def main():
 
     if args.only_leg:
         leg = {"batched": run_batched, "clustered": run_clustered, "uneven": run_uneven,
-               "paper_kernels": run_paper_kernels, "100m": run_100m, "targets": run_targets}
+               "paper_kernels": run_paper_kernels, "100m": run_100m, "targets": run_targets,
+               "nonsym": run_nonsym}
         print(json.dumps({args.only_leg: leg[args.only_leg](args)}), flush=True)
         return
 
@@ -500,6 +532,8 @@ def main():
         out["uniform100m"] = run_100m(args)
     if not args.no_targets:
         out["targets"] = run_targets(args)
+    if not args.no_nonsym:
+        out["nonsymmetric"] = run_nonsym(args)
     print(json.dumps(out), flush=True)
 
 

@@ -64,6 +64,9 @@ extern "C" {
 #define EIFMM_K_SQDIST 3  /* r^2: rank-5 test kernel, the EIM is exact           */
 #define EIFMM_K_COSR 4    /* cos(w r)/r, w = kernel_param, singular (Sec. 5.4)   */
 #define EIFMM_K_MQ 5      /* sqrt(r^2 + c), c = kernel_param > 0 (Sec. 5.4)       */
+#define EIFMM_K_ADVDIFF 6 /* exp(a (z_x - r))/r, a = kernel_param >= 0, singular:
+                             the steady advection-diffusion kernel (flow along x),
+                             not symmetric, so two EIMs per level (Sec. 3.1)     */
 
 /* precision of the pass */
 #define EIFMM_PREC_FP64 0  /* every step in FP64                                   */
@@ -76,6 +79,11 @@ extern "C" {
 /* flags */
 #define EIFMM_FLAG_HOST_ONLY 1 /* plan_create runs the host setup only (no device
                                   tables); only eifmm_get_level/get_stats work   */
+#define EIFMM_FLAG_TWO_EIM 4    /* use the general form of Sec. 3.1 (a second EIM
+                                   on D_x = J_0, D_y = I_0 per level) for a
+                                   symmetric kernel too; kernels that are not
+                                   symmetric always use it.  Not with M2L
+                                   compression or in batches.                   */
 #define EIFMM_FLAG_HOST_SETUP 2 /* run the Algorithm 1 iterations on the host even
                                    for a device plan (by default a device plan
                                    runs them on the GPU; both select the same
@@ -146,6 +154,8 @@ typedef struct {
   int32_t reserved;
   int64_t near_point_pairs;          /* ordered point pairs (targets x sources) of
                                         the near field, self pairs included      */
+  int32_t d2[EIFMM_MAX_DEPTH + 1];   /* d of the second EIM per level (the size of
+                                        g, l and lhat), 0 with one EIM           */
 } eifmm_stats;
 
 /* Per-level EIM plan: runs Algorithm 1 for k = 2..depth on the training sets,
@@ -194,6 +204,12 @@ int eifmm_get_stats(eifmm_plan plan, eifmm_stats *out);
 int eifmm_get_level(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
                     int64_t *ib, double *B, double *Gamma);
 
+/* The same for the second EIM of level k (Sec. 3.1: D_x = J_0, D_y = I_0, so X
+ * holds J_0 points and Y holds I_0 points; its Delta is Delta^{J_0,I_0}).
+ * EIFMM_EINVAL for a plan with one EIM per level. */
+int eifmm_get_level2(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
+                     int64_t *ib, double *B, double *Gamma);
+
 /* Host copies of level k's M2L compression (Sec. 4.2): *r (0 when off), the d_k
  * singular values of [K^delta_1 .. K^delta_316] in descending order, and U
  * (d_k x r row-major: the kept left singular vectors).  Outputs may be NULL. */
@@ -216,7 +232,8 @@ int eifmm_export_lists(eifmm_plan plan, int32_t level, int64_t *nactive, uint32_
 
 /* Host copy of one expansion of the last evaluate, right-hand side `rhs`, as a
  * dense 8^k x d_k array in key order (zeros for empty boxes).  which: 0 = W,
- * 1 = What (= Delta W), 2 = g (M2L output), 3 = l, 4 = lhat (level depth only).
+ * 1 = What (= Delta W), 2 = g (M2L output), 3 = l, 4 = lhat (level depth only);
+ * with two EIMs per level, g, l and lhat have the second EIM's d_k values.
  * With M2L compression the pass applies the factor B^{-T} of Delta = B^{-T}
  * Gamma^{-1} inside the projection (What' = U^T B^{-T} (Gamma^{-1} W)), so What
  * of a compressed level is computed by this call, on the device, from W. */

@@ -46,12 +46,18 @@ int upload(T **p, const T *src, size_t count, std::vector<void *> &track) {
   return EIFMM_OK;
 }
 
+// the general form of Sec. 3.1 (two EIMs per level)
+bool uses_two_eim(const eifmm_config &c) {
+  return c.kernel == EIFMM_K_ADVDIFF || (c.flags & EIFMM_FLAG_TWO_EIM);
+}
+
 int validate(const eifmm_config *c) {
   if (!c || c->struct_size != (int32_t)sizeof(eifmm_config)) return EIFMM_EINVAL;
-  if (c->kernel < EIFMM_K_LAPLACE || c->kernel > EIFMM_K_MQ) return EIFMM_EINVAL;
+  if (c->kernel < EIFMM_K_LAPLACE || c->kernel > EIFMM_K_ADVDIFF) return EIFMM_EINVAL;
   if ((c->kernel == EIFMM_K_GAUSS && !(c->kernel_param > 0)) ||
       (c->kernel == EIFMM_K_MQ && !(c->kernel_param > 0)) ||
-      (c->kernel == EIFMM_K_YUKAWA && !(c->kernel_param >= 0)) || !std::isfinite(c->kernel_param))
+      ((c->kernel == EIFMM_K_YUKAWA || c->kernel == EIFMM_K_ADVDIFF) && !(c->kernel_param >= 0)) ||
+      !std::isfinite(c->kernel_param))
     return EIFMM_EINVAL;
   if (!(c->L > 0) || !std::isfinite(c->L)) return EIFMM_EINVAL;
   for (int a = 0; a < 3; ++a)
@@ -66,6 +72,7 @@ int validate(const eifmm_config *c) {
   if (c->precision != EIFMM_PREC_FP64 && c->precision != EIFMM_PREC_MIXED) return EIFMM_EINVAL;
   if (c->dmax < 0 || c->dmax > 4096) return EIFMM_EINVAL;
   if (!(c->compress_tol >= 0) || !std::isfinite(c->compress_tol)) return EIFMM_EINVAL;
+  if (uses_two_eim(*c) && c->compress_tol > 0) return EIFMM_EINVAL;
   return EIFMM_OK;
 }
 
@@ -158,6 +165,10 @@ int setup_tables(eifmm_plan h) {
       TRY(upload(&D.l2l, H.l2l.data(), H.l2l.size(), tr));
     }
     TRY(upload(&D.X, H.X.data(), H.X.size(), tr));
+    if (P.two_eim)
+      TRY(upload(&D.XL, H.XL.data(), H.XL.size(), tr));
+    else
+      D.XL = D.X;
     if (H.r > 0) {
       TRY(upload(&D.ufrag, H.ufrag.data(), H.ufrag.size(), tr));
       TRY(upload(&D.pfrag, H.pfrag.data(), H.pfrag.size(), tr));
@@ -227,11 +238,13 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
     } else if (mixed) {
       TRY(dalloc(&D.Wh32, m, tr));
     }
-    TRY(dalloc(&D.g, m, tr));
+    // g and l have the second EIM's size (the first's with one EIM)
+    const size_t mb = D.cap * (size_t)R * (size_t)P.lh[k].dpB;
+    TRY(dalloc(&D.g, mb, tr));
     if (k == 2)
       D.l = D.g;  // l^2 = g^2 (Algorithm 3, step 5)
     else
-      TRY(dalloc(&D.l, m, tr));
+      TRY(dalloc(&D.l, mb, tr));
   }
   P.sk_groups = stream_k_groups(P.device);
   if (shared_ws)
@@ -239,7 +252,7 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
   else
     TRY(dalloc(&P.sk_ws, stream_k_ws_len(P.sk_groups), tr));
   if (depth >= 2)
-    TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dp, tr));
+    TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dpB, tr));
 #undef TRY
   return EIFMM_OK;
 }
@@ -313,6 +326,8 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
     const LevelHost &TH = T.lh[k];
     H.d = TH.d;
     H.dp = TH.dp;
+    H.dB = TH.dB;
+    H.dpB = TH.dpB;
     H.scale = TH.scale;
     H.err = TH.err;
     H.r = TH.r;
@@ -325,6 +340,7 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
     D.l2l = TD.l2l;
     for (int q = 0; q < 4; ++q) D.tri[q] = TD.tri[q];
     D.X = TD.X;
+    D.XL = TD.XL;
     D.ufrag = TD.ufrag;
     D.pfrag = TD.pfrag;
   }
@@ -498,6 +514,7 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   P.max_rhs = cfg->max_rhs;
   P.host_only = (cfg->flags & EIFMM_FLAG_HOST_ONLY) != 0;
   P.gpu_setup = !P.host_only && !(cfg->flags & EIFMM_FLAG_HOST_SETUP);
+  P.two_eim = uses_two_eim(*cfg);
   if (!P.host_only) hipGetDevice(&P.device);
   st = build_tables(P);
   if (st == EIFMM_OK && !P.host_only) {
@@ -620,6 +637,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
     s.d[k] = P.lh[k].d;
     s.dpad[k] = P.lh[k].dp;
     s.rank[k] = P.lh[k].r;
+    s.d2[k] = P.two_eim ? P.lhB[k].d : 0;
     s.eim_err[k] = P.lh[k].err;
   }
   s.setup_ms = P.setup_ms;
@@ -640,12 +658,9 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
   return EIFMM_OK;
 }
 
-int eifmm_get_level(eifmm_plan h, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
-                    int64_t *ib, double *B, double *G) {
-  if (!h) return EIFMM_EINVAL;
-  Plan &P = h->P;
-  if (k < 2 || k > P.depth) return EIFMM_EINVAL;
-  const LevelHost &L = P.lh[k];
+namespace {
+int get_level_impl(const LevelHost &L, int32_t *d, double *X, double *Y, int64_t *ia,
+                   int64_t *ib, double *B, double *G) {
   if (d) *d = L.d;
   if (X) std::memcpy(X, L.X.data(), sizeof(double) * L.X.size());
   if (Y) std::memcpy(Y, L.Y.data(), sizeof(double) * L.Y.size());
@@ -654,6 +669,23 @@ int eifmm_get_level(eifmm_plan h, int32_t k, int32_t *d, double *X, double *Y, i
   if (B) std::memcpy(B, L.B.data(), sizeof(double) * L.B.size());
   if (G) std::memcpy(G, L.G.data(), sizeof(double) * L.G.size());
   return EIFMM_OK;
+}
+}  // namespace
+
+int eifmm_get_level(eifmm_plan h, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
+                    int64_t *ib, double *B, double *G) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (k < 2 || k > P.depth) return EIFMM_EINVAL;
+  return get_level_impl(P.lh[k], d, X, Y, ia, ib, B, G);
+}
+
+int eifmm_get_level2(eifmm_plan h, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
+                     int64_t *ib, double *B, double *G) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (!P.two_eim || k < 2 || k > P.depth) return EIFMM_EINVAL;
+  return get_level_impl(P.lhB[k], d, X, Y, ia, ib, B, G);
 }
 
 int eifmm_get_compression(eifmm_plan h, int32_t k, int32_t *r, double *sv, double *U) {
@@ -716,7 +748,10 @@ int eifmm_export_expansion(eifmm_plan h, int32_t which, int32_t k, int32_t rhs, 
   int st = materialize_expansion(P, which, k);
   if (st) return st;
   const LevelDev &D = P.ld[k];
-  const int d = P.lh[k].d, dp = P.lh[k].dp, R = P.last_rhs;
+  // W and What have the first EIM's size, g, l and lhat the second's
+  const bool second = which >= 2;
+  const int d = second ? P.lh[k].dB : P.lh[k].d, dp = second ? P.lh[k].dpB : P.lh[k].dp,
+            R = P.last_rhs;
   const int64_t na = P.nact[k];
   std::vector<double> buf((size_t)na * R * dp);
   const double *src = nullptr;
@@ -762,7 +797,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
     int st = validate(&c);
     if (st) return st;
     if (c.depth < 2 || c.max_rhs != 1 || (c.flags & EIFMM_FLAG_HOST_ONLY) ||
-        c.precision != cfgs[0].precision || c.n_targets != 0)
+        c.precision != cfgs[0].precision || c.n_targets != 0 || uses_two_eim(c))
       return EIFMM_EINVAL;
   }
   eifmm_batch b = new (std::nothrow) eifmm_batch_s();

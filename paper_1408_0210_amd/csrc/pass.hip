@@ -23,10 +23,12 @@ namespace eifmm {
 // ------------------------------------------------------------------ kernels k
 template <int KIND>
 struct KF {
-  static constexpr bool singular =
-      (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA || KIND == EIFMM_K_COSR);
-  // p: Yukawa a, Gauss 1/h2, cos(w r)/r w, multiquadric c
-  __device__ static inline double eval(double r2, double p) {
+  static constexpr bool singular = (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA ||
+                                     KIND == EIFMM_K_COSR || KIND == EIFMM_K_ADVDIFF);
+  // k at z with r2 = |z|^2 and zx its first component (read by the kernel that
+  // is not radial); p: Yukawa a, Gauss 1/h2, cos(w r)/r w, multiquadric c,
+  // advection-diffusion a
+  __device__ static inline double eval(double r2, double zx, double p) {
     if constexpr (KIND == EIFMM_K_LAPLACE) {
       return rsqrt(r2);
     } else if constexpr (KIND == EIFMM_K_YUKAWA) {
@@ -39,11 +41,14 @@ struct KF {
       return cos(p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_MQ) {
       return sqrt(r2 + p);
+    } else if constexpr (KIND == EIFMM_K_ADVDIFF) {
+      double ri = rsqrt(r2);
+      return exp(p * (zx - r2 * ri)) * ri;
     } else {
       return r2;
     }
   }
-  __device__ static inline float evalf(float r2, float p) {
+  __device__ static inline float evalf(float r2, float zx, float p) {
     if constexpr (KIND == EIFMM_K_LAPLACE) {
       return rsqrtf(r2);
     } else if constexpr (KIND == EIFMM_K_YUKAWA) {
@@ -56,6 +61,9 @@ struct KF {
       return cosf(p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_MQ) {
       return sqrtf(r2 + p);
+    } else if constexpr (KIND == EIFMM_K_ADVDIFF) {
+      float ri = rsqrtf(r2);
+      return expf(p * (zx - r2 * ri)) * ri;
     } else {
       return r2;
     }
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       for (int u = u0; u < u1; ++u) {
         const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
         const double r2 = dx * dx + dy * dy + dz * dz;
-        double kv = KF<KIND>::eval(r2, D.p);
+        double kv = KF<KIND>::eval(r2, dx, D.p);
         if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
       for (int u = u0; u < u1; ++u) {
         const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
         const float r2 = dx * dx + dy * dy + dz * dz;
-        float kv = KF<KIND>::evalf(r2, p);
+        float kv = KF<KIND>::evalf(r2, dx, p);
         if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
         for (int u = 0; u < 4; ++u) {
           if (u < nu) {
             const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
-            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, D.p);
+            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) acc[u][rr] += ps[q * RB + rr] * kv;
           }
@@ -428,7 +436,8 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
     O = io[prob];
   else
     O = ione;
-  const int dp = D.dp, d = D.d, nrhs = D.nrhs;
+  // lhat and its points: the second EIM's size and y^{I_0} with two EIMs per level
+  const int dp = D.dpL, d = D.dL, nrhs = D.nrhs;
   const int64_t n = D.n;
   double *sX = sm, *sl = sm + 3 * dp;
   const int lane = threadIdx.x, half = lane >> 5;
@@ -439,7 +448,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
-  for (int e = lane; e < 3 * d; e += 64) sX[e] = D.X[e];
+  for (int e = lane; e < 3 * d; e += 64) sX[e] = D.XL[e];
   const bool tv = i < b;
   const double xc = tv ? D.xyz[i] - cx : 0.0, yc = tv ? D.xyz[n + i] - cy : 0.0,
                zc = tv ? D.xyz[2 * n + i] - cz : 0.0;
@@ -456,7 +465,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
     for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
     for (int l = l0; l < l1; ++l) {
       const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
-      const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, D.p);
+      const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
     }
@@ -1145,11 +1154,12 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     int tiles = 0;
     jt.m2l_first = (int)h.size();
     const LevelHost &F = P.lh[depth];
-    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dp) / 16);
+    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16);
     double flops = 0;
     for (int k = depth; k >= 2; --k) {
       const bool cz = P.lh[k].r > 0;
-      const int dm = cz ? P.lh[k].rp : P.lh[k].dp;
+      // rows: g (the second EIM's size); columns: What
+      const int dm = cz ? P.lh[k].rp : P.lh[k].dpB, dk = cz ? P.lh[k].rp : P.lh[k].dp;
       for (int c = 0; c < 8; ++c) {
         const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
         if (nt == 0) continue;
@@ -1164,10 +1174,11 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
         J.tgt_keys = P.ld[k].act;
         J.src_slot = P.ld[k].slot;
         J.terms = P.dlist + 189 * c;
-        J.a_stride = (int64_t)dm * dm;
+        J.a_stride = (int64_t)dm * dk;
         J.ntgt = (int)nt;
         J.nterms = 189;
-        J.dpm = J.dpk = dm;
+        J.dpm = dm;
+        J.dpk = dk;
         J.level = k;
         J.cls = c;
         J.mode = MODE_M2L;
@@ -1175,8 +1186,8 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
         finish_job(J, tiles, jt.m2l_rbt);
         h.push_back(J);
       }
-      const double rk = cz ? P.lh[k].r : P.lh[k].d;
-      flops += 2.0 * rk * rk * (double)P.il_pairs[k] * nrhs;
+      const double rm = cz ? P.lh[k].r : P.lh[k].dB, rk = cz ? P.lh[k].r : P.lh[k].d;
+      flops += 2.0 * rm * rk * (double)P.il_pairs[k] * nrhs;
     }
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
@@ -1223,11 +1234,11 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       J.tgt = P.ld[k].cls + P.cls_off[k][c];
       J.tgt_keys = P.ld[k].act;
       J.src_slot = P.ld[k - 1].slot;
-      J.a_stride = (int64_t)P.lh[k].dp * P.lh[k - 1].dp;
+      J.a_stride = (int64_t)P.lh[k].dpB * P.lh[k - 1].dpB;
       J.ntgt = (int)nt;
       J.nterms = 1;
-      J.dpm = P.lh[k].dp;
-      J.dpk = P.lh[k - 1].dp;
+      J.dpm = P.lh[k].dpB;
+      J.dpk = P.lh[k - 1].dpB;
       J.level = k;
       J.cls = c;
       J.mode = MODE_L2L;
@@ -1402,6 +1413,7 @@ LeafDesc leaf_desc(const Plan &P, int nrhs) {
   D.perm = P.idx;
   D.xyz = P.xyz;
   D.X = P.ld[depth].X;
+  D.XL = P.ld[depth].XL;
   D.lhat = P.lhat;
   D.sig = P.sig;
   D.fnear = P.fnear;
@@ -1413,6 +1425,8 @@ LeafDesc leaf_desc(const Plan &P, int nrhs) {
   D.nrhs = nrhs;
   D.d = depth >= 2 ? P.lh[depth].d : 0;
   D.dp = depth >= 2 ? P.lh[depth].dp : 0;
+  D.dL = depth >= 2 ? P.lh[depth].dB : 0;
+  D.dpL = depth >= 2 ? P.lh[depth].dpB : 0;
   D.lo0 = P.cfg.lo[0];
   D.lo1 = P.cfg.lo[1];
   D.lo2 = P.cfg.lo[2];
@@ -1507,7 +1521,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
       launch_gemm<double, MODE_L2L>(P, P.jobs.l2l_first[k], P.jobs.l2l_n[k], P.jobs.l2l_tiles[k],
                                     P.jobs.l2l_units[k], s, P.jobs.l2l_rbt[k]);
   }
-  // step 6: lhat = Delta^T l on the leaf level
+  // step 6: lhat = Delta^{J_0,I_0} l on the leaf level (Delta^T l with one EIM)
   {
     Timer tm(P, s, EIFMM_PH_LHAT);
     SolveArgs A{};
@@ -1518,16 +1532,16 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     A.lv[0].Tf = LL.tri[2];
     A.lv[0].Tb = LL.tri[3];
     A.lv[0].ncols = nc;
-    A.lv[0].dp = HL.dp;
+    A.lv[0].dp = HL.dpB;
     A.lv[0].blk_start = 0;
     A.nlev = 1;
     if (nc > 0)
-      hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64), trsm_shm(HL.dp), s, A);
+      hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64), trsm_shm(HL.dpB), s, A);
   }
   // step 7: L2P and the final sum
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_L2P);
-    launch_l2p<KIND, false>(nrhs, nchunk, HL.dp, LD, io, nullptr, nullptr, 0, s);
+    launch_l2p<KIND, false>(nrhs, nchunk, HL.dpB, LD, io, nullptr, nullptr, 0, s);
   }
 }
 
@@ -1571,6 +1585,9 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
       break;
     case EIFMM_K_MQ:
       run_kind<EIFMM_K_MQ>(P, nrhs, io, s);
+      break;
+    case EIFMM_K_ADVDIFF:
+      run_kind<EIFMM_K_ADVDIFF>(P, nrhs, io, s);
       break;
     default:
       run_kind<EIFMM_K_SQDIST>(P, nrhs, io, s);
@@ -1840,7 +1857,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
       ch += P.nchunk;
       lf += P.nact[P.depth];
       pts += P.n;
-      g.dpmax = std::max(g.dpmax, P.lh[P.depth].dp);
+      g.dpmax = std::max(g.dpmax, std::max(P.lh[P.depth].dp, P.lh[P.depth].dpB));
       leaf[q] = D;
     }
     g.nchunk = ch;
@@ -1884,7 +1901,7 @@ int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans_in, int m2l_rbt
       D.Tf = P.ld[k].tri[2];
       D.Tb = P.ld[k].tri[3];
       D.ncols = nc;
-      D.dp = P.lh[k].dp;
+      D.dp = P.lh[k].dpB;
       D.blk_start = bl;
       bl += (nc + 15) / 16;
       B.lhat_shm = std::max(B.lhat_shm, trsm_shm(D.dp));

@@ -17,6 +17,10 @@ constexpr int kNumOffsets = 316;  // 7^3 - 3^3 distinct M2L offsets (Sec. 4.2)
 struct LevelHost {
   int d = 0;   // number of interpolation points d_k
   int dp = 0;  // d rounded up to a multiple of 16 (MFMA row blocks)
+  // size of the local expansions g, l, lhat: the second EIM's d (kernels that
+  // are not symmetric, Sec. 3.1), else d
+  int dB = 0, dpB = 0;
+  std::vector<double> XL;       // L2P points y^{I_0} (dB x 3): the second EIM's Y, else X
   double scale = 0, err = 0;
   std::vector<double> X, Y;     // d x 3, physical units: X in I_0^k, Y in J_0^k
   std::vector<int64_t> ia, ib;  // training-set indices of X and Y
@@ -40,7 +44,8 @@ struct LevelDev {
   float *kfrag32 = nullptr;
   double *m2m = nullptr, *l2l = nullptr;
   double *tri[4] = {nullptr, nullptr, nullptr, nullptr};
-  double *X = nullptr;  // d x 3 (leaf level: P2M / L2P)
+  double *X = nullptr;   // d x 3 (leaf level: P2M)
+  double *XL = nullptr;  // dB x 3 (leaf level: L2P); = X with one EIM
   // per-query workspaces
   size_t cap = 0;        // max active boxes at this level: min(8^k, n)
   uint32_t *act = nullptr;   // active box keys, ascending
@@ -97,13 +102,15 @@ struct LeafDesc {
   const int *near_ptr, *near_src;
   const int *perm;          // sorted position -> input index
   const double *xyz;        // sorted points
-  const double *X;          // leaf-level EIM points X (d x 3)
+  const double *X;          // leaf-level EIM points X (d x 3): P2M
+  const double *XL;         // leaf-level L2P points (dL x 3)
   const double *lhat;
   double *sig, *fnear, *W;  // sorted sigma, near field, leaf W
   int64_t n;
   int64_t nsrc;             // input indices below nsrc are sources (sigma rows)
   int64_t toff;             // target t has input index toff + t (f row t)
   int nleaf, nrhs, d, dp;
+  int dL, dpL;              // size of lhat (L2P)
   double lo0, lo1, lo2, h, p;  // domain corner, leaf width, device kernel parameter
   int64_t chunk_base, leaf_base, pt_base;  // batch launches: first chunk / leaf / element
 };
@@ -187,6 +194,8 @@ struct Plan {
   int device = 0;
   bool host_only = false;
   bool gpu_setup = false;  // Algorithm 1 iterations on the device
+  bool two_eim = false;    // second EIM per level (lhB): kernels that are not symmetric
+  LevelHost lhB[kMaxLevels];  // the second EIM (D_x = J_0, D_y = I_0): X in J_0, Y in I_0
   int depth = 0;
   LevelHost lh[kMaxLevels];
   LevelDev ld[kMaxLevels];

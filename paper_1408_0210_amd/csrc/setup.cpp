@@ -10,6 +10,10 @@
 //    stop once the largest residual is <= tau * scale (end of Sec. 2);
 //  * M = K(X, Y) factored without pivoting as M = Gamma B^T (Crout), so that
 //    Delta = B^{-T} Gamma^{-1} = M^{-1} (eq. (5));
+//  * for a kernel that is not symmetric (or when asked), the second EIM of Sec.
+//    3.1 per level, on D_x = J_0 and D_y = I_0 (the training sets exchanged): its
+//    J_0 points are the rows of the M2L and L2L operators, its I_0 points the L2P
+//    points, and its M_B^{-1} = Delta^{J_0,I_0} gives lhat and the L2L operators;
 //  * M2M / L2L operators K M^{-1} and K M^{-T} formed row by row with
 //    triangular solves, never with an explicit inverse (Sec. 4.1);
 //  * the 316 M2L matrices K^delta = K(Y, Y + 2 l_k delta) (Sec. 4.2), and, when
@@ -50,6 +54,10 @@ inline double kern_host(int kind, double p, double zx, double zy, double zz) {
     }
     case EIFMM_K_MQ:
       return std::sqrt(r2 + p);
+    case EIFMM_K_ADVDIFF: {
+      double r = std::sqrt(r2);
+      return std::exp(p * (zx - r)) / r;
+    }
   }
   return NAN;
 }
@@ -166,11 +174,14 @@ void finish_eim(const std::vector<double> &tx, const std::vector<double> &ty, do
     }
 }
 
+// swap: the second EIM of Sec. 3.1, with D_x = J_0 and D_y = I_0 (X then holds
+// J_0 points, Y holds I_0 points)
 int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, double abs_scale,
-               bool gpu, LevelHost &out) {
+               bool gpu, bool swap, LevelHost &out) {
   const double lk = std::ldexp(L, -level - 1);
   std::vector<double> tx, ty;
   training_sets(kind, level, lk, tx, ty);
+  if (swap) std::swap(tx, ty);
   const int64_t nx = (int64_t)tx.size() / 3, ny = (int64_t)ty.size() / 3;
   std::vector<double> R((size_t)(nx * ny));
   parallel_for(nx, [&](int64_t a0, int64_t a1) {
@@ -481,19 +492,37 @@ int build_tables(Plan &P) {
   const int depth = c.depth, kind = c.kernel;
   const double p = c.kernel_param, L = c.L;
   const int dmax = c.dmax > 0 ? c.dmax : 1024;
-  double abs_scale = 0;
+  double abs_scale = 0, abs_scale2 = 0;
   for (int k = depth; k >= 2; --k) {
     LevelHost &lv = P.lh[k];
     int st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale : 0.0,
-                        P.gpu_setup, lv);
+                        P.gpu_setup, false, lv);
     if (st != EIFMM_OK) return st;
     if (k == depth && c.tol_mode == 1) abs_scale = lv.scale;
     crout(kind, p, lv);
     lv.dp = ((lv.d + 15) / 16) * 16;
     if (lv.dp == 0) lv.dp = 16;
+    lv.dB = lv.d;
+    lv.dpB = lv.dp;
+    if (P.two_eim) {
+      // the second EIM (Sec. 3.1): its X (J_0) are the local expansions' check
+      // points, its Y (I_0) the L2P points, its Delta = M_B^{-1} gives lhat
+      LevelHost &lb = P.lhB[k];
+      st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale2 : 0.0,
+                      P.gpu_setup, true, lb);
+      if (st != EIFMM_OK) return st;
+      if (k == depth && c.tol_mode == 1) abs_scale2 = lb.scale;
+      crout(kind, p, lb);
+      lb.dp = ((lb.d + 15) / 16) * 16;
+      if (lb.dp == 0) lb.dp = 16;
+      lv.dB = lb.d;
+      lv.dpB = lb.dp;
+      lv.XL = lb.Y;
+    }
   }
   // translation-invariant M2L matrices K^delta (Sec. 4.2): rows m' (target check
-  // points Y_m'), columns l (source equivalent points Y_l + 2 l_k delta)
+  // points x^{J_0}_m': the second EIM's X, else Y), columns l (source equivalent
+  // points Y_l + 2 l_k delta)
   int delta[kNumOffsets][3];
   {
     int id = 0;
@@ -510,15 +539,16 @@ int build_tables(Plan &P) {
   }
   for (int k = 2; k <= depth; ++k) {
     LevelHost &lv = P.lh[k];
-    const int d = lv.d, dp = lv.dp;
+    const int d = lv.d, dp = lv.dp, dB = lv.dB, dpB = lv.dpB;
+    const double *xr = P.two_eim ? P.lhB[k].X.data() : lv.Y.data();  // row points
     const double h = std::ldexp(L, -k);  // box side 2 l_k
-    auto kdelta = [&](int o, std::vector<double> &A) {
+    auto kdelta = [&](int o, std::vector<double> &A) {  // dB x d
       const double sx = delta[o][0] * h, sy = delta[o][1] * h, sz = delta[o][2] * h;
-      for (int i = 0; i < d; ++i)
+      for (int i = 0; i < dB; ++i)
         for (int j = 0; j < d; ++j)
-          A[(size_t)i * d + j] = kern_host(kind, p, lv.Y[3 * i] - (lv.Y[3 * j] + sx),
-                                           lv.Y[3 * i + 1] - (lv.Y[3 * j + 1] + sy),
-                                           lv.Y[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
+          A[(size_t)i * d + j] = kern_host(kind, p, xr[3 * i] - (lv.Y[3 * j] + sx),
+                                           xr[3 * i + 1] - (lv.Y[3 * j + 1] + sy),
+                                           xr[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
     };
     lv.r = lv.rp = 0;
     if (c.compress_tol > 0 && d > 0) {
@@ -563,14 +593,15 @@ int build_tables(Plan &P) {
       to_fragments(Pm.data(), lv.r, d, lv.rp, dp, lv.pfrag.data());
     }
     const int r = lv.r, rp = lv.rp;
-    const int dm = r > 0 ? rp : dp;  // size of the transferred expansions
-    lv.kfrag.assign((size_t)kNumOffsets * dm * dm, 0.0);
+    // rows (g) and columns (What) of the transferred expansions
+    const int dmr = r > 0 ? rp : dpB, dmc = r > 0 ? rp : dp;
+    lv.kfrag.assign((size_t)kNumOffsets * dmr * dmc, 0.0);
     parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
-      std::vector<double> A((size_t)d * d), KU, C;
+      std::vector<double> A((size_t)dB * d), KU, C;
       for (int64_t o = o0; o < o1; ++o) {
         kdelta((int)o, A);
         if (r == 0) {
-          to_fragments(A.data(), d, d, dp, dp, &lv.kfrag[(size_t)o * dp * dp]);
+          to_fragments(A.data(), dB, d, dpB, dp, &lv.kfrag[(size_t)o * dpB * dp]);
           continue;
         }
         // C^delta = U^T K^delta U
@@ -597,20 +628,29 @@ int build_tables(Plan &P) {
     });
     trsm_table(lv.G, d, dp, false, true, lv.tri[0]);   // Gamma    (forward, Delta)
     trsm_table(lv.B, d, dp, true, false, lv.tri[1]);   // B^T      (backward, Delta)
-    trsm_table(lv.B, d, dp, false, true, lv.tri[2]);   // B        (forward, Delta^T)
-    trsm_table(lv.G, d, dp, true, false, lv.tri[3]);   // Gamma^T  (backward, Delta^T)
+    if (P.two_eim) {  // lhat = Delta^{J_0,I_0} l = M_B^{-1} l: the second EIM's factors
+      const LevelHost &lb = P.lhB[k];
+      trsm_table(lb.G, dB, dpB, false, true, lv.tri[2]);  // Gamma_B  (forward)
+      trsm_table(lb.B, dB, dpB, true, false, lv.tri[3]);  // B_B^T    (backward)
+    } else {
+      trsm_table(lv.B, d, dp, false, true, lv.tri[2]);   // B        (forward, Delta^T)
+      trsm_table(lv.G, d, dp, true, false, lv.tri[3]);   // Gamma^T  (backward, Delta^T)
+    }
   }
   // M2M (Sec. 4.1): for parent level k and child i with c_C - c_P = s_i,
   //   M2M_i = K(X^k - s_i, Y^{k+1}) (M^{k+1})^{-1}        (d_k x d_{k+1})
-  // L2L: L2L_i = K(Y^{k+1} + s_i, X^k) (M^k)^{-T}          (d_{k+1} x d_k)
+  // L2L: L2L_i = K(x^{J_0,k+1} + s_i, y^{I_0,k}) Delta^{J_0,I_0,k}, with the second
+  // EIM's points and M_B^{-1}; one EIM: K(Y^{k+1} + s_i, X^k) (M^k)^{-T}
   for (int k = 2; k < depth; ++k) {
     LevelHost &lp = P.lh[k], &lc = P.lh[k + 1];
-    const int dk = lp.d, dc = lc.d;
+    const int dk = lp.d, dc = lc.d, dkB = lp.dB, dcB = lc.dB;
+    const double *xbc = P.two_eim ? P.lhB[k + 1].X.data() : lc.Y.data();
+    const double *ybp = P.two_eim ? P.lhB[k].Y.data() : lp.X.data();
     const double lc_half = std::ldexp(L, -k - 2);  // l_{k+1}
     lp.m2m.assign((size_t)8 * lp.dp * lc.dp, 0.0);
-    lp.l2l.assign((size_t)8 * lc.dp * lp.dp, 0.0);
+    lp.l2l.assign((size_t)8 * lc.dpB * lp.dpB, 0.0);
     parallel_for(8, [&](int64_t i0, int64_t i1) {
-      std::vector<double> A((size_t)dk * dc), Bm((size_t)dc * dk), row;
+      std::vector<double> A((size_t)dk * dc), Bm((size_t)dcB * dkB), row;
       for (int64_t i = i0; i < i1; ++i) {
         double s[3];
         for (int a = 0; a < 3; ++a) s[a] = ((i >> a) & 1) ? lc_half : -lc_half;
@@ -624,16 +664,20 @@ int build_tables(Plan &P) {
           std::memcpy(&A[(size_t)m * dc], row.data(), sizeof(double) * dc);
         }
         to_fragments(A.data(), dk, dc, lp.dp, lc.dp, &lp.m2m[(size_t)i * lp.dp * lc.dp]);
-        for (int m = 0; m < dc; ++m) {
-          row.assign((size_t)dk, 0.0);
-          for (int q = 0; q < dk; ++q)
-            row[q] = kern_host(kind, p, (lc.Y[3 * m] + s[0]) - lp.X[3 * q],
-                               (lc.Y[3 * m + 1] + s[1]) - lp.X[3 * q + 1],
-                               (lc.Y[3 * m + 2] + s[2]) - lp.X[3 * q + 2]);
-          solve_minv(lp, row.data());  // row M^{-T} = (M^{-1} row^T)^T
-          std::memcpy(&Bm[(size_t)m * dk], row.data(), sizeof(double) * dk);
+        for (int m = 0; m < dcB; ++m) {
+          row.assign((size_t)dkB, 0.0);
+          for (int q = 0; q < dkB; ++q)
+            row[q] = kern_host(kind, p, (xbc[3 * m] + s[0]) - ybp[3 * q],
+                               (xbc[3 * m + 1] + s[1]) - ybp[3 * q + 1],
+                               (xbc[3 * m + 2] + s[2]) - ybp[3 * q + 2]);
+          if (P.two_eim)
+            solve_mtinv(P.lhB[k], row.data());  // row M_B^{-1} = (M_B^{-T} row^T)^T
+          else
+            solve_minv(lp, row.data());  // row M^{-T} = (M^{-1} row^T)^T
+          std::memcpy(&Bm[(size_t)m * dkB], row.data(), sizeof(double) * dkB);
         }
-        to_fragments(Bm.data(), dc, dk, lc.dp, lp.dp, &lp.l2l[(size_t)i * lc.dp * lp.dp]);
+        to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB,
+                     &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
       }
     });
   }

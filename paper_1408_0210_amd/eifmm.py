@@ -13,10 +13,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libeifmm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "eifmm.h")
 
-KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3, "cosr": 4, "mq": 5}
+KERNELS = {"laplace": 0, "yukawa": 1, "gauss": 2, "sqdist": 3, "cosr": 4, "mq": 5,
+           "advdiff": 6}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FLAG_HOST_ONLY = 1
 FLAG_HOST_SETUP = 2
+FLAG_TWO_EIM = 4
 MAX_DEPTH = 8
 NPHASE = 10
 PHASES = ["tree", "p2p", "p2m", "m2m", "what", "m2l", "l2l", "lhat", "l2p", "proj"]
@@ -50,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("active_boxes", ctypes.c_int64 * (MAX_DEPTH + 1)),
                 ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
                 ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("near_point_pairs", ctypes.c_int64)]
+                ("near_point_pairs", ctypes.c_int64), ("d2", ctypes.c_int32 * (MAX_DEPTH + 1))]
 
 
 class BatchInfo(ctypes.Structure):
@@ -83,6 +85,7 @@ def lib():
         L.eifmm_set_timing.argtypes = [vp, i32]
         L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.eifmm_get_level.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
+        L.eifmm_get_level2.argtypes = L.eifmm_get_level.argtypes
         L.eifmm_get_compression.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp]
         L.eifmm_export_tree.argtypes = [vp, vp, vp, vp]
         L.eifmm_export_lists.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp]
@@ -100,7 +103,8 @@ def lib():
         L.eifmm_status_str.restype = ctypes.c_char_p
         for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_set_points_targets",
                   "eifmm_evaluate", "eifmm_set_timing",
-                  "eifmm_get_stats", "eifmm_get_level", "eifmm_get_compression",
+                  "eifmm_get_stats", "eifmm_get_level", "eifmm_get_level2",
+                  "eifmm_get_compression",
                   "eifmm_export_tree", "eifmm_export_lists",
                   "eifmm_export_expansion", "eifmm_plan_destroy", "eifmm_batch_create",
                   "eifmm_batch_set_points", "eifmm_batch_evaluate",
@@ -134,7 +138,8 @@ def _stream():
 
 
 def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
-                dmax=0, host_only=False, compress_tol=0.0, n_targets=0, host_setup=False):
+                dmax=0, host_only=False, compress_tol=0.0, n_targets=0, host_setup=False,
+                two_eim=False):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.kernel = KERNELS[kernel]
@@ -149,7 +154,8 @@ def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64"
     c.tol_mode = int(tol_mode)
     c.precision = PRECISIONS[precision]
     c.dmax = int(dmax)
-    c.flags = (FLAG_HOST_ONLY if host_only else 0) | (FLAG_HOST_SETUP if host_setup else 0)
+    c.flags = ((FLAG_HOST_ONLY if host_only else 0) | (FLAG_HOST_SETUP if host_setup else 0)
+               | (FLAG_TWO_EIM if two_eim else 0))
     c.compress_tol = float(compress_tol)
     c.n_targets = int(n_targets)
     return c
@@ -165,6 +171,7 @@ def _stats_dict(s, depth):
                 m2l_flops=s.m2l_flops,
                 active_boxes={k: s.active_boxes[k] for k in range(depth + 1)},
                 il_pairs={k: s.il_pairs[k] for k in lv}, near_pairs=s.near_pairs,
+                d2={k: s.d2[k] for k in lv},
                 near_point_pairs=s.near_point_pairs, hip_error=s.hip_error)
 
 
@@ -175,9 +182,9 @@ class Plan:
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
                  tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0,
-                 host_setup=False):
+                 host_setup=False, two_eim=False):
         c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
-                        host_only, compress_tol, n_targets, host_setup)
+                        host_only, compress_tol, n_targets, host_setup, two_eim)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.n_targets = int(n_targets)
@@ -232,16 +239,18 @@ class Plan:
         _check(lib().eifmm_get_stats(self._h, ctypes.byref(s)), "eifmm_get_stats")
         return _stats_dict(s, self.depth)
 
-    def level(self, k):
+    def level(self, k, second=False):
+        """EIM data of level k (second=True: the second EIM of a two-EIM plan)."""
+        fn = lib().eifmm_get_level2 if second else lib().eifmm_get_level
         d = ctypes.c_int32()
-        _check(lib().eifmm_get_level(self._h, k, ctypes.byref(d), None, None, None, None, None,
-                                     None), "eifmm_get_level")
+        _check(fn(self._h, k, ctypes.byref(d), None, None, None, None, None, None),
+               "eifmm_get_level")
         d = d.value
         X, Y = np.empty((d, 3)), np.empty((d, 3))
         ia, ib = np.empty(d, dtype=np.int64), np.empty(d, dtype=np.int64)
         B, G = np.empty((d, d)), np.empty((d, d))
-        _check(lib().eifmm_get_level(self._h, k, None, _np_ptr(X), _np_ptr(Y), _np_ptr(ia),
-                                     _np_ptr(ib), _np_ptr(B), _np_ptr(G)), "eifmm_get_level")
+        _check(fn(self._h, k, None, _np_ptr(X), _np_ptr(Y), _np_ptr(ia), _np_ptr(ib),
+                  _np_ptr(B), _np_ptr(G)), "eifmm_get_level")
         return dict(d=d, X=X, Y=Y, ia=ia, ib=ib, B=B, G=G)
 
     def compression(self, k):
@@ -286,6 +295,9 @@ class Plan:
         """which in ('W', 'What', 'g', 'l', 'lhat'): dense (8^k, d_k) array."""
         w = ["W", "What", "g", "l", "lhat"].index(which)
         d = self.level(k)["d"]
+        if w >= 2:  # g, l and lhat have the second EIM's size, if there is one
+            d2 = self.stats()["d2"][k]
+            d = d2 if d2 else d
         out = np.empty((1 << (3 * k), d))
         _check(lib().eifmm_export_expansion(self._h, w, k, rhs, _np_ptr(out)),
                "eifmm_export_expansion")

@@ -108,3 +108,30 @@ def test_host_compression_matches_oracle_svd(E, oracle_lib):
     assert np.abs(U @ U.T - Uf @ Uf.T).max() < 1e-9
     assert np.abs(U.T @ U - np.eye(r)).max() < 1e-12
     P.close()
+
+
+@pytest.mark.parametrize("kernel,param,two", [("advdiff", 1.0, False), ("laplace", 0.0, True)])
+def test_host_setup_second_eim_matches_oracle(E, oracle_lib, kernel, param, two):
+    """The second EIM of Sec. 3.1 (D_x = J_0, D_y = I_0), run for a kernel that is
+    not symmetric or on request: the same points and factors as the oracle's."""
+    P = E.Plan(kernel, param, [0, 0, 0], 1.0, 10, 3, 1e-5, host_only=True, two_eim=two)
+    O = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, 3, 1e-5, two_eim=two)
+    for k in (2, 3):
+        for second, ref in ((False, O.levels[k]), (True, O.levels2[k])):
+            a = P.level(k, second=second)
+            assert a["d"] == ref["d"]
+            np.testing.assert_array_equal(a["ia"], ref["ia"])
+            np.testing.assert_array_equal(a["ib"], ref["ib"])
+            np.testing.assert_array_equal(a["X"], ref["X"])
+            np.testing.assert_array_equal(a["Y"], ref["Y"])
+            assert np.abs(a["G"] - ref["G"]).max() <= 1e-12 * np.abs(ref["G"]).max()
+            assert np.abs(a["B"] - ref["B"]).max() <= 1e-12
+        assert P.stats()["d2"][k] == O.levels2[k]["d"]
+    P.close()
+
+
+def test_two_eim_refuses_compression(E):
+    with pytest.raises(E.EifmmError):
+        E.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-4)
+    with pytest.raises(E.EifmmError):
+        E.Plan("advdiff", -1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True)
