@@ -92,8 +92,12 @@ def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     ctol = args.compress_tol if args.compress_tol is not None else w.get("compress_tol", 1e-6)
+    ctol2 = getattr(args, "compress_tol2", None)
+    ctol2 = ctol2 if ctol2 is not None else w.get("compress_tol2", 0.0)
+    if not ctol:
+        ctol2 = 0.0
     plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, n, w["depth"], tau,
-                  precision=precision, compress_tol=ctol)
+                  precision=precision, compress_tol=ctol, compress_tol2=ctol2)
     setup_s = time.perf_counter() - t0
     xd = torch.from_numpy(x).to(dev)
     sd = torch.from_numpy(s).to(dev)
@@ -116,7 +120,7 @@ def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data
     plan.set_timing(False)
     fh = f.cpu().numpy()
     return dict(w=w, tau=tau, n=n, ms=ms, stats=st, setup_s=setup_s, f=fh, x=x, s=s, plan=plan,
-                compress_tol=ctol)
+                compress_tol=ctol, compress_tol2=ctol2)
 
 
 def run_clustered(args):
@@ -450,6 +454,8 @@ def main():
                     help="run only this leg and print its result (for profiling)")
     ap.add_argument("--batched-tau", type=float, default=1e-6)
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--compress-tol2", type=float, default=None,
+                    help="second M2L compression stage (Sec. 4.2); default: the workload's")
     ap.add_argument("--compress-tol", type=float, default=None,
                     help="M2L compression tolerance (Sec. 4.2); default: the workload's; 0 disables it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -492,8 +498,9 @@ def main():
         src = open(os.path.join(ROOT, "paper_1408_0210_amd", "csrc", "pass.hip")).read()
         # the gathered-GEMM kernel source (M2L runs in it): counters taken on another
         # version of this kernel do not describe it
-        a = src.index("// ------------------------------------------------------------------ gathered GEMM")
-        b = src.index("// ------------------------------------------------------------------ host side")
+        rule = "// ------------------------------------------------------------------ "
+        a = src.index(rule + "gathered GEMM")
+        b = src.index(rule, a + len(rule))  # the next section
         cur = hashlib.sha256(src[a:b].encode()).hexdigest()
         if (key in tr and tr[key].get("valid", False) and tr[key].get("gemm_source_sha256") == cur
                 and tr[key].get("compress_tol") == r["compress_tol"] and not args.tau

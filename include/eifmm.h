@@ -117,6 +117,10 @@ typedef struct {
   int64_t n_targets;    /* 0: the targets are the n sources; > 0: that many separate
                            target points (eifmm_set_points_targets), fixed per
                            plan; n + n_targets <= 2^30 - 1                       */
+  double compress_tol2; /* > 0 (with compress_tol > 0): the second stage of Sec. 4.2,
+                           each compressed matrix C^delta replaced by its rank-s
+                           truncation, s from the same two filters on its own
+                           singular values with this tolerance; 0 = off        */
 } eifmm_config;
 
 /* evaluation phases timed when timing is enabled (eifmm_set_timing) */
@@ -214,6 +218,10 @@ int eifmm_get_level2(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *
  * singular values of [K^delta_1 .. K^delta_316] in descending order, and U
  * (d_k x r row-major: the kept left singular vectors).  Outputs may be NULL. */
 int eifmm_get_compression(eifmm_plan plan, int32_t k, int32_t *r, double *sv, double *U);
+
+/* The ranks s of the second compression stage of level k, one per M2L offset
+ * (316, offset-id order; all 0 when the stage is off). */
+int eifmm_get_compression2(eifmm_plan plan, int32_t k, int32_t *s);
 
 /* Host copies of the current tree: perm[n] (input index of each Morton-ordered
  * point), leaf_start[8^depth + 1], keys[n] (leaf key of each sorted point).

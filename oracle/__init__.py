@@ -78,6 +78,7 @@ def lib():
         L.orc_plan_free.argtypes = [vp]
         L.orc_plan_free.restype = None
         L.orc_plan_set_compression.argtypes = [vp, i32, i32, vp]
+        L.orc_plan_set_compression2.argtypes = [vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -239,6 +240,23 @@ def compression_rank(s, eps):
     return max(r1, r2)
 
 
+def compression_factors(C, eps, ranks=None):
+    """Second stage of Sec. 4.2 on each compressed matrix C^delta (r x r): an SVD
+    (in place of the bivariate ACA and the two QR decompositions), the two filters
+    with eps (or the given ranks), and the split of the kept singular values
+    between the factors: C^delta ~ Ut Vt with Ut = P_s sqrt(S_s), Vt = sqrt(S_s) Q_s^T.
+    Returns the ranks s_o and the factor lists."""
+    s_list, Ut, Vt = [], [], []
+    for o, Co in enumerate(C):
+        P, sv, Qt = np.linalg.svd(Co)
+        so = compression_rank(sv, eps) if ranks is None else int(ranks[o])
+        h = np.sqrt(sv[:so])
+        Ut.append(np.ascontiguousarray(P[:, :so] * h[None, :]))
+        Vt.append(np.ascontiguousarray(h[:, None] * Qt[:so, :]))
+        s_list.append(so)
+    return np.array(s_list, dtype=np.int32), Ut, Vt
+
+
 def compression_basis(kernel, param, Y, level, eps, L=1.0, rank=None):
     """Sec. 4.2, first stage, with an exact SVD in place of the bivariate ACA:
     K_fat = [K^delta_1 ... K^delta_316] = U S V^T; keep the leading r columns of U
@@ -256,7 +274,7 @@ class Plan:
     (levels2); two_eim=True gives it to a symmetric kernel too."""
 
     def __init__(self, kernel, param, lo, L, depth, tau, dmax=1024, tol_mode=0, compress_tol=0.0,
-                 compress_rank=None, two_eim=False):
+                 compress_rank=None, two_eim=False, compress_tol2=0.0, compress_rank2=None):
         self.kernel, self.param = kernel, _params(param)
         self.lo = np.ascontiguousarray(lo, dtype=np.float64)
         self.L, self.depth, self.tau = float(L), int(depth), float(tau)
@@ -279,6 +297,20 @@ class Plan:
                 st = lib().orc_plan_set_compression(self._h, k, r, _p(U))
                 if st:
                     raise OracleError(st, "set_compression")
+                if compress_tol2 > 0:
+                    # second stage (Sec. 4.2): each C^delta = U^T K^delta U factored
+                    Kd = m2l_matrices(kernel, self.param, self.levels[k]["Y"], k, self.L)
+                    C = np.einsum("ia,oij,jb->oab", U, Kd, U, optimize=True)
+                    r2 = compress_rank2.get(k) if isinstance(compress_rank2, dict) else None
+                    r2 = None if r2 is None else np.asarray(r2)
+                    s2, Ut, Vt = compression_factors(C, compress_tol2, r2)
+                    self.levels[k].update(s2=s2)
+                    # Ut_o (r x s_o) and Vt_o (s_o x r), each row-major, offset after offset
+                    up = np.ascontiguousarray(np.concatenate([u.ravel() for u in Ut]))
+                    vp = np.ascontiguousarray(np.concatenate([v.ravel() for v in Vt]))
+                    st = lib().orc_plan_set_compression2(self._h, k, _p(s2), _p(up), _p(vp))
+                    if st:
+                        raise OracleError(st, "set_compression2")
 
     def _level(self, k, which=0):
         d = ctypes.c_int()

@@ -647,6 +647,11 @@ typedef struct {
   oeim a, b;
   int r;      /* M2L compression rank (0: uncompressed) */
   double *U;  /* d x r orthonormal basis of the M2L matrices (Sec. 4.2) */
+  /* second stage of Sec. 4.2 (NULL: off): C^delta ~ Ut_o Vt_o with Ut_o r x s_o and
+   * Vt_o s_o x r, packed offset by offset (row-major); s2[o] = s_o, p2[o] = the
+   * offset of factor o in both packs (in units of r doubles) */
+  int *s2, *p2;
+  double *Ut, *Vt;
 } olevel;
 
 typedef struct {
@@ -678,6 +683,7 @@ void orc_plan_free(orc_plan *P) {
     eim_free(&P->lv[k].a);
     eim_free(&P->lv[k].b);
     free(P->lv[k].U);
+    free(P->lv[k].s2); free(P->lv[k].p2); free(P->lv[k].Ut); free(P->lv[k].Vt);
   }
   free(P);
 }
@@ -697,6 +703,42 @@ int orc_plan_set_compression(orc_plan *P, int k, int r, const double *U) {
   if (!lv->U) return ORC_ENOMEM;
   memcpy(lv->U, U, sizeof(double) * (size_t)lv->a.d * (size_t)r);
   lv->r = r;
+  return ORC_OK;
+}
+
+/* Second stage of the M2L compression (Sec. 4.2): each compressed matrix C^delta
+ * (r x r, from orc_plan_set_compression) is replaced by the product of its two
+ * factors Ut_o (r x s[o]) and Vt_o (s[o] x r), given packed offset after offset
+ * (row-major); the M2L step then applies Vt_o, then Ut_o, per interaction.
+ * s = NULL removes it. */
+int orc_plan_set_compression2(orc_plan *P, int k, const int *s, const double *Ut,
+                              const double *Vt) {
+  if (!P || k < 2 || k > P->depth) return ORC_EINVAL;
+  olevel *lv = &P->lv[k];
+  free(lv->s2); free(lv->p2); free(lv->Ut); free(lv->Vt);
+  lv->s2 = lv->p2 = NULL;
+  lv->Ut = lv->Vt = NULL;
+  if (!s) return ORC_OK;
+  const int r = lv->r;
+  if (r <= 0) return ORC_EINVAL;
+  int tot = 0;
+  for (int o = 0; o < 316; o++) {
+    if (s[o] < 0 || s[o] > r || s[o] > 1024) return ORC_EINVAL;
+    tot += s[o];
+  }
+  lv->s2 = (int *)malloc(sizeof(int) * 316);
+  lv->p2 = (int *)malloc(sizeof(int) * 316);
+  lv->Ut = (double *)malloc(sizeof(double) * ((size_t)tot * r + 1));
+  lv->Vt = (double *)malloc(sizeof(double) * ((size_t)tot * r + 1));
+  if (!lv->s2 || !lv->p2 || !lv->Ut || !lv->Vt) return ORC_ENOMEM;
+  int off = 0;
+  for (int o = 0; o < 316; o++) {
+    lv->s2[o] = s[o];
+    lv->p2[o] = off;
+    off += s[o];
+  }
+  memcpy(lv->Ut, Ut, sizeof(double) * (size_t)tot * r);
+  memcpy(lv->Vt, Vt, sizeof(double) * (size_t)tot * r);
   return ORC_OK;
 }
 
@@ -1030,6 +1072,24 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           uint32_t kj = morton3((uint32_t)nJ[0], (uint32_t)nJ[1], (uint32_t)nJ[2], k);
           if (box_count(ls, depth, k, kj, NULL) == 0) continue;
           const double *wj = Wsrc + (size_t)kj * (size_t)dc;
+          if (r > 0 && lvl->s2) {
+            /* second stage: g' += Ut_o (Vt_o What'_J) */
+            const int so = lvl->s2[o];
+            const double *Uo = lvl->Ut + (size_t)lvl->p2[o] * r;
+            const double *Vo = lvl->Vt + (size_t)lvl->p2[o] * r;
+            double tv[1024];
+            for (int j = 0; j < so; j++) {
+              double t = 0.0;
+              for (int ll = 0; ll < r; ll++) t += Vo[(size_t)j * r + ll] * wj[ll];
+              tv[j] = t;
+            }
+            for (int mp = 0; mp < r; mp++) {
+              double t = 0.0;
+              for (int j = 0; j < so; j++) t += Uo[(size_t)mp * so + j] * tv[j];
+              gI[mp] += t;
+            }
+            continue;
+          }
           const double *A = Ad + (size_t)o * (size_t)dr * (size_t)dc;
           for (int mp = 0; mp < dr; mp++) {
             double s = 0.0;

@@ -73,6 +73,9 @@ int validate(const eifmm_config *c) {
   if (c->dmax < 0 || c->dmax > 4096) return EIFMM_EINVAL;
   if (!(c->compress_tol >= 0) || !std::isfinite(c->compress_tol)) return EIFMM_EINVAL;
   if (uses_two_eim(*c) && c->compress_tol > 0) return EIFMM_EINVAL;
+  if (!(c->compress_tol2 >= 0) || !std::isfinite(c->compress_tol2) ||
+      (c->compress_tol2 > 0 && !(c->compress_tol > 0)))
+    return EIFMM_EINVAL;
   return EIFMM_OK;
 }
 
@@ -95,6 +98,9 @@ void release(eifmm_plan h) {
   }
   if (P.job_dev) hipFree(P.job_dev);
   if (P.job_pin) hipHostFree(P.job_pin);
+  if (P.m2l2_dev) hipFree(P.m2l2_dev);
+  if (P.m2l2_pin) hipHostFree(P.m2l2_pin);
+  if (P.m2l2_ws) hipFree(P.m2l2_ws);
   delete h;
 }
 
@@ -172,6 +178,23 @@ int setup_tables(eifmm_plan h) {
     if (H.r > 0) {
       TRY(upload(&D.ufrag, H.ufrag.data(), H.ufrag.size(), tr));
       TRY(upload(&D.pfrag, H.pfrag.data(), H.pfrag.size(), tr));
+      if (!H.s2.empty()) {
+        int *sp = nullptr;
+        int64_t *vo = nullptr, *uo = nullptr;
+        double *vf = nullptr, *uf = nullptr;
+        TRY(upload(&sp, H.sp2.data(), H.sp2.size(), tr));
+        TRY(upload(&vo, H.voff2.data(), H.voff2.size(), tr));
+        TRY(upload(&uo, H.uoff2.data(), H.uoff2.size(), tr));
+        TRY(upload(&vf, H.vf2.data(), H.vf2.size(), tr));
+        TRY(upload(&uf, H.uf2.data(), H.uf2.size(), tr));
+        D.sp2 = sp;
+        D.voff2 = vo;
+        D.uoff2 = uo;
+        D.vf2 = vf;
+        D.uf2 = uf;
+        std::vector<double>().swap(H.vf2);
+        std::vector<double>().swap(H.uf2);
+      }
     }
   }
   return EIFMM_OK;
@@ -343,6 +366,11 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
     D.XL = TD.XL;
     D.ufrag = TD.ufrag;
     D.pfrag = TD.pfrag;
+    D.sp2 = TD.sp2;
+    D.voff2 = TD.voff2;
+    D.uoff2 = TD.uoff2;
+    D.vf2 = TD.vf2;
+    D.uf2 = TD.uf2;
   }
   P.dvec = T.dvec;
   P.code2id = T.code2id;
@@ -696,6 +724,15 @@ int eifmm_get_compression(eifmm_plan h, int32_t k, int32_t *r, double *sv, doubl
   if (r) *r = L.r;
   if (sv && !L.sv.empty()) std::memcpy(sv, L.sv.data(), sizeof(double) * L.sv.size());
   if (U && L.r > 0) std::memcpy(U, L.U.data(), sizeof(double) * L.U.size());
+  return EIFMM_OK;
+}
+
+int eifmm_get_compression2(eifmm_plan h, int32_t k, int32_t *s) {
+  if (!h || !s) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (k < 2 || k > P.depth) return EIFMM_EINVAL;
+  const LevelHost &L = P.lh[k];
+  for (int o = 0; o < kNumOffsets; ++o) s[o] = L.s2.empty() ? 0 : L.s2[o];
   return EIFMM_OK;
 }
 

@@ -1035,6 +1035,156 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ factored M2L
+// Second compression stage (Sec. 4.2): per offset o the r x r matrix C^delta is
+// the product Ut_o Vt_o of an r x s_o and an s_o x r factor, so a column's
+// contribution is Ut_o (Vt_o w), w the What' column of its source.  A work item is
+// (64-column tile, range of terms); each of the 4 waves owns 16 columns and all
+// rp rows of g'.  Per term a wave forms t = Vt_o w (s_o x 16) on FP64 MFMA, with
+// w loaded straight from memory in the gathered GEMM's k order, then
+// g' += Ut_o t, feeding t from its result registers as the B operand: result
+// register q of lane l holds row (l / 16) + 4 q, the k order of the Ut fragments.
+// Factor fragments are read from memory; the tiles of a class walk the same terms
+// in the same order, so they stay in L1 / L2.
+constexpr int kM2l2Sb = kMaxRank2 / 16;  // most 16-row blocks of t
+
+template <int RB>
+__global__ __launch_bounds__(256, 2) void k_m2l2(const M2l2Job *__restrict__ jobs, int njobs,
+                                                 int nitems, const int8_t *__restrict__ dvec,
+                                                 double *__restrict__ ws) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  constexpr int rp = 16 * RB;
+  const int item = blockIdx.x;
+  if (item >= nitems) return;
+  const int ji = find_last_le(njobs, item, [&](int m) { return (int64_t)jobs[m].item_start; });
+  const M2l2Job J = jobs[ji];
+  const int local = item - J.item_start;
+  const int tile = local / kM2l2Parts, part = local - tile * kM2l2Parts;
+  const int term0 = 189 * part / kM2l2Parts, term1 = 189 * (part + 1) / kM2l2Parts;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = tile * 64 + 16 * w + (lane & 15);
+  const bool cv = col < J.ntgt * J.nrhs;
+  const int tt = cv ? col / J.nrhs : 0;
+  const int rr = cv ? col - tt * J.nrhs : 0;
+  const int tsl = cv ? J.tgt[tt] : 0;
+  const uint32_t tkey = cv ? J.keys[tsl] : 0u;
+  const int side = 1 << J.level;
+  const int c0 = (int)morton_axis(tkey, 0), c1 = (int)morton_axis(tkey, 1),
+            c2 = (int)morton_axis(tkey, 2);
+  const int g4 = 4 * (lane >> 4);
+  v4 acc[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb] = v4{0, 0, 0, 0};
+  for (int term = term0; term < term1; ++term) {
+    const int o = J.terms[term];
+    const int sp = J.sp[o];
+    if (sp == 0) continue;
+    const int nsb = sp >> 4;
+    int sl = -1;
+    if (cv) {
+      const int m0 = c0 + dvec[3 * o], m1 = c1 + dvec[3 * o + 1], m2 = c2 + dvec[3 * o + 2];
+      if (m0 >= 0 && m1 >= 0 && m2 >= 0 && m0 < side && m1 < side && m2 < side)
+        sl = J.slot[morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2)];
+    }
+    const double *src = sl >= 0 ? J.B + ((int64_t)sl * J.nrhs + rr) * rp : nullptr;
+    const double *V = J.vf + J.voff[o] + lane;
+    const double *U = J.uf + J.uoff[o] + lane;
+    v4 t[kM2l2Sb];
+#pragma unroll
+    for (int sb = 0; sb < kM2l2Sb; ++sb) t[sb] = v4{0, 0, 0, 0};
+    // t = Vt_o w
+#pragma unroll
+    for (int kc = 0; kc < RB; ++kc) {
+      double b[4] = {0, 0, 0, 0};
+      if (src) {
+        const double2 *s2 = (const double2 *)(src + kc * 16 + g4);
+        const double2 x = s2[0], y = s2[1];
+        b[0] = x.x;
+        b[1] = x.y;
+        b[2] = y.x;
+        b[3] = y.y;
+      }
+#pragma unroll
+      for (int sb = 0; sb < kM2l2Sb; ++sb)
+        if (sb < nsb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            t[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                V[((int64_t)sb * (rp / 4) + kc * 4 + q) * 64], b[q], t[sb], 0, 0, 0);
+        }
+    }
+    // g' += Ut_o t
+#pragma unroll
+    for (int sb = 0; sb < kM2l2Sb; ++sb)
+      if (sb < nsb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                U[((int64_t)rb * (sp / 4) + sb * 4 + q) * 64], t[sb][q], acc[rb], 0, 0, 0);
+      }
+  }
+  // partial block of the item, column-major: ws[item][column][row]
+  double *out = ws + (size_t)item * rp * 64 + (size_t)(16 * w + (lane & 15)) * rp;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[16 * rb + (lane >> 4) + 4 * q] = acc[rb][q];
+}
+
+// g' of each tile: the kM2l2Parts partial blocks added in part order
+__global__ __launch_bounds__(256) void k_m2l2_sum(const M2l2Job *__restrict__ jobs, int njobs,
+                                                  int ntiles, const double *__restrict__ ws) {
+  const int tg = blockIdx.x;
+  if (tg >= ntiles) return;
+  const int ji = find_last_le(njobs, tg, [&](int m) { return (int64_t)jobs[m].tile_start; });
+  const M2l2Job J = jobs[ji];
+  const int tile = tg - J.tile_start, rp = J.rp;
+  const int ncols = J.ntgt * J.nrhs;
+  const size_t blk = (size_t)rp * 64;
+  const double *base = ws + (size_t)(J.item_start + tile * kM2l2Parts) * blk;
+  for (int e = threadIdx.x; e < rp * 64; e += 256) {
+    const int jc = e / rp, row = e - jc * rp;
+    const int col = tile * 64 + jc;
+    if (col >= ncols) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0; p < kM2l2Parts; ++p) v += base[p * blk + e];
+    const int tt = col / J.nrhs, r = col - tt * J.nrhs;
+    J.C[((int64_t)J.tgt[tt] * J.nrhs + r) * rp + row] = v;
+  }
+}
+
+template <int RB>
+void launch_m2l2_rb(const M2l2Job *jobs, const M2l2Launch &L, const int8_t *dvec, double *ws,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_m2l2<RB>, dim3(L.nitems), dim3(256), 0, s, jobs + L.first_job, L.njobs,
+                     L.nitems, dvec, ws + L.ws_off);
+  hipLaunchKernelGGL(k_m2l2_sum, dim3(L.ntiles), dim3(256), 0, s, jobs + L.first_job, L.njobs,
+                     L.ntiles, ws + L.ws_off);
+}
+
+void launch_m2l2(const M2l2Job *jobs, const M2l2Launch &L, const int8_t *dvec, double *ws,
+                 hipStream_t s) {
+  if (L.nitems == 0) return;
+  switch (L.rb) {
+    case 4: launch_m2l2_rb<4>(jobs, L, dvec, ws, s); break;
+    case 5: launch_m2l2_rb<5>(jobs, L, dvec, ws, s); break;
+    case 6: launch_m2l2_rb<6>(jobs, L, dvec, ws, s); break;
+    case 7: launch_m2l2_rb<7>(jobs, L, dvec, ws, s); break;
+    case 8: launch_m2l2_rb<8>(jobs, L, dvec, ws, s); break;
+    case 9: launch_m2l2_rb<9>(jobs, L, dvec, ws, s); break;
+    case 10: launch_m2l2_rb<10>(jobs, L, dvec, ws, s); break;
+    case 11: launch_m2l2_rb<11>(jobs, L, dvec, ws, s); break;
+    case 12: launch_m2l2_rb<12>(jobs, L, dvec, ws, s); break;
+    case 13: launch_m2l2_rb<13>(jobs, L, dvec, ws, s); break;
+    case 14: launch_m2l2_rb<14>(jobs, L, dvec, ws, s); break;
+    case 15: launch_m2l2_rb<15>(jobs, L, dvec, ws, s); break;
+    default: launch_m2l2_rb<16>(jobs, L, dvec, ws, s); break;
+  }
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -1157,6 +1307,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16);
     double flops = 0;
     for (int k = depth; k >= 2; --k) {
+      if (uses_m2l2(P, k)) continue;  // the factored M2L below
       const bool cz = P.lh[k].r > 0;
       // rows: g (the second EIM's size); columns: What
       const int dm = cz ? P.lh[k].rp : P.lh[k].dpB, dk = cz ? P.lh[k].rp : P.lh[k].dp;
@@ -1192,6 +1343,54 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
     jt.m2l_units = finish_units(h, jt.m2l_first);
+    // factored M2L levels: one job per child class, grouped by rp; algorithmic
+    // flops 2 (r s_o + s_o r) per interaction pair, with the mean s_o over the
+    // 316 offsets standing in for the offsets the pairs actually use
+    auto &mj = P.m2l2_host;
+    auto &ml = P.m2l2_launch;
+    mj.clear();
+    ml.clear();
+    int item = 0, tilec = 0;
+    for (int rb = kM2l2RbMin; rb <= kM2l2RbMax; ++rb) {
+      M2l2Launch L{(int)mj.size(), 0, item, 0, tilec, 0, rb};
+      for (int k = depth; k >= 2; --k) {
+        if (!uses_m2l2(P, k) || P.lh[k].rp != 16 * rb) continue;
+        double smean = 0;
+        for (int o = 0; o < kNumOffsets; ++o) smean += P.lh[k].s2[o];
+        smean /= kNumOffsets;
+        flops += 4.0 * P.lh[k].r * smean * (double)P.il_pairs[k] * nrhs;
+        for (int c = 0; c < 8; ++c) {
+          const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
+          if (nt == 0) continue;
+          M2l2Job J{};
+          J.tgt = P.ld[k].cls + P.cls_off[k][c];
+          J.keys = P.ld[k].act;
+          J.slot = P.ld[k].slot;
+          J.B = P.ld[k].Whp;
+          J.C = P.ld[k].gp;
+          J.terms = P.dlist + 189 * c;
+          J.vf = P.ld[k].vf2;
+          J.uf = P.ld[k].uf2;
+          J.voff = P.ld[k].voff2;
+          J.uoff = P.ld[k].uoff2;
+          J.sp = P.ld[k].sp2;
+          J.ntgt = (int)nt;
+          J.nrhs = nrhs;
+          J.level = k;
+          J.rp = P.lh[k].rp;
+          J.ntiles = (int)((nt * nrhs + 63) / 64);
+          J.tile_start = tilec - L.first_tile;
+          J.item_start = item - L.first_item;
+          tilec += J.ntiles;
+          item += J.ntiles * kM2l2Parts;
+          mj.push_back(J);
+        }
+      }
+      L.njobs = (int)mj.size() - L.first_job;
+      L.nitems = item - L.first_item;
+      L.ntiles = tilec - L.first_tile;
+      if (L.njobs) ml.push_back(L);
+    }
     P.m2l_flops = flops;
   }
   // g = U g' on compressed levels
@@ -1276,6 +1475,48 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     std::memcpy(P.job_pin, h.data(), sizeof(GemmJob) * h.size());
     if (hipMemcpyAsync(P.job_dev, P.job_pin, sizeof(GemmJob) * h.size(), hipMemcpyHostToDevice,
                        s) != hipSuccess ||
+        hipEventRecord(P.job_evt, s) != hipSuccess)
+      return EIFMM_EHIP;
+  }
+  if (!P.m2l2_host.empty()) {
+    // factored M2L jobs: the same pinned, asynchronous upload; the workspace
+    // holds one rp x 64 block per work item, launch after launch
+    const size_t nj = P.m2l2_host.size();
+    size_t need = 0;
+    for (auto &L : P.m2l2_launch) {
+      L.ws_off = need;
+      need += (size_t)L.nitems * 16 * L.rb * 64;
+    }
+    if (P.job_evt) hipEventSynchronize(P.job_evt);
+    if (nj > P.m2l2_cap) {
+      if (P.m2l2_dev) hipFree(P.m2l2_dev);
+      if (P.m2l2_pin) hipHostFree(P.m2l2_pin);
+      P.m2l2_dev = nullptr;
+      P.m2l2_pin = nullptr;
+      P.m2l2_cap = 0;
+      const size_t cap = nj + nj / 2 + 8;
+      if (hipMalloc(&P.m2l2_dev, sizeof(M2l2Job) * cap) != hipSuccess ||
+          hipHostMalloc((void **)&P.m2l2_pin, sizeof(M2l2Job) * cap) != hipSuccess) {
+        hipGetLastError();
+        return EIFMM_ENOMEM;
+      }
+      P.m2l2_cap = cap;
+    }
+    if (need > P.m2l2_ws_cap) {
+      if (P.m2l2_ws) hipFree(P.m2l2_ws);
+      P.m2l2_ws = nullptr;
+      P.m2l2_ws_cap = 0;
+      if (hipMalloc(&P.m2l2_ws, sizeof(double) * need) != hipSuccess) {
+        hipGetLastError();
+        return EIFMM_ENOMEM;
+      }
+      P.m2l2_ws_cap = need;
+    }
+    if (!P.job_evt && hipEventCreateWithFlags(&P.job_evt, hipEventDisableTiming) != hipSuccess)
+      return EIFMM_EHIP;
+    std::memcpy(P.m2l2_pin, P.m2l2_host.data(), sizeof(M2l2Job) * nj);
+    if (hipMemcpyAsync(P.m2l2_dev, P.m2l2_pin, sizeof(M2l2Job) * nj, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
         hipEventRecord(P.job_evt, s) != hipSuccess)
       return EIFMM_EHIP;
   }
@@ -1508,6 +1749,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     else
       launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles,
                                     P.jobs.m2l_units, s, P.jobs.m2l_rbt);
+    for (const M2l2Launch &L : P.m2l2_launch) launch_m2l2(P.m2l2_dev, L, P.dvec, P.m2l2_ws, s);
   }
   if (P.jobs.post_n) {
     Timer tm(P, s, EIFMM_PH_PROJ);

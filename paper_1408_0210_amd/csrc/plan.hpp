@@ -12,6 +12,8 @@ namespace eifmm {
 
 constexpr int kMaxLevels = EIFMM_MAX_DEPTH + 1;
 constexpr int kNumOffsets = 316;  // 7^3 - 3^3 distinct M2L offsets (Sec. 4.2)
+constexpr int kMaxRank2 = 96;     // largest second-stage rank the factored M2L takes
+constexpr int kM2l2RbMin = 4, kM2l2RbMax = 16;  // 16-row blocks of r the factored M2L takes
 
 // Host copy of one level's EIM data (Algorithm 1 and the factors of eq. (5)).
 struct LevelHost {
@@ -36,6 +38,13 @@ struct LevelHost {
   std::vector<double> U;        // d x r, row-major
   std::vector<double> ufrag;    // U          (dp x rp), fragment order: g = U g'
   std::vector<double> pfrag;    // U^T B^{-T} (rp x dp), fragment order: What' = U^T B^{-T} Gamma^{-1} W
+  // second compression stage (Sec. 4.2): rank s2[o] of each C^delta (empty: off),
+  // padded rank sp2[o] (multiple of 16, 0 when s2[o] = 0) and the factors in
+  // operand fragment order, offset after offset: vf2 = Vt (sp x rp, the k order of
+  // the gathered loads), uf2 = Ut (rp x sp, the k order of MFMA results)
+  std::vector<int> s2, sp2;
+  std::vector<int64_t> voff2, uoff2;
+  std::vector<double> vf2, uf2;
 };
 
 // Device copy of one level's tables.
@@ -55,6 +64,10 @@ struct LevelDev {
   float *Wh32 = nullptr;  // FP32 copy of What (mixed precision M2L)
   // compressed M2L
   double *ufrag = nullptr, *pfrag = nullptr;
+  // second compression stage (null: off)
+  const int *sp2 = nullptr;
+  const int64_t *voff2 = nullptr, *uoff2 = nullptr;
+  const double *vf2 = nullptr, *uf2 = nullptr;
   double *Whp = nullptr, *gp = nullptr;  // What' = U^T What and g' (rp per box and RHS)
   float *Whp32 = nullptr;
 };
@@ -171,6 +184,29 @@ struct BatchExec {
   std::vector<void *> track;       // device allocations of the tables above
 };
 
+// Factored M2L (second compression stage, Sec. 4.2) of one (level, child class):
+// g'[:, col] += Ut_o (Vt_o What'[:, src(col, o)]) over the class's offsets o.
+// Its 64-column tiles are split into kM2l2Parts term ranges (work items), each
+// summed into its own workspace block and added up in part order afterwards.
+constexpr int kM2l2Parts = 3;
+struct M2l2Job {
+  const int *tgt;             // target slots of the class
+  const uint32_t *keys;       // active keys of the level (by slot)
+  const int *slot;            // slot map of the level (by key)
+  const double *B;            // What' [slot * nrhs + r][rp]
+  double *C;                  // g'    [slot * nrhs + r][rp]
+  const int16_t *terms;       // the class's 189 offset ids
+  const double *vf, *uf;      // factor fragments of the level
+  const int64_t *voff, *uoff; // first element of each offset's fragments
+  const int *sp;              // padded rank of each offset (multiple of 16, 0 = none)
+  int ntgt, nrhs, level, rp;
+  int item_start, tile_start, ntiles;
+};
+struct M2l2Launch {           // jobs sharing rp (one kernel instance)
+  int first_job, njobs, first_item, nitems, first_tile, ntiles, rb;
+  size_t ws_off;              // first workspace element of its items
+};
+
 // Index ranges of the gathered-GEMM jobs of one (points, nrhs) pair.
 struct JobTables {
   int nrhs = -1;
@@ -245,6 +281,13 @@ struct Plan {
   // gathered-GEMM job tables (rebuilt when the points or nrhs change)
   JobTables jobs;
   GemmJob *job_dev = nullptr;
+  // factored M2L (second compression stage), FP64 passes
+  std::vector<M2l2Job> m2l2_host;
+  std::vector<M2l2Launch> m2l2_launch;
+  M2l2Job *m2l2_dev = nullptr, *m2l2_pin = nullptr;
+  size_t m2l2_cap = 0;
+  double *m2l2_ws = nullptr;       // partial sums, one rp x 64 block per work item
+  size_t m2l2_ws_cap = 0;          // in doubles
   size_t job_cap = 0;             // jobs job_dev and job_pin hold
   GemmJob *job_pin = nullptr;     // pinned staging copy of the job table
   hipEvent_t job_evt = nullptr;   // recorded after the last copy from job_pin
@@ -291,6 +334,10 @@ int materialize_expansion(Plan &P, int which, int k);
 // On a compressed level the solve for What stops at z = Gamma^{-1} W: the
 // projection applies U^T B^{-T} (pass.hip)
 inline bool solves_what(const Plan &P, int k) { return P.lh[k].r == 0; }
+// the FP64 pass applies the second compression stage as two factor products
+inline bool uses_m2l2(const Plan &P, int k) {
+  return P.cfg.precision == EIFMM_PREC_FP64 && P.lh[k].r > 0 && !P.lh[k].s2.empty();
+}
 // batches (pass.hip): m2l_rbt <= 0 picks the M2L tile height from the operators
 int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans, int m2l_rbt, int sk_groups,
                   double *sk_ws);

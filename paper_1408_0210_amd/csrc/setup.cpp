@@ -333,6 +333,19 @@ void to_fragments(const double *A, int rows, int cols, int rpad, int cpad, doubl
       }
 }
 
+// The same with the k order of an MFMA result used as the B operand: within each
+// 16-column chunk, k-step q of lane l takes column (l / 16) + 4 q.
+void to_fragments_nat(const double *A, int rows, int cols, int rpad, int cpad, double *out) {
+  const int nrb = rpad / 16, nks = cpad / 4;
+  for (int rb = 0; rb < nrb; ++rb)
+    for (int ks = 0; ks < nks; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        int r = 16 * rb + (l & 15), c = 16 * (ks >> 2) + (l >> 4) + 4 * (ks & 3);
+        out[((size_t)rb * nks + ks) * 64 + l] =
+            (r < rows && c < cols) ? A[(size_t)r * cols + c] : 0.0;
+      }
+}
+
 // Operand table of a blocked triangular solve with 16 x 16 tiles, for the MFMA
 // solver: T (d x d, or its transpose) is padded to dp with the identity; tile
 // (bi, bj) of the triangle holds -T[bi][bj] off the diagonal and the inverse of
@@ -381,6 +394,8 @@ void trsm_table(const std::vector<double> &T, int d, int dp, bool transpose, boo
     }
 }
 
+void jacobi_left(std::vector<double> &G, int d, std::vector<double> &U, std::vector<double> &s);
+
 // Singular values (descending) and left singular vectors (U, d x d row-major,
 // column p = vector p) of the d x m matrix whose rows are given in A (row-major,
 // m >= d; A is overwritten).  Householder QR of A^T = Q R, then a one-sided
@@ -411,7 +426,13 @@ void svd_rows(std::vector<double> &A, int d, int64_t m, std::vector<double> &U,
     for (int c = j + 1; c < d; ++c) R[(size_t)j * d + c] = A[(size_t)c * m + j];
   }
   // columns of G = R^T are the rows of R
-  std::vector<double> G(R);
+  jacobi_left(R, d, U, s);
+}
+
+// One-sided Jacobi on the d columns of a d x d matrix M, given as the rows of G
+// (G[p][i] = M[i][p]; overwritten): M V = U diag(s), s descending, U d x d
+// row-major (column p = vector p).  Serial.
+void jacobi_left(std::vector<double> &G, int d, std::vector<double> &U, std::vector<double> &s) {
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rotated = false;
     for (int p = 0; p < d - 1; ++p)
@@ -474,6 +495,110 @@ int filter_rank(const std::vector<double> &s, double eps) {
     }
   }
   return std::max(r1, r2);
+}
+
+// Q R of the k columns of the r x k matrix A (row-major): modified Gram-Schmidt,
+// each column orthogonalised twice; Q r x k row-major, R k x k upper triangular.
+void qr_mgs(const std::vector<double> &A, int r, int k, std::vector<double> &Q,
+            std::vector<double> &R) {
+  Q = A;
+  R.assign((size_t)k * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < j; ++i) {
+        double dot = 0.0;
+        for (int a = 0; a < r; ++a) dot += Q[(size_t)a * k + i] * Q[(size_t)a * k + j];
+        R[(size_t)i * k + j] += dot;
+        for (int a = 0; a < r; ++a) Q[(size_t)a * k + j] -= dot * Q[(size_t)a * k + i];
+      }
+    double n2 = 0.0;
+    for (int a = 0; a < r; ++a) n2 += Q[(size_t)a * k + j] * Q[(size_t)a * k + j];
+    const double nr = std::sqrt(n2);
+    R[(size_t)j * k + j] = nr;
+    for (int a = 0; a < r; ++a) Q[(size_t)a * k + j] = nr > 0 ? Q[(size_t)a * k + j] / nr : 0.0;
+  }
+}
+
+// Second compression stage of Sec. 4.2 for one compressed M2L matrix C (r x r,
+// row-major): cross approximation with complete pivoting C ~ U V (stopping at
+// 1e-13 of max |C|, so it only fixes the numerical rank), QR of U and of V^T, an
+// SVD of R_U R_V^T, the two filters with eps, and the kept singular values split
+// between the factors: C ~ Ut Vt, Ut = Q_U P_s sqrt(S_s) (r x s),
+// Vt = sqrt(S_s) (Q_V Q_s)^T (s x r).  Returns s.
+int stage2_factors(const std::vector<double> &C, int r, double eps, std::vector<double> &Ut,
+                   std::vector<double> &Vt) {
+  std::vector<double> Rm(C), U, V;
+  double cmax = 0.0;
+  for (double x : C) cmax = std::max(cmax, std::fabs(x));
+  int k = 0;
+  while (k < r && cmax > 0) {
+    int64_t best = 0;
+    double bv = -1.0;
+    for (int64_t e = 0; e < (int64_t)r * r; ++e)
+      if (std::fabs(Rm[e]) > bv) {
+        bv = std::fabs(Rm[e]);
+        best = e;
+      }
+    if (bv <= 1e-13 * cmax) break;
+    const int p = (int)(best / r), q = (int)(best % r);
+    const double piv = Rm[best];
+    std::vector<double> u(r), v(r);
+    for (int a = 0; a < r; ++a) u[a] = Rm[(size_t)a * r + q];
+    for (int b = 0; b < r; ++b) v[b] = Rm[(size_t)p * r + b] / piv;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) Rm[(size_t)a * r + b] -= u[a] * v[b];
+    U.insert(U.end(), u.begin(), u.end());  // column k of U, stored k-major
+    V.insert(V.end(), v.begin(), v.end());  // row k of V
+    ++k;
+  }
+  if (k == 0) {
+    Ut.clear();
+    Vt.clear();
+    return 0;
+  }
+  std::vector<double> Ua((size_t)r * k), Va((size_t)r * k), Qu, Ru, Qv, Rv;
+  for (int j = 0; j < k; ++j)
+    for (int a = 0; a < r; ++a) {
+      Ua[(size_t)a * k + j] = U[(size_t)j * r + a];
+      Va[(size_t)a * k + j] = V[(size_t)j * r + a];
+    }
+  qr_mgs(Ua, r, k, Qu, Ru);
+  qr_mgs(Va, r, k, Qv, Rv);
+  // M = R_U R_V^T (k x k); its SVD M = P S Qs^T
+  std::vector<double> M((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double t = 0.0;
+      for (int l = 0; l < k; ++l) t += Ru[(size_t)i * k + l] * Rv[(size_t)j * k + l];
+      M[(size_t)i * k + j] = t;
+    }
+  std::vector<double> G((size_t)k * k), P, sv;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) G[(size_t)j * k + i] = M[(size_t)i * k + j];
+  jacobi_left(G, k, P, sv);
+  const int so = sv[0] > 0 ? filter_rank(sv, eps) : 0;
+  Ut.assign((size_t)r * so, 0.0);
+  Vt.assign((size_t)so * r, 0.0);
+  for (int a = 0; a < so; ++a) {
+    const double h = std::sqrt(sv[a]);
+    // Qs column a = M^T P_a / s_a
+    std::vector<double> qs(k, 0.0);
+    for (int j = 0; j < k; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < k; ++i) t += M[(size_t)i * k + j] * P[(size_t)i * k + a];
+      qs[j] = t / sv[a];
+    }
+    for (int i = 0; i < r; ++i) {
+      double tu = 0.0, tv = 0.0;
+      for (int l = 0; l < k; ++l) {
+        tu += Qu[(size_t)i * k + l] * P[(size_t)l * k + a];
+        tv += Qv[(size_t)i * k + l] * qs[l];
+      }
+      Ut[(size_t)i * so + a] = tu * h;
+      Vt[(size_t)a * r + i] = tv * h;
+    }
+  }
+  return so;
 }
 
 }  // namespace
@@ -596,6 +721,9 @@ int build_tables(Plan &P) {
     // rows (g) and columns (What) of the transferred expansions
     const int dmr = r > 0 ? rp : dpB, dmc = r > 0 ? rp : dp;
     lv.kfrag.assign((size_t)kNumOffsets * dmr * dmc, 0.0);
+    if (r > 0 && c.compress_tol2 > 0) lv.s2.assign(kNumOffsets, 0);
+    std::vector<std::vector<double>> fUt(lv.s2.empty() ? 0 : kNumOffsets),
+        fVt(lv.s2.empty() ? 0 : kNumOffsets);
     parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
       std::vector<double> A((size_t)dB * d), KU, C;
       for (int64_t o = o0; o < o1; ++o) {
@@ -623,9 +751,49 @@ int build_tables(Plan &P) {
             for (int b = 0; b < r; ++b) ca[b] += u * ki[b];
           }
         }
+        if (c.compress_tol2 > 0) {
+          // second stage (Sec. 4.2): C^delta ~ Ut Vt, applied as two products by
+          // the FP64 pass; the dense product serves the FP32 pass
+          std::vector<double> &Ut = fUt[o], &Vt = fVt[o];
+          const int so = stage2_factors(C, r, c.compress_tol2, Ut, Vt);
+          lv.s2[o] = so;
+          for (int i = 0; i < r; ++i)
+            for (int b = 0; b < r; ++b) {
+              double t = 0.0;
+              for (int a2 = 0; a2 < so; ++a2) t += Ut[(size_t)i * so + a2] * Vt[(size_t)a2 * r + b];
+              C[(size_t)i * r + b] = t;
+            }
+        }
         to_fragments(C.data(), r, r, rp, rp, &lv.kfrag[(size_t)o * rp * rp]);
       }
     });
+    if (!lv.s2.empty()) {
+      // pack the factors in fragment order; a level whose ranks exceed the
+      // kernel's bound (kMaxRank2) keeps only the dense product
+      int smax = 0;
+      for (int o = 0; o < kNumOffsets; ++o) smax = std::max(smax, lv.s2[o]);
+      if (smax > kMaxRank2 || rp / 16 < kM2l2RbMin || rp / 16 > kM2l2RbMax) {
+        lv.s2.clear();
+      } else {
+        lv.sp2.assign(kNumOffsets, 0);
+        lv.voff2.assign(kNumOffsets, 0);
+        lv.uoff2.assign(kNumOffsets, 0);
+        int64_t tot = 0;
+        for (int o = 0; o < kNumOffsets; ++o) {
+          lv.sp2[o] = ((lv.s2[o] + 15) / 16) * 16;
+          lv.voff2[o] = lv.uoff2[o] = tot;
+          tot += (int64_t)lv.sp2[o] * rp;
+        }
+        lv.vf2.assign((size_t)std::max<int64_t>(tot, 1), 0.0);
+        lv.uf2.assign((size_t)std::max<int64_t>(tot, 1), 0.0);
+        for (int o = 0; o < kNumOffsets; ++o) {
+          const int so = lv.s2[o], sp = lv.sp2[o];
+          if (sp == 0) continue;
+          to_fragments(fVt[o].data(), so, r, sp, rp, &lv.vf2[lv.voff2[o]]);
+          to_fragments_nat(fUt[o].data(), r, so, rp, sp, &lv.uf2[lv.uoff2[o]]);
+        }
+      }
+    }
     trsm_table(lv.G, d, dp, false, true, lv.tri[0]);   // Gamma    (forward, Delta)
     trsm_table(lv.B, d, dp, true, false, lv.tri[1]);   // B^T      (backward, Delta)
     if (P.two_eim) {  // lhat = Delta^{J_0,I_0} l = M_B^{-1} l: the second EIM's factors

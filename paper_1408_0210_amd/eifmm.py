@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
                 ("max_rhs", ctypes.c_int32), ("eim_tol", ctypes.c_double),
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("compress_tol", ctypes.c_double), ("n_targets", ctypes.c_int64)]
+                ("compress_tol", ctypes.c_double), ("n_targets", ctypes.c_int64),
+                ("compress_tol2", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -86,6 +87,7 @@ def lib():
         L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.eifmm_get_level.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
         L.eifmm_get_level2.argtypes = L.eifmm_get_level.argtypes
+        L.eifmm_get_compression2.argtypes = [vp, i32, vp]
         L.eifmm_get_compression.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp]
         L.eifmm_export_tree.argtypes = [vp, vp, vp, vp]
         L.eifmm_export_lists.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp]
@@ -104,7 +106,7 @@ def lib():
         for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_set_points_targets",
                   "eifmm_evaluate", "eifmm_set_timing",
                   "eifmm_get_stats", "eifmm_get_level", "eifmm_get_level2",
-                  "eifmm_get_compression",
+                  "eifmm_get_compression", "eifmm_get_compression2",
                   "eifmm_export_tree", "eifmm_export_lists",
                   "eifmm_export_expansion", "eifmm_plan_destroy", "eifmm_batch_create",
                   "eifmm_batch_set_points", "eifmm_batch_evaluate",
@@ -139,7 +141,7 @@ def _stream():
 
 def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
                 dmax=0, host_only=False, compress_tol=0.0, n_targets=0, host_setup=False,
-                two_eim=False):
+                two_eim=False, compress_tol2=0.0):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.kernel = KERNELS[kernel]
@@ -158,6 +160,7 @@ def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64"
                | (FLAG_TWO_EIM if two_eim else 0))
     c.compress_tol = float(compress_tol)
     c.n_targets = int(n_targets)
+    c.compress_tol2 = float(compress_tol2)
     return c
 
 
@@ -182,9 +185,9 @@ class Plan:
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
                  tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0,
-                 host_setup=False, two_eim=False):
+                 host_setup=False, two_eim=False, compress_tol2=0.0):
         c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
-                        host_only, compress_tol, n_targets, host_setup, two_eim)
+                        host_only, compress_tol, n_targets, host_setup, two_eim, compress_tol2)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.n_targets = int(n_targets)
@@ -252,6 +255,12 @@ class Plan:
         _check(fn(self._h, k, None, _np_ptr(X), _np_ptr(Y), _np_ptr(ia), _np_ptr(ib),
                   _np_ptr(B), _np_ptr(G)), "eifmm_get_level")
         return dict(d=d, X=X, Y=Y, ia=ia, ib=ib, B=B, G=G)
+
+    def compression2(self, k):
+        """Second-stage ranks of level k (316, offset-id order; zeros when off)."""
+        out = np.zeros(316, dtype=np.int32)
+        _check(lib().eifmm_get_compression2(self._h, k, _np_ptr(out)), "eifmm_get_compression2")
+        return out
 
     def compression(self, k):
         """(r, singular values, U) of level k's M2L compression."""

@@ -315,3 +315,48 @@ def test_compressed_finite_rank_exact(E, torch_dev, oracle_lib):
     f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
     assert _rel(f, oracle_lib.direct("sqdist", 0, x, x, s)) < 1e-11
     plan.close()
+
+
+def test_compressed_stage2_vs_oracle(E, torch_dev, oracle_lib, c1_inputs, c1_direct):
+    """Second compression stage (Sec. 4.2): each C^delta replaced by the product of
+    its two factors; the FP64 pass applies the factors (two MFMA products per
+    interaction), the FP32 pass their dense product.  Against the oracle's pass
+    with the same ranks (its factors from an exact SVD)."""
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  compress_tol=1e-6, compress_tol2=1e-6)
+    ranks = plan.stats()["rank"]
+    s2 = {k: plan.compression2(k) for k in ranks}
+    assert all(0 < v.max() < ranks[k] for k, v in s2.items())
+    plan.set_points(torch.from_numpy(x).to(dev))
+    f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
+    O = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
+                        compress_tol=1e-6, compress_rank=ranks, compress_tol2=1e-6,
+                        compress_rank2=s2)
+    assert _rel(f, O.evaluate(x, s)) < 1e-10
+    assert _rel(f, c1_direct) < 1e-6
+    plan.close()
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  compress_tol=1e-6, compress_tol2=1e-6, precision="mixed", max_rhs=2)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    S = np.stack([s, -s])
+    F = plan.evaluate(torch.from_numpy(S).to(dev)).cpu().numpy()
+    assert _rel(F[0], f) < 1e-6
+    np.testing.assert_array_equal(F[1], -F[0])
+    plan.close()
+
+
+def test_compressed_stage2_multi_rhs(E, torch_dev, c1_inputs):
+    """nrhs = 3 (ragged 64-column tiles) equals three single passes, FP64."""
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["n"], w["depth"], w["tau"],
+                  compress_tol=1e-6, compress_tol2=1e-6, max_rhs=3)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    S = np.stack([s, W.potentials(w["n"], 95), W.potentials(w["n"], 96)])
+    F = plan.evaluate(torch.from_numpy(S).to(dev)).cpu().numpy()
+    for r in range(3):
+        fr = plan.evaluate(torch.from_numpy(S[r]).to(dev)).cpu().numpy()
+        assert _rel(F[r], fr) < 1e-13
+    plan.close()
