@@ -82,8 +82,7 @@ extern "C" {
 #define EIFMM_FLAG_TWO_EIM 4    /* use the general form of Sec. 3.1 (a second EIM
                                    on D_x = J_0, D_y = I_0 per level) for a
                                    symmetric kernel too; kernels that are not
-                                   symmetric always use it.  Not with M2L
-                                   compression or in batches.                   */
+                                   symmetric always use it.  Not in batches.    */
 #define EIFMM_FLAG_HOST_SETUP 2 /* run the Algorithm 1 iterations on the host even
                                    for a device plan (by default a device plan
                                    runs them on the GPU; both select the same
@@ -113,7 +112,9 @@ typedef struct {
                            SVD of [K^delta_1 .. K^delta_316] per level; the rank r
                            is the larger of the two filters (s_j/s_0 > eps, and the
                            prefix holding 1 - eps of the sum of singular values),
-                           rounded up to the MFMA tile granularity; 0 = off      */
+                           rounded up to the MFMA tile granularity; 0 = off.
+                           With two EIMs the stacked matrices give the basis of
+                           the columns and r is the larger of the two ranks     */
   int64_t n_targets;    /* 0: the targets are the n sources; > 0: that many separate
                            target points (eifmm_set_points_targets), fixed per
                            plan; n + n_targets <= 2^30 - 1                       */
@@ -214,9 +215,12 @@ int eifmm_get_level(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y
 int eifmm_get_level2(eifmm_plan plan, int32_t k, int32_t *d, double *X, double *Y, int64_t *ia,
                      int64_t *ib, double *B, double *Gamma);
 
-/* Host copies of level k's M2L compression (Sec. 4.2): *r (0 when off), the d_k
- * singular values of [K^delta_1 .. K^delta_316] in descending order, and U
- * (d_k x r row-major: the kept left singular vectors).  Outputs may be NULL. */
+/* Host copies of level k's M2L compression (Sec. 4.2): *r (0 when off), the
+ * singular values of K_fat = [K^delta_1 .. K^delta_316] in descending order, and
+ * U (row-major: the kept left singular vectors, r columns).  K^delta has one row
+ * per M2L row point: d_k of them with one EIM per level, the second EIM's size
+ * with two (then the columns are projected on the right singular vectors of the
+ * stacked matrices, which stay internal).  Outputs may be NULL. */
 int eifmm_get_compression(eifmm_plan plan, int32_t k, int32_t *r, double *sv, double *U);
 
 /* The ranks s of the second compression stage of level k, one per M2L offset

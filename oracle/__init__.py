@@ -77,7 +77,7 @@ def lib():
         L.orc_plan_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.orc_plan_free.argtypes = [vp]
         L.orc_plan_free.restype = None
-        L.orc_plan_set_compression.argtypes = [vp, i32, i32, vp]
+        L.orc_plan_set_compression.argtypes = [vp, i32, i32, vp, vp]
         L.orc_plan_set_compression2.argtypes = [vp, i32, vp, vp, vp]
         _lib = L
     return _lib
@@ -221,13 +221,15 @@ def apply_delta(B, G, v, transpose=False):
     return w
 
 
-def m2l_matrices(kernel, param, Y, level, L=1.0):
+def m2l_matrices(kernel, param, Y, level, L=1.0, X=None):
     """The 316 translation-invariant M2L matrices of a level (Sec. 4.2):
-    K^delta[m', l] = K(Y_m', Y_l + 2 l_k delta), in offset-id order."""
+    K^delta[m', l] = K(X_m', Y_l + 2 l_k delta), in offset-id order; the rows X are
+    the second EIM's points when there is one, else X = Y."""
+    X = Y if X is None else X
     h = L * 2.0 ** (-level)
     dt = offset_table().astype(np.float64)
-    z = Y[None, :, None, :] - (Y[None, None, :, :] + h * dt[:, None, None, :])
-    return kernel_eval(kernel, param, z.reshape(-1, 3)).reshape(316, len(Y), len(Y))
+    z = X[None, :, None, :] - (Y[None, None, :, :] + h * dt[:, None, None, :])
+    return kernel_eval(kernel, param, z.reshape(-1, 3)).reshape(316, len(X), len(Y))
 
 
 def compression_rank(s, eps):
@@ -268,6 +270,18 @@ def compression_basis(kernel, param, Y, level, eps, L=1.0, rank=None):
     return np.ascontiguousarray(U[:, :r]), s, r
 
 
+def compression_bases(kernel, param, X, Y, level, eps, L=1.0, rank=None):
+    """Sec. 4.2, first stage, for M2L matrices that are not symmetric (two EIMs):
+    U from the SVD of K_fat = [K^delta_1 ... K^delta_316] (its column space, rows X)
+    and V from the SVD of K_thin, the matrices stacked (their common row space).
+    r is the larger of the two filtered ranks (or `rank`)."""
+    Kd = m2l_matrices(kernel, param, Y, level, L, X=X)
+    U, su, _ = np.linalg.svd(np.concatenate(list(Kd), axis=1), full_matrices=False)
+    _, sv, Vt = np.linalg.svd(np.concatenate(list(Kd), axis=0), full_matrices=False)
+    r = max(compression_rank(su, eps), compression_rank(sv, eps)) if rank is None else int(rank)
+    return np.ascontiguousarray(U[:, :r]), np.ascontiguousarray(Vt[:r].T), su, sv, r
+
+
 class Plan:
     """Per-level EIM data (levels 2..depth) and the Algorithm-3 evaluation.
     A kernel that is not symmetric gets the second EIM of Sec. 3.1 on every level
@@ -291,16 +305,25 @@ class Plan:
         if compress_tol > 0:
             for k in range(2, self.depth + 1):
                 rk = compress_rank.get(k) if isinstance(compress_rank, dict) else compress_rank
-                U, sv, r = compression_basis(kernel, self.param, self.levels[k]["Y"], k,
-                                             compress_tol, self.L, rank=rk)
-                self.levels[k].update(U=U, sv=sv, r=r)
-                st = lib().orc_plan_set_compression(self._h, k, r, _p(U))
+                Y = self.levels[k]["Y"]
+                X = self.levels2[k]["X"] if self.two else None
+                if self.two:
+                    U, V, sv, sv2, r = compression_bases(kernel, self.param, X, Y, k,
+                                                         compress_tol, self.L, rank=rk)
+                    self.levels[k].update(U=U, V=V, sv=sv, sv2=sv2, r=r)
+                else:
+                    U, sv, r = compression_basis(kernel, self.param, Y, k, compress_tol, self.L,
+                                                 rank=rk)
+                    V = U
+                    self.levels[k].update(U=U, sv=sv, r=r)
+                st = lib().orc_plan_set_compression(self._h, k, r, _p(U),
+                                                    _p(V) if self.two else None)
                 if st:
                     raise OracleError(st, "set_compression")
                 if compress_tol2 > 0:
-                    # second stage (Sec. 4.2): each C^delta = U^T K^delta U factored
-                    Kd = m2l_matrices(kernel, self.param, self.levels[k]["Y"], k, self.L)
-                    C = np.einsum("ia,oij,jb->oab", U, Kd, U, optimize=True)
+                    # second stage (Sec. 4.2): each C^delta = U^T K^delta V factored
+                    Kd = m2l_matrices(kernel, self.param, Y, k, self.L, X=X)
+                    C = np.einsum("ia,oij,jb->oab", U, Kd, V, optimize=True)
                     r2 = compress_rank2.get(k) if isinstance(compress_rank2, dict) else None
                     r2 = None if r2 is None else np.asarray(r2)
                     s2, Ut, Vt = compression_factors(C, compress_tol2, r2)

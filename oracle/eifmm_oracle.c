@@ -646,7 +646,8 @@ typedef struct {
 typedef struct {
   oeim a, b;
   int r;      /* M2L compression rank (0: uncompressed) */
-  double *U;  /* d x r orthonormal basis of the M2L matrices (Sec. 4.2) */
+  double *U;  /* d_B x r orthonormal basis of the column space of the M2L matrices (Sec. 4.2) */
+  double *V;  /* d x r basis of their row space (two EIMs); NULL: V = U (symmetric kernel) */
   /* second stage of Sec. 4.2 (NULL: off): C^delta ~ Ut_o Vt_o with Ut_o r x s_o and
    * Vt_o s_o x r, packed offset by offset (row-major); s2[o] = s_o, p2[o] = the
    * offset of factor o in both packs (in units of r doubles) */
@@ -682,26 +683,37 @@ void orc_plan_free(orc_plan *P) {
   for (int k = 0; k < 16; k++) {
     eim_free(&P->lv[k].a);
     eim_free(&P->lv[k].b);
-    free(P->lv[k].U);
+    free(P->lv[k].U); free(P->lv[k].V);
     free(P->lv[k].s2); free(P->lv[k].p2); free(P->lv[k].Ut); free(P->lv[k].Vt);
   }
   free(P);
 }
 
-/* M2L compression of level k (Sec. 4.2, first stage): U (d x r, row-major) spans
- * the dominant left singular vectors of [K^delta_1 ... K^delta_316]; for a
- * symmetric kernel the compressed matrices are C^delta = U^T K^delta U and the
- * M2L step becomes g = U sum_J C^delta (U^T What^J).  r = 0 removes it. */
-int orc_plan_set_compression(orc_plan *P, int k, int r, const double *U) {
-  if (!P || P->two || k < 2 || k > P->depth || r < 0 || r > P->lv[k].a.d) return ORC_EINVAL;
+/* M2L compression of level k (Sec. 4.2, first stage): U (d_B x r, row-major)
+ * spans the dominant left singular vectors of K_fat = [K^delta_1 ... K^delta_316],
+ * V (d x r) the dominant right singular vectors of K_thin, the 316 matrices
+ * stacked.  The compressed matrices are C^delta = U^T K^delta V and the M2L step
+ * becomes g = U sum_J C^delta (V^T What^J).  For a symmetric kernel
+ * (K^{-delta} = (K^delta)^T, one EIM) both spaces are the same and V = NULL stands
+ * for V = U; with two EIMs V is required.  r = 0 removes it. */
+int orc_plan_set_compression(orc_plan *P, int k, int r, const double *U, const double *V) {
+  if (!P || k < 2 || k > P->depth || r < 0) return ORC_EINVAL;
   olevel *lv = &P->lv[k];
+  const int d = lv->a.d, db = P->two ? lv->b.d : lv->a.d;
+  if (r > d || r > db || (P->two && r > 0 && !V)) return ORC_EINVAL;
   free(lv->U);
-  lv->U = NULL;
+  free(lv->V);
+  lv->U = lv->V = NULL;
   lv->r = 0;
   if (r == 0) return ORC_OK;
-  lv->U = (double *)malloc(sizeof(double) * (size_t)lv->a.d * (size_t)r);
+  lv->U = (double *)malloc(sizeof(double) * (size_t)db * (size_t)r);
   if (!lv->U) return ORC_ENOMEM;
-  memcpy(lv->U, U, sizeof(double) * (size_t)lv->a.d * (size_t)r);
+  memcpy(lv->U, U, sizeof(double) * (size_t)db * (size_t)r);
+  if (V) {
+    lv->V = (double *)malloc(sizeof(double) * (size_t)d * (size_t)r);
+    if (!lv->V) return ORC_ENOMEM;
+    memcpy(lv->V, V, sizeof(double) * (size_t)d * (size_t)r);
+  }
   lv->r = r;
   return ORC_OK;
 }
@@ -1001,9 +1013,9 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
                 K2(K, xb + 3 * mp, yl);
           }
       }
-      /* compressed form (one EIM only, so db = d): C^delta = U^T K^delta U (r x r),
-       * What' = U^T What */
+      /* compressed form: C^delta = U^T K^delta V (r x r), What' = V^T What */
       const int r = lvl->r;
+      const double *Vr = lvl->V ? lvl->V : lvl->U;
       const int dr = r > 0 ? r : db, dc = r > 0 ? r : d; /* rows (g) and columns (What) */
       const double *Ad = Kd;
       double *Cd = NULL, *Whp = NULL, *gp = NULL;
@@ -1020,18 +1032,18 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
 #pragma omp parallel for schedule(dynamic, 4)
 #endif
         for (int o = 0; o < 316; o++) {
-          const double *A = Kd + (size_t)o * (size_t)d * (size_t)d;
-          double *KU = (double *)malloc(sizeof(double) * (size_t)d * (size_t)r);
-          for (int i = 0; i < d; i++)
+          const double *A = Kd + (size_t)o * (size_t)db * (size_t)d;
+          double *KU = (double *)malloc(sizeof(double) * (size_t)db * (size_t)r);
+          for (int i = 0; i < db; i++)
             for (int b = 0; b < r; b++) {
               double t = 0.0;
-              for (int j = 0; j < d; j++) t += A[(size_t)i * d + j] * lvl->U[(size_t)j * r + b];
+              for (int j = 0; j < d; j++) t += A[(size_t)i * d + j] * Vr[(size_t)j * r + b];
               KU[(size_t)i * r + b] = t;
             }
           for (int a = 0; a < r; a++)
             for (int b = 0; b < r; b++) {
               double t = 0.0;
-              for (int i = 0; i < d; i++) t += lvl->U[(size_t)i * r + a] * KU[(size_t)i * r + b];
+              for (int i = 0; i < db; i++) t += lvl->U[(size_t)i * r + a] * KU[(size_t)i * r + b];
               Cd[((size_t)o * r + a) * r + b] = t;
             }
           free(KU);
@@ -1044,7 +1056,7 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
           for (int a = 0; a < r; a++) {
             double t = 0.0;
             for (int i = 0; i < d; i++)
-              t += lvl->U[(size_t)i * r + a] * Wh[k][(size_t)key * (size_t)d + (size_t)i];
+              t += Vr[(size_t)i * r + a] * Wh[k][(size_t)key * (size_t)d + (size_t)i];
             Whp[(size_t)key * r + a] = t;
           }
         }
@@ -1105,10 +1117,10 @@ int orc_plan_eval(const orc_plan *P, int64_t n, const double *xyz, const double 
 #endif
         for (int64_t key = 0; key < nb; key++) {
           if (box_count(ls, depth, k, (uint32_t)key, NULL) == 0) continue;
-          for (int i = 0; i < d; i++) {
+          for (int i = 0; i < db; i++) {
             double t = 0.0;
             for (int a = 0; a < r; a++) t += lvl->U[(size_t)i * r + a] * gp[(size_t)key * r + a];
-            g[k][(size_t)key * (size_t)d + (size_t)i] = t;
+            g[k][(size_t)key * (size_t)db + (size_t)i] = t;
           }
         }
         free(Cd); free(Whp); free(gp);

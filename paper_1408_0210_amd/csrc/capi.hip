@@ -72,7 +72,6 @@ int validate(const eifmm_config *c) {
   if (c->precision != EIFMM_PREC_FP64 && c->precision != EIFMM_PREC_MIXED) return EIFMM_EINVAL;
   if (c->dmax < 0 || c->dmax > 4096) return EIFMM_EINVAL;
   if (!(c->compress_tol >= 0) || !std::isfinite(c->compress_tol)) return EIFMM_EINVAL;
-  if (uses_two_eim(*c) && c->compress_tol > 0) return EIFMM_EINVAL;
   if (!(c->compress_tol2 >= 0) || !std::isfinite(c->compress_tol2) ||
       (c->compress_tol2 > 0 && !(c->compress_tol > 0)))
     return EIFMM_EINVAL;
@@ -178,7 +177,7 @@ int setup_tables(eifmm_plan h) {
     if (H.r > 0) {
       TRY(upload(&D.ufrag, H.ufrag.data(), H.ufrag.size(), tr));
       TRY(upload(&D.pfrag, H.pfrag.data(), H.pfrag.size(), tr));
-      if (!H.s2.empty()) {
+      if (!H.sp2.empty()) {
         int *sp = nullptr;
         int64_t *vo = nullptr, *uo = nullptr;
         double *vf = nullptr, *uf = nullptr;

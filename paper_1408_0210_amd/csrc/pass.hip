@@ -1292,7 +1292,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       J.nrhs = nrhs;
       finish_job(J, tiles, jt.pre_rbt);
       h.push_back(J);
-      pf += 4.0 * P.lh[k].d * (double)P.lh[k].r * (double)P.nact[k] * nrhs;
+      pf += 2.0 * (P.lh[k].d + P.lh[k].dB) * (double)P.lh[k].r * (double)P.nact[k] * nrhs;
     }
     jt.pre_n = (int)h.size() - jt.pre_first;
     jt.pre_tiles = tiles;
@@ -1397,7 +1397,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
   {
     int tiles = 0;
     jt.post_first = (int)h.size();
-    jt.post_rbt = pick_rbt(P.lh[depth].dp / 16);
+    jt.post_rbt = pick_rbt(P.lh[depth].dpB / 16);
     for (int k = depth; k >= 2; --k) {
       if (P.lh[k].r == 0 || P.nact[k] == 0) continue;
       GemmJob J{};
@@ -1406,7 +1406,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       J.C = P.ld[k].g;
       J.ntgt = (int)P.nact[k];
       J.nterms = 1;
-      J.dpm = P.lh[k].dp;
+      J.dpm = P.lh[k].dpB;
       J.dpk = P.lh[k].rp;
       J.level = k;
       J.mode = MODE_PROJ;

@@ -35,11 +35,13 @@ struct LevelHost {
   // M2L compression (Sec. 4.2): rank r (0 = off), padded rp; C^delta = U^T K^delta U
   int r = 0, rp = 0;
   std::vector<double> sv;       // singular values of [K^delta_1 .. K^delta_316]
-  std::vector<double> U;        // d x r, row-major
-  std::vector<double> ufrag;    // U          (dp x rp), fragment order: g = U g'
-  std::vector<double> pfrag;    // U^T B^{-T} (rp x dp), fragment order: What' = U^T B^{-T} Gamma^{-1} W
+  std::vector<double> U;        // dB x r, row-major: basis of the M2L rows (g) space
+  std::vector<double> V;        // d x r basis of the columns' space (two EIMs; else V = U)
+  std::vector<double> ufrag;    // U          (dpB x rp), fragment order: g = U g'
+  std::vector<double> pfrag;    // V^T B^{-T} (rp x dp), fragment order: What' = V^T B^{-T} Gamma^{-1} W
   // second compression stage (Sec. 4.2): rank s2[o] of each C^delta (empty: off),
-  // padded rank sp2[o] (multiple of 16, 0 when s2[o] = 0) and the factors in
+  // padded rank sp2[o] (multiple of 16, 0 when s2[o] = 0; empty when a rank exceeds
+  // what the factored M2L takes, and the dense product serves) and the factors in
   // operand fragment order, offset after offset: vf2 = Vt (sp x rp, the k order of
   // the gathered loads), uf2 = Ut (rp x sp, the k order of MFMA results)
   std::vector<int> s2, sp2;
@@ -336,7 +338,7 @@ int materialize_expansion(Plan &P, int which, int k);
 inline bool solves_what(const Plan &P, int k) { return P.lh[k].r == 0; }
 // the FP64 pass applies the second compression stage as two factor products
 inline bool uses_m2l2(const Plan &P, int k) {
-  return P.cfg.precision == EIFMM_PREC_FP64 && P.lh[k].r > 0 && !P.lh[k].s2.empty();
+  return P.cfg.precision == EIFMM_PREC_FP64 && P.lh[k].r > 0 && !P.lh[k].sp2.empty();
 }
 // batches (pass.hip): m2l_rbt <= 0 picks the M2L tile height from the operators
 int batch_prepare(BatchExec &B, const std::vector<Plan *> &plans, int m2l_rbt, int sk_groups,

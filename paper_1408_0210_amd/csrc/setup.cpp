@@ -676,45 +676,63 @@ int build_tables(Plan &P) {
                                            xr[3 * i + 2] - (lv.Y[3 * j + 2] + sz));
     };
     lv.r = lv.rp = 0;
-    if (c.compress_tol > 0 && d > 0) {
-      // K_fat = [K^delta_1 .. K^delta_316]: row i holds K^delta[i][:] for every delta
-      const int64_t m = (int64_t)kNumOffsets * d;
-      std::vector<double> Kfat((size_t)d * m);
+    if (c.compress_tol > 0 && d > 0 && dB > 0) {
+      // K_fat = [K^delta_1 .. K^delta_316]: row i holds K^delta[i][:] for every delta.
+      // With two EIMs the matrices are not symmetric: their common row space comes
+      // from K_thin (the matrices stacked), taken as the rows of its transpose,
+      // row j holding K^delta[:][j] for every delta
+      const int64_t m = (int64_t)kNumOffsets * d, mt = (int64_t)kNumOffsets * dB;
+      std::vector<double> Kfat((size_t)dB * m), Kthin(P.two_eim ? (size_t)d * mt : 0);
       parallel_for(kNumOffsets, [&](int64_t o0, int64_t o1) {
-        std::vector<double> A((size_t)d * d);
+        std::vector<double> A((size_t)dB * d);
         for (int64_t o = o0; o < o1; ++o) {
           kdelta((int)o, A);
-          for (int i = 0; i < d; ++i)
+          for (int i = 0; i < dB; ++i)
             std::memcpy(&Kfat[(size_t)i * m + (size_t)o * d], &A[(size_t)i * d], sizeof(double) * d);
+          if (P.two_eim)
+            for (int i = 0; i < dB; ++i)
+              for (int j = 0; j < d; ++j) Kthin[(size_t)j * mt + (size_t)o * dB + i] = A[(size_t)i * d + j];
         }
       });
-      std::vector<double> Ufull;
-      svd_rows(Kfat, d, m, Ufull, lv.sv);
+      std::vector<double> Ufull, Vfull, sv2;
+      svd_rows(Kfat, dB, m, Ufull, lv.sv);
+      int fr = filter_rank(lv.sv, c.compress_tol);
+      if (P.two_eim) {
+        svd_rows(Kthin, d, mt, Vfull, sv2);
+        fr = std::max(fr, filter_rank(sv2, c.compress_tol));
+      }
       // rank from the filters, rounded up to whole 16-row blocks that split evenly
       // into GEMM tiles (extra singular vectors only improve the approximation)
-      int nrb = (filter_rank(lv.sv, c.compress_tol) + 15) / 16;
-      while (nrb * 16 < d && nrb % 6 && nrb % 5 && nrb % 4) ++nrb;
-      lv.r = std::min(d, nrb * 16);
+      const int dmin = std::min(d, dB);
+      int nrb = (fr + 15) / 16;
+      while (nrb * 16 < dmin && nrb % 6 && nrb % 5 && nrb % 4) ++nrb;
+      lv.r = std::min(dmin, nrb * 16);
       lv.rp = ((lv.r + 15) / 16) * 16;
-      lv.U.assign((size_t)d * lv.r, 0.0);
-      for (int i = 0; i < d; ++i)
-        for (int a = 0; a < lv.r; ++a) lv.U[(size_t)i * lv.r + a] = Ufull[(size_t)i * d + a];
-      // What' = U^T What = (U^T B^{-T}) (Gamma^{-1} W): the well-conditioned factor
-      // B^T is folded into the projection (row a is (B^{-1} u_a)^T), the solve with
+      lv.U.assign((size_t)dB * lv.r, 0.0);
+      for (int i = 0; i < dB; ++i)
+        for (int a = 0; a < lv.r; ++a) lv.U[(size_t)i * lv.r + a] = Ufull[(size_t)i * dB + a];
+      if (P.two_eim) {
+        lv.V.assign((size_t)d * lv.r, 0.0);
+        for (int i = 0; i < d; ++i)
+          for (int a = 0; a < lv.r; ++a) lv.V[(size_t)i * lv.r + a] = Vfull[(size_t)i * d + a];
+      }
+      const std::vector<double> &Vb = P.two_eim ? lv.V : lv.U;  // d x r, column side
+      // What' = V^T What = (V^T B^{-T}) (Gamma^{-1} W): the well-conditioned factor
+      // B^T is folded into the projection (row a is (B^{-1} v_a)^T), the solve with
       // the ill-conditioned Gamma stays a solve
       std::vector<double> Pm((size_t)lv.r * d);
       for (int a = 0; a < lv.r; ++a) {
         double *row = &Pm[(size_t)a * d];
-        for (int i = 0; i < d; ++i) row[i] = lv.U[(size_t)i * lv.r + a];
+        for (int i = 0; i < d; ++i) row[i] = Vb[(size_t)i * lv.r + a];
         for (int i = 0; i < d; ++i) {  // B row = u_a, B unit lower
           double t = row[i];
           for (int j = 0; j < i; ++j) t -= lv.B[(size_t)i * d + j] * row[j];
           row[i] = t;
         }
       }
-      lv.ufrag.assign((size_t)dp * lv.rp, 0.0);
+      lv.ufrag.assign((size_t)dpB * lv.rp, 0.0);
       lv.pfrag.assign((size_t)lv.rp * dp, 0.0);
-      to_fragments(lv.U.data(), d, lv.r, dp, lv.rp, lv.ufrag.data());
+      to_fragments(lv.U.data(), dB, lv.r, dpB, lv.rp, lv.ufrag.data());
       to_fragments(Pm.data(), lv.r, d, lv.rp, dp, lv.pfrag.data());
     }
     const int r = lv.r, rp = lv.rp;
@@ -732,17 +750,18 @@ int build_tables(Plan &P) {
           to_fragments(A.data(), dB, d, dpB, dp, &lv.kfrag[(size_t)o * dpB * dp]);
           continue;
         }
-        // C^delta = U^T K^delta U
-        KU.assign((size_t)d * r, 0.0);
-        for (int i = 0; i < d; ++i)
+        // C^delta = U^T K^delta V (V = U for a symmetric kernel)
+        const std::vector<double> &Vb = P.two_eim ? lv.V : lv.U;
+        KU.assign((size_t)dB * r, 0.0);
+        for (int i = 0; i < dB; ++i)
           for (int j = 0; j < d; ++j) {
             const double a = A[(size_t)i * d + j];
-            const double *uj = &lv.U[(size_t)j * r];
+            const double *vj = &Vb[(size_t)j * r];
             double *ki = &KU[(size_t)i * r];
-            for (int b = 0; b < r; ++b) ki[b] += a * uj[b];
+            for (int b = 0; b < r; ++b) ki[b] += a * vj[b];
           }
         C.assign((size_t)r * r, 0.0);
-        for (int i = 0; i < d; ++i) {
+        for (int i = 0; i < dB; ++i) {
           const double *ui = &lv.U[(size_t)i * r];
           const double *ki = &KU[(size_t)i * r];
           for (int a = 0; a < r; ++a) {
@@ -773,7 +792,7 @@ int build_tables(Plan &P) {
       int smax = 0;
       for (int o = 0; o < kNumOffsets; ++o) smax = std::max(smax, lv.s2[o]);
       if (smax > kMaxRank2 || rp / 16 < kM2l2RbMin || rp / 16 > kM2l2RbMax) {
-        lv.s2.clear();
+        lv.sp2.clear();  // the ranks stay (exported); the product serves the pass
       } else {
         lv.sp2.assign(kNumOffsets, 0);
         lv.voff2.assign(kNumOffsets, 0);

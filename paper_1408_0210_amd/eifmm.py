@@ -263,8 +263,9 @@ class Plan:
         return out
 
     def compression(self, k):
-        """(r, singular values, U) of level k's M2L compression."""
-        d = self.level(k)["d"]
+        """(r, singular values, U) of level k's M2L compression; U has one row per
+        M2L row point (the second EIM's size when there are two EIMs)."""
+        d = self.stats()["d2"][k] or self.level(k)["d"]  # d2 is 0 with one EIM
         r = ctypes.c_int32()
         _check(lib().eifmm_get_compression(self._h, k, ctypes.byref(r), None, None),
                "eifmm_get_compression")

@@ -80,12 +80,12 @@ WORKLOADS["uniform100m_gauss1_d7"] = dict(n=100_000_000, dist="uniform", seed_pt
                                           tau=1e-6)
 
 
-# A kernel that is not symmetric (two EIMs per level, no M2L compression): the
-# steady advection-diffusion kernel exp(a (z_x - r))/r with a = 1 on the 1e6-point
-# cube, depth 5, tau 1e-6.
+# A kernel that is not symmetric (two EIMs per level): the steady
+# advection-diffusion kernel exp(a (z_x - r))/r with a = 1 on the 1e6-point cube,
+# depth 5, tau 1e-6, M2L compressed at 5e-6 (bases from K_fat and K_thin).
 WORKLOADS["uniform1m_advdiff1_d5"] = dict(n=1_000_000, dist="uniform", seed_pts=3, seed_sigma=4,
                                           kernel="advdiff", param=1.0, depth=5, tau=1e-6,
-                                          compress_tol=0.0)
+                                          compress_tol=5e-6)
 
 # Separate targets: 1e6 sources and 1e6 targets, both uniform in the cube
 # (independent seeds), 1/r, depth 5, tau 1e-6, M2L compressed as above.

@@ -130,8 +130,24 @@ def test_host_setup_second_eim_matches_oracle(E, oracle_lib, kernel, param, two)
     P.close()
 
 
-def test_two_eim_refuses_compression(E):
-    with pytest.raises(E.EifmmError):
-        E.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-4)
+def test_two_eim_compression_matches_oracle_svd(E, oracle_lib):
+    """Compression with two EIMs (Sec. 4.2 for K^delta that are not symmetric): the
+    singular values of K_fat (rows: the second EIM's x points) and the projector on
+    U against numpy's; r covers both filtered ranks, of K_fat and of K_thin."""
+    P = E.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-4)
+    k = 2
+    r, sv, U = P.compression(k)
+    X, Y = P.level(k, second=True)["X"], P.level(k)["Y"]
+    Uo, Vo, svo, sv2o, ro = oracle_lib.compression_bases("advdiff", 1.0, X, Y, k, 1e-4)
+    m = svo / svo[0] > 1e-12
+    assert np.abs(sv[m] - svo[m]).max() <= 1e-12 * svo[0]
+    assert ro <= r and (r % 16 == 0 or r == min(len(X), len(Y)))
+    Uf, _, _, _, _ = oracle_lib.compression_bases("advdiff", 1.0, X, Y, k, 1e-4, rank=r)
+    assert U.shape == (len(X), r)
+    assert np.abs(U @ U.T - Uf @ Uf.T).max() < 1e-9
+    P.close()
+
+
+def test_advdiff_rejects_negative_flow(E):
     with pytest.raises(E.EifmmError):
         E.Plan("advdiff", -1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True)

@@ -253,15 +253,17 @@ def test_targets1m_sampled(precision, E, torch_dev, oracle_lib):
     plan.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_advdiff1m_sampled(precision, E, torch_dev, oracle_lib):
+@pytest.mark.parametrize("precision,ctol", [("fp64", 0.0), ("fp64", 5e-6), ("mixed", 5e-6)])
+def test_advdiff1m_sampled(precision, ctol, E, torch_dev, oracle_lib):
     """The advection-diffusion kernel exp(z_x - r)/r (two EIMs per level) on the
-    1e6-point cube, depth 5, tau 1e-6: sampled targets against the direct sum."""
+    1e6-point cube, depth 5, tau 1e-6, with and without M2L compression: sampled
+    targets against the direct sum."""
     case = Case("uniform1m_advdiff1_d5", torch_dev, oracle_lib)
-    plan = _plan(E, case, precision=precision, compress_tol=0.0)
+    plan = _plan(E, case, precision=precision, compress_tol=ctol)
     f = _eval(torch_dev, plan, case.s)
     err = _rel(f[case.idx], case.ref())
-    print(f"advdiff1m {precision}: d={plan.stats()['d']} d2={plan.stats()['d2']} "
-          f"sampled rel-L2 {err:.3e}", flush=True)
+    print(f"advdiff1m {precision} compress {ctol}: d={plan.stats()['d']} "
+          f"d2={plan.stats()['d2']} rank={plan.stats()['rank']} sampled rel-L2 {err:.3e}",
+          flush=True)
     assert err <= 1e-6
     plan.close()

@@ -2,7 +2,8 @@
 with the flow along x), two EIMs per level (Sec. 3.1).  The GPU pass against
 the oracle's two-EIM pass (same setup, bit for bit: tests/test_abi.py) on the
 same inputs, stage by stage, and against the direct sum; the general form on
-1/r against the one-EIM pass."""
+1/r against the one-EIM pass; the same with the M2L compression of Sec. 4.2
+(both stages), the oracle taking the library's ranks."""
 import numpy as np
 import pytest
 
@@ -110,6 +111,69 @@ def test_advdiff_clustered_and_targets(E, torch_dev, oracle_lib):
     f = plan.evaluate(torch.from_numpy(s).to(dev)).cpu().numpy()
     plan.close()
     assert _rel(f, oracle_lib.direct("advdiff", 2.0, xt, xs, s)) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def c1c(E, torch_dev, oracle_lib):
+    """The compressed pass (Sec. 4.2 with two EIMs: U from K_fat, V from K_thin):
+    the oracle takes the library's ranks."""
+    x, s = W.uniform_points(2000, 1), W.potentials(2000, 2)
+    plan, f = _eval(E, torch_dev, "advdiff", 1.0, x, s, 3, 1e-6, compress_tol=1e-6)
+    ranks = plan.stats()["rank"]
+    O = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 3, 1e-6, compress_tol=1e-6,
+                        compress_rank=ranks)
+    fo, D = O.evaluate(x, s, dumps=True)
+    yield x, s, plan, f, ranks, O, fo, D
+    plan.close()
+
+
+def test_advdiff_compressed_vs_oracle(c1c, c1):
+    x, s, plan, f, ranks, O, fo, D = c1c
+    fd = c1[5]
+    assert all(0 < ranks[k] < plan.stats()["d"][k] for k in (2, 3))
+    assert _rel(f, fo) < 1e-10
+    assert _rel(f, fd) < 1e-6
+    for k in (2, 3):
+        for name in ("g", "l"):
+            e = _rel(plan.export_expansion(name, k), D[name][k])
+            assert e < 1e-10, (name, k, e)
+
+
+def test_advdiff_compressed_mixed_and_multi_rhs(E, torch_dev, c1c, c1):
+    x, s, plan, f, ranks, O, fo, D = c1c
+    fd = c1[5]
+    pm, fm = _eval(E, torch_dev, "advdiff", 1.0, x, s, 3, 1e-6, compress_tol=1e-6,
+                   precision="mixed")
+    assert _rel(fm, fd) < 1e-6
+    pm.close()
+    S = np.stack([s, 0.5 * s + W.potentials(2000, 3)])
+    p2, F = _eval(E, torch_dev, "advdiff", 1.0, x, S, 3, 1e-6, compress_tol=1e-6, max_rhs=2)
+    assert _rel(F[0], f) < 1e-13
+    assert _rel(F[1], O.evaluate(x, S[1])) < 1e-10
+    p2.close()
+
+
+def test_two_eim_compressed_laplace_equals_one_eim(E, torch_dev):
+    x, s = W.uniform_points(2000, 1), W.potentials(2000, 2)
+    p2, f2 = _eval(E, torch_dev, "laplace", 0.0, x, s, 3, 1e-6, two_eim=True, compress_tol=1e-6)
+    p1, f1 = _eval(E, torch_dev, "laplace", 0.0, x, s, 3, 1e-6, compress_tol=1e-6)
+    assert p2.stats()["rank"] == p1.stats()["rank"]
+    p1.close()
+    p2.close()
+    assert _rel(f2, f1) < 1e-10
+
+
+def test_advdiff_compressed_stage2_vs_oracle(E, torch_dev, oracle_lib):
+    x, s = W.uniform_points(2000, 1), W.potentials(2000, 2)
+    plan, f = _eval(E, torch_dev, "advdiff", 1.0, x, s, 3, 1e-6, compress_tol=1e-6,
+                    compress_tol2=1e-6)
+    ranks = plan.stats()["rank"]
+    s2 = {k: plan.compression2(k) for k in ranks}
+    assert all(s2[k].max() > 0 for k in ranks)
+    plan.close()
+    O = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 3, 1e-6, compress_tol=1e-6,
+                        compress_rank=ranks, compress_tol2=1e-6, compress_rank2=s2)
+    assert _rel(f, O.evaluate(x, s)) < 1e-10
 
 
 def test_two_eim_not_in_batches(E):

@@ -33,6 +33,8 @@ MUTANTS = {
         "if (0) continue;\n            s += ss[j]"),
     "interaction_list_parent_rule": ("if (!inside || pc > 1) continue;",
                                      "if (!inside || pc > 2) continue;"),
+    "two_eim_compression_columns_use_row_basis": ("const double *Vr = lvl->V ? lvl->V : lvl->U;",
+                                                  "const double *Vr = lvl->U;"),
     "stage2_second_factor_transposed": ("t += Vo[(size_t)j * r + ll] * wj[ll];",
                                         "t += Vo[(size_t)ll * so + j] * wj[ll];"),
 }
@@ -55,6 +57,6 @@ def test_mutant_is_caught(name, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_nonsym.py"),
                         os.path.join(ROOT, "tests", "test_oracle_compress2.py"),
                         "-k", "finite_rank or gamma or interpolation or c1_accuracy or swapped "
-                              "or two_eim or advdiff_two or stage2"],
+                              "or two_eim or advdiff_two or stage2 or sides_random"],
                        env=env, capture_output=True, text=True, cwd=ROOT)
     assert r.returncode != 0, f"mutant {name} survived:\n{r.stdout[-2000:]}"

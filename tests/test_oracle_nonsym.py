@@ -10,6 +10,14 @@ that is not symmetric.  Pins, none of which reuses the oracle's own formulas:
     equals the direct sum to rounding;
   * the advection-diffusion kernel exp(a (z_x - r))/r meets the accuracy of the
     EIM tolerance against the direct sum, and its two EIMs differ.
+
+The compression of Sec. 4.2 with two EIMs (U from K_fat, rows x^{J_0}; V from
+K_thin, columns y^{J_0}) is pinned the same way: finite-rank kernels stay exact;
+1/r through the two-EIM pass equals the one-EIM compressed pass; with r = d any
+orthogonal U and V leave the pass unchanged; with random bases of rank r < d, g of
+a box equals U U^T sum_J K(x^{J_0} + c_I, y^{J_0} + c_J) V V^T What^J summed over
+its interaction list box by box, with kernel values from the box centres (no
+offset tables), which fixes the side each basis sits on.
 """
 import numpy as np
 import pytest
@@ -80,3 +88,77 @@ def test_advdiff_kernel_values(oracle_lib):
     np.testing.assert_allclose(got, want, rtol=1e-15)
     assert got[0] == pytest.approx(1 / 0.3, rel=1e-15)
     assert got[1] == pytest.approx(np.exp(-0.9) / 0.3, rel=1e-15)
+
+
+def _centre(key, level):
+    n = [0, 0, 0]
+    for b in range(level):
+        for a in range(3):
+            n[a] |= ((int(key) >> (3 * b + a)) & 1) << b
+    return (np.array(n) + 0.5) / (1 << level)
+
+
+def test_two_eim_compression_sides_random_bases(pts, oracle_lib):
+    x, s = pts
+    P = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 2, 1e-4)
+    d, db = P.levels[2]["d"], P.levels2[2]["d"]
+    r = min(d, db) // 2
+    rng = np.random.default_rng(8)
+    U = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((db, db)))[0][:, :r])
+    V = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((d, d)))[0][:, :r])
+    L = oracle_lib.lib()
+    assert L.orc_plan_set_compression(P._h, 2, r, oracle_lib._p(U), oracle_lib._p(V)) == 0
+    f, D = P.evaluate(x, s, dumps=True)
+    _, _, ls = oracle_lib.tree(x, [0, 0, 0], 1.0, 2)
+    li = oracle_lib.lists(ls, 2, 2)
+    XB, Y = P.levels2[2]["X"], P.levels[2]["Y"]
+    act = li["active"]
+    for t in (0, len(act) // 2, len(act) - 1):
+        I = int(act[t])
+        acc = np.zeros(db)
+        for J in li["il_src"][li["il_ptr"][t]:li["il_ptr"][t + 1]]:
+            z = (XB + _centre(I, 2))[:, None, :] - (Y + _centre(J, 2))[None, :, :]
+            K = oracle_lib.kernel_eval("advdiff", 1.0, z.reshape(-1, 3)).reshape(db, d)
+            acc += K @ (V @ (V.T @ D["What"][2][int(J)]))
+        want = U @ (U.T @ acc)
+        np.testing.assert_allclose(D["g"][2][I], want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_two_eim_compression_full_rank_random_bases(pts, oracle_lib):
+    x, s = pts
+    P0 = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 2, 1e-4)
+    P = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 2, 1e-4)
+    d, db = P.levels[2]["d"], P.levels2[2]["d"]
+    assert d == db
+    rng = np.random.default_rng(7)
+    U = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((db, db)))[0])
+    V = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((d, d)))[0])
+    L = oracle_lib.lib()
+    assert L.orc_plan_set_compression(P._h, 2, d, oracle_lib._p(U), None) == oracle_lib.EINVAL
+    assert L.orc_plan_set_compression(P._h, 2, d, oracle_lib._p(U), oracle_lib._p(V)) == 0
+    assert _rel(P.evaluate(x, s), P0.evaluate(x, s)) < 1e-12
+
+
+@pytest.mark.parametrize("kernel,param,two", [("expdot", [1.0, 0.5, -0.3], False),
+                                              ("cosdot", [3.0, 1.0, 2.0], True)])
+def test_two_eim_compression_finite_rank_exact(kernel, param, two, pts, oracle_lib):
+    x, s = pts
+    P = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, 3, 1e-11, two_eim=two, compress_tol=1e-12)
+    assert P.two
+    assert _rel(P.evaluate(x, s), oracle_lib.direct(kernel, param, x, x, s)) < 1e-12
+
+
+def test_two_eim_compression_equals_one_eim_for_laplace(pts, oracle_lib):
+    x, s = pts
+    P1 = oracle_lib.Plan("laplace", 0.0, [0, 0, 0], 1.0, 2, 1e-4, compress_tol=1e-6)
+    P2 = oracle_lib.Plan("laplace", 0.0, [0, 0, 0], 1.0, 2, 1e-4, compress_tol=1e-6,
+                         two_eim=True)
+    assert P1.levels[2]["r"] == P2.levels[2]["r"] < P1.levels[2]["d"]
+    assert _rel(P2.evaluate(x, s), P1.evaluate(x, s)) < 1e-12
+
+
+def test_advdiff_two_eim_compressed_accuracy(pts, oracle_lib):
+    x, s = pts
+    P = oracle_lib.Plan("advdiff", 1.0, [0, 0, 0], 1.0, 2, 1e-6, compress_tol=1e-6)
+    assert P.levels[2]["r"] < 0.7 * P.levels[2]["d"]
+    assert _rel(P.evaluate(x, s), oracle_lib.direct("advdiff", 1.0, x, x, s)) < 1e-6
