@@ -165,7 +165,7 @@ int setup_tables(eifmm_plan h) {
     }
     std::vector<double>().swap(H.kfrag);
     for (int q = 0; q < 4; ++q) TRY(upload(&D.tri[q], H.tri[q].data(), H.tri[q].size(), tr));
-    if (k < depth) {
+    if (k < depth && !P.gpu_ops) {
       TRY(upload(&D.m2m, H.m2m.data(), H.m2m.size(), tr));
       TRY(upload(&D.l2l, H.l2l.data(), H.l2l.size(), tr));
     }
@@ -196,6 +196,15 @@ int setup_tables(eifmm_plan h) {
       }
     }
   }
+  // M2M / L2L operators (Sec. 4.1): solved on the device with the solve tables
+  // just uploaded, packed on the host, uploaded
+  if (P.gpu_ops)
+    for (int k = 2; k < depth; ++k) {
+      TRY(solve_operators_gpu(P, k));
+      pack_operators(P, k);
+      TRY(upload(&P.ld[k].m2m, P.lh[k].m2m.data(), P.lh[k].m2m.size(), tr));
+      TRY(upload(&P.ld[k].l2l, P.lh[k].l2l.data(), P.lh[k].l2l.size(), tr));
+    }
   return EIFMM_OK;
 }
 
@@ -541,6 +550,7 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   P.max_rhs = cfg->max_rhs;
   P.host_only = (cfg->flags & EIFMM_FLAG_HOST_ONLY) != 0;
   P.gpu_setup = !P.host_only && !(cfg->flags & EIFMM_FLAG_HOST_SETUP);
+  P.gpu_ops = P.gpu_setup;
   P.two_eim = uses_two_eim(*cfg);
   if (!P.host_only) hipGetDevice(&P.device);
   st = build_tables(P);

@@ -1874,6 +1874,66 @@ int materialize_expansion(Plan &P, int which, int k) {
   return EIFMM_OK;
 }
 
+// M2M and L2L operators of parent level k (Sec. 4.1) by the blocked MFMA solves of
+// the pass, one launch for both: the M2M rows K(X^k - s_i, Y^{k+1}) times
+// M^{-1} of the child, i.e. M^{-T} applied to each row (B forward, Gamma^T
+// backward); the L2L rows times the parent's Delta^T (one EIM: M^{-1} applied to
+// each row, Gamma forward, B^T backward) or M_B^{-1} (two EIMs: M_B^{-T} applied,
+// B_B forward, Gamma_B^T backward).  Rows are padded to the solve's dp with
+// zeros, which the identity-padded tables keep at zero.
+int solve_operators_gpu(Plan &P, int k) {
+  LevelHost &lp = P.lh[k], &lc = P.lh[k + 1];
+  const int n0 = 8 * lp.d, n1 = 8 * lc.dB;
+  const int dp0 = lc.dp, dp1 = lp.dpB;
+  const size_t sz0 = (size_t)n0 * dp0, sz1 = (size_t)n1 * dp1;
+  if (lp.m2m_rows.size() != sz0 || lp.l2l_rows.size() != sz1) return EIFMM_EINVAL;
+  double *rows = nullptr, *tabs[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipMalloc(&rows, sizeof(double) * (sz0 + sz1 > 0 ? sz0 + sz1 : 1));
+  if (e == hipSuccess && sz0) e = hipMemcpy(rows, lp.m2m_rows.data(), sizeof(double) * sz0, hipMemcpyHostToDevice);
+  if (e == hipSuccess && sz1)
+    e = hipMemcpy(rows + sz0, lp.l2l_rows.data(), sizeof(double) * sz1, hipMemcpyHostToDevice);
+  const double *T[4];
+  if (P.two_eim) {
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) {
+      e = hipMalloc(&tabs[q], sizeof(double) * std::max<size_t>(lp.op_tri[q].size(), 1));
+      if (e == hipSuccess && !lp.op_tri[q].empty())
+        e = hipMemcpy(tabs[q], lp.op_tri[q].data(), sizeof(double) * lp.op_tri[q].size(),
+                      hipMemcpyHostToDevice);
+      T[q] = tabs[q];
+    }
+  } else {
+    T[0] = P.ld[k + 1].tri[2];  // the child's Delta^T tables: B, Gamma^T
+    T[1] = P.ld[k + 1].tri[3];
+    T[2] = P.ld[k].tri[0];      // the parent's Delta tables: Gamma, B^T
+    T[3] = P.ld[k].tri[1];
+  }
+  if (e == hipSuccess) {
+    SolveArgs A{};
+    A.lv[0] = SolveDesc{rows, rows, nullptr, T[0], T[1], n0, dp0, 0, 0};
+    A.lv[1] = SolveDesc{rows + sz0, rows + sz0, nullptr, T[2], T[3], n1, dp1, (n0 + 15) / 16, 0};
+    A.nlev = 2;
+    const int blk = (n0 + 15) / 16 + (n1 + 15) / 16;
+    // in place: a wave reads all tiles of its columns (forward pass) before it
+    // writes any (backward pass)
+    if (blk > 0) {
+      hipLaunchKernelGGL(k_trsm, dim3(blk), dim3(64), trsm_shm(std::max(dp0, dp1)), nullptr, A);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess && sz0)
+    e = hipMemcpy(lp.m2m_rows.data(), rows, sizeof(double) * sz0, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && sz1)
+    e = hipMemcpy(lp.l2l_rows.data(), rows + sz0, sizeof(double) * sz1, hipMemcpyDeviceToHost);
+  hipFree(rows);
+  for (double *t : tabs) hipFree(t);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? EIFMM_ENOMEM : EIFMM_EHIP;
+  }
+  return EIFMM_OK;
+}
+
 // ------------------------------------------------------------------ batches
 // A batch runs the pass of many independent problems (one plan each) as a fixed,
 // short sequence of launches, each covering every problem: the leaf-level

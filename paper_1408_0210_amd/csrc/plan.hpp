@@ -45,6 +45,11 @@ struct LevelHost {
   // operand fragment order, offset after offset: vf2 = Vt (sp x rp, the k order of
   // the gathered loads), uf2 = Ut (rp x sp, the k order of MFMA results)
   std::vector<int> s2, sp2;
+  // M2M / L2L operators of this (parent) level before their solves, for the device
+  // solves: kernel rows padded to the child's dp (M2M, 8 d rows) and to this level's
+  // dpB (L2L, 8 d_B(child) rows); with two EIMs also the solve tables they need
+  // (M2M: the child's first-EIM B, Gamma^T; L2L: this level's B_B, Gamma_B^T)
+  std::vector<double> m2m_rows, l2l_rows, op_tri[4];
   std::vector<int64_t> voff2, uoff2;
   std::vector<double> vf2, uf2;
 };
@@ -232,6 +237,7 @@ struct Plan {
   int device = 0;
   bool host_only = false;
   bool gpu_setup = false;  // Algorithm 1 iterations on the device
+  bool gpu_ops = false;    // M2M / L2L operator solves on the device
   bool two_eim = false;    // second EIM per level (lhB): kernels that are not symmetric
   LevelHost lhB[kMaxLevels];  // the second EIM (D_x = J_0, D_y = I_0): X in J_0, Y in I_0
   int depth = 0;
@@ -333,6 +339,11 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
 // Writes an expansion of the last pass that the pass itself skipped (What of a
 // compressed level), on the null stream.
 int materialize_expansion(Plan &P, int which, int k);
+// solves the M2M / L2L operator rows of parent level k on the device
+// (LevelHost::m2m_rows, l2l_rows, solved in place)
+int solve_operators_gpu(Plan &P, int k);
+// packs the solved rows into the operator tables (fragment order) and frees them
+void pack_operators(Plan &P, int k);
 // On a compressed level the solve for What stops at z = Gamma^{-1} W: the
 // projection applies U^T B^{-T} (pass.hip)
 inline bool solves_what(const Plan &P, int k) { return P.lh[k].r == 0; }

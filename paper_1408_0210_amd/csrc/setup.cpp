@@ -834,8 +834,22 @@ int build_tables(Plan &P) {
     const double *xbc = P.two_eim ? P.lhB[k + 1].X.data() : lc.Y.data();
     const double *ybp = P.two_eim ? P.lhB[k].Y.data() : lp.X.data();
     const double lc_half = std::ldexp(L, -k - 2);  // l_{k+1}
-    lp.m2m.assign((size_t)8 * lp.dp * lc.dp, 0.0);
-    lp.l2l.assign((size_t)8 * lc.dpB * lp.dpB, 0.0);
+    // device solves: the kernel rows only, padded; the solves and the packing
+    // follow once the solve tables are on the device
+    const bool dev = P.gpu_ops;
+    if (dev) {
+      lp.m2m_rows.assign((size_t)8 * dk * lc.dp, 0.0);
+      lp.l2l_rows.assign((size_t)8 * dcB * lp.dpB, 0.0);
+      if (P.two_eim) {
+        trsm_table(lc.B, dc, lc.dp, false, true, lp.op_tri[0]);                // B      (forward)
+        trsm_table(lc.G, dc, lc.dp, true, false, lp.op_tri[1]);                // Gamma^T (backward)
+        trsm_table(P.lhB[k].B, dkB, lp.dpB, false, true, lp.op_tri[2]);      // B_B
+        trsm_table(P.lhB[k].G, dkB, lp.dpB, true, false, lp.op_tri[3]);      // Gamma_B^T
+      }
+    } else {
+      lp.m2m.assign((size_t)8 * lp.dp * lc.dp, 0.0);
+      lp.l2l.assign((size_t)8 * lc.dpB * lp.dpB, 0.0);
+    }
     parallel_for(8, [&](int64_t i0, int64_t i1) {
       std::vector<double> A((size_t)dk * dc), Bm((size_t)dcB * dkB), row;
       for (int64_t i = i0; i < i1; ++i) {
@@ -847,30 +861,64 @@ int build_tables(Plan &P) {
             row[q] = kern_host(kind, p, (lp.X[3 * m] - s[0]) - lc.Y[3 * q],
                                (lp.X[3 * m + 1] - s[1]) - lc.Y[3 * q + 1],
                                (lp.X[3 * m + 2] - s[2]) - lc.Y[3 * q + 2]);
+          if (dev) {
+            std::memcpy(&lp.m2m_rows[((size_t)i * dk + m) * lc.dp], row.data(), sizeof(double) * dc);
+            continue;
+          }
           solve_mtinv(lc, row.data());  // row M^{-1} = (M^{-T} row^T)^T
           std::memcpy(&A[(size_t)m * dc], row.data(), sizeof(double) * dc);
         }
-        to_fragments(A.data(), dk, dc, lp.dp, lc.dp, &lp.m2m[(size_t)i * lp.dp * lc.dp]);
+        if (!dev)
+          to_fragments(A.data(), dk, dc, lp.dp, lc.dp, &lp.m2m[(size_t)i * lp.dp * lc.dp]);
         for (int m = 0; m < dcB; ++m) {
           row.assign((size_t)dkB, 0.0);
           for (int q = 0; q < dkB; ++q)
             row[q] = kern_host(kind, p, (xbc[3 * m] + s[0]) - ybp[3 * q],
                                (xbc[3 * m + 1] + s[1]) - ybp[3 * q + 1],
                                (xbc[3 * m + 2] + s[2]) - ybp[3 * q + 2]);
+          if (dev) {
+            std::memcpy(&lp.l2l_rows[((size_t)i * dcB + m) * lp.dpB], row.data(),
+                        sizeof(double) * dkB);
+            continue;
+          }
           if (P.two_eim)
             solve_mtinv(P.lhB[k], row.data());  // row M_B^{-1} = (M_B^{-T} row^T)^T
           else
             solve_minv(lp, row.data());  // row M^{-T} = (M^{-1} row^T)^T
           std::memcpy(&Bm[(size_t)m * dkB], row.data(), sizeof(double) * dkB);
         }
-        to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB,
-                     &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
+        if (!dev)
+          to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB,
+                       &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
       }
     });
   }
   P.setup_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return EIFMM_OK;
+}
+
+void pack_operators(Plan &P, int k) {
+  LevelHost &lp = P.lh[k], &lc = P.lh[k + 1];
+  const int dk = lp.d, dc = lc.d, dkB = lp.dB, dcB = lc.dB;
+  lp.m2m.assign((size_t)8 * lp.dp * lc.dp, 0.0);
+  lp.l2l.assign((size_t)8 * lc.dpB * lp.dpB, 0.0);
+  parallel_for(8, [&](int64_t i0, int64_t i1) {
+    std::vector<double> A((size_t)dk * dc), Bm((size_t)dcB * dkB);
+    for (int64_t i = i0; i < i1; ++i) {
+      for (int m = 0; m < dk; ++m)
+        std::memcpy(&A[(size_t)m * dc], &lp.m2m_rows[((size_t)i * dk + m) * lc.dp],
+                    sizeof(double) * dc);
+      to_fragments(A.data(), dk, dc, lp.dp, lc.dp, &lp.m2m[(size_t)i * lp.dp * lc.dp]);
+      for (int m = 0; m < dcB; ++m)
+        std::memcpy(&Bm[(size_t)m * dkB], &lp.l2l_rows[((size_t)i * dcB + m) * lp.dpB],
+                    sizeof(double) * dkB);
+      to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB, &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
+    }
+  });
+  std::vector<double>().swap(lp.m2m_rows);
+  std::vector<double>().swap(lp.l2l_rows);
+  for (auto &t : lp.op_tri) std::vector<double>().swap(t);
 }
 
 }  // namespace eifmm
