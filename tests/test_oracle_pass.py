@@ -141,13 +141,21 @@ def c1_compressed(oracle_lib, c1_inputs):
                            compress_tol=1e-6)
 
 
-def test_compression_without_truncation_is_exact(oracle_lib, c1_inputs, c1_plan):
+@pytest.fixture(scope="module")
+def small_case(oracle_lib):
+    """1000 uniform points, 1/r, depth 2, tau 1e-4 (d about 146): a cheap plan for
+    the compression pins that need several plans."""
+    x, s = W.uniform_points(1000, 61), W.potentials(1000, 62)
+    P = oracle_lib.Plan("laplace", 0, [0, 0, 0], 1.0, 2, 1e-4)
+    return x, s, P.evaluate(x, s)
+
+
+def test_compression_without_truncation_is_exact(oracle_lib, small_case):
     """Keeping every singular vector (U U^T = I) reproduces the uncompressed M2L."""
-    x, s, w = c1_inputs
-    P = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
-                        compress_tol=1e-14)
+    x, s, f0 = small_case
+    P = oracle_lib.Plan("laplace", 0, [0, 0, 0], 1.0, 2, 1e-4, compress_tol=1e-14)
     assert all(P.levels[k]["r"] == P.levels[k]["d"] for k in P.levels)
-    assert _rel(P.evaluate(x, s), c1_plan.evaluate(x, s)) < 1e-13
+    assert _rel(P.evaluate(x, s), f0) < 1e-13
 
 
 def test_compression_accuracy_and_rank(c1_compressed, c1_inputs, c1_direct):
@@ -161,13 +169,11 @@ def test_compression_accuracy_and_rank(c1_compressed, c1_inputs, c1_direct):
     assert _rel(c1_compressed.evaluate(x, s), c1_direct) < 1e-6
 
 
-def test_compression_error_decreases(oracle_lib, c1_inputs, c1_plan):
-    x, s, w = c1_inputs
-    f0 = c1_plan.evaluate(x, s)
+def test_compression_error_decreases(oracle_lib, small_case):
+    x, s, f0 = small_case
     errs = []
-    for eps in (1e-3, 1e-5, 1e-7):
-        P = oracle_lib.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, w["depth"], w["tau"],
-                            compress_tol=eps)
+    for eps in (1e-2, 1e-4, 1e-6):
+        P = oracle_lib.Plan("laplace", 0, [0, 0, 0], 1.0, 2, 1e-4, compress_tol=eps)
         errs.append(_rel(P.evaluate(x, s), f0))
     assert errs[0] > errs[1] > errs[2], errs
 
