@@ -70,9 +70,13 @@ int hw_threads() {
 }
 
 template <class F>
-void parallel_for(int64_t n, F fn) {
+void parallel_for(int64_t n, F fn, bool small_ok = false) {
+  if (n <= 0) return;
   int nt = hw_threads();
-  if (n < 2 * nt) nt = 1;
+  if (small_ok)
+    nt = (int)std::min<int64_t>(nt, n);  // each item is large work
+  else if (n < 2 * nt)
+    nt = 1;
   std::vector<std::thread> th;
   int64_t chunk = (n + nt - 1) / nt;
   for (int t = 0; t < nt; t++) {
@@ -396,34 +400,82 @@ void trsm_table(const std::vector<double> &T, int d, int dp, bool transpose, boo
 
 void jacobi_left(std::vector<double> &G, int d, std::vector<double> &U, std::vector<double> &s);
 
+// x . y with eight interleaved partial sums added in a fixed order (a long
+// single accumulator chain is latency bound)
+inline double dot8(const double *x, const double *y, int64_t n) {
+  double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t i = 0;
+  for (; i + 8 <= n; i += 8)
+    for (int l = 0; l < 8; ++l) p[l] += x[i + l] * y[i + l];
+  for (int l = 0; i < n; ++i, ++l) p[l] += x[i] * y[i];
+  return ((p[0] + p[4]) + (p[1] + p[5])) + ((p[2] + p[6]) + (p[3] + p[7]));
+}
+
 // Singular values (descending) and left singular vectors (U, d x d row-major,
 // column p = vector p) of the d x m matrix whose rows are given in A (row-major,
 // m >= d; A is overwritten).  Householder QR of A^T = Q R, then a one-sided
 // Jacobi SVD of R^T: R^T V = U diag(s), so A = R^T Q^T = U diag(s) (Q V)^T.
+// The reflectors are formed in blocks of 16 columns: inside a block each one is
+// applied to the block's remaining columns at once, and each column right of the
+// block then receives the block's 16 reflectors in order while it is in cache.
 void svd_rows(std::vector<double> &A, int d, int64_t m, std::vector<double> &U,
               std::vector<double> &s) {
-  std::vector<double> R((size_t)d * d, 0.0), v;
-  for (int j = 0; j < d; ++j) {
-    double *cj = &A[(size_t)j * m];
-    double n2 = 0.0;
-    for (int64_t i = j; i < m; ++i) n2 += cj[i] * cj[i];
-    const double alpha = cj[j] >= 0 ? -std::sqrt(n2) : std::sqrt(n2);
-    v.assign(cj + j, cj + m);
-    v[0] -= alpha;
-    double vtv = 0.0;
-    for (double x : v) vtv += x * x;
-    R[(size_t)j * d + j] = alpha;
-    if (vtv == 0.0) continue;
-    parallel_for(d - j - 1, [&](int64_t a0, int64_t a1) {
-      for (int64_t c = j + 1 + a0; c < j + 1 + a1; ++c) {
-        double *cc = &A[(size_t)c * m];
-        double dot = 0.0;
-        for (int64_t i = j; i < m; ++i) dot += v[i - j] * cc[i];
-        const double f = 2.0 * dot / vtv;
-        for (int64_t i = j; i < m; ++i) cc[i] -= f * v[i - j];
+  constexpr int kb = 16;
+  std::vector<double> R((size_t)d * d, 0.0), vtv(kb);
+  std::vector<std::vector<double>> vs(kb);
+  // reflector j (slot jl of the block) applied to column cc, rows j..m-1
+  auto apply = [&](int j, int jl, double *cc) {
+    const double *v = vs[jl].data();
+    const double f = 2.0 * dot8(v, cc + j, m - j) / vtv[jl];
+    for (int64_t i = j; i < m; ++i) cc[i] -= f * v[i - j];
+  };
+  for (int j0 = 0; j0 < d; j0 += kb) {
+    const int j1 = std::min(d, j0 + kb);
+    for (int j = j0; j < j1; ++j) {
+      double *cj = &A[(size_t)j * m];
+      const double n2 = dot8(cj + j, cj + j, m - j);
+      const double alpha = cj[j] >= 0 ? -std::sqrt(n2) : std::sqrt(n2);
+      std::vector<double> &v = vs[j - j0];
+      v.assign(cj + j, cj + m);
+      v[0] -= alpha;
+      vtv[j - j0] = dot8(v.data(), v.data(), m - j);
+      R[(size_t)j * d + j] = alpha;
+      if (vtv[j - j0] == 0.0) continue;
+      parallel_for(
+          j1 - j - 1,
+          [&](int64_t a0, int64_t a1) {
+            for (int64_t c = j + 1 + a0; c < j + 1 + a1; ++c) apply(j, j - j0, &A[(size_t)c * m]);
+          },
+          true);
+    }
+    // columns right of the block, two at a time so that each pass over a
+    // reflector serves both (same arithmetic per column as apply)
+    const int64_t npair = (d - j1 + 1) / 2;
+    parallel_for(npair, [&](int64_t a0, int64_t a1) {
+      for (int64_t q = a0; q < a1; ++q) {
+        const int64_t c = j1 + 2 * q;
+        double *c0 = &A[(size_t)c * m];
+        if (c + 1 >= d) {
+          for (int j = j0; j < j1; ++j)
+            if (vtv[j - j0] != 0.0) apply(j, j - j0, c0);
+          continue;
+        }
+        double *c1 = c0 + m;
+        for (int j = j0; j < j1; ++j) {
+          if (vtv[j - j0] == 0.0) continue;
+          const double *v = vs[j - j0].data();
+          const double f0 = 2.0 * dot8(v, c0 + j, m - j) / vtv[j - j0];
+          const double f1 = 2.0 * dot8(v, c1 + j, m - j) / vtv[j - j0];
+          for (int64_t i = j; i < m; ++i) {
+            c0[i] -= f0 * v[i - j];
+            c1[i] -= f1 * v[i - j];
+          }
+        }
       }
     });
-    for (int c = j + 1; c < d; ++c) R[(size_t)j * d + c] = A[(size_t)c * m + j];
+    // row j of R is final once reflector j has reached the columns right of it
+    for (int j = j0; j < j1; ++j)
+      for (int c = j + 1; c < d; ++c) R[(size_t)j * d + c] = A[(size_t)c * m + j];
   }
   // columns of G = R^T are the rows of R
   jacobi_left(R, d, U, s);
@@ -438,12 +490,7 @@ void jacobi_left(std::vector<double> &G, int d, std::vector<double> &U, std::vec
     for (int p = 0; p < d - 1; ++p)
       for (int q = p + 1; q < d; ++q) {
         double *gp = &G[(size_t)p * d], *gq = &G[(size_t)q * d];
-        double a = 0, b = 0, c = 0;
-        for (int i = 0; i < d; ++i) {
-          a += gp[i] * gp[i];
-          b += gq[i] * gq[i];
-          c += gp[i] * gq[i];
-        }
+        const double a = dot8(gp, gp, d), b = dot8(gq, gq, d), c = dot8(gp, gq, d);
         if (std::fabs(c) <= 1e-15 * std::sqrt(a * b) || c == 0.0) continue;
         rotated = true;
         const double zeta = (b - a) / (2.0 * c);

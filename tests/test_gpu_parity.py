@@ -214,6 +214,33 @@ def test_deterministic(E, torch_dev, c1_inputs):
         plan.close()
 
 
+def test_degenerate_inputs(E, torch_dev, oracle_lib):
+    """No points; one point; 300 copies of one point.  A singular kernel skips
+    every pair at distance 0, so 1/r gives exactly zero for coincident points;
+    exp(-r^2) counts them all (f_i = sum of sigma)."""
+    torch, dev = torch_dev
+    P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 0, 3, 1e-4)
+    P.set_points(torch.zeros(3, 0, dtype=torch.float64, device=dev))
+    f = P.evaluate(torch.zeros(0, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    assert f.numel() == 0
+    P.close()
+    one = np.array([[0.25], [0.5], [0.75]])
+    P, f = _gpu_eval(E, torch_dev, "laplace", 0, one, np.array([2.0]), 3, 1e-4)
+    P.close()
+    np.testing.assert_array_equal(f, [0.0])
+    same = np.repeat(np.array([[0.3], [0.6], [0.9]]), 300, axis=1)
+    s = W.potentials(300, 5)
+    P, f = _gpu_eval(E, torch_dev, "laplace", 0, same, s, 3, 1e-4)
+    P.close()
+    np.testing.assert_array_equal(f, np.zeros(300))
+    P, f = _gpu_eval(E, torch_dev, "gauss", 1.0, same, s, 3, 1e-6)
+    P.close()
+    np.testing.assert_allclose(f, np.full(300, s.sum()), rtol=0, atol=1e-12 * np.abs(s).sum())
+    np.testing.assert_allclose(oracle_lib.direct("gauss", 1.0, same, same, s), f, rtol=0,
+                               atol=1e-12 * np.abs(s).sum())
+
+
 def test_error_paths(E, torch_dev):
     torch, dev = torch_dev
     x = W.uniform_points(100, 81)
