@@ -523,13 +523,28 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = cv ? x[16 * bi + rs + 4 * q] : 0.0;
     const double *Ar = D.Tf + (int64_t)bi * nb * 256 + lane;
-    for (int bj = 0; bj < bi; ++bj) {
+    // two independent accumulation chains (even and odd tiles), added at the end
+    v4 acc2 = {0, 0, 0, 0};
+    int bj = 0;
+    for (; bj + 1 < bi; bj += 2) {
+      const double *Ab = Ar + bj * 256;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
+                                                   0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[256 + ks * 64],
+                                                    zs[((bj + 1) * 4 + ks) * 64 + lane], acc2, 0,
+                                                    0, 0);
+      }
+    }
+    if (bj < bi) {
       const double *Ab = Ar + bj * 256;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
                                                    0, 0, 0);
     }
+    acc += acc2;
     const double *Ad = Ar + bi * 256;
     v4 z = {0, 0, 0, 0};
 #pragma unroll
@@ -548,13 +563,27 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = zs[(bi * 4 + q) * 64 + lane];
     const double *Ar = D.Tb + (int64_t)bi * nb * 256 + lane;
-    for (int bj = bi + 1; bj < nb; ++bj) {
+    v4 acc2 = {0, 0, 0, 0};
+    int bj = bi + 1;
+    for (; bj + 1 < nb; bj += 2) {
+      const double *Ab = Ar + bj * 256;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
+                                                   0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[256 + ks * 64],
+                                                    zs[((bj + 1) * 4 + ks) * 64 + lane], acc2, 0,
+                                                    0, 0);
+      }
+    }
+    if (bj < nb) {
       const double *Ab = Ar + bj * 256;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
                                                    0, 0, 0);
     }
+    acc += acc2;
     const double *Ad = Ar + bi * 256;
     v4 w = {0, 0, 0, 0};
 #pragma unroll
@@ -869,9 +898,13 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
+      // up to 5 row blocks every block is multiplied: the A chunk holds zeros
+      // beyond the operator's rows (their results are not stored), and a branch
+      // per block would split the products into pieces that each wait for their
+      // LDS reads.  With 6 blocks the unbranched form runs out of registers.
 #pragma unroll
       for (int i = 0; i < RBT; ++i)
-        if (rowok[i]) {
+        if (RBT <= 5 || rowok[i]) {
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
