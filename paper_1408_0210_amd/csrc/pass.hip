@@ -21,6 +21,16 @@
 namespace eifmm {
 
 // ------------------------------------------------------------------ kernels k
+// 1/sqrt(r2) for r2 > 0: the hardware reciprocal square root y, refined with
+// t = 1 - r2 y^2 by the series (1 - t)^(-1/2) = 1 + t/2 + 3 t^2 / 8 + ...,
+// i.e. y (1 + t (1/2 + 3 t / 8)).  r2 = 0 gives NaN; the callers that can meet
+// it (the near field of a singular kernel) replace the value.
+__device__ inline double rsq_refined(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double t = fma(-r2 * y, y, 1.0);
+  return fma(y * t, fma(t, 0.375, 0.5), y);
+}
+
 template <int KIND>
 struct KF {
   static constexpr bool singular = (KIND == EIFMM_K_LAPLACE || KIND == EIFMM_K_YUKAWA ||
@@ -30,19 +40,19 @@ struct KF {
   // advection-diffusion a
   __device__ static inline double eval(double r2, double zx, double p) {
     if constexpr (KIND == EIFMM_K_LAPLACE) {
-      return rsqrt(r2);
+      return rsq_refined(r2);
     } else if constexpr (KIND == EIFMM_K_YUKAWA) {
-      double ri = rsqrt(r2);
+      double ri = rsq_refined(r2);
       return exp(-p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_GAUSS) {
       return exp(-r2 * p);
     } else if constexpr (KIND == EIFMM_K_COSR) {
-      double ri = rsqrt(r2);
+      double ri = rsq_refined(r2);
       return cos(p * (r2 * ri)) * ri;
     } else if constexpr (KIND == EIFMM_K_MQ) {
       return sqrt(r2 + p);
     } else if constexpr (KIND == EIFMM_K_ADVDIFF) {
-      double ri = rsqrt(r2);
+      double ri = rsq_refined(r2);
       return exp(p * (zx - r2 * ri)) * ri;
     } else {
       return r2;
