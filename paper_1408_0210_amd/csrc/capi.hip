@@ -91,6 +91,12 @@ void release(eifmm_plan h) {
     hipEventDestroy(e.b);
   }
   for (void *p : owned(h)) hipFree(p);
+  if (P.side) {
+    hipStreamSynchronize(P.side);
+    hipStreamDestroy(P.side);
+  }
+  if (P.ev_fork) hipEventDestroy(P.ev_fork);
+  if (P.ev_join) hipEventDestroy(P.ev_join);
   if (P.job_evt) {
     hipEventSynchronize(P.job_evt);
     hipEventDestroy(P.job_evt);
@@ -557,6 +563,11 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   if (st == EIFMM_OK && !P.host_only) {
     st = setup_tables(h);
     if (st == EIFMM_OK) st = setup_workspaces(h, nullptr);
+    if (st == EIFMM_OK &&
+        (hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming) != hipSuccess))
+      st = EIFMM_EHIP;
     if (st == EIFMM_OK) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) st = EIFMM_EHIP;

@@ -1728,11 +1728,22 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   const int64_t nchunk = P.nchunk;
   const LeafDesc LD = leaf_desc(P, nrhs);
   LevelDev &LL = P.ld[depth];
-  // near field
-  if (nleafa > 0) {
-    Timer tm(P, s, EIFMM_PH_P2P);
-    launch_p2p<KIND, false>(mixed, nrhs, nchunk, LD, nullptr, 0, s);
-  }
+  // near field: with a far field to compute it runs on the plan's second stream,
+  // started after P2M so that it overlaps M2M, the solves and the projections
+  // (small MFMA launches that leave the vector units idle); L2P waits for it
+  const bool fork = depth >= 2 && nleafa > 0 && P.side;
+  auto near_field = [&](hipStream_t sn) {
+    if (sn != s) {
+      hipEventRecord(P.ev_fork, s);
+      hipStreamWaitEvent(sn, P.ev_fork, 0);
+    }
+    {
+      Timer tm(P, sn, EIFMM_PH_P2P);
+      launch_p2p<KIND, false>(mixed, nrhs, nchunk, LD, nullptr, 0, sn);
+    }
+    if (sn != s) hipEventRecord(P.ev_join, sn);
+  };
+  if (nleafa > 0 && !fork) near_field(s);
   if (depth < 2) {
     const int64_t m = n * nrhs;
     if (m > 0)
@@ -1746,6 +1757,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_P2M);
     launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, HL.dp, LD, nullptr, 0, s);
   }
+  if (fork) near_field(P.side);
   // step 2: M2M
   {
     Timer tm(P, s, EIFMM_PH_M2M);
@@ -1823,7 +1835,8 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     if (nc > 0)
       hipLaunchKernelGGL(k_trsm, dim3((nc + 15) / 16), dim3(64), trsm_shm(HL.dpB), s, A);
   }
-  // step 7: L2P and the final sum
+  // step 7: L2P and the final sum (after the near field)
+  if (fork) hipStreamWaitEvent(s, P.ev_join, 0);
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_L2P);
     launch_l2p<KIND, false>(nrhs, nchunk, HL.dpB, LD, io, nullptr, nullptr, 0, s);

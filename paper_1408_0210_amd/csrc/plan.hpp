@@ -299,6 +299,10 @@ struct Plan {
   size_t job_cap = 0;             // jobs job_dev and job_pin hold
   GemmJob *job_pin = nullptr;     // pinned staging copy of the job table
   hipEvent_t job_evt = nullptr;   // recorded after the last copy from job_pin
+  // second stream of the pass: the near field runs on it beside the upward pass
+  // (fork after the potentials are gathered, join before L2P)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
