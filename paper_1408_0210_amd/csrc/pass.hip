@@ -232,16 +232,18 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
     double px = 0, py = 0, pz = 0, ps[RB];
+    // a block past the end is padded with the last source at zero potential, so
+    // every block has 64 sources and the pair loop a fixed trip count
     auto load = [&](int base) {
       const int v = base + lane;
-      if (v < S.total) {
-        const int sidx = near_point(v, S.nq, pre, start);
+      if (S.total > 0) {
+        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start);
         px = xyz[sidx];
         py = xyz[n + sidx];
         pz = xyz[2 * n + sidx];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr)
-          ps[rr] = (r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
+          ps[rr] = (v < S.total && r0 + rr < nrhs) ? sig[(int64_t)sidx * nrhs + r0 + rr] : 0.0;
       }
     };
     load(0);
@@ -254,8 +256,10 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
-      const int u0 = 32 * half, u1 = min(u0 + 32, S.total - base);
-      for (int u = u0; u < u1; ++u) {
+      const int u0 = 32 * half;
+      constexpr int kUnroll = RB == 1 ? 8 : 2;  // several RHS hold RB sums per pair already
+#pragma unroll kUnroll
+      for (int u = u0; u < u0 + 32; ++u) {
         const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
         const double r2 = dx * dx + dy * dy + dz * dz;
         double kv = KF<KIND>::eval(r2, dx, D.p);
@@ -307,16 +311,19 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
     for (int rr = 0; rr < RB; ++rr) sum[rr] = cmp[rr] = 0.f;
     double px = 0, py = 0, pz = 0;
     float ps[RB];
+    // padding past the end as in k_p2p64 (zero potential adds exactly zero to
+    // the compensated sums)
     auto load = [&](int base) {
       const int v = base + lane;
-      if (v < S.total) {
-        const int sidx = near_point(v, S.nq, pre, start);
+      if (S.total > 0) {
+        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start);
         px = xyz[sidx];
         py = xyz[n + sidx];
         pz = xyz[2 * n + sidx];
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr)
-          ps[rr] = (r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr] : 0.f;
+          ps[rr] = (v < S.total && r0 + rr < nrhs) ? (float)sig[(int64_t)sidx * nrhs + r0 + rr]
+                                                   : 0.f;
       }
     };
     load(0);
@@ -329,8 +336,10 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
       for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
-      const int u0 = 32 * half, u1 = min(u0 + 32, S.total - base);
-      for (int u = u0; u < u1; ++u) {
+      const int u0 = 32 * half;
+      constexpr int kUnroll = RB == 1 ? 4 : 2;
+#pragma unroll kUnroll
+      for (int u = u0; u < u0 + 32; ++u) {
         const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
         const float r2 = dx * dx + dy * dy + dz * dz;
         float kv = KF<KIND>::evalf(r2, dx, p);
