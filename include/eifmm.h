@@ -193,7 +193,11 @@ int eifmm_set_points_targets(eifmm_plan plan, const double *src_xyz_dev, const d
 /* f = K sigma for nrhs right-hand sides: sigma_dev (n x nrhs, column-major,
  * leading dimension ld >= n) in input order; f_dev (m x nrhs, leading dimension
  * ldf >= m, m = n_targets if > 0, else n) is overwritten in input order.
- * Requires set_points (set_points_targets); nrhs <= max_rhs. */
+ * Requires set_points (set_points_targets); nrhs <= max_rhs.  The work is
+ * ordered on hip_stream: the near field runs on a second stream owned by the
+ * plan, forked from and joined back to hip_stream with events, so completion
+ * of hip_stream's work implies completion of the pass.  Calls on one plan must
+ * not overlap (they share its workspaces). */
 int eifmm_evaluate(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
                    double *f_dev, int64_t ldf, void *hip_stream);
 

@@ -241,6 +241,27 @@ def test_degenerate_inputs(E, torch_dev, oracle_lib):
                                atol=1e-12 * np.abs(s).sum())
 
 
+def test_evaluate_on_another_stream(E, torch_dev, c1_inputs):
+    """The pass follows the caller's stream (its near field forks to the plan's
+    second stream and joins back): the same bits on a side torch stream."""
+    torch, dev = torch_dev
+    x, s, w = c1_inputs
+    plan = E.Plan(w["kernel"], w["param"], [0, 0, 0], 1.0, x.shape[1], w["depth"], w["tau"])
+    plan.set_points(torch.from_numpy(x).to(dev))
+    sd = torch.from_numpy(s).to(dev)
+    f0 = plan.evaluate(sd)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        f1 = plan.evaluate(sd)
+        f2 = plan.evaluate(sd)
+    side.synchronize()
+    np.testing.assert_array_equal(f1.cpu().numpy(), f0.cpu().numpy())
+    np.testing.assert_array_equal(f2.cpu().numpy(), f0.cpu().numpy())
+    plan.close()
+
+
 def test_error_paths(E, torch_dev):
     torch, dev = torch_dev
     x = W.uniform_points(100, 81)
