@@ -280,7 +280,7 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
 
 // Mixed-precision near field: the coordinate differences are taken in FP64 and
 // rounded once to FP32 (so a close pair keeps its relative accuracy however
-// crowded the leaf), kernel values and products in FP32, Neumaier-compensated
+// crowded the leaf), kernel values and products in FP32, two-sum-compensated
 // FP32 sums per half, the two halves and their compensations added in FP64.
 template <int KIND, int RB, bool BATCH>
 __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__restrict__ many,
@@ -346,9 +346,12 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
         if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
+          // the rounding error of sum + w, exactly, by the branch-free two-sum
+          // (Knuth): no magnitude comparison as in Neumaier's form
           const float w = ss[u * RB + rr] * kv;
           const float tsum = sum[rr] + w;
-          cmp[rr] += (fabsf(sum[rr]) >= fabsf(w)) ? ((sum[rr] - tsum) + w) : ((w - tsum) + sum[rr]);
+          const float bv = tsum - sum[rr];
+          cmp[rr] += (sum[rr] - (tsum - bv)) + (w - bv);
           sum[rr] = tsum;
         }
       }
