@@ -557,6 +557,7 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out) {
   P.host_only = (cfg->flags & EIFMM_FLAG_HOST_ONLY) != 0;
   P.gpu_setup = !P.host_only && !(cfg->flags & EIFMM_FLAG_HOST_SETUP);
   P.gpu_ops = P.gpu_setup;
+  P.il_lazy = true;  // a single plan counts its interaction pairs when asked
   P.two_eim = uses_two_eim(*cfg);
   if (!P.host_only) hipGetDevice(&P.device);
   st = build_tables(P);

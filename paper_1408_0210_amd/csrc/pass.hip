@@ -1360,7 +1360,6 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     jt.m2l_first = (int)h.size();
     const LevelHost &F = P.lh[depth];
     jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16);
-    double flops = 0;
     for (int k = depth; k >= 2; --k) {
       if (uses_m2l2(P, k)) continue;  // the factored M2L below
       const bool cz = P.lh[k].r > 0;
@@ -1392,8 +1391,6 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
         finish_job(J, tiles, jt.m2l_rbt);
         h.push_back(J);
       }
-      const double rm = cz ? P.lh[k].r : P.lh[k].dB, rk = cz ? P.lh[k].r : P.lh[k].d;
-      flops += 2.0 * rm * rk * (double)P.il_pairs[k] * nrhs;
     }
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
@@ -1410,10 +1407,6 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       M2l2Launch L{(int)mj.size(), 0, item, 0, tilec, 0, rb};
       for (int k = depth; k >= 2; --k) {
         if (!uses_m2l2(P, k) || P.lh[k].rp != 16 * rb) continue;
-        double smean = 0;
-        for (int o = 0; o < kNumOffsets; ++o) smean += P.lh[k].s2[o];
-        smean /= kNumOffsets;
-        flops += 4.0 * P.lh[k].r * smean * (double)P.il_pairs[k] * nrhs;
         for (int c = 0; c < 8; ++c) {
           const int64_t nt = P.cls_off[k][c + 1] - P.cls_off[k][c];
           if (nt == 0) continue;
@@ -1446,7 +1439,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       L.ntiles = tilec - L.first_tile;
       if (L.njobs) ml.push_back(L);
     }
-    P.m2l_flops = flops;
+    P.m2l_flops = m2l_flops_of(P, nrhs);
   }
   // g = U g' on compressed levels
   {
@@ -1910,6 +1903,29 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
   }
   P.last_rhs = nrhs;
   return EIFMM_OK;
+}
+
+// 2 (rows x columns) per interaction pair on dense and stage-1 levels (the
+// compressed sizes where compressed); 2 (r s + s r) with the factored M2L, s the
+// mean second-stage rank over the 316 offsets standing in for the offsets the
+// pairs actually use
+double m2l_flops_of(const Plan &P, int nrhs) {
+  double f = 0;
+  for (int k = 2; k <= P.depth; ++k) {
+    const LevelHost &L = P.lh[k];
+    const double pairs = (double)P.il_pairs[k] * nrhs;
+    if (uses_m2l2(P, k)) {
+      double smean = 0;
+      for (int o = 0; o < kNumOffsets; ++o) smean += L.s2[o];
+      smean /= kNumOffsets;
+      f += 4.0 * L.r * smean * pairs;
+    } else {
+      const bool cz = L.r > 0;
+      const double rm = cz ? L.r : L.dB, rk = cz ? L.r : L.d;
+      f += 2.0 * rm * rk * pairs;
+    }
+  }
+  return f;
 }
 
 int materialize_expansion(Plan &P, int which, int k) {

@@ -276,6 +276,10 @@ struct Plan {
   int64_t cls_off[kMaxLevels][9] = {{0}};
   int64_t near_total = 0;
   int64_t il_pairs[kMaxLevels] = {0};
+  // interaction-pair counts (statistics: M2L flops) counted on demand, when the
+  // statistics are read, instead of with every tree (il_lazy); il_pending: the
+  // current tree's counts are not taken yet
+  bool il_lazy = false, il_pending = false;
 
   // per-evaluate buffers
   int max_rhs = 1;
@@ -343,6 +347,9 @@ int pass_run(Plan &P, const double *sigma, int nrhs, int64_t ld, double *f, int6
 // Writes an expansion of the last pass that the pass itself skipped (What of a
 // compressed level), on the null stream.
 int materialize_expansion(Plan &P, int which, int k);
+// algorithmic M2L flops of one evaluation with nrhs right-hand sides, from the
+// interaction-pair counts
+double m2l_flops_of(const Plan &P, int nrhs);
 // solves the M2M / L2L operator rows of parent level k on the device
 // (LevelHost::m2m_rows, l2l_rows, solved in place)
 int solve_operators_gpu(Plan &P, int k);

@@ -450,6 +450,17 @@ int64_t build_list(Plan &P, int k, int mode, int *ptr, int *src, int16_t *off, s
 
 }  // namespace
 
+// interaction-list pairs of levels 2..depth (64-bit count in ints 10-11 of each
+// level's block of counts_dev, zeroed with the tree)
+void il_count_launch(Plan &P, hipStream_t s) {
+  for (int k = 2; k <= P.depth; ++k) {
+    const int grid = (int)((P.ld[k].cap + 255) / 256);
+    hipLaunchKernelGGL(k_il_count, dim3(grid), dim3(256), 0, s, k, P.ld[k].act,
+                       P.counts_dev + 16 * k + 8, P.ld[k].slot,
+                       (unsigned long long *)(P.counts_dev + 16 * k + 10));
+  }
+}
+
 int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   const int64_t n = P.n;
   const int depth = P.depth;
@@ -475,13 +486,7 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s,
                        n, P.keys, nleaf, 1, 1, P.tgt_begin);
   for (int k = std::min(2, depth); k <= depth; ++k) build_active(P, k, s);
-  for (int k = 2; k <= depth; ++k) {
-    const int grid = (int)((P.ld[k].cap + 255) / 256);
-    // 64-bit pair count in ints 10-11 of the level's block (8-byte aligned)
-    hipLaunchKernelGGL(k_il_count, dim3(grid), dim3(256), 0, s, k, P.ld[k].act,
-                       P.counts_dev + 16 * k + 8, P.ld[k].slot,
-                       (unsigned long long *)(P.counts_dev + 16 * k + 10));
-  }
+  if (!P.il_lazy) il_count_launch(P, s);
   int host_counts[16 * kMaxLevels + 1];
   hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
                  s);
@@ -497,10 +502,13 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     P.nact[k] = host_counts[16 * k + 8];
     for (int c = 0; c < 8; ++c) P.cls_off[k][c] = host_counts[16 * k + c];
     P.cls_off[k][8] = P.nact[k];
-    unsigned long long ilp = 0;
-    std::memcpy(&ilp, &host_counts[16 * k + 10], sizeof(ilp));
-    P.il_pairs[k] = k >= 2 ? (int64_t)ilp : 0;
+    if (!P.il_lazy) {
+      unsigned long long ilp = 0;
+      std::memcpy(&ilp, &host_counts[16 * k + 10], sizeof(ilp));
+      P.il_pairs[k] = k >= 2 ? (int64_t)ilp : 0;
+    }
   }
+  P.il_pending = P.il_lazy;
   // near lists of the leaf level (used by the near-field pass); at most 27
   // entries per box, within near_cap = 27 cap
   build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, true, s);
@@ -532,6 +540,22 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
 // Copies the counts the tree build leaves on the device (near-list entries,
 // near-field point pairs) to the plan; synchronises the host with the device.
 int tree_counts(Plan &P) {
+  if (P.il_pending) {
+    // the tree's interaction pairs, counted now (the tree is complete once the
+    // device is idle), and the M2L flops of the jobs built on it
+    int hc[16 * kMaxLevels];
+    if (hipDeviceSynchronize() != hipSuccess) return EIFMM_EHIP;
+    il_count_launch(P, nullptr);
+    if (hipMemcpy(hc, P.counts_dev, sizeof(hc), hipMemcpyDeviceToHost) != hipSuccess)
+      return EIFMM_EHIP;
+    for (int k = 2; k <= P.depth; ++k) {
+      unsigned long long ilp = 0;
+      std::memcpy(&ilp, &hc[16 * k + 10], sizeof(ilp));
+      P.il_pairs[k] = (int64_t)ilp;
+    }
+    P.il_pending = false;
+    if (P.jobs.nrhs > 0) P.m2l_flops = m2l_flops_of(P, P.jobs.nrhs);
+  }
   if (!P.counts_pending) return EIFMM_OK;
   const int depth = P.depth;
   int total = 0;
