@@ -52,29 +52,124 @@ def _rel_sample(f, idx, ref):
     return float(np.linalg.norm(f[idx] - ref) / np.linalg.norm(ref))
 
 
-def cpu_baseline(kernel, param, x, s, gpu_f, target_seconds=12.0):
-    """Time the oracle direct sum on a bounded sample of targets; reuse its values
-    as the reference for the sampled accuracy of the GPU result.  A probe of 1024
-    targets (long enough to hide the thread start-up) sizes the sample."""
-    import oracle
+def host_info():
+    """The host's logical CPU count (nproc), the CPUs this process may run on (its
+    affinity mask), the CPU model (/proc/cpuinfo) and the cgroup CPU quota in
+    cores (None when unlimited or unreadable)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    return dict(nproc=os.cpu_count() or 1, available=avail, model=model, cgroup_quota=quota)
+
+
+def ref_threads():
+    """Threads for the oracle's reference values (accuracy checks): every CPU this
+    process may run on."""
+    return host_info()["available"]
+
+
+def _direct_rate(oracle, kernel, param, x, s, threads, target_seconds, rng):
+    """The oracle's direct sum of a random sample of targets against all sources at
+    the given thread count, the sample sized by a probe to about target_seconds."""
     n = x.shape[1]
-    cores = min(os.cpu_count() or 1, 16)
-    rng = np.random.default_rng(12345)
-    npr = min(n, 1024)
+    npr = min(n, 256 if threads == 1 else 1024)
     probe = rng.choice(n, npr, replace=False)
     t0 = time.perf_counter()
-    oracle.direct(kernel, param, x[:, probe].copy(), x, s, threads=cores)
+    oracle.direct(kernel, param, x[:, probe].copy(), x, s, threads=threads)
     dt = max(time.perf_counter() - t0, 1e-6)
-    m = int(min(n, max(256, npr * target_seconds / dt)))
+    m = int(min(n, max(64, npr * target_seconds / dt)))
     idx = np.sort(rng.choice(n, m, replace=False))
     t0 = time.perf_counter()
-    ref = oracle.direct(kernel, param, x[:, idx].copy(), x, s, threads=cores)
+    ref = oracle.direct(kernel, param, x[:, idx].copy(), x, s, threads=threads)
     dt = time.perf_counter() - t0
-    rate = m * n / dt
+    return m * n / dt, m, dt, idx, ref
+
+
+def cpu_baseline(kernel, param, x, s, gpu_f, oracle_eifmm=None):
+    """The oracle as it stands, timed on this host's cores: its direct sum on a
+    bounded sample of targets (all N sources) with one thread and with every
+    logical CPU (the all-core sample's values also give the sampled rel-L2 error
+    of the GPU result), and its plain EIFMM (Algorithm 3) timed in a separate
+    process (oracle_eifmm, see oracle_eifmm_timing)."""
+    import oracle
+    n = x.shape[1]
+    h = host_info()
+    th = h["available"]
+    rng = np.random.default_rng(12345)
+    r1, m1, dt1, _, _ = _direct_rate(oracle, kernel, param, x, s, 1, 6.0, rng)
+    ra, ma, dta, idx, ref = _direct_rate(oracle, kernel, param, x, s, th, 12.0, rng)
     err = _rel_sample(gpu_f, idx, ref) if gpu_f is not None else None
-    return dict(value=rate, unit="interactions/s", cores=cores, kind="oracle",
-                sample=f"direct sum of {m} random targets against all {n} sources "
-                       f"({dt:.1f} s), rate scaled to N^2/t"), err, idx, ref
+    out = dict(value=ra, unit="interactions/s", cores=th, kind="oracle",
+               sample=f"direct sum of {ma} random targets against all {n} sources on "
+                      f"{th} threads ({dta:.1f} s), rate scaled to N^2/t",
+               nproc=h["nproc"], cpus_available=th, cgroup_cpu_quota=h["cgroup_quota"],
+               cpu_model=h["model"],
+               one_core=dict(value=r1, targets=m1, seconds=dt1),
+               all_core=dict(value=ra, threads=th, targets=ma, seconds=dta))
+    if oracle_eifmm is not None:
+        out["oracle_eifmm"] = oracle_eifmm
+    return out, err, idx, ref
+
+
+ORACLE_EIFMM_CASES = (("uniform2k_laplace_d3", 2000, 3, 1, 2), ("uniform100k_laplace_d4", 100_000, 4, 5, 6))
+
+
+def oracle_eifmm_timing():
+    """Child-process body: the oracle's plain EIFMM (one thread: its evaluation
+    is a sequence of plain loops) on the 2000-point case and on a 1e5-point cube
+    (1/r, tau 1e-6, depths 3 and 4): setup (Algorithm 1 per level and the
+    operators) and one evaluation, timed separately; prints one JSON line."""
+    import oracle
+    from paper_1408_0210_amd import workloads as W
+    try:  # one CPU of the set, the last; the parent's reference sums leave it free
+        os.sched_setaffinity(0, {max(os.sched_getaffinity(0))})
+    except (AttributeError, OSError):
+        pass
+    out = {}
+    for name, n, depth, sp, ss in ORACLE_EIFMM_CASES:
+        x, s = W.uniform_points(n, sp), W.potentials(n, ss)
+        t0 = time.perf_counter()
+        P = oracle.Plan("laplace", 0.0, [0, 0, 0], 1.0, depth, 1e-6)
+        ts = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        P.evaluate(x, s, threads=1)
+        te = time.perf_counter() - t0
+        out[name] = dict(n=n, depth=depth, tau=1e-6, threads=1, setup_s=ts, evaluate_s=te,
+                         value=float(n) ** 2 / te, unit="interactions/s (N^2/t, evaluate)")
+        del P
+    print(json.dumps(out), flush=True)
+
+
+def start_oracle_eifmm():
+    """Starts oracle_eifmm_timing in a child process on one core (it overlaps the
+    GPU legs; the direct-sum samples wait for it)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-eifmm-child"],
+                            stdout=subprocess.PIPE, text=True, env=env, cwd=ROOT)
+
+
+def finish_oracle_eifmm(proc):
+    out, _ = proc.communicate()
+    if proc.returncode != 0:
+        return {"error": f"exit status {proc.returncode}"}
+    return json.loads(out.strip().splitlines()[-1])
 
 
 def run_plain(args, workload=None, precision=None, steps=None, warmup=None, data=None,
@@ -140,7 +235,7 @@ def run_clustered(args):
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(w["n"], 1000, replace=False))
     ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
-                        threads=min(os.cpu_count() or 1, 16))
+                        threads=ref_threads())
     ctol = args.compress_tol if args.compress_tol is not None else w["compress_tol"]
     B = E.Batch([dict(kernel=w["kernel"], param=w["param"], n=w["n"], tau=w["tau"],
                       compress_tol=ctol, depth=None)], precision="mixed")
@@ -190,7 +285,7 @@ def run_paper_kernels(args):
         rng = np.random.default_rng(13)
         idx = np.sort(rng.choice(w["n"], 500, replace=False))
         ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
-                            threads=min(os.cpu_count() or 1, 16))
+                            threads=ref_threads())
         st = r["stats"]
         out[name] = {"kernel": w["kernel"], "param": w["param"], "tau": w["tau"],
                      "ms_per_step": r["ms"], "value": float(w["n"]) ** 2 / (r["ms"] * 1e-3),
@@ -215,7 +310,7 @@ def run_targets(args):
     xs, xt, s = W.make_points(w), W.make_targets(w), W.make_sigma(w)
     idx = np.sort(np.random.default_rng(17).choice(w["n_targets"], 2000, replace=False))
     ref = oracle.direct(w["kernel"], w["param"], xt[:, idx].copy(), xs, s,
-                        threads=min(os.cpu_count() or 1, 16))
+                        threads=ref_threads())
     dev = torch.device("cuda:0")
     xsd, xtd, sd = (torch.from_numpy(a).to(dev) for a in (xs, xt, s))
     out = {"workload": name, "n_sources": w["n"], "n_targets": w["n_targets"],
@@ -255,7 +350,7 @@ def run_nonsym(args):
     data = (W.make_points(w), W.make_sigma(w))
     idx = np.sort(np.random.default_rng(19).choice(w["n"], 500, replace=False))
     ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
-                        threads=min(os.cpu_count() or 1, 16))
+                        threads=ref_threads())
     out = {"workload": name, "n": w["n"], "kernel": w["kernel"], "param": w["param"],
            "depth": w["depth"], "tau": w["tau"]}
     for key, prec, ctol in (("fp64", "fp64", w["compress_tol"]), ("mixed", "mixed", w["compress_tol"]),
@@ -285,7 +380,7 @@ def run_100m(args):
     rng = np.random.default_rng(5)
     idx = np.sort(rng.choice(w["n"], 100, replace=False))
     ref = oracle.direct(w["kernel"], w["param"], data[0][:, idx].copy(), data[0], data[1],
-                        threads=min(os.cpu_count() or 1, 16))
+                        threads=ref_threads())
     out = {"workload": "uniform100m_gauss1_d7", "n": w["n"], "depth": w["depth"],
            "tau": w["tau"], "paper_seconds_1core_total": 2636, "paper_rel_acc": 7e-5}
     for prec in ("fp64", "mixed"):
@@ -349,7 +444,7 @@ def run_batched(args):
     errs = []
     for r in (0, 21, 42, 63):
         ref = oracle.direct(w["kernel"], w["param"], x[:, idx].copy(), x, S[:, r].copy(),
-                            threads=min(os.cpu_count() or 1, 16))
+                            threads=ref_threads())
         errs.append(_rel_sample(fh[r], idx, ref))
     m2l_ms = st["phase_ms"]["m2l"] / max(1, st["phase_calls"]["m2l"])
     plan.close()
@@ -414,7 +509,7 @@ def run_uneven(args):
     for p, q in enumerate(probs):
         idx = np.sort(rng.choice(q["n"], min(50, q["n"]), replace=False))
         fd = oracle.direct(q["kernel"], q["param"], q["points"][:, idx].copy(), q["points"],
-                           q["sigma"], threads=min(os.cpu_count() or 1, 16))
+                           q["sigma"], threads=ref_threads())
         worst = max(worst, _rel_sample(F[p], idx, fd))
     sn2 = float(sum(float(q["n"]) ** 2 for q in probs))
     return dict(value=sn2 / (ms * 1e-3), unit="interactions/s", nprob=len(probs),
@@ -427,6 +522,102 @@ def run_uneven(args):
                 rel_l2_sampled_max=worst, tolerances=W.BATCH_TOLERANCES,
                 note="value = sum N_p^2 / t; t = one graph replay of the fused pass over all "
                      "256 problems (trees built once); errors on 50 sampled targets per problem")
+
+
+# Roofline constants (MI355X, 256 CUs at 2.4 GHz).  MFMA: the dense FP64 and FP32
+# peaks.  VALU: one wave64 instruction per 4 cycles per SIMD, 4 SIMDs per CU, i.e.
+# 256 * 4 * 0.6e9 * 64 = 39.3e12 lane-instruction slots per second (the FP64
+# vector peak of 78.6 TFLOP/s counts an FMA slot as 2 flops).  VALU_SLOTS: issue
+# slots per kernel evaluation of the built gfx950 inner loops for 1/r in FP64 with
+# one right-hand side, read from the AMD assembly of these kernels, with the
+# quarter-rate reciprocal square root counted 4 times: near field 16 instructions
+# (3 differences, r^2 in 3, v_rsq_f64, 5 refinement steps, compare and 2 selects
+# for r = 0, the accumulation) = 19 slots; P2M 13 + 4 = 17; L2P 16 + 4 = 20 (its
+# loop is not unrolled and carries 3 integer instructions).  Tree: bytes per point
+# of the sort and gathers (points read 24 B, keys written 4 B, two radix passes of
+# 16 B each way, sorted points written 24 B, permutation 4 B).
+VALU_PEAK_SLOTS = 256 * 4 * (2.4e9 / 4) * 64
+VALU_SLOTS = {"p2p": 19, "p2m": 17, "l2p": 20}
+HBM_PEAK = 8.0e12
+TREE_BYTES_PER_POINT = 24 + 4 + 2 * 32 + 24 + 4
+
+
+def phase_roofline(st, n, ms_step, precision, kernel):
+    """Per-phase algorithmic work, bound and fraction of that bound, and the
+    composite T_roof / t with T_roof = sum over phases of work / peak.  Phase
+    times are per evaluation (per tree build for the tree) from the plan's
+    events; the near field runs on a second stream beside the upward pass, so
+    phase times overlap and the composite uses the step time."""
+    depth = st["depth"]
+    d, nact, r = st["d"], st["active_boxes"], st["rank"]
+    nev = max(1, st["phase_calls"]["m2l"])
+    ph = {k: st["phase_ms"][k] / nev for k in st["phase_ms"]}
+    ph["tree"] = st["phase_ms"]["tree"] / max(1, st["phase_calls"]["tree"])
+    m2m = sum(2.0 * d[k] * d[k + 1] * nact[k + 1] for k in range(2, depth))
+    l2l = sum(2.0 * d[k] * d[k - 1] * nact[k] for k in range(3, depth + 1))
+    what = sum((1.0 if r[k] else 2.0) * d[k] ** 2 * nact[k] for k in range(2, depth + 1))
+    lhat = 2.0 * d[depth] ** 2 * nact[depth]
+    mfma64 = PEAK_TFLOPS["fp64"] * 1e12
+    m2l_peak = PEAK_TFLOPS[precision] * 1e12
+    rows = {
+        "tree": (TREE_BYTES_PER_POINT * n, "B", "hbm", HBM_PEAK),
+        "m2m": (m2m, "flop", "mfma", mfma64),
+        "what": (what, "flop", "mfma", mfma64),
+        "proj": (st["proj_flops"], "flop", "mfma", mfma64),
+        "m2l": (st["m2l_flops"], "flop", "mfma", m2l_peak),
+        "l2l": (l2l, "flop", "mfma", mfma64),
+        "lhat": (lhat, "flop", "mfma", mfma64),
+    }
+    if precision == "fp64" and kernel == "laplace":
+        rows["p2p"] = (st["near_point_pairs"] * VALU_SLOTS["p2p"], "VALU slots", "alu",
+                       VALU_PEAK_SLOTS)
+        rows["p2m"] = (float(n) * d[depth] * VALU_SLOTS["p2m"], "VALU slots", "alu",
+                       VALU_PEAK_SLOTS)
+        rows["l2p"] = (float(n) * d[depth] * VALU_SLOTS["l2p"], "VALU slots", "alu",
+                       VALU_PEAK_SLOTS)
+    out, troof = {}, 0.0
+    for k, (work, unit, bound, peak) in rows.items():
+        t_min = work / peak
+        troof += t_min
+        ms = ph.get(k, 0.0)
+        out[k] = {"work": work, "unit": unit, "bound": bound, "peak": peak, "ms": ms,
+                  "frac": (t_min / (ms * 1e-3)) if ms > 0 else None}
+    return out, troof * 1e3, troof * 1e3 / ms_step
+
+
+def run_tau_sweep(args, data, idx, ref):
+    """Sec. 5.3 presents the 1/r cube as time against accuracy: the headline
+    workload at EIM tolerances 1e-4 and 1e-8 (1e-6 is the headline itself), with
+    the compression tolerance 6 tau in each, timed like the main run (3 steps)."""
+    out = {}
+    for tau in (1e-4, 1e-8):
+        a = argparse.Namespace(**vars(args))
+        a.tau, a.compress_tol = tau, 6 * tau
+        r = run_plain(a, steps=3, warmup=1, data=data)
+        st = r["stats"]
+        err = _rel_sample(r["f"], idx, ref)
+        out[f"{tau:.0e}"] = {"tau": tau, "compress_tol": 6 * tau, "ms_per_step": r["ms"],
+                             "value": float(r["n"]) ** 2 / (r["ms"] * 1e-3),
+                             "rel_l2_sampled": err, "meets_1e-6": err <= 1e-6,
+                             "d": st["d"], "rank": st["rank"], "setup_s": r["setup_s"]}
+        r["plan"].close()
+    return out
+
+
+def run_mixed_single(args, data, idx, ref):
+    """The headline workload (one right-hand side) in mixed precision: FP32 M2L on
+    MFMA and FP32 near field, the rest FP64; with the phase times that explain
+    where it gains or loses against FP64."""
+    r = run_plain(args, precision="mixed", data=data)
+    st = r["stats"]
+    nev = max(1, st["phase_calls"]["m2l"])
+    out = {"ms_per_step": r["ms"], "value": float(r["n"]) ** 2 / (r["ms"] * 1e-3),
+           "rel_l2_sampled": _rel_sample(r["f"], idx, ref), "rank": st["rank"],
+           "phase_ms_per_step": {k: st["phase_ms"][k] / (nev if k != "tree" else
+                                                         max(1, st["phase_calls"]["tree"]))
+                                 for k in st["phase_ms"]}}
+    r["plan"].close()
+    return out
 
 
 def main():
@@ -465,7 +656,13 @@ def main():
                     help="M2L compression tolerance (Sec. 4.2); default: the workload's; 0 disables it")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (counter calibration) and exit")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the tau sweep and the mixed single-RHS run")
+    ap.add_argument("--oracle-eifmm-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_eifmm_child:
+        oracle_eifmm_timing()
+        return
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda:0")
@@ -486,6 +683,7 @@ def main():
         print(json.dumps({args.only_leg: leg[args.only_leg](args)}), flush=True)
         return
 
+    child = None if args.no_cpu else start_oracle_eifmm()
     r = run_plain(args)
     st, n, ms = r["stats"], r["n"], r["ms"]
     print(f"[bench] {args.workload} precision={args.precision} tau={r['tau']} "
@@ -512,6 +710,7 @@ def main():
                 and not args.depth):
             traffic = tr[key]["bytes_per_launch"]
     phases = {k: st["phase_ms"][k] / max(1, st["phase_calls"][k]) for k in st["phase_ms"]}
+    prow, troof_ms, troof_frac = phase_roofline(st, n, ms, args.precision, r["w"]["kernel"])
     out = {
         "metric": METRIC, "value": float(n) ** 2 / (ms * 1e-3), "unit": "interactions/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -525,13 +724,38 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_gemm M2L (all levels, one launch)",
-                     "flops_per_launch": st["m2l_flops"], "ms_per_launch": m2l_ms},
+                     "flops_per_launch": st["m2l_flops"], "ms_per_launch": m2l_ms,
+                     "rank_filtered": st["rank"], "rank_used": st["rpad"],
+                     "flops_executed": st["m2l_flops_exec"],
+                     "frac_executed": st["m2l_flops_exec"] / (m2l_ms * 1e-3) / (peak * 1e12),
+                     "note": "flops_per_launch: 2 r_k^2 per interaction pair with r_k the rank "
+                             "of the Sec. 4.2 filters (the method's work); flops_executed: what "
+                             "the MFMAs run (rank padded to 16-row blocks, every offset of a "
+                             "child class including sources outside the domain)"},
+        "phase_roofline": prow, "t_roof_ms": troof_ms, "t_roof_frac": troof_frac,
     }
-    if not args.no_cpu:
-        cb, err, _, _ = cpu_baseline(r["w"]["kernel"], r["w"]["param"], r["x"], r["s"], r["f"])
+    r["plan"].close()
+    data = (r["x"], r["s"])
+    rng = np.random.default_rng(23)
+    sidx = np.sort(rng.choice(n, 2000, replace=False))
+    if child is not None:  # keep one CPU free for the oracle EIFMM child
+        import oracle
+        sref = oracle.direct(r["w"]["kernel"], r["w"]["param"], r["x"][:, sidx].copy(), r["x"],
+                             r["s"], threads=max(1, ref_threads() - 1))
+    else:
+        import oracle
+        sref = oracle.direct(r["w"]["kernel"], r["w"]["param"], r["x"][:, sidx].copy(), r["x"],
+                             r["s"], threads=ref_threads())
+    out["config"]["rel_l2_sampled_2000"] = _rel_sample(r["f"], sidx, sref)
+    if not args.no_sweep:
+        out["tau_sweep"] = run_tau_sweep(args, data, sidx, sref)
+        out["mixed_single_rhs"] = run_mixed_single(args, data, sidx, sref)
+    if child is not None:
+        oe = finish_oracle_eifmm(child)
+        cb, err, _, _ = cpu_baseline(r["w"]["kernel"], r["w"]["param"], r["x"], r["s"], r["f"],
+                                     oracle_eifmm=oe)
         out["cpu_baseline"] = cb
         out["config"]["rel_l2_sampled"] = err
-    r["plan"].close()
     if not args.no_batched:
         out["batched_mixed"] = run_batched(args)
     if not args.no_clustered:

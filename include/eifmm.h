@@ -104,15 +104,17 @@ typedef struct {
   int32_t max_rhs;      /* largest nrhs accepted by evaluate (>= 1)                 */
   double eim_tol;       /* tau > 0: the greedy stops when eps_k <= tau * scale       */
   int32_t tol_mode;     /* 0: scale = max |K| over the level's training grid;
-                           1: scale = that of the finest level, for all levels      */
+                           1: scale = that of one level (scale_level, by default
+                           the finest), for all levels                         */
   int32_t precision;    /* EIFMM_PREC_*                                             */
-  int32_t dmax;         /* cap on d_k (0 = 1024); reaching it is EIFMM_EEIM          */
+  int32_t dmax;         /* cap on d_k, 0..1024 (0 = 1024); reaching it is EIFMM_EEIM */
   int32_t flags;        /* EIFMM_FLAG_*                                             */
   double compress_tol;  /* > 0: compress the M2L matrices (Sec. 4.2, first stage):
                            SVD of [K^delta_1 .. K^delta_316] per level; the rank r
                            is the larger of the two filters (s_j/s_0 > eps, and the
-                           prefix holding 1 - eps of the sum of singular values),
-                           rounded up to the MFMA tile granularity; 0 = off.
+                           prefix holding 1 - eps of the sum of singular values);
+                           the device pads it to whole 16-row MFMA blocks with
+                           zero rows and columns (eifmm_stats.rpad); 0 = off.
                            With two EIMs the stacked matrices give the basis of
                            the columns and r is the larger of the two ranks     */
   int64_t n_targets;    /* 0: the targets are the n sources; > 0: that many separate
@@ -122,6 +124,10 @@ typedef struct {
                            each compressed matrix C^delta replaced by its rank-s
                            truncation, s from the same two filters on its own
                            singular values with this tolerance; 0 = off        */
+  int32_t scale_level;  /* tol_mode 1: the level (2..EIFMM_MAX_DEPTH) whose training
+                           grid's max |K| is the scale of every level's stopping
+                           rule; 0 = the plan's depth.  Ignored with tol_mode 0  */
+  int32_t reserved_cfg; /* must be 0                                             */
 } eifmm_config;
 
 /* evaluation phases timed when timing is enabled (eifmm_set_timing) */
@@ -156,11 +162,20 @@ typedef struct {
   int64_t il_pairs[EIFMM_MAX_DEPTH + 1];     /* interaction-list pairs per level */
   int64_t near_pairs;                /* ordered leaf pairs in the near lists      */
   int32_t hip_error;                 /* last hipError_t seen (0 = none)           */
-  int32_t reserved;
+  int32_t scale_level;               /* tol_mode 1: the level whose training max |K|
+                                        scales every stopping rule; 0 otherwise   */
   int64_t near_point_pairs;          /* ordered point pairs (targets x sources) of
                                         the near field, self pairs included      */
   int32_t d2[EIFMM_MAX_DEPTH + 1];   /* d of the second EIM per level (the size of
                                         g, l and lhat), 0 with one EIM           */
+  int32_t rpad[EIFMM_MAX_DEPTH + 1]; /* compressed levels: the rank padded to whole
+                                        16-row MFMA blocks, as the device runs it */
+  int32_t reserved_st;
+  double m2l_flops_exec;             /* M2L flops the MFMAs of the last evaluate
+                                        execute: padded rows and columns (rpad or
+                                        dpad), and every one of the 189 offsets of
+                                        a box's child class, sources outside the
+                                        domain included                          */
 } eifmm_stats;
 
 /* Per-level EIM plan: runs Algorithm 1 for k = 2..depth on the training sets,

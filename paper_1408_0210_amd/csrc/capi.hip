@@ -69,8 +69,13 @@ int validate(const eifmm_config *c) {
   if (c->max_rhs < 1 || c->max_rhs > 4096) return EIFMM_EINVAL;
   if (!(c->eim_tol > 0) || !std::isfinite(c->eim_tol)) return EIFMM_EINVAL;
   if (c->tol_mode < 0 || c->tol_mode > 1) return EIFMM_EINVAL;
+  if (c->scale_level != 0 && (c->scale_level < 2 || c->scale_level > EIFMM_MAX_DEPTH))
+    return EIFMM_EINVAL;
+  if (c->reserved_cfg != 0) return EIFMM_EINVAL;
   if (c->precision != EIFMM_PREC_FP64 && c->precision != EIFMM_PREC_MIXED) return EIFMM_EINVAL;
-  if (c->dmax < 0 || c->dmax > 4096) return EIFMM_EINVAL;
+  // d_k <= 1024: the triangular solves keep a wave's 16 solved columns in LDS
+  // (128 dp bytes) and the near-field / L2P launches stage d_k points
+  if (c->dmax < 0 || c->dmax > 1024) return EIFMM_EINVAL;
   if (!(c->compress_tol >= 0) || !std::isfinite(c->compress_tol)) return EIFMM_EINVAL;
   if (!(c->compress_tol2 >= 0) || !std::isfinite(c->compress_tol2) ||
       (c->compress_tol2 > 0 && !(c->compress_tol > 0)))
@@ -334,7 +339,7 @@ bool same_tables(const eifmm_config &a, const eifmm_config &b) {
   return a.kernel == b.kernel && a.kernel_param == b.kernel_param && a.lo[0] == b.lo[0] &&
          a.lo[1] == b.lo[1] && a.lo[2] == b.lo[2] && a.L == b.L && a.eim_tol == b.eim_tol &&
          a.tol_mode == b.tol_mode && a.dmax == b.dmax && a.compress_tol == b.compress_tol &&
-         a.precision == b.precision;
+         a.precision == b.precision && (a.tol_mode == 0 || a.scale_level == b.scale_level);
 }
 
 // depths the autotuner tries for n points: around log8(n / 32), within 2..8
@@ -353,6 +358,9 @@ int shared_plan(eifmm_batch b, int p, int depth, eifmm_plan *out) {
   Plan &P = h->P;
   P.cfg = b->cfg[p];
   P.cfg.depth = depth;
+  // the absolute stopping rule of the shared tables takes its scale from their
+  // deepest level unless the configuration names one
+  if (P.cfg.tol_mode == 1 && P.cfg.scale_level == 0) P.cfg.scale_level = T.depth;
   P.depth = depth;
   P.n = P.ns = P.cfg.n;
   P.max_rhs = 1;
@@ -686,6 +694,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
     s.d[k] = P.lh[k].d;
     s.dpad[k] = P.lh[k].dp;
     s.rank[k] = P.lh[k].r;
+    s.rpad[k] = P.lh[k].rp;
     s.d2[k] = P.two_eim ? P.lhB[k].d : 0;
     s.eim_err[k] = P.lh[k].err;
   }
@@ -695,7 +704,9 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
     s.phase_calls[q] = P.phase_calls[q];
   }
   s.m2l_flops = P.m2l_flops;
+  s.m2l_flops_exec = P.m2l_flops_exec;
   s.proj_flops = P.proj_flops;
+  if (P.cfg.tol_mode == 1) s.scale_level = P.cfg.scale_level > 0 ? P.cfg.scale_level : P.depth;
   for (int k = 0; k <= P.depth; ++k) {
     s.active_boxes[k] = P.nact[k];
     s.il_pairs[k] = P.il_pairs[k];

@@ -367,8 +367,8 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
 
 // ------------------------------------------------------------------ P2M
 // W^I_m = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I)  (Algorithm 3, step 1)
-// One NT-thread workgroup per leaf (NT = 64 when d <= 64, else 256); thread t
-// owns rows m = t + NT u, u < 4.
+// One NT-thread workgroup per leaf (NT = 64 when d <= 64, else 256); rows are
+// taken in groups of 4 NT, thread t owning rows m0 + t + NT u, u < 4, of group m0.
 template <int KIND, int RB, bool BATCH, int NT>
 __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__restrict__ many,
                                              int nmany) {
@@ -386,54 +386,57 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
-  const int nu = (dp + NT - 1) / NT;
-  double xm[4], ym[4], zm[4];
+  for (int m0 = 0; m0 < dp; m0 += 4 * NT) {
+    const int nu = min(4, (dp - m0 + NT - 1) / NT);
+    double xm[4], ym[4], zm[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int m = t + NT * u;
-    const bool ok = u < nu && m < d;
-    xm[u] = ok ? D.X[3 * m] : 0.0;
-    ym[u] = ok ? D.X[3 * m + 1] : 0.0;
-    zm[u] = ok ? D.X[3 * m + 2] : 0.0;
-  }
-  for (int r0 = 0; r0 < nrhs; r0 += RB) {
-    double acc[4][RB];
+    for (int u = 0; u < 4; ++u) {
+      const int m = m0 + t + NT * u;
+      const bool ok = u < nu && m < d;
+      xm[u] = ok ? D.X[3 * m] : 0.0;
+      ym[u] = ok ? D.X[3 * m + 1] : 0.0;
+      zm[u] = ok ? D.X[3 * m + 2] : 0.0;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+      double acc[4][RB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) acc[u][rr] = 0.0;
-    for (int s0 = a; s0 < b; s0 += 64) {
-      const int cnt = min(64, b - s0);
-      __syncthreads();
-      if (t < cnt) {
-        const int s = s0 + t;
-        px[t] = xyz[s] - cx;
-        py[t] = xyz[n + s] - cy;
-        pz[t] = xyz[2 * n + s] - cz;
+        for (int rr = 0; rr < RB; ++rr) acc[u][rr] = 0.0;
+      for (int s0 = a; s0 < b; s0 += 64) {
+        const int cnt = min(64, b - s0);
+        __syncthreads();
+        if (t < cnt) {
+          const int s = s0 + t;
+          px[t] = xyz[s] - cx;
+          py[t] = xyz[n + s] - cy;
+          pz[t] = xyz[2 * n + s] - cz;
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-          ps[t * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)s * nrhs + r0 + rr] : 0.0;
-      }
-      __syncthreads();
-      for (int q = 0; q < cnt; ++q) {
+          for (int rr = 0; rr < RB; ++rr)
+            ps[t * RB + rr] = (r0 + rr < nrhs) ? sig[(int64_t)s * nrhs + r0 + rr] : 0.0;
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt; ++q) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (u < nu) {
-            const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
-            const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
+          for (int u = 0; u < 4; ++u) {
+            if (u < nu) {
+              const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
+              const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
 #pragma unroll
-            for (int rr = 0; rr < RB; ++rr) acc[u][rr] += ps[q * RB + rr] * kv;
+              for (int rr = 0; rr < RB; ++rr) acc[u][rr] += ps[q * RB + rr] * kv;
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int m = t + NT * u;
-      if (u < nu && m < dp) {
+      for (int u = 0; u < 4; ++u) {
+        const int m = m0 + t + NT * u;
+        if (u < nu && m < dp) {
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < nrhs) D.W[((int64_t)j * nrhs + r0 + rr) * dp + m] = m < d ? acc[u][rr] : 0.0;
+          for (int rr = 0; rr < RB; ++rr)
+            if (r0 + rr < nrhs)
+              D.W[((int64_t)j * nrhs + r0 + rr) * dp + m] = m < d ? acc[u][rr] : 0.0;
+        }
       }
     }
   }
@@ -1395,6 +1398,13 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     jt.m2l_n = (int)h.size() - jt.m2l_first;
     jt.m2l_tiles = tiles;
     jt.m2l_units = finish_units(h, jt.m2l_first);
+    // executed work: every column walks all terms of its class, over whole row
+    // tiles of the padded operators
+    double fx = 0;
+    for (int j = jt.m2l_first; j < jt.m2l_first + jt.m2l_n; ++j)
+      fx += 2.0 * (double)h[j].nrowtiles * 16 * jt.m2l_rbt * h[j].dpk * (double)h[j].ntgt *
+            h[j].nrhs * h[j].nterms;
+    P.m2l_flops_exec = fx;
     // factored M2L levels: one job per child class, grouped by rp; algorithmic
     // flops 2 (r s_o + s_o r) per interaction pair, with the mean s_o over the
     // 316 offsets standing in for the offsets the pairs actually use

@@ -311,6 +311,7 @@ struct Plan {
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
   double m2l_flops = 0, proj_flops = 0;
+  double m2l_flops_exec = 0;  // what the M2L MFMAs execute (padding, empty sources)
 
   // stats
   bool timing = false;

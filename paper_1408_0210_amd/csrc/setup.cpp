@@ -178,6 +178,32 @@ void finish_eim(const std::vector<double> &tx, const std::vector<double> &ty, do
     }
 }
 
+// max |K| over the training grid of `level`: the scale of the absolute stopping
+// rule (tol_mode 1); swap: the second EIM's grid (D_x = J_0, D_y = I_0).  The
+// same kernel values the greedy of that level starts from, so its first pivot
+// has this magnitude.
+double training_scale(int kind, double p, int level, double L, bool swap) {
+  const double lk = std::ldexp(L, -level - 1);
+  std::vector<double> tx, ty;
+  training_sets(kind, level, lk, tx, ty);
+  if (swap) std::swap(tx, ty);
+  const int64_t nx = (int64_t)tx.size() / 3, ny = (int64_t)ty.size() / 3;
+  std::vector<double> rowmax((size_t)nx, 0.0);
+  parallel_for(nx, [&](int64_t a0, int64_t a1) {
+    for (int64_t a = a0; a < a1; ++a) {
+      double m = 0.0;
+      for (int64_t b = 0; b < ny; ++b)
+        m = std::max(m, std::fabs(kern_host(kind, p, tx[3 * a] - ty[3 * b],
+                                            tx[3 * a + 1] - ty[3 * b + 1],
+                                            tx[3 * a + 2] - ty[3 * b + 2])));
+      rowmax[(size_t)a] = m;
+    }
+  });
+  double m = 0.0;
+  for (double v : rowmax) m = std::max(m, v);
+  return m;
+}
+
 // swap: the second EIM of Sec. 3.1, with D_x = J_0 and D_y = I_0 (X then holds
 // J_0 points, Y holds I_0 points)
 int greedy_eim(int kind, double p, int level, double L, double tau, int dmax, double abs_scale,
@@ -650,12 +676,19 @@ int stage2_factors(const std::vector<double> &C, int r, double eps, std::vector<
 
 }  // namespace
 
-// Row blocks per gathered-GEMM tile for nrb 16-row blocks: a divisor when possible.
+// Row blocks per gathered-GEMM tile for nrb 16-row blocks: the height (4, 5 or 6
+// blocks) that leaves the fewest idle blocks in the last row tile, the taller
+// one on a tie (fewer row tiles read each gathered column).
 int pick_rbt(int nrb) {
-  if (nrb % 6 == 0) return 6;
-  if (nrb % 5 == 0) return 5;
-  if (nrb % 4 == 0) return 4;
-  return 6;
+  int best = 6, waste = 1 << 30;
+  for (int rbt = 6; rbt >= 4; --rbt) {
+    const int w = (nrb + rbt - 1) / rbt * rbt - nrb;
+    if (w < waste) {
+      waste = w;
+      best = rbt;
+    }
+  }
+  return best;
 }
 
 int build_tables(Plan &P) {
@@ -664,13 +697,18 @@ int build_tables(Plan &P) {
   const int depth = c.depth, kind = c.kernel;
   const double p = c.kernel_param, L = c.L;
   const int dmax = c.dmax > 0 ? c.dmax : 1024;
+  // absolute stopping rule: the scale of level scale_level (default: the finest)
   double abs_scale = 0, abs_scale2 = 0;
+  if (c.tol_mode == 1 && depth >= 2) {
+    const int ls = c.scale_level > 0 ? c.scale_level : depth;
+    abs_scale = training_scale(kind, p, ls, L, false);
+    if (P.two_eim) abs_scale2 = training_scale(kind, p, ls, L, true);
+  }
   for (int k = depth; k >= 2; --k) {
     LevelHost &lv = P.lh[k];
     int st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale : 0.0,
                         P.gpu_setup, false, lv);
     if (st != EIFMM_OK) return st;
-    if (k == depth && c.tol_mode == 1) abs_scale = lv.scale;
     crout(kind, p, lv);
     lv.dp = ((lv.d + 15) / 16) * 16;
     if (lv.dp == 0) lv.dp = 16;
@@ -683,7 +721,6 @@ int build_tables(Plan &P) {
       st = greedy_eim(kind, p, k, L, c.eim_tol, dmax, c.tol_mode == 1 ? abs_scale2 : 0.0,
                       P.gpu_setup, true, lb);
       if (st != EIFMM_OK) return st;
-      if (k == depth && c.tol_mode == 1) abs_scale2 = lb.scale;
       crout(kind, p, lb);
       lb.dp = ((lb.d + 15) / 16) * 16;
       if (lb.dp == 0) lb.dp = 16;
@@ -748,12 +785,9 @@ int build_tables(Plan &P) {
         svd_rows(Kthin, d, mt, Vfull, sv2);
         fr = std::max(fr, filter_rank(sv2, c.compress_tol));
       }
-      // rank from the filters, rounded up to whole 16-row blocks that split evenly
-      // into GEMM tiles (extra singular vectors only improve the approximation)
-      const int dmin = std::min(d, dB);
-      int nrb = (fr + 15) / 16;
-      while (nrb * 16 < dmin && nrb % 6 && nrb % 5 && nrb % 4) ++nrb;
-      lv.r = std::min(dmin, nrb * 16);
+      // the rank is the filters' rank; the device tables pad it with zero rows
+      // and columns to whole 16-row MFMA blocks (rp), which changes no result
+      lv.r = std::min(std::min(d, dB), fr);
       lv.rp = ((lv.r + 15) / 16) * 16;
       lv.U.assign((size_t)dB * lv.r, 0.0);
       for (int i = 0; i < dB; ++i)

@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dmax", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("compress_tol", ctypes.c_double), ("n_targets", ctypes.c_int64),
-                ("compress_tol2", ctypes.c_double)]
+                ("compress_tol2", ctypes.c_double), ("scale_level", ctypes.c_int32),
+                ("reserved_cfg", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -52,8 +53,10 @@ class Stats(ctypes.Structure):
                 ("m2l_flops", ctypes.c_double), ("proj_flops", ctypes.c_double),
                 ("active_boxes", ctypes.c_int64 * (MAX_DEPTH + 1)),
                 ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
-                ("hip_error", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("near_point_pairs", ctypes.c_int64), ("d2", ctypes.c_int32 * (MAX_DEPTH + 1))]
+                ("hip_error", ctypes.c_int32), ("scale_level", ctypes.c_int32),
+                ("near_point_pairs", ctypes.c_int64), ("d2", ctypes.c_int32 * (MAX_DEPTH + 1)),
+                ("rpad", ctypes.c_int32 * (MAX_DEPTH + 1)), ("reserved_st", ctypes.c_int32),
+                ("m2l_flops_exec", ctypes.c_double)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -141,7 +144,7 @@ def _stream():
 
 def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64", tol_mode=0,
                 dmax=0, host_only=False, compress_tol=0.0, n_targets=0, host_setup=False,
-                two_eim=False, compress_tol2=0.0):
+                two_eim=False, compress_tol2=0.0, scale_level=0):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.kernel = KERNELS[kernel]
@@ -161,13 +164,16 @@ def make_config(kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64"
     c.compress_tol = float(compress_tol)
     c.n_targets = int(n_targets)
     c.compress_tol2 = float(compress_tol2)
+    c.scale_level = int(scale_level)
     return c
 
 
 def _stats_dict(s, depth):
     lv = range(2, depth + 1)
     return dict(depth=s.depth, d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
-                rank={k: s.rank[k] for k in lv}, proj_flops=s.proj_flops,
+                rank={k: s.rank[k] for k in lv}, rpad={k: s.rpad[k] for k in lv},
+                proj_flops=s.proj_flops, m2l_flops_exec=s.m2l_flops_exec,
+                scale_level=s.scale_level,
                 eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
                 phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},
                 phase_calls={PHASES[q]: s.phase_calls[q] for q in range(NPHASE)},
@@ -185,9 +191,10 @@ class Plan:
 
     def __init__(self, kernel, param, lo, L, n, depth, tau, max_rhs=1, precision="fp64",
                  tol_mode=0, dmax=0, host_only=False, compress_tol=0.0, n_targets=0,
-                 host_setup=False, two_eim=False, compress_tol2=0.0):
+                 host_setup=False, two_eim=False, compress_tol2=0.0, scale_level=0):
         c = make_config(kernel, param, lo, L, n, depth, tau, max_rhs, precision, tol_mode, dmax,
-                        host_only, compress_tol, n_targets, host_setup, two_eim, compress_tol2)
+                        host_only, compress_tol, n_targets, host_setup, two_eim, compress_tol2,
+                        scale_level)
         self.cfg = c
         self.n, self.depth, self.max_rhs = int(n), int(depth), int(max_rhs)
         self.n_targets = int(n_targets)
@@ -218,15 +225,33 @@ class Plan:
         Returns f, (m,) or (nrhs, m) with m the target count, in input order."""
         import torch
         assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
+        assert sigma.dim() in (1, 2)
         nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
         assert sigma.shape[-1] == self.n
+        shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
         if out is None:
-            shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
             out = torch.empty(shape, dtype=torch.float64, device=sigma.device)
+        else:
+            # the library writes nrhs columns of n_out doubles at out's address
+            self.check_out(out, shape, sigma.device)
         _check(lib().eifmm_evaluate(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs, self.n,
                                     ctypes.c_void_p(out.data_ptr()), self.n_out, _stream()),
                "eifmm_evaluate")
         return out
+
+    @staticmethod
+    def check_out(out, shape, device):
+        """An output tensor the library may write: float64, contiguous, on the
+        device of sigma, of the expected shape (raises ValueError otherwise)."""
+        import torch
+        if not isinstance(out, torch.Tensor) or out.dtype != torch.float64:
+            raise ValueError("out must be a float64 tensor")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+        if out.device != device:
+            raise ValueError(f"out is on {out.device}, sigma on {device}")
+        if tuple(out.shape) != tuple(shape):
+            raise ValueError(f"out has shape {tuple(out.shape)}, expected {tuple(shape)}")
 
     def evaluate_raw(self, sigma_ptr, nrhs, ld, f_ptr, ldf, stream=None):
         """Direct pass-through of eifmm_evaluate (for tests of the argument checks)."""
@@ -338,7 +363,8 @@ class Batch:
             arr[i] = make_config(q["kernel"], q.get("param", 0.0), q.get("lo", (0, 0, 0)),
                                  q.get("L", 1.0), q["n"], -1 if depth is None else depth,
                                  q["tau"], 1, precision, q.get("tol_mode", 0), q.get("dmax", 0),
-                                 False, q.get("compress_tol", 0.0))
+                                 False, q.get("compress_tol", 0.0),
+                                 scale_level=q.get("scale_level", 0))
         self.ns = [int(q["n"]) for q in problems]
         self.nprob = n
         h = ctypes.c_void_p()

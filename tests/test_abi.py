@@ -95,7 +95,7 @@ def test_host_setup_matches_oracle(E, oracle_lib, kernel, param, depth, tau):
 def test_host_compression_matches_oracle_svd(E, oracle_lib):
     """The library's SVD (Householder QR, then one-sided Jacobi) against numpy's:
     singular values and the projector onto the kept vectors; the kept rank is the
-    filter rank rounded up to whole 16-row blocks that split into GEMM tiles."""
+    rank of the two filters of Sec. 4.2, as the oracle counts it on numpy's values."""
     P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-4)
     k = 2
     r, sv, U = P.compression(k)
@@ -103,7 +103,7 @@ def test_host_compression_matches_oracle_svd(E, oracle_lib):
     Uo, svo, ro = oracle_lib.compression_basis("laplace", 0, Y, k, 1e-4)
     m = svo / svo[0] > 1e-12
     assert np.abs(sv[m] - svo[m]).max() <= 1e-12 * svo[0]
-    assert ro <= r <= min(P.level(k)["d"], ro + 16 * 4) and r % 16 == 0 or r == P.level(k)["d"]
+    assert r == ro
     Uf, _, _ = oracle_lib.compression_basis("laplace", 0, Y, k, 1e-4, rank=r)
     assert np.abs(U @ U.T - Uf @ Uf.T).max() < 1e-9
     assert np.abs(U.T @ U - np.eye(r)).max() < 1e-12
@@ -141,7 +141,7 @@ def test_two_eim_compression_matches_oracle_svd(E, oracle_lib):
     Uo, Vo, svo, sv2o, ro = oracle_lib.compression_bases("advdiff", 1.0, X, Y, k, 1e-4)
     m = svo / svo[0] > 1e-12
     assert np.abs(sv[m] - svo[m]).max() <= 1e-12 * svo[0]
-    assert ro <= r and (r % 16 == 0 or r == min(len(X), len(Y)))
+    assert r == ro
     Uf, _, _, _, _ = oracle_lib.compression_bases("advdiff", 1.0, X, Y, k, 1e-4, rank=r)
     assert U.shape == (len(X), r)
     assert np.abs(U @ U.T - Uf @ Uf.T).max() < 1e-9
@@ -151,3 +151,61 @@ def test_two_eim_compression_matches_oracle_svd(E, oracle_lib):
 def test_advdiff_rejects_negative_flow(E):
     with pytest.raises(E.EifmmError):
         E.Plan("advdiff", -1.0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True)
+
+def test_scale_level_absolute_rule(E, oracle_lib):
+    """tol_mode 1 with scale_level: the depth itself gives the same tables as the
+    default; a finer level's scale (larger |K| for the Gaussian) gives the points
+    the oracle's greedy selects with that level's training max as the scale."""
+    kw = dict(tol_mode=1, host_only=True)
+    a = E.Plan("gauss", 0.1, [0, 0, 0], 1.0, 10, 2, 1e-4, **kw)
+    b = E.Plan("gauss", 0.1, [0, 0, 0], 1.0, 10, 2, 1e-4, scale_level=2, **kw)
+    c = E.Plan("gauss", 0.1, [0, 0, 0], 1.0, 10, 2, 1e-4, scale_level=3, **kw)
+    assert a.stats()["scale_level"] == 2 and c.stats()["scale_level"] == 3
+    np.testing.assert_array_equal(a.level(2)["ia"], b.level(2)["ia"])
+    sc = oracle_lib.eim("gauss", 0.1, 3, 1.0, 1e-4)["scale"]
+    o = oracle_lib.eim("gauss", 0.1, 2, 1.0, 1e-4, abs_scale=sc)
+    lc = c.level(2)
+    assert lc["d"] == o["d"] < a.level(2)["d"]
+    np.testing.assert_array_equal(lc["ia"], o["ia"])
+    np.testing.assert_array_equal(lc["ib"], o["ib"])
+    for P in (a, b, c):
+        P.close()
+    for bad in (1, EIFMM_MAX_DEPTH_PLUS_1, -1):
+        with pytest.raises(E.EifmmError):
+            E.Plan("gauss", 0.1, [0, 0, 0], 1.0, 10, 2, 1e-4, scale_level=bad, **kw)
+    with pytest.raises(E.EifmmError):  # d_k above 1024 does not fit the device solves
+        E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-4, dmax=2000, host_only=True)
+
+
+EIFMM_MAX_DEPTH_PLUS_1 = 9
+
+
+def test_host_ranks_match_oracle(E, oracle_lib):
+    """Both compression stages count their ranks with the filters of Sec. 4.2; the
+    library's (its own SVDs) equal the oracle's (numpy SVDs) level by level and,
+    for the second stage, offset by offset."""
+    P = E.Plan("laplace", 0, [0, 0, 0], 1.0, 10, 2, 1e-4, host_only=True, compress_tol=1e-5,
+               compress_tol2=1e-5)
+    O = oracle_lib.Plan("laplace", 0, [0, 0, 0], 1.0, 2, 1e-4, compress_tol=1e-5,
+                        compress_tol2=1e-5)
+    assert P.stats()["rank"][2] == O.levels[2]["r"]
+    assert P.stats()["rpad"][2] == 16 * ((O.levels[2]["r"] + 15) // 16)
+    np.testing.assert_array_equal(P.compression2(2), O.levels[2]["s2"])
+    P.close()
+
+
+def test_evaluate_out_checked(E):
+    """An output tensor the library would write past or through a wrong layout is
+    refused on the host, before any launch."""
+    import torch
+    cpu = torch.device("cpu")
+    good = torch.empty(2, 10, dtype=torch.float64)
+    E.Plan.check_out(good, (2, 10), cpu)
+    for bad, exc in ((torch.empty(2, 10, dtype=torch.float32), "float64"),
+                     (torch.empty(10, 2, dtype=torch.float64).t(), "contiguous"),
+                     (torch.empty(2, 9, dtype=torch.float64), "shape"),
+                     (torch.empty(20, dtype=torch.float64), "shape")):
+        with pytest.raises(ValueError, match=exc):
+            E.Plan.check_out(bad, (2, 10), cpu)
+    with pytest.raises(ValueError, match="on"):
+        E.Plan.check_out(good, (2, 10), torch.device("cuda", 0))

@@ -1,8 +1,8 @@
 """Batches of independent problems (eifmm_batch_*): the fused, graph-replayed pass.
 
-  * each problem of a batch equals its own plan at the same depth (same level
-    tables when tol_mode is 0): the fused launches do per problem what the plan
-    does, except that a gathered-GEMM tile split across workgroups may be summed
+  * each problem of a batch equals its own plan at the same depth, built on the
+    same level tables (with the absolute stopping rule, the scale level the
+    batch reports): the fused launches do per problem what the plan does, except that a gathered-GEMM tile split across workgroups may be summed
     in another order, so the bound is 1e-12 rather than bit equality;
   * every problem against the oracle's direct sum: the requested 1e-6 (rel-L2);
   * graph replays, changed buffers and new points give the same results.
@@ -11,12 +11,9 @@ import numpy as np
 import pytest
 
 from paper_1408_0210_amd import workloads as W
+from parity_util import assert_close, rel as _rel
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module")
@@ -78,10 +75,13 @@ def test_batch_matches_plans(E, torch_dev, small):
             assert st["depth"] == q["depth"]
         else:
             assert 2 <= st["depth"] <= 8
-        if q["tol_mode"] != 0:
-            continue  # absolute EIM scale depends on the deepest tabulated level
+        # with the absolute stopping rule the shared tables take their scale from
+        # their deepest level, which the problem's stats name: the plan uses it too
+        assert (st["scale_level"] >= st["depth"]) if q["tol_mode"] == 1 else st["scale_level"] == 0
         plan = E.Plan(q["kernel"], q["param"], [0, 0, 0], 1.0, q["n"], st["depth"], q["tau"],
-                      tol_mode=q["tol_mode"], compress_tol=q["compress_tol"])
+                      tol_mode=q["tol_mode"], compress_tol=q["compress_tol"],
+                      scale_level=st["scale_level"])
+        assert plan.stats()["d"] == st["d"]
         plan.set_points(xs[p])
         f1 = plan.evaluate(ss[p]).cpu().numpy()
         plan.close()
@@ -89,6 +89,28 @@ def test_batch_matches_plans(E, torch_dev, small):
             np.testing.assert_array_equal(F[p], f1)
         else:
             assert _rel(F[p], f1) <= 1e-12, p
+
+
+def test_batch_mixed_vs_direct(E, torch_dev, oracle_lib, small):
+    """The same ten problems as one mixed-precision batch (FP32 M2L and near field):
+    every problem within 1e-6 of the direct sum, and of the FP64 batch."""
+    torch, dev = torch_dev
+    _, probs, xs, ss, F = small
+    B = E.Batch(probs, precision="mixed")
+    B.set_points(xs)
+    G = [f.cpu().numpy() for f in B.evaluate(ss)]
+    again = [f.cpu().numpy() for f in B.evaluate(ss)]
+    B.close()
+    for p, q in enumerate(probs):
+        np.testing.assert_array_equal(again[p], G[p])
+        if q["n"] == 1:
+            assert G[p][0] == 0.0
+            continue
+        fd = oracle_lib.direct(q["kernel"], q["param"], q["points"], q["points"], q["sigma"])
+        err = _rel(G[p], fd)
+        print(f"mixed problem {p}: n={q['n']} {q['kernel']} rel-L2 {err:.3e}", flush=True)
+        assert err <= 1e-6, p
+        assert _rel(G[p], F[p]) <= 1e-6, p
 
 
 def test_batch_vs_direct(oracle_lib, small):

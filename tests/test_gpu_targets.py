@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1408_0210_amd import workloads as W
+from parity_util import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -73,14 +74,13 @@ def test_targets_vs_oracle_union(kernel, param, depth, compress, E, torch_dev, o
     plan, f = _run(E, torch_dev, kernel, param, xs, xt, s, depth, 1e-6, compress_tol=compress)
     xu = np.concatenate([xs, xt], axis=1)
     su = np.concatenate([s, np.zeros(2000)])
-    kw = {}
+    O = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, depth, 1e-6, compress_tol=compress)
     if compress:
-        kw = dict(compress_tol=compress, compress_rank=plan.stats()["rank"])
-    O = oracle_lib.Plan(kernel, param, [0, 0, 0], 1.0, depth, 1e-6, **kw)
+        assert plan.stats()["rank"] == {k: O.levels[k]["r"] for k in range(2, depth + 1)}
     fo = O.evaluate(xu, su)[3000:]
-    assert _rel(f, fo) < 1e-10
+    assert_close(f, fo, 1e-10, "vs oracle EIFMM on the union")
     fd = oracle_lib.direct(kernel, param, xt, xs, s)
-    assert _rel(f, fd) < 1e-6
+    assert_close(f, fd, 1e-6, "vs direct sum", max_tol=1e-5)
     plan.close()
 
 

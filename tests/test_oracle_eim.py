@@ -137,3 +137,44 @@ def test_inhomogeneous_rank_falls_with_depth(oracle_lib):
     points on deeper levels."""
     ds = [oracle_lib.eim("gauss", 1.0, k, 1.0, 1e-6)["d"] for k in (2, 3, 4)]
     assert ds[0] > ds[1] > ds[2]
+
+
+@pytest.mark.parametrize("kern,param,tau", [("gauss", 1.0, 1e-6), ("cosr", 20.0, 1e-4),
+                                            ("mq", 1.0, 1e-6)])
+def test_heldout_error_bounded_volume(oracle_lib, kern, param, tau):
+    """The kernels of Sec. 5.4 obey no maximum principle, so their training sets
+    fill the volumes (an 11^3 grid of J_0 and close shells through I_0): at points
+    drawn anywhere in I_0 x J_0, away from every training point, the interpolation
+    error must stay within 1.25 tau * eps_0, i.e. the training grid resolves the
+    residual of the whole domain (trained on the surfaces only, exp(-r^2) and
+    sqrt(r^2+1) miss interior maxima of 2.0 and 1.5 tau at level 2)."""
+    k = 2
+    e = oracle_lib.eim(kern, param, k, 1.0, tau)
+    lk = 2.0 ** -(k + 1)
+    top = 2 ** (k + 1) - 1
+    r = np.random.default_rng(17)
+    u = r.uniform(-top, top, (12000, 3))
+    xs = u[np.abs(u).max(1) >= 3][:2500] * lk
+    ys = r.uniform(-1, 1, (300, 3)) * lk
+    Kt = _K(oracle_lib, kern, param, xs, ys)
+    KxY = _K(oracle_lib, kern, param, xs, e["Y"])
+    KXy = _K(oracle_lib, kern, param, e["X"], ys)
+    DK = np.stack([oracle_lib.apply_delta(e["B"], e["G"], KXy[:, j]) for j in range(len(ys))], 1)
+    err = np.abs(Kt - KxY @ DK).max() / e["scale"]
+    assert err <= 1.25 * tau, err
+
+
+def test_absolute_rule_scale_is_training_max(oracle_lib):
+    """tol_mode 1 (one absolute threshold for all levels): the scale handed to a
+    level's greedy is the largest |K| over another level's training grid, which is
+    the first pivot of that level's own greedy; a larger scale (a finer level of
+    the Gaussian, whose values near the box are larger) can only stop earlier."""
+    kern, param, tau = "gauss", 0.1, 1e-4
+    e2, e3 = (oracle_lib.eim(kern, param, k, 1.0, tau) for k in (2, 3))
+    tx, ty = oracle_lib.training_sets(kern, 3)
+    lk = 2.0 ** -4
+    assert e3["scale"] == np.abs(_K(oracle_lib, kern, param, tx * lk, ty * lk)).max()
+    a = oracle_lib.eim(kern, param, 2, 1.0, tau, abs_scale=e3["scale"])
+    assert a["scale"] == e3["scale"] > 1.5 * e2["scale"]
+    assert 0 < a["d"] < e2["d"]
+    assert np.abs(a["G"][a["d"] - 1, a["d"] - 1]) > tau * e3["scale"] >= a["eps"][a["d"]]

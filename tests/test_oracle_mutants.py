@@ -37,6 +37,11 @@ MUTANTS = {
                                                   "const double *Vr = lvl->U;"),
     "stage2_second_factor_transposed": ("t += Vo[(size_t)j * r + ll] * wj[ll];",
                                         "t += Vo[(size_t)ll * so + j] * wj[ll];"),
+    "cosr_phase_uses_r_squared": ("return cos(K->p[0] * r) / r;",
+                                  "return cos(K->p[0] * r2) / r;"),
+    "mq_constant_outside_root": ("return sqrt(r2 + K->p[0]);", "return sqrt(r2) + K->p[0];"),
+    "volume_kernels_trained_on_surfaces": ("static int kernel_is_volume(int kind) {\n  return !(",
+                                           "static int kernel_is_volume(int kind) {\n  return 0 && !("),
 }
 
 
@@ -54,12 +59,14 @@ def _run_mutant(name, base):
                     "-D_DEFAULT_SOURCE", "-o", str(so), str(mut), "-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(so), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_direct.py"),
                         os.path.join(ROOT, "tests", "test_oracle_pass.py"),
                         os.path.join(ROOT, "tests", "test_oracle_eim.py"),
                         os.path.join(ROOT, "tests", "test_oracle_nonsym.py"),
                         os.path.join(ROOT, "tests", "test_oracle_compress2.py"),
-                        "-k", "finite_rank or gamma or interpolation or c1_accuracy or swapped "
-                              "or two_eim or advdiff_two or stage2 or sides_random"],
+                        "-k", "hand_values or finite_rank or gamma or interpolation or c1_accuracy "
+                              "or swapped or two_eim or advdiff_two or stage2 or sides_random "
+                              "or heldout"],
                        env=env, capture_output=True, text=True, cwd=ROOT)
     return r.returncode, r.stdout[-2000:]
 
