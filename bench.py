@@ -43,6 +43,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA peaks, FP64 and FP32
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "m2l_traffic.json")
 
 
+def _progress(what):
+    print(f"[bench] {what} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -748,27 +752,38 @@ def main():
                              r["s"], threads=ref_threads())
     out["config"]["rel_l2_sampled_2000"] = _rel_sample(r["f"], sidx, sref)
     if not args.no_sweep:
+        _progress("tau sweep")
         out["tau_sweep"] = run_tau_sweep(args, data, sidx, sref)
+        _progress("mixed single right-hand side")
         out["mixed_single_rhs"] = run_mixed_single(args, data, sidx, sref)
     if child is not None:
+        _progress("waiting for the oracle EIFMM timing")
         oe = finish_oracle_eifmm(child)
+        _progress("CPU direct-sum baselines")
         cb, err, _, _ = cpu_baseline(r["w"]["kernel"], r["w"]["param"], r["x"], r["s"], r["f"],
                                      oracle_eifmm=oe)
         out["cpu_baseline"] = cb
         out["config"]["rel_l2_sampled"] = err
     if not args.no_batched:
+        _progress("64 right-hand sides, mixed")
         out["batched_mixed"] = run_batched(args)
     if not args.no_clustered:
+        _progress("clustered")
         out["clustered"] = run_clustered(args)
     if not args.no_uneven:
+        _progress("uneven_batch")
         out["uneven_batch"] = run_uneven(args)
     if not args.no_paper_kernels:
+        _progress("paper_kernels")
         out["paper_kernels"] = run_paper_kernels(args)
     if not args.no_100m:
+        _progress("uniform100m")
         out["uniform100m"] = run_100m(args)
     if not args.no_targets:
+        _progress("targets")
         out["targets"] = run_targets(args)
     if not args.no_nonsym:
+        _progress("nonsymmetric")
         out["nonsymmetric"] = run_nonsym(args)
     print(json.dumps(out), flush=True)
 
