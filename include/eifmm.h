@@ -216,6 +216,25 @@ int eifmm_set_points_targets(eifmm_plan plan, const double *src_xyz_dev, const d
 int eifmm_evaluate(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
                    double *f_dev, int64_t ldf, void *hip_stream);
 
+/* eifmm_evaluate for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same pass and arguments, with no hipMalloc, hipFree or other
+ * allocating call.  The plan's expansions and tables were allocated by
+ * eifmm_plan_create; the partial tiles of the Stream-K tails of the gathered-GEMM
+ * launches, which eifmm_evaluate keeps in a workspace of the plan, go to a
+ * device array of the library instead: 32 MiB per device, held until the
+ * process ends, each launch splitting its tail over as many workgroups as fit
+ * it.  Every call on a device shares that array, so calls that overlap in time
+ * on one device (on different streams or from different threads, any plans)
+ * race and must be serialised by the caller; each launch writes every piece
+ * it reads, so nothing must be cleared between calls.  Per-phase timing is not
+ * recorded.  Errors as eifmm_evaluate, plus EIFMM_EINVAL for a plan with the
+ * second compression stage (its factored M2L keeps a workspace of its own) and
+ * EIFMM_EHIP if the array's device address cannot be obtained.  Results equal
+ * eifmm_evaluate's up to the order in which split tiles are summed. */
+int eifmm_evaluate_noalloc(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
+                           double *f_dev, int64_t ldf, void *hip_stream);
+
 /* Enables (1) or disables (0) per-phase HIP-event timing; resets the totals. */
 int eifmm_set_timing(eifmm_plan plan, int32_t enable);
 

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "devutil.hpp"
@@ -120,7 +121,6 @@ int stream_k_groups(int device) {
   return std::max(8, 2 * cus);
 }
 
-size_t stream_k_ws_len(int groups) { return (size_t)2 * groups * 6 * 16 * 128; }
 
 #define TRY(x)            \
   do {                    \
@@ -295,6 +295,19 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
     TRY(dalloc(&P.sk_ws, stream_k_ws_len(P.sk_groups), tr));
   if (depth >= 2)
     TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dpB, tr));
+  // the gathered-GEMM job table at its largest size, so that no evaluation
+  // allocates (build_jobs grows it only past this bound, which it cannot reach)
+  {
+    const size_t cap = max_gemm_jobs(depth);
+    if (hipMalloc(&P.job_dev, sizeof(GemmJob) * cap) != hipSuccess ||
+        hipHostMalloc((void **)&P.job_pin, sizeof(GemmJob) * cap) != hipSuccess) {
+      hipGetLastError();
+      return EIFMM_ENOMEM;
+    }
+    P.job_cap = cap;
+    if (hipEventCreateWithFlags(&P.job_evt, hipEventDisableTiming) != hipSuccess)
+      return EIFMM_EHIP;
+  }
 #undef TRY
   return EIFMM_OK;
 }
@@ -664,6 +677,67 @@ int eifmm_evaluate(eifmm_plan h, const double *sigma, int32_t nrhs, int64_t ld, 
     return EIFMM_EINVAL;
   hipSetDevice(P.device);
   return pass_run(P, sigma, nrhs, ld, f, ldf, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ no allocation
+// Scratch of eifmm_evaluate_noalloc: the partial tiles of the Stream-K tails of
+// its gathered-GEMM launches (M2M, the projections, M2L, L2L), in place of the
+// plan's own workspace.  One copy per device, held until the process ends.
+// Host code must not use the name `scratch` as a device address: it takes the
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchDoubles = (size_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `dev` (taken once per device, with that
+// device current); nullptr if the runtime cannot give it
+double *scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dev) return nullptr;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int eifmm_evaluate_noalloc(eifmm_plan h, const double *sigma, int32_t nrhs, int64_t ld,
+                           double *f, int64_t ldf, void *stream) {
+  if (!h) return EIFMM_EINVAL;
+  Plan &P = h->P;
+  if (P.host_only || !P.points_set) return EIFMM_ESTATE;
+  if (nrhs < 1 || nrhs > P.max_rhs) return EIFMM_EINVAL;
+  const int64_t nout = P.nt ? P.nt : P.ns;
+  if ((P.ns > 0 && (!sigma || ld < P.ns)) || (nout > 0 && (!f || ldf < nout)))
+    return EIFMM_EINVAL;
+  // the factored M2L of the second compression stage keeps a workspace of its own
+  for (int k = 2; k <= P.depth; ++k)
+    if (uses_m2l2(P, k)) return EIFMM_EINVAL;
+  if (hipSetDevice(P.device) != hipSuccess) return EIFMM_EHIP;
+  double *ws = scratch_on(P.device);
+  if (!ws) return EIFMM_EHIP;
+  // the scratch replaces the plan's Stream-K workspace for this pass; the
+  // per-phase timing events (created on demand) stay off
+  const bool timing = P.timing;
+  P.timing = false;
+  P.run_ws = ws;
+  P.run_ws_len = kNoAllocScratchDoubles;
+  const int st = pass_run(P, sigma, nrhs, ld, f, ldf, (hipStream_t)stream);
+  P.run_ws = nullptr;
+  P.run_ws_len = 0;
+  P.timing = timing;
+  return st;
 }
 
 int eifmm_set_timing(eifmm_plan h, int32_t enable) {

@@ -992,7 +992,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
 
 template <typename T, int MODE, bool FOLD, int RBT>
 __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
-                                                 int ntiles, int64_t units, int G,
+                                                 int ntiles, int64_t units, int G, int GT,
                                                  double *__restrict__ ws,
                                                  const int8_t *__restrict__ dvec) {
   constexpr int TILE = RBT * 16 * GT_COLS;
@@ -1014,7 +1014,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
   const int64_t R = units - S;
-  const int Gt = (int)min((int64_t)G, R);  // workgroups sharing the tail: each owns >= 1 unit
+  // workgroups sharing the tail (at most GT, so that the 2 GT pieces fit the
+  // workspace): each owns >= 1 unit
+  const int Gt = (int)min((int64_t)GT, R);
   if (g >= Gt) return;
   const int64_t ua = S + sk_bound(g, R, Gt), ub = S + sk_bound(g + 1, R, Gt);
   for (int64_t u = ua; u < ub;) {
@@ -1034,7 +1036,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
 // Adds the pieces of the tiles split between workgroups (one block per tile).
 template <int RBT>
 __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
-                                                    int ntiles, int64_t units, int G,
+                                                    int ntiles, int64_t units, int G, int GT,
                                                     const double *__restrict__ ws) {
   constexpr int TILE = RBT * 16 * GT_COLS;
   const int full = (ntiles / G) * G;
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
   const int64_t R = units - S;
-  const int Gt = (int)min((int64_t)G, R);
+  const int Gt = (int)min((int64_t)GT, R);
   const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
   const int tile_local = tile - J.tiles_start;
   // unit range of the tile relative to S
@@ -1584,54 +1586,68 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
 
 namespace {
 
+// ws holds ws_len doubles: the pieces of the Stream-K tail, TILE doubles each, 2
+// per tail workgroup, so the tail is split over at most ws_len / (2 TILE)
+// workgroups (G itself for the plan's own workspace, fewer for a smaller one)
 template <typename T, int MODE, int RBT>
 void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int gmax,
-                     double *ws, const int8_t *dvec, hipStream_t s) {
+                     double *ws, size_t ws_len, const int8_t *dvec, hipStream_t s) {
   const int G = (int)std::min<int64_t>(units, gmax);
+  const int GT = (int)std::min<size_t>((size_t)G, ws_len / (2 * (size_t)RBT * 16 * GT_COLS));
   constexpr bool fold = sizeof(T) == 4;
   hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, jobs, n, tiles,
-                     units, G, ws, dvec);
+                     units, G, GT, ws, dvec);
   const int rest = tiles - (tiles / G) * G;
   if (G > 1 && rest > 0)
     hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest), dim3(256), 0, s, jobs, n, tiles, units,
-                       G, ws);
+                       G, GT, ws);
 }
 
 template <typename T, int MODE>
 void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int rbt, int gmax,
-                     double *ws, const int8_t *dvec, hipStream_t s) {
+                     double *ws, size_t ws_len, const int8_t *dvec, hipStream_t s) {
   if (n == 0 || tiles == 0 || units == 0) return;
   switch (rbt) {
-    case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
-    case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
-    default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, dvec, s); break;
+    case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
+    case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
+    default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
   }
 }
 
+// a plan's launch: its Stream-K workspace, or the one its caller lends for this
+// pass (P.run_ws, P.run_ws_len)
 template <typename T, int MODE>
 void launch_gemm(Plan &P, int first, int n, int tiles, int64_t units, hipStream_t s,
                  int rbt = 6) {
-  launch_gemm_tab<T, MODE>(P.job_dev + first, n, tiles, units, rbt, P.sk_groups, P.sk_ws, P.dvec,
+  double *ws = P.run_ws ? P.run_ws : P.sk_ws;
+  const size_t len = P.run_ws ? P.run_ws_len : stream_k_ws_len(P.sk_groups);
+  launch_gemm_tab<T, MODE>(P.job_dev + first, n, tiles, units, rbt, P.sk_groups, ws, len, P.dvec,
                            s);
 }
 
 void launch_gemm_fused(const FusedGemm &F, int mode, bool fp32, int gmax, double *ws,
                        const int8_t *dvec, hipStream_t s) {
+  const size_t len = stream_k_ws_len(gmax);
   switch (mode) {
     case MODE_M2M:
-      launch_gemm_tab<double, MODE_M2M>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      launch_gemm_tab<double, MODE_M2M>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, len, dvec,
+                                        s);
       break;
     case MODE_L2L:
-      launch_gemm_tab<double, MODE_L2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      launch_gemm_tab<double, MODE_L2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, len, dvec,
+                                        s);
       break;
     case MODE_PROJ:
-      launch_gemm_tab<double, MODE_PROJ>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+      launch_gemm_tab<double, MODE_PROJ>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, len, dvec,
+                                         s);
       break;
     default:
       if (fp32)
-        launch_gemm_tab<float, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+        launch_gemm_tab<float, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, len, dvec,
+                                         s);
       else
-        launch_gemm_tab<double, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, dvec, s);
+        launch_gemm_tab<double, MODE_M2L>(F.dev, F.n, F.tiles, F.units, F.rbt, gmax, ws, len, dvec,
+                                          s);
   }
 }
 

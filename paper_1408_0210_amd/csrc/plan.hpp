@@ -310,6 +310,9 @@ struct Plan {
   std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
+  // a Stream-K workspace lent for one pass (null: sk_ws), run_ws_len doubles
+  double *run_ws = nullptr;
+  size_t run_ws_len = 0;
   double m2l_flops = 0, proj_flops = 0;
   double m2l_flops_exec = 0;  // what the M2L MFMAs execute (padding, empty sources)
 
@@ -321,6 +324,13 @@ struct Plan {
   int last_hip_error = 0;
   int last_rhs = 0;
 };
+
+// Stream-K workspace of `groups` persistent workgroups: 2 pieces of the largest
+// tile (6 x 16 x 128 doubles) each
+inline size_t stream_k_ws_len(int groups) { return (size_t)2 * groups * 6 * 16 * 128; }
+// gathered-GEMM jobs a plan of this depth can have: M2M and the two projections
+// one per level, M2L and L2L one per level and child class
+inline size_t max_gemm_jobs(int depth) { return (size_t)19 * (depth > 0 ? depth : 1) + 16; }
 
 // setup.cpp
 int build_tables(Plan &P);

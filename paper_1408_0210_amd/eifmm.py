@@ -86,6 +86,7 @@ def lib():
         L.eifmm_set_points.argtypes = [vp, vp, vp]
         L.eifmm_set_points_targets.argtypes = [vp, vp, vp, vp]
         L.eifmm_evaluate.argtypes = [vp, vp, i32, i64, vp, i64, vp]
+        L.eifmm_evaluate_noalloc.argtypes = [vp, vp, i32, i64, vp, i64, vp]
         L.eifmm_set_timing.argtypes = [vp, i32]
         L.eifmm_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.eifmm_get_level.argtypes = [vp, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
@@ -107,7 +108,7 @@ def lib():
         L.eifmm_status_str.argtypes = [ctypes.c_int]
         L.eifmm_status_str.restype = ctypes.c_char_p
         for f in ("eifmm_plan_create", "eifmm_set_points", "eifmm_set_points_targets",
-                  "eifmm_evaluate", "eifmm_set_timing",
+                  "eifmm_evaluate", "eifmm_evaluate_noalloc", "eifmm_set_timing",
                   "eifmm_get_stats", "eifmm_get_level", "eifmm_get_level2",
                   "eifmm_get_compression", "eifmm_get_compression2",
                   "eifmm_export_tree", "eifmm_export_lists",
@@ -237,6 +238,20 @@ class Plan:
         _check(lib().eifmm_evaluate(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs, self.n,
                                     ctypes.c_void_p(out.data_ptr()), self.n_out, _stream()),
                "eifmm_evaluate")
+        return out
+
+    def evaluate_noalloc(self, sigma, out):
+        """eifmm_evaluate_noalloc: as evaluate, into a caller-allocated `out`, with
+        no device allocation inside the call."""
+        import torch
+        assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
+        assert sigma.dim() in (1, 2) and sigma.shape[-1] == self.n
+        nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
+        shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
+        self.check_out(out, shape, sigma.device)
+        _check(lib().eifmm_evaluate_noalloc(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs,
+                                            self.n, ctypes.c_void_p(out.data_ptr()), self.n_out,
+                                            _stream()), "eifmm_evaluate_noalloc")
         return out
 
     @staticmethod
