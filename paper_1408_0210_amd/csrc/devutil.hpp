@@ -29,6 +29,24 @@ __host__ __device__ inline uint32_t morton_encode(uint32_t x, uint32_t y, uint32
   return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }
 
+// Loads and stores through global-memory (address space 1) pointers.  A pointer
+// the kernel reads from memory (a job table, a descriptor) is generic to the
+// compiler, which then emits flat instructions; those count against the LDS wait
+// counter as well, so waiting for an LDS read would also wait for every memory
+// load in flight, the prefetches included.  T must be a scalar or an
+// ext_vector_type (HIP's double2 class copies through a generic pointer).
+#define EIFMM_GLOBAL_AS __attribute__((address_space(1)))
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ inline T ldg(const T *p) {
+  return *(const EIFMM_GLOBAL_AS T *)p;
+}
+template <typename T>
+__device__ inline void stg(T *p, T v) {
+  *(EIFMM_GLOBAL_AS T *)p = v;
+}
+
 // index along axis a (0 = x, 1 = y, 2 = z) of a Morton key
 __host__ __device__ inline uint32_t morton_axis(uint32_t key, int a) { return compact3(key >> a); }
 

@@ -672,7 +672,7 @@ struct Mfma;
 template <>
 struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
-  typedef double2 p2;
+  typedef d2v p2;
   __device__ static inline v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -681,7 +681,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
-  typedef float2 p2;
+  typedef f2v p2;
   __device__ static inline v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -701,7 +701,7 @@ __device__ inline int gemm_source_slot(const GemmJob &J, int term, bool cvalid, 
   } else {
     uint32_t skey;
     if constexpr (MODE == MODE_M2L) {
-      const int id = J.terms[term];
+      const int id = ldg(J.terms + term);
       const int side = 1 << J.level;
       const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
       const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
@@ -713,7 +713,7 @@ __device__ inline int gemm_source_slot(const GemmJob &J, int term, bool cvalid, 
     } else {
       skey = tkey >> 3;
     }
-    return src_slot[skey];
+    return ldg(src_slot + skey);
   }
 }
 
@@ -726,7 +726,7 @@ template <typename T, int MODE>
 __device__ inline const T *gemm_operand(const GemmJob &J, int term) {
   int64_t idx;
   if constexpr (MODE == MODE_M2L)
-    idx = J.terms[term];
+    idx = ldg(J.terms + term);
   else if constexpr (MODE == MODE_M2M)
     idx = term;
   else if constexpr (MODE == MODE_L2L)
@@ -822,12 +822,12 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
         const ColRef cr = J.colref[tt];
         const ColSrc &cs = J.colsrc[cr.rec];
         c.tsl = cr.slot;
-        c.tkey = cs.keys[cr.slot];
+        c.tkey = ldg(cs.keys + cr.slot);
         c.slot_map = cs.slot;
         c.B = cs.B;
       } else {
-        c.tsl = J.tgt ? J.tgt[tt] : tt;
-        if (MODE != MODE_PROJ) c.tkey = J.tgt_keys[c.tsl];
+        c.tsl = J.tgt ? ldg(J.tgt + tt) : tt;
+        if (MODE != MODE_PROJ) c.tkey = ldg(J.tgt_keys + c.tsl);
       }
     }
     my[jj] = c;
@@ -878,7 +878,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       const int e = t + 256 * q;  // pair index in the chunk
       const int rb = rb0 + (e >> 7);
       if (e < NA && rb < nrb)
-        ra[q] = *(const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127));
+        ra[q] = ldg((const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127)));
       else
         ra[q] = P2{0, 0};
     }
@@ -886,8 +886,8 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     for (int jj = 0; jj < 2; ++jj) {
       if (srcp[jj]) {
         const P2 *s2 = (const P2 *)(srcp[jj] + kc * 16 + koff);
-        bn[jj][0] = s2[0];
-        bn[jj][1] = s2[1];
+        bn[jj][0] = ldg(s2);
+        bn[jj][1] = ldg(s2 + 1);
       } else {
         bn[jj][0] = P2{0, 0};
         bn[jj][1] = P2{0, 0};
@@ -923,13 +923,13 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
-      // up to 5 row blocks every block is multiplied: the A chunk holds zeros
+      // every block is multiplied (except with 6 blocks): the A chunk holds zeros
       // beyond the operator's rows (their results are not stored), and a branch
       // per block would split the products into pieces that each wait for their
       // LDS reads.  With 6 blocks the unbranched form runs out of registers.
 #pragma unroll
       for (int i = 0; i < RBT; ++i)
-        if (RBT <= 5 || rowok[i]) {
+        if (RBT != 6 || rowok[i]) {
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
@@ -963,7 +963,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       tso = cr.slot;
       Cout = J.colsrc[cr.rec].C;
     } else {
-      tso = J.tgt ? J.tgt[tt] : tt;
+      tso = J.tgt ? ldg(J.tgt + tt) : tt;
     }
     const int64_t cbase = ((int64_t)tso * J.nrhs + ro) * J.dpm;
 #pragma unroll
@@ -978,12 +978,12 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
         else
           v = (double)acc[i][jj][q];
         if (part) {
-          part[(size_t)rt * GT_COLS + jt] = v;
+          stg(part + (size_t)rt * GT_COLS + jt, v);
         } else {
           const int64_t o = cbase + 16 * rb0 + rt;
-          if constexpr (MODE == MODE_L2L) v += J.Cadd[o];
-          Cout[o] = v;
-          if (J.C32) J.C32[o] = (float)v;
+          if constexpr (MODE == MODE_L2L) v += ldg(J.Cadd + o);
+          stg(Cout + o, v);
+          if (J.C32) stg(J.C32 + o, (float)v);
         }
       }
     }
@@ -1086,12 +1086,12 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
       tso = cr.slot;
       Cout = J.colsrc[cr.rec].C;
     } else {
-      tso = J.tgt ? J.tgt[tt] : tt;
+      tso = J.tgt ? ldg(J.tgt + tt) : tt;
     }
     const int64_t o = ((int64_t)tso * J.nrhs + ro) * J.dpm + 16 * rb0 + rt;
-    if (J.mode == MODE_L2L) v += J.Cadd[o];
-    Cout[o] = v;
-    if (J.C32) J.C32[o] = (float)v;
+    if (J.mode == MODE_L2L) v += ldg(J.Cadd + o);
+    stg(Cout + o, v);
+    if (J.C32) stg(J.C32 + o, (float)v);
   }
 }
 
@@ -1610,6 +1610,7 @@ void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int r
   switch (rbt) {
     case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
     case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
+
     default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
   }
 }
