@@ -661,7 +661,11 @@ __global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ 
 // so FP32 rounding grows with one matrix product (d_k terms) rather than with
 // the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
-constexpr int GT_CB = 8, GT_COLS = 16 * GT_CB;
+// 16-column blocks per wave: 2 (128-column tiles), or 1 (64 columns) for the
+// 8-block (128-row) tiles, whose 8 accumulators per column block take the
+// registers of the second block
+__host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 8 ? 1 : 2; }
+__host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
 constexpr int kMaxPieces = 512;  // pieces of one split tile: at most its terms + 1
 
 // Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
@@ -795,22 +799,23 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   typedef typename Mfma<T>::v4 V4;
   typedef typename Mfma<T>::p2 P2;
   typedef double D4 __attribute__((ext_vector_type(4)));
+  constexpr int CPW = gemm_cpw(RBT), COLS = 64 * CPW;
   constexpr int NA = RBT * 128;         // A chunk, in pairs
   constexpr int QA = (NA + 255) / 256;  // pairs per thread
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
-  const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
+  const int rb0 = rowtile * RBT, col0 = coltile * COLS;
   const int nrb = J.dpm >> 4, nks = J.dpk >> 2, nkc = J.dpk >> 4;
   const int ncols = J.ntgt * J.nrhs;
   const int koff = 4 * (lane >> 4);
 
-  // the two columns of this lane (one per 16-column block of the wave); their
+  // the CPW columns of this lane (one per 16-column block of the wave); their
   // source metadata waits in LDS (this thread's own slots) until each term
   // starts, which keeps it out of the registers the accumulators need
-  ColState *my = cst + 2 * t;
+  ColState *my = cst + CPW * t;
 #pragma unroll
-  for (int jj = 0; jj < 2; ++jj) {
-    const int jc = col0 + 16 * (2 * w + jj) + (lane & 15);
+  for (int jj = 0; jj < CPW; ++jj) {
+    const int jc = col0 + 16 * (CPW * w + jj) + (lane & 15);
     ColState c{};
     c.valid = jc < ncols;
     c.slot_map = J.src_slot;
@@ -832,30 +837,35 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     }
     my[jj] = c;
   }
-  V4 acc[RBT][2];
-  D4 sum[RBT][2];
+  V4 acc[RBT][CPW];
+  D4 sum[RBT][CPW];
   bool rowok[RBT];
 #pragma unroll
   for (int i = 0; i < RBT; ++i) {
     rowok[i] = rb0 + i < nrb;
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
+    for (int jj = 0; jj < CPW; ++jj) {
       acc[i][jj] = V4{0, 0, 0, 0};
       if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
     }
   }
   P2 ra[QA];
-  P2 bn[2][2], bc[2][2];  // B of the next and the current chunk: [column][pair]
-  const T *srcp[2] = {nullptr, nullptr};
+  P2 bn[CPW][2], bc[CPW][2];  // B of the next and the current chunk: [column][pair]
+  const T *srcp[CPW];
   const T *Ap = nullptr;
   // the source slots of term + 1 are looked up halfway through term, so the
   // dependent loads (slot, then data) do not stall the start of the next term
-  int nslot[2] = {-1, -1};
+  int nslot[CPW];
+#pragma unroll
+  for (int jj = 0; jj < CPW; ++jj) {
+    srcp[jj] = nullptr;
+    nslot[jj] = -1;
+  }
   int pre_term = -1;
   const int kmid = nkc >> 1;
   auto lookup = [&](int term) {
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
+    for (int jj = 0; jj < CPW; ++jj) {
       const ColState c = my[jj];
       nslot[jj] = gemm_source_slot<MODE>(J, term, c.valid, c.tkey, c.tsl, dvec, c.slot_map);
     }
@@ -866,7 +876,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     if (kc == 0) {
       if (pre_term != term) lookup(term);
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
+      for (int jj = 0; jj < CPW; ++jj) {
         const ColState c = my[jj];
         srcp[jj] = gemm_source_ptr<T>(J, nslot[jj], c.r, (const T *)c.B);
       }
@@ -883,7 +893,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
         ra[q] = P2{0, 0};
     }
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
+    for (int jj = 0; jj < CPW; ++jj) {
       if (srcp[jj]) {
         const P2 *s2 = (const P2 *)(srcp[jj] + kc * 16 + koff);
         bn[jj][0] = ldg(s2);
@@ -911,18 +921,18 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   for (int it = it0; it < it1; ++it) {
     const int cur = (it - it0) & 1;
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
+    for (int jj = 0; jj < CPW; ++jj) {
       bc[jj][0] = bn[jj][0];
       bc[jj][1] = bn[jj][1];
     }
     if (it + 1 < it1) fetch(it + 1);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      T a[RBT], b[2];
+      T a[RBT], b[CPW];
 #pragma unroll
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
+      for (int jj = 0; jj < CPW; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
       // every block is multiplied (except with 6 blocks): the A chunk holds zeros
       // beyond the operator's rows (their results are not stored), and a branch
       // per block would split the products into pieces that each wait for their
@@ -931,7 +941,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       for (int i = 0; i < RBT; ++i)
         if (RBT != 6 || rowok[i]) {
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
+          for (int jj = 0; jj < CPW; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
     if constexpr (FOLD) {
@@ -939,7 +949,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
 #pragma unroll
         for (int i = 0; i < RBT; ++i)
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
+          for (int jj = 0; jj < CPW; ++jj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
             acc[i][jj] = V4{0, 0, 0, 0};
@@ -951,8 +961,8 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   }
 
 #pragma unroll
-  for (int jj = 0; jj < 2; ++jj) {
-    const int jt = 16 * (2 * w + jj) + (lane & 15);
+  for (int jj = 0; jj < CPW; ++jj) {
+    const int jt = 16 * (CPW * w + jj) + (lane & 15);
     const int jo = col0 + jt;
     if (jo >= ncols) continue;
     const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
@@ -978,7 +988,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
         else
           v = (double)acc[i][jj][q];
         if (part) {
-          stg(part + (size_t)rt * GT_COLS + jt, v);
+          stg(part + (size_t)rt * COLS + jt, v);
         } else {
           const int64_t o = cbase + 16 * rb0 + rt;
           if constexpr (MODE == MODE_L2L) v += ldg(J.Cadd + o);
@@ -995,7 +1005,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
                                                  int ntiles, int64_t units, int G, int GT,
                                                  double *__restrict__ ws,
                                                  const int8_t *__restrict__ dvec) {
-  constexpr int TILE = RBT * 16 * GT_COLS;
+  constexpr int TILE = RBT * 16 * 64 * gemm_cpw(RBT);
   __shared__ T As[2][RBT * 4 * 64];
   __shared__ ColState cst[2 * 256];
   const int g = blockIdx.x;
@@ -1038,7 +1048,7 @@ template <int RBT>
 __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
                                                     int ntiles, int64_t units, int G, int GT,
                                                     const double *__restrict__ ws) {
-  constexpr int TILE = RBT * 16 * GT_COLS;
+  constexpr int COLS = 64 * gemm_cpw(RBT), TILE = RBT * 16 * COLS;
   const int full = (ntiles / G) * G;
   const int tile = full + blockIdx.x;
   if (tile >= ntiles) return;
@@ -1069,11 +1079,11 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   __syncthreads();
   const int np = npieces;
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
-  const int rb0 = rowtile * RBT, col0 = coltile * GT_COLS;
+  const int rb0 = rowtile * RBT, col0 = coltile * COLS;
   const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
   const int ncols = J.ntgt * J.nrhs;
   for (int e = threadIdx.x; e < TILE; e += 256) {
-    const int rt = e / GT_COLS, jt = e - rt * GT_COLS;
+    const int rt = e / COLS, jt = e - rt * COLS;
     const int jo = col0 + jt;
     if (rt >= nrows || jo >= ncols) continue;
     double v = 0.0;
@@ -1278,7 +1288,7 @@ int tiles_of(const GemmJob &J) { return J.ncoltiles * J.nrowtiles; }
 
 void finish_job(GemmJob &J, int &tiles, int rbt) {
   const int ncols = J.ntgt * J.nrhs;
-  J.ncoltiles = (ncols + GT_COLS - 1) / GT_COLS;
+  J.ncoltiles = (ncols + gemm_cols(rbt) - 1) / gemm_cols(rbt);
   J.nrowtiles = (J.dpm / 16 + rbt - 1) / rbt;
   J.tiles_start = tiles;
   tiles += tiles_of(J);
@@ -1364,7 +1374,9 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     int tiles = 0;
     jt.m2l_first = (int)h.size();
     const LevelHost &F = P.lh[depth];
-    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16);
+    // 128-row tiles (8 blocks, 64 columns) read each gathered column once per
+    // term when the operators have 8 blocks; the M2L's registers allow them
+    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16, true);
     for (int k = depth; k >= 2; --k) {
       if (uses_m2l2(P, k)) continue;  // the factored M2L below
       const bool cz = P.lh[k].r > 0;
@@ -1593,7 +1605,7 @@ template <typename T, int MODE, int RBT>
 void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int gmax,
                      double *ws, size_t ws_len, const int8_t *dvec, hipStream_t s) {
   const int G = (int)std::min<int64_t>(units, gmax);
-  const int GT = (int)std::min<size_t>((size_t)G, ws_len / (2 * (size_t)RBT * 16 * GT_COLS));
+  const int GT = (int)std::min<size_t>((size_t)G, ws_len / (2 * (size_t)RBT * 16 * gemm_cols(RBT)));
   constexpr bool fold = sizeof(T) == 4;
   hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, jobs, n, tiles,
                      units, G, GT, ws, dvec);
@@ -1610,6 +1622,7 @@ void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int r
   switch (rbt) {
     case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
     case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
+    case 8: launch_gemm_rbt<T, MODE, 8>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
 
     default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
   }
