@@ -47,6 +47,16 @@ __device__ inline void stg(T *p, T v) {
   *(EIFMM_GLOBAL_AS T *)p = v;
 }
 
+// Workgroup barrier for hand-offs through LDS: a release/acquire on the LDS
+// address space only, so the compiler waits for the LDS accesses before the
+// barrier but leaves global loads in flight (a full __syncthreads waits for
+// every outstanding memory operation, which ends any prefetch at the barrier).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // index along axis a (0 = x, 1 = y, 2 = z) of a Morton key
 __host__ __device__ inline uint32_t morton_axis(uint32_t key, int a) { return compact3(key >> a); }
 

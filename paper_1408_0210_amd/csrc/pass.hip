@@ -661,12 +661,18 @@ __global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ 
 // so FP32 rounding grows with one matrix product (d_k terms) rather than with
 // the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
-// 16-column blocks per wave: 2 (128-column tiles), or 1 (64 columns) for the
-// 8-block (128-row) tiles, whose 8 accumulators per column block take the
-// registers of the second block
-__host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 8 ? 1 : 2; }
+// 16-column blocks per wave: 2 (128-column tiles) for 4-block tiles, 1 (64
+// columns) for taller ones, whose accumulators and three sets of prefetched
+// operands would not fit the registers of two waves per SIMD otherwise
+__host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 5 ? 1 : 2; }
+static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2, "tile widths");
 __host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
 constexpr int kMaxPieces = 512;  // pieces of one split tile: at most its terms + 1
+constexpr int kMaxTerms = 189;   // terms of one job (M2L: the offsets of a child class)
+// zeros, read in place of a missing source column or of operator rows past the
+// operator, so that every chunk issues the same loads (static device memory is
+// zero-initialized; 1024 covers the longest column, d_k <= 1024)
+__device__ double g_gemm_zero[1024];
 
 // Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result layouts differ: FP64 keeps rows (l / 16) + 4 q of column l % 16 in
@@ -692,33 +698,33 @@ struct Mfma<float> {
   __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-// Slot of the source box that term `term` pairs with target (tkey, ts): M2L
-// the box at offset delta (-1 outside the domain or empty), M2M child `term`,
-// L2L the parent, PROJ the box itself.
+// Where the slot of the source box that term `term` pairs with target (tkey, ts)
+// is read: M2L the box at offset delta, M2M child `term`, L2L the parent (entries
+// of the source level's slot map, which holds -1 for an empty box); PROJ needs
+// no read (the box itself).  *ok is false for a missing column or a source
+// outside the domain; the address is then a valid dummy, so that every lane
+// reads and the number of loads in flight does not depend on the data.
 template <int MODE>
-__device__ inline int gemm_source_slot(const GemmJob &J, int term, bool cvalid, uint32_t tkey,
-                                       int ts, const int8_t *__restrict__ dvec,
-                                       const int *__restrict__ src_slot) {
-  if (!cvalid) return -1;
-  if constexpr (MODE == MODE_PROJ) {
-    return ts;
+__device__ inline const int *gemm_source_addr(const GemmJob &J, int term, bool cvalid,
+                                              uint32_t tkey, const int *sdel,
+                                              const int *__restrict__ src_slot, bool *ok) {
+  uint32_t skey;
+  bool v = cvalid;
+  if constexpr (MODE == MODE_M2L) {
+    const int pk = sdel[term];  // the term's offset, packed (LDS)
+    const int side = 1 << J.level;
+    const int m0 = (int)morton_axis(tkey, 0) + (pk & 7) - 3;
+    const int m1 = (int)morton_axis(tkey, 1) + ((pk >> 3) & 7) - 3;
+    const int m2 = (int)morton_axis(tkey, 2) + ((pk >> 6) & 7) - 3;
+    v = v && m0 >= 0 && m1 >= 0 && m2 >= 0 && m0 < side && m1 < side && m2 < side;
+    skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
+  } else if constexpr (MODE == MODE_M2M) {
+    skey = tkey * 8u + (uint32_t)term;
   } else {
-    uint32_t skey;
-    if constexpr (MODE == MODE_M2L) {
-      const int id = ldg(J.terms + term);
-      const int side = 1 << J.level;
-      const int m0 = (int)morton_axis(tkey, 0) + dvec[3 * id];
-      const int m1 = (int)morton_axis(tkey, 1) + dvec[3 * id + 1];
-      const int m2 = (int)morton_axis(tkey, 2) + dvec[3 * id + 2];
-      if (m0 < 0 || m1 < 0 || m2 < 0 || m0 >= side || m1 >= side || m2 >= side) return -1;
-      skey = morton_encode((uint32_t)m0, (uint32_t)m1, (uint32_t)m2);
-    } else if constexpr (MODE == MODE_M2M) {
-      skey = tkey * 8u + (uint32_t)term;
-    } else {
-      skey = tkey >> 3;
-    }
-    return ldg(src_slot + skey);
+    skey = tkey >> 3;
   }
+  *ok = v && src_slot;
+  return *ok ? src_slot + skey : (const int *)g_gemm_zero;
 }
 
 template <typename T>
@@ -727,10 +733,10 @@ __device__ inline const T *gemm_source_ptr(const GemmJob &J, int s, int r, const
 }
 
 template <typename T, int MODE>
-__device__ inline const T *gemm_operand(const GemmJob &J, int term) {
+__device__ inline const T *gemm_operand(const GemmJob &J, int term, const int *sdel) {
   int64_t idx;
   if constexpr (MODE == MODE_M2L)
-    idx = ldg(J.terms + term);
+    idx = sdel[term] >> 9;  // the offset id, from the LDS term table
   else if constexpr (MODE == MODE_M2M)
     idx = term;
   else if constexpr (MODE == MODE_L2L)
@@ -795,7 +801,7 @@ struct ColState {
 template <typename T, int MODE, bool FOLD, int RBT>
 __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, int term1,
                                  double *__restrict__ part, const int8_t *__restrict__ dvec,
-                                 T (*As)[RBT * 4 * 64], ColState *cst) {
+                                 T (*As)[RBT * 4 * 64], ColState *cst, int *sdel) {
   typedef typename Mfma<T>::v4 V4;
   typedef typename Mfma<T>::p2 P2;
   typedef double D4 __attribute__((ext_vector_type(4)));
@@ -837,6 +843,17 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     }
     my[jj] = c;
   }
+  // the job's terms in LDS, packed (dx+3) | (dy+3) << 3 | (dz+3) << 6 | id << 9
+  // (offset and offset id): a source lookup then waits on no global load but
+  // the slot map's, and the operator address on none
+  if constexpr (MODE == MODE_M2L) {
+    for (int i = t; i < J.nterms; i += 256) {
+      const int id = ldg(J.terms + i);
+      sdel[i] = (dvec[3 * id] + 3) | ((dvec[3 * id + 1] + 3) << 3) |
+                ((dvec[3 * id + 2] + 3) << 6) | (id << 9);
+    }
+    lds_barrier();
+  }
   V4 acc[RBT][CPW];
   D4 sum[RBT][CPW];
   bool rowok[RBT];
@@ -849,90 +866,105 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       if constexpr (FOLD) sum[i][jj] = D4{0, 0, 0, 0};
     }
   }
-  P2 ra[QA];
-  P2 bn[CPW][2], bc[CPW][2];  // B of the next and the current chunk: [column][pair]
+  // Chunks are loaded two ahead of their products: during the products of
+  // chunk it, the loads of chunk it + 2 are in flight and chunk it + 1 goes from
+  // registers into the LDS buffer that chunk it - 1 used.  The barriers order
+  // LDS accesses only, so loads stay in flight across them.  Three register sets
+  // (R, B) rotate by name over a loop unrolled by 3 (a copy from a register a
+  // load is filling would wait for that load), and every chunk issues the same
+  // loads, so that the waits for them are exact.
+  P2 R0[QA], R1[QA], R2[QA];               // A of a chunk, on its way to LDS
+  P2 B0[CPW][2], B1[CPW][2], B2[CPW][2];   // B of a chunk: [column][pair]
   const T *srcp[CPW];
   const T *Ap = nullptr;
-  // the source slots of term + 1 are looked up halfway through term, so the
-  // dependent loads (slot, then data) do not stall the start of the next term
+  // source slots of the next term: read by the fetch of a term's last chunk
+  // (the other fetches read a dummy), used at the next term's first chunk
   int nslot[CPW];
+  bool nok[CPW];
 #pragma unroll
   for (int jj = 0; jj < CPW; ++jj) {
     srcp[jj] = nullptr;
     nslot[jj] = -1;
+    nok[jj] = false;
   }
-  int pre_term = -1;
-  const int kmid = nkc >> 1;
-  auto lookup = [&](int term) {
+  auto lookup = [&](int term, bool real) {
 #pragma unroll
     for (int jj = 0; jj < CPW; ++jj) {
       const ColState c = my[jj];
-      nslot[jj] = gemm_source_slot<MODE>(J, term, c.valid, c.tkey, c.tsl, dvec, c.slot_map);
-    }
-    pre_term = term;
-  };
-  auto fetch = [&](int it) {
-    const int term = it / nkc, kc = it - term * nkc;
-    if (kc == 0) {
-      if (pre_term != term) lookup(term);
-#pragma unroll
-      for (int jj = 0; jj < CPW; ++jj) {
-        const ColState c = my[jj];
-        srcp[jj] = gemm_source_ptr<T>(J, nslot[jj], c.r, (const T *)c.B);
+      if constexpr (MODE == MODE_PROJ) {
+        nok[jj] = c.valid;
+        nslot[jj] = c.tsl;
+      } else {
+        const int *addr = (const int *)g_gemm_zero;
+        bool ok = false;
+        if (real) addr = gemm_source_addr<MODE>(J, term, c.valid, c.tkey, sdel, c.slot_map, &ok);
+        nslot[jj] = ldg(addr);
+        nok[jj] = ok;
       }
-      Ap = gemm_operand<T, MODE>(J, term);
     }
-    if (kc == kmid && term + 1 < term1) lookup(term + 1);
+  };
+  // loads chunk (fterm, fkc), the next one in order, into raD and bD; with live
+  // false (past the last chunk) the same loads read zeros
+  int fterm = term0, fkc = 0;
+  const T *zero = (const T *)g_gemm_zero;
+  auto fetch = [&](P2(&raD)[QA], P2(&bD)[CPW][2], bool live) {
+    const int term = fterm, kc = fkc;
+    if (live) {
+      if (++fkc == nkc) {
+        fkc = 0;
+        ++fterm;
+      }
+      if (kc == 0) {
+#pragma unroll
+        for (int jj = 0; jj < CPW; ++jj) {
+          const ColState c = my[jj];
+          srcp[jj] = gemm_source_ptr<T>(J, nok[jj] ? nslot[jj] : -1, c.r, (const T *)c.B);
+        }
+        Ap = gemm_operand<T, MODE>(J, term, sdel);
+      }
+    }
+    // the slots of the next term, at the term's last chunk
+    lookup(term + 1, live && kc == nkc - 1 && term + 1 < term1);
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = t + 256 * q;  // pair index in the chunk
       const int rb = rb0 + (e >> 7);
-      if (e < NA && rb < nrb)
-        ra[q] = ldg((const P2 *)(Ap + ((int64_t)rb * nks + kc * 4) * 64 + 2 * (e & 127)));
-      else
-        ra[q] = P2{0, 0};
+      if (e < NA) {
+        const T *src = (live && rb < nrb) ? Ap + ((int64_t)rb * nks + kc * 4) * 64 : zero;
+        raD[q] = ldg((const P2 *)(src + 2 * (e & 127)));
+      }
     }
 #pragma unroll
     for (int jj = 0; jj < CPW; ++jj) {
-      if (srcp[jj]) {
-        const P2 *s2 = (const P2 *)(srcp[jj] + kc * 16 + koff);
-        bn[jj][0] = ldg(s2);
-        bn[jj][1] = ldg(s2 + 1);
-      } else {
-        bn[jj][0] = P2{0, 0};
-        bn[jj][1] = P2{0, 0};
-      }
+      const T *col = (live && srcp[jj]) ? srcp[jj] + kc * 16 : zero;
+      const P2 *s2 = (const P2 *)(col + koff);
+      bD[jj][0] = ldg(s2);
+      bD[jj][1] = ldg(s2 + 1);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, const P2(&raS)[QA]) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = t + 256 * q;
-      if (e < NA) *(P2 *)(&As[buf][2 * e]) = ra[q];
+      if (e < NA) *(P2 *)(&As[buf][2 * e]) = raS[q];
     }
   };
-
   const int it0 = term0 * nkc, it1 = term1 * nkc;
-  if (it0 < it1) {
-    fetch(it0);
-    stash(0);
-    __syncthreads();
-  }
-  for (int it = it0; it < it1; ++it) {
+  int mkc = 0;  // k chunk of the current term
+  // the products of chunk it (its A in LDS buffer (it - it0) & 1, its B in Bc),
+  // with the loads of chunk it + 2 into (Rf, Bf) and chunk it + 1 (Rn) stashed
+  auto step = [&](int it, const P2(&Bc)[CPW][2], const P2(&Rn)[QA], P2(&Rf)[QA],
+                  P2(&Bf)[CPW][2]) {
     const int cur = (it - it0) & 1;
-#pragma unroll
-    for (int jj = 0; jj < CPW; ++jj) {
-      bc[jj][0] = bn[jj][0];
-      bc[jj][1] = bn[jj][1];
-    }
-    if (it + 1 < it1) fetch(it + 1);
+    fetch(Rf, Bf, it + 2 < it1);
+    stash(cur ^ 1, Rn);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       T a[RBT], b[CPW];
 #pragma unroll
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
-      for (int jj = 0; jj < CPW; ++jj) b[jj] = (ks & 1) ? bc[jj][ks >> 1].y : bc[jj][ks >> 1].x;
+      for (int jj = 0; jj < CPW; ++jj) b[jj] = (ks & 1) ? Bc[jj][ks >> 1].y : Bc[jj][ks >> 1].x;
       // every block is multiplied (except with 6 blocks): the A chunk holds zeros
       // beyond the operator's rows (their results are not stored), and a branch
       // per block would split the products into pieces that each wait for their
@@ -944,8 +976,9 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
           for (int jj = 0; jj < CPW; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
-    if constexpr (FOLD) {
-      if ((it + 1) % nkc == 0) {  // a term is complete
+    if (++mkc == nkc) {
+      mkc = 0;
+      if constexpr (FOLD) {  // a term is complete
 #pragma unroll
         for (int i = 0; i < RBT; ++i)
 #pragma unroll
@@ -956,8 +989,23 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
           }
       }
     }
-    if (it + 1 < it1) stash(cur ^ 1);
-    __syncthreads();
+    lds_barrier();
+  };
+
+  if (it0 < it1) {
+    lookup(term0, true);
+    fetch(R0, B0, true);
+    stash(0, R0);
+    fetch(R1, B1, it0 + 1 < it1);
+    lds_barrier();
+    int it = it0;
+    for (; it + 3 <= it1; it += 3) {
+      step(it, B0, R1, R2, B2);
+      step(it + 1, B1, R2, R0, B0);
+      step(it + 2, B2, R0, R1, B1);
+    }
+    if (it < it1) step(it, B0, R1, R2, B2);
+    if (it + 1 < it1) step(it + 1, B1, R2, R0, B0);
   }
 
 #pragma unroll
@@ -1008,6 +1056,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   constexpr int TILE = RBT * 16 * 64 * gemm_cpw(RBT);
   __shared__ T As[2][RBT * 4 * 64];
   __shared__ ColState cst[2 * 256];
+  __shared__ int sdel[kMaxTerms];
   const int g = blockIdx.x;
   // whole tiles, G at a time; the tiles of one XCD (g mod 8) are contiguous
   const int full = (ntiles / G) * G;
@@ -1017,7 +1066,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
     const int tile = t0 + gx;
     const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
     gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, 0, J.nterms, nullptr, dvec, As,
-                                  cst);
+                                  cst, sdel);
   }
   if (full == ntiles) return;
   // the remaining units, split evenly
@@ -1039,7 +1088,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
     u = ts + term1;
     const bool whole = term0 == 0 && term1 == J.nterms;
     double *part = whole ? nullptr : ws + (size_t)(2 * g + (ua >= ts ? 0 : 1)) * TILE;
-    gemm_tile<T, MODE, FOLD, RBT>(J, tile_local, term0, term1, part, dvec, As, cst);
+    gemm_tile<T, MODE, FOLD, RBT>(J, tile_local, term0, term1, part, dvec, As, cst, sdel);
   }
 }
 
@@ -1374,9 +1423,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     int tiles = 0;
     jt.m2l_first = (int)h.size();
     const LevelHost &F = P.lh[depth];
-    // 128-row tiles (8 blocks, 64 columns) read each gathered column once per
-    // term when the operators have 8 blocks; the M2L's registers allow them
-    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16, true);
+    jt.m2l_rbt = pick_rbt((F.r ? F.rp : F.dpB) / 16);
     for (int k = depth; k >= 2; --k) {
       if (uses_m2l2(P, k)) continue;  // the factored M2L below
       const bool cz = P.lh[k].r > 0;
@@ -1622,7 +1669,6 @@ void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int r
   switch (rbt) {
     case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
     case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
-    case 8: launch_gemm_rbt<T, MODE, 8>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
 
     default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
   }

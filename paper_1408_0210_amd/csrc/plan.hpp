@@ -344,7 +344,7 @@ struct EimResult {
 };
 int eim_iterate_gpu(const std::vector<double> &R, int64_t nx, int64_t ny, double tau,
                     double abs_scale, int dmax, EimResult &res);
-int pick_rbt(int nrb, bool tall = false);
+int pick_rbt(int nrb);
 
 // device-side entry points (tree.hip, pass.hip)
 int tree_build(Plan &P, const double *xyz_in, hipStream_t s);

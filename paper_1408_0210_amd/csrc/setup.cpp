@@ -677,13 +677,11 @@ int stage2_factors(const std::vector<double> &C, int r, double eps, std::vector<
 }  // namespace
 
 // Row blocks per gathered-GEMM tile for nrb 16-row blocks: the height (4, 5 or 6
-// blocks, and 8 when `tall`; 8-block tiles are 64 columns wide, the others 128)
-// that leaves the fewest idle blocks in the last row tile, the taller one on a
-// tie (fewer row tiles read each gathered column).
-int pick_rbt(int nrb, bool tall) {
+// blocks; 4-block tiles are 128 columns wide, the others 64) that leaves the
+// fewest idle blocks in the last row tile, the taller one on a tie.
+int pick_rbt(int nrb) {
   int best = 6, waste = 1 << 30;
-  for (int rbt = tall ? 8 : 6; rbt >= 4; --rbt) {
-    if (rbt == 7) continue;
+  for (int rbt = 6; rbt >= 4; --rbt) {
     const int w = (nrb + rbt - 1) / rbt * rbt - nrb;
     if (w < waste) {
       waste = w;
