@@ -334,7 +334,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
  * eifmm_set_points).  At the first call, a problem with depth -1 gets, among
  * the depths around log8(n_p / 32) (at most 4 of them, within 2..8), the one
  * whose evaluation runs fastest here; later calls keep it.  The first call also
- * times the fused M2L launch with tiles of 4, 5 and 6 MFMA row blocks and keeps
+ * times the fused M2L launch with tiles of 3, 4, 5 and 6 MFMA row blocks and keeps
  * the fastest.  Drops the captured graph.  Errors as eifmm_set_points; after
  * an error the batch must get points again before evaluating. */
 int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream);

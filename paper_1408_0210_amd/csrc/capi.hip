@@ -1083,7 +1083,7 @@ int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream
         st = eifmm_set_points(b->plans[p], xyz[p], s);
     }
     if (!st && changed) st = prepare(b, 0);
-    // tile height of the fused M2L launch: the M2L launch alone for 4, 5 and 6
+    // tile height of the fused M2L launch: the M2L launch alone for 3, 4, 5 and 6
     // row blocks, after one full pass that fills the expansions
     if (!st) st = stage_io(b, nullptr, nullptr, s);
     if (!st) batch_run(b->ex, s);
@@ -1092,7 +1092,7 @@ int eifmm_batch_set_points(eifmm_batch b, const double *const *xyz, void *stream
     hipEventCreate(&e1);
     double best = 0;
     int pick = 6;
-    for (int rbt = 4; rbt <= 6 && !st; ++rbt) {
+    for (int rbt = 3; rbt <= 6 && !st; ++rbt) {
       if ((st = prepare(b, rbt))) break;
       batch_run_m2l(b->ex, s);
       hipEventRecord(e0, s);

@@ -661,11 +661,11 @@ __global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ 
 // so FP32 rounding grows with one matrix product (d_k terms) rather than with
 // the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
-// 16-column blocks per wave: 2 (128-column tiles) for 4-block tiles, 1 (64
-// columns) for taller ones, whose accumulators and three sets of prefetched
+// 16-column blocks per wave: 2 (128-column tiles) for 3- and 4-block tiles, 1
+// (64 columns) for taller ones, whose accumulators and three sets of prefetched
 // operands would not fit the registers of two waves per SIMD otherwise
 __host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 5 ? 1 : 2; }
-static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2, "tile widths");
+static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2 && gemm_cpw(3) == 2, "tile widths");
 __host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
 constexpr int kMaxPieces = 512;  // pieces of one split tile: at most its terms + 1
 constexpr int kMaxTerms = 189;   // terms of one job (M2L: the offsets of a child class)
@@ -1668,6 +1668,7 @@ void launch_gemm_tab(const GemmJob *jobs, int n, int tiles, int64_t units, int r
   if (n == 0 || tiles == 0 || units == 0) return;
   switch (rbt) {
     case 4: launch_gemm_rbt<T, MODE, 4>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
+    case 3: launch_gemm_rbt<T, MODE, 3>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
     case 5: launch_gemm_rbt<T, MODE, 5>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;
 
     default: launch_gemm_rbt<T, MODE, 6>(jobs, n, tiles, units, gmax, ws, ws_len, dvec, s); break;

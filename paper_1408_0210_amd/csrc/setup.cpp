@@ -676,12 +676,12 @@ int stage2_factors(const std::vector<double> &C, int r, double eps, std::vector<
 
 }  // namespace
 
-// Row blocks per gathered-GEMM tile for nrb 16-row blocks: the height (4, 5 or 6
-// blocks; 4-block tiles are 128 columns wide, the others 64) that leaves the
-// fewest idle blocks in the last row tile, the taller one on a tie.
+// Row blocks per gathered-GEMM tile for nrb 16-row blocks: the height (3 to 6
+// blocks; 3- and 4-block tiles are 128 columns wide, the others 64) that leaves
+// the fewest idle blocks in the last row tile, the taller one on a tie.
 int pick_rbt(int nrb) {
   int best = 6, waste = 1 << 30;
-  for (int rbt = 6; rbt >= 4; --rbt) {
+  for (int rbt = 6; rbt >= 3; --rbt) {
     const int w = (nrb + rbt - 1) / rbt * rbt - nrb;
     if (w < waste) {
       waste = w;

@@ -62,9 +62,10 @@ WORKLOADS = {
                              seed_pts=6, seed_sigma=7, kernel="yukawa", param=1.0, depth=5,
                              tau=1e-6, compress_tol=8e-6),
     # Many right-hand sides: 2^20 uniform points, 64 sigma vectors, depth 5.
+    # Mixed precision over 64 RHS measured 1.0e-6 at rank 128 (6e-6): 3e-6 keeps 144.
     "uniform1m_laplace_d5_rhs64": dict(n=1 << 20, dist="uniform", seed_pts=8,
                                        seed_sigma=list(range(100, 164)), kernel="laplace",
-                                       param=0.0, depth=5, tau=1e-6, compress_tol=6e-6),
+                                       param=0.0, depth=5, tau=1e-6, compress_tol=3e-6),
 }
 
 # The paper's inhomogeneous-kernel test cases (Sec. 5.4, Table 3): 1e6 points

@@ -68,7 +68,7 @@ def test_batch_matches_plans(E, torch_dev, small):
     B, probs, xs, ss, F = small
     info = B.info()
     print("batch info", info, flush=True)
-    assert info["graph_nodes"] > 0 and info["m2l_rbt"] in (4, 5, 6)
+    assert info["graph_nodes"] > 0 and info["m2l_rbt"] in (3, 4, 5, 6)
     for p, q in enumerate(probs):
         st = B.stats(p)
         if q["depth"] is not None:
