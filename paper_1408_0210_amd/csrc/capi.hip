@@ -109,6 +109,7 @@ void release(eifmm_plan h) {
   }
   if (P.job_dev) hipFree(P.job_dev);
   if (P.job_pin) hipHostFree(P.job_pin);
+  if (P.counts_pin) hipHostFree(P.counts_pin);
   if (P.m2l2_dev) hipFree(P.m2l2_dev);
   if (P.m2l2_pin) hipHostFree(P.m2l2_pin);
   if (P.m2l2_ws) hipFree(P.m2l2_ws);
@@ -253,10 +254,15 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
     TRY(dalloc(&D.act, D.cap, tr));
     TRY(dalloc(&D.slot, nb, tr));
     TRY(dalloc(&D.cls, D.cap, tr));
+    if (k >= 2 && k <= kMaxOrderLevel) TRY(dalloc(&D.ord, D.cap, tr));
   }
   const size_t scan_len = std::max<size_t>((size_t)256 * P.ntiles_sort, maxcap + 2);
   TRY(dalloc(&P.scan_tmp, scan_len / 1024 + 64, tr));
-  TRY(dalloc(&P.blkcnt, ((size_t)(nleaf + 255) / 256 + 1) * 9, tr));
+  {
+    size_t blocks = 1;  // blocks of 256 boxes over the levels of the active-box compaction
+    for (int k = std::min(2, depth); k <= depth; ++k) blocks += ((size_t)1 << (3 * k)) / 256 + 1;
+    TRY(dalloc(&P.blkcnt, blocks * 9, tr));
+  }
   TRY(dalloc(&P.list_cnt, maxcap + 2, tr));
   TRY(dalloc(&P.counts_dev, (size_t)16 * kMaxLevels, tr));
   TRY(dalloc(&P.errflag, 1, tr));
@@ -300,7 +306,9 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
   {
     const size_t cap = max_gemm_jobs(depth);
     if (hipMalloc(&P.job_dev, sizeof(GemmJob) * cap) != hipSuccess ||
-        hipHostMalloc((void **)&P.job_pin, sizeof(GemmJob) * cap) != hipSuccess) {
+        hipHostMalloc((void **)&P.job_pin, sizeof(GemmJob) * cap) != hipSuccess ||
+        hipHostMalloc((void **)&P.counts_pin, sizeof(int) * (16 * kMaxLevels + 1)) !=
+            hipSuccess) {
       hipGetLastError();
       return EIFMM_ENOMEM;
     }

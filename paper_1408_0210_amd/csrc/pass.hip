@@ -667,7 +667,6 @@ constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
 __host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 5 ? 1 : 2; }
 static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2 && gemm_cpw(3) == 2, "tile widths");
 __host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
-constexpr int kMaxPieces = 512;  // pieces of one split tile: at most its terms + 1
 constexpr int kMaxTerms = 189;   // terms of one job (M2L: the offsets of a child class)
 // zeros, read in place of a missing source column or of operator rows past the
 // operator, so that every chunk issues the same loads (static device memory is
@@ -907,7 +906,10 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   // false (past the last chunk) the same loads read zeros
   int fterm = term0, fkc = 0;
   const T *zero = (const T *)g_gemm_zero;
-  auto fetch = [&](P2(&raD)[QA], P2(&bD)[CPW][2], bool live) {
+  // M2L: 1 when none of this wave's columns has a source in the current fetch
+  // term; the wave's products would add zeros and are skipped
+  uint32_t curskip = 0;
+  auto fetch = [&](P2(&raD)[QA], P2(&bD)[CPW][2], uint32_t &skD, bool live) {
     const int term = fterm, kc = fkc;
     if (live) {
       if (++fkc == nkc) {
@@ -921,8 +923,15 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
           srcp[jj] = gemm_source_ptr<T>(J, nok[jj] ? nslot[jj] : -1, c.r, (const T *)c.B);
         }
         Ap = gemm_operand<T, MODE>(J, term, sdel);
+        if constexpr (MODE == MODE_M2L) {
+          bool any = false;
+#pragma unroll
+          for (int jj = 0; jj < CPW; ++jj) any = any || srcp[jj] != nullptr;
+          curskip = __ballot(any) == 0 ? 1u : 0u;
+        }
       }
     }
+    skD = curskip;
     // the slots of the next term, at the term's last chunk
     lookup(term + 1, live && kc == nkc - 1 && term + 1 < term1);
 #pragma unroll
@@ -953,11 +962,8 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   int mkc = 0;  // k chunk of the current term
   // the products of chunk it (its A in LDS buffer (it - it0) & 1, its B in Bc),
   // with the loads of chunk it + 2 into (Rf, Bf) and chunk it + 1 (Rn) stashed
-  auto step = [&](int it, const P2(&Bc)[CPW][2], const P2(&Rn)[QA], P2(&Rf)[QA],
-                  P2(&Bf)[CPW][2]) {
-    const int cur = (it - it0) & 1;
-    fetch(Rf, Bf, it + 2 < it1);
-    stash(cur ^ 1, Rn);
+  // the products of one chunk
+  auto products = [&](int cur, const P2(&Bc)[CPW][2]) {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       T a[RBT], b[CPW];
@@ -965,10 +971,10 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
 #pragma unroll
       for (int jj = 0; jj < CPW; ++jj) b[jj] = (ks & 1) ? Bc[jj][ks >> 1].y : Bc[jj][ks >> 1].x;
-      // every block is multiplied (except with 6 blocks): the A chunk holds zeros
-      // beyond the operator's rows (their results are not stored), and a branch
-      // per block would split the products into pieces that each wait for their
-      // LDS reads.  With 6 blocks the unbranched form runs out of registers.
+      // every row block is multiplied (except with 6 blocks): the A chunk holds
+      // zeros beyond the operator's rows (their results are not stored), and a
+      // branch per block would split the products into pieces that each wait for
+      // their LDS reads.  With 6 blocks the unbranched form runs out of registers.
 #pragma unroll
       for (int i = 0; i < RBT; ++i)
         if (RBT != 6 || rowok[i]) {
@@ -976,6 +982,13 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
           for (int jj = 0; jj < CPW; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
+  };
+  auto step = [&](int it, const P2(&Bc)[CPW][2], uint32_t skc, const P2(&Rn)[QA], P2(&Rf)[QA],
+                  P2(&Bf)[CPW][2], uint32_t &skf) {
+    const int cur = (it - it0) & 1;
+    fetch(Rf, Bf, skf, it + 2 < it1);
+    stash(cur ^ 1, Rn);
+    if (MODE != MODE_M2L || skc == 0) products(cur, Bc);
     if (++mkc == nkc) {
       mkc = 0;
       if constexpr (FOLD) {  // a term is complete
@@ -994,18 +1007,19 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
 
   if (it0 < it1) {
     lookup(term0, true);
-    fetch(R0, B0, true);
+    uint32_t S0 = 0, S1 = 0, S2 = 0;  // skip flags of the chunks in B0, B1, B2
+    fetch(R0, B0, S0, true);
     stash(0, R0);
-    fetch(R1, B1, it0 + 1 < it1);
+    fetch(R1, B1, S1, it0 + 1 < it1);
     lds_barrier();
     int it = it0;
     for (; it + 3 <= it1; it += 3) {
-      step(it, B0, R1, R2, B2);
-      step(it + 1, B1, R2, R0, B0);
-      step(it + 2, B2, R0, R1, B1);
+      step(it, B0, S0, R1, R2, B2, S2);
+      step(it + 1, B1, S1, R2, R0, B0, S0);
+      step(it + 2, B2, S2, R0, R1, B1, S1);
     }
-    if (it < it1) step(it, B0, R1, R2, B2);
-    if (it + 1 < it1) step(it + 1, B1, R2, R0, B0);
+    if (it < it1) step(it, B0, S0, R1, R2, B2, S2);
+    if (it + 1 < it1) step(it + 1, B1, S1, R2, R0, B0, S0);
   }
 
 #pragma unroll
@@ -1092,14 +1106,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   }
 }
 
-// Adds the pieces of the tiles split between workgroups (one block per tile).
+// Adds the pieces of the tiles split between workgroups; kFixupSplit blocks per
+// tile, each adding a slice of its elements.  The workgroups meeting a tile are
+// consecutive, glo..ghi: glo's piece is in slot 2 glo + 1 unless glo starts at
+// the tile (then 2 glo), the others start inside it (slot 2 g).  The pieces are
+// added in workgroup order, 8 loads in flight at a time.
+constexpr int kFixupSplit = 4;
 template <int RBT>
 __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
                                                     int ntiles, int64_t units, int G, int GT,
                                                     const double *__restrict__ ws) {
   constexpr int COLS = 64 * gemm_cpw(RBT), TILE = RBT * 16 * COLS;
+  constexpr int SLICE = TILE / kFixupSplit;
+  static_assert(SLICE % 256 == 0 && 256 % COLS == 0, "fixup slices");
   const int full = (ntiles / G) * G;
-  const int tile = full + blockIdx.x;
+  const int tile = full + (int)(blockIdx.x / kFixupSplit);
+  const int slice = (int)(blockIdx.x % kFixupSplit);
   if (tile >= ntiles) return;
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
@@ -1107,47 +1129,55 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   const int Gt = (int)min((int64_t)GT, R);
   const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
   const int tile_local = tile - J.tiles_start;
-  // unit range of the tile relative to S
+  // unit range of the tile relative to S; workgroup g starts at unit
+  // sk_bound(g) = floor(g R / Gt), so the last one starting at or before ts is
+  // floor(((ts + 1) Gt - 1) / R) and the last one starting before te is
+  // floor((te Gt - 1) / R)
   const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms - S, te = ts + J.nterms;
-  int64_t glo = ts * Gt / R;
-  while (glo + 1 < Gt && sk_bound(glo + 1, R, Gt) <= ts) ++glo;
-  while (glo > 0 && sk_bound(glo, R, Gt) > ts) --glo;
-  int64_t ghi = glo;
-  while (ghi + 1 < Gt && sk_bound(ghi + 1, R, Gt) < te) ++ghi;
+  const int64_t glo = min(((ts + 1) * Gt - 1) / R, (int64_t)Gt - 1);
+  const int64_t ghi = min((te * Gt - 1) / R, (int64_t)Gt - 1);
   if (ghi == glo) return;  // written directly
-  // workspace slots of the pieces, in workgroup order (every workgroup of the
-  // tail owns at least one unit, so each one in [glo, ghi] wrote a piece)
-  __shared__ int slot[kMaxPieces];
-  __shared__ int npieces;
-  if (threadIdx.x == 0) {
-    int np = 0;
-    for (int64_t g = glo; g <= ghi && np < kMaxPieces; ++g)
-      slot[np++] = (int)(2 * g + (sk_bound(g, R, Gt) >= ts ? 0 : 1));
-    npieces = np;
-  }
-  __syncthreads();
-  const int np = npieces;
+  const int np = (int)(ghi - glo + 1);
+  const int first = (int)(2 * glo + (sk_bound(glo, R, Gt) == ts ? 0 : 1));
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * COLS;
   const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
   const int ncols = J.ntgt * J.nrhs;
-  for (int e = threadIdx.x; e < TILE; e += 256) {
-    const int rt = e / COLS, jt = e - rt * COLS;
-    const int jo = col0 + jt;
-    if (rt >= nrows || jo >= ncols) continue;
+  // this thread's column (the same for all its elements, 256 being a multiple of COLS)
+  const int jt = (int)threadIdx.x % COLS;
+  const int jo = col0 + jt;
+  if (jo >= ncols) return;
+  const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
+  int tso;
+  double *Cout = J.C;
+  if (J.colref) {
+    const ColRef cr = J.colref[tt];
+    tso = cr.slot;
+    Cout = J.colsrc[cr.rec].C;
+  } else {
+    tso = J.tgt ? ldg(J.tgt + tt) : tt;
+  }
+  const int64_t obase = ((int64_t)tso * J.nrhs + ro) * J.dpm + 16 * rb0;
+  for (int e = slice * SLICE + (int)threadIdx.x; e < (slice + 1) * SLICE; e += 256) {
+    const int rt = e / COLS;
+    if (rt >= nrows) break;
     double v = 0.0;
-    for (int i = 0; i < np; ++i) v += ws[(size_t)slot[i] * TILE + e];
-    const int tt = jo / J.nrhs, ro = jo - tt * J.nrhs;
-    int tso;
-    double *Cout = J.C;
-    if (J.colref) {
-      const ColRef cr = J.colref[tt];
-      tso = cr.slot;
-      Cout = J.colsrc[cr.rec].C;
-    } else {
-      tso = J.tgt ? ldg(J.tgt + tt) : tt;
+    int i = 0;
+    for (; i + 8 <= np; i += 8) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int sl = i + u == 0 ? first : (int)(2 * (glo + i + u));
+        p[u] = ldg(ws + (size_t)sl * TILE + e);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += p[u];
     }
-    const int64_t o = ((int64_t)tso * J.nrhs + ro) * J.dpm + 16 * rb0 + rt;
+    for (; i < np; ++i) {
+      const int sl = i == 0 ? first : (int)(2 * (glo + i));
+      v += ldg(ws + (size_t)sl * TILE + e);
+    }
+    const int64_t o = obase + rt;
     if (J.mode == MODE_L2L) v += ldg(J.Cadd + o);
     stg(Cout + o, v);
     if (J.C32) stg(J.C32 + o, (float)v);
@@ -1439,7 +1469,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
         else
           J.Bsrc = mixed ? (const void *)P.ld[k].Wh32 : (const void *)P.ld[k].Wh;
         J.C = cz ? P.ld[k].gp : P.ld[k].g;
-        J.tgt = P.ld[k].cls + P.cls_off[k][c];
+        J.tgt = (P.ld[k].ord ? P.ld[k].ord : P.ld[k].cls) + P.cls_off[k][c];
         J.tgt_keys = P.ld[k].act;
         J.src_slot = P.ld[k].slot;
         J.terms = P.dlist + 189 * c;
@@ -1658,8 +1688,8 @@ void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int g
                      units, G, GT, ws, dvec);
   const int rest = tiles - (tiles / G) * G;
   if (G > 1 && rest > 0)
-    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest), dim3(256), 0, s, jobs, n, tiles, units,
-                       G, GT, ws);
+    hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest * kFixupSplit), dim3(256), 0, s, jobs, n,
+                       tiles, units, G, GT, ws);
 }
 
 template <typename T, int MODE>

@@ -11,6 +11,8 @@
 namespace eifmm {
 
 constexpr int kMaxLevels = EIFMM_MAX_DEPTH + 1;
+// deepest level whose M2L columns are ordered by boundary faces (8^6 boxes)
+constexpr int kMaxOrderLevel = 6;
 constexpr int kNumOffsets = 316;  // 7^3 - 3^3 distinct M2L offsets (Sec. 4.2)
 constexpr int kMaxRank2 = 96;     // largest second-stage rank the factored M2L takes
 constexpr int kM2l2RbMin = 4, kM2l2RbMax = 16;  // 16-row blocks of r the factored M2L takes
@@ -67,6 +69,10 @@ struct LevelDev {
   uint32_t *act = nullptr;   // active box keys, ascending
   int *slot = nullptr;       // [8^k] slot of each key, -1 if empty
   int *cls = nullptr;        // slots grouped by child class (key & 7), ascending key
+  // M2L target order: each class's slots grouped by which faces of the domain
+  // the parent touches (so that a 16-column block shares its missing sources),
+  // ascending key within a group; levels up to kMaxOrderLevel, else null
+  int *ord = nullptr;
   double *W = nullptr, *Wh = nullptr, *g = nullptr, *l = nullptr;
   float *Wh32 = nullptr;  // FP32 copy of What (mixed precision M2L)
   // compressed M2L
@@ -262,6 +268,7 @@ struct Plan {
   int *list_cnt = nullptr;       // per-box entry counts of a list build
   int *counts_dev = nullptr;    // small counter block
   int *errflag = nullptr;
+  int *counts_pin = nullptr;    // pinned host copy of counts_dev and errflag
   int *near_ptr = nullptr;      // leaf level near lists (CSR over active slots)
   int *near_src = nullptr;      // source leaf slots
   size_t near_cap = 0;

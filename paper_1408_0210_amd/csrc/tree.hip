@@ -190,14 +190,37 @@ __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict_
   cnt[j] = c;
 }
 
-__global__ __launch_bounds__(256) void k_act_count(const int *__restrict__ ls, int shift,
-                                                   int64_t nb, int *__restrict__ blkcnt) {
+// The active boxes of every level from 2 to the leaf level, in three launches
+// for all levels: a box is active when its subtree holds a point (a non-empty
+// range of leaf_start).  Blocks of 256 boxes; block numbers run over the levels
+// one after another (blk0), and blkcnt holds 9 counts per block (one per child
+// class, then the total).
+struct ActLevels {
+  int n;                        // levels
+  int shift[kMaxLevels];        // 3 (depth - k)
+  int64_t nb[kMaxLevels];       // 8^k boxes
+  int blk0[kMaxLevels + 1];     // first block of each level; blk0[n] = all blocks
+  uint32_t *act[kMaxLevels];    // compact keys, ascending
+  int *slot[kMaxLevels];        // dense map key -> compact index or -1
+  int *cls[kMaxLevels];         // compact indices grouped by child class
+  int *counts[kMaxLevels];      // class offsets [0, 8) and the total [8]
+};
+
+__device__ inline int act_level(const ActLevels &L, int blk) {
+  int q = 0;
+  while (q + 1 < L.n && L.blk0[q + 1] <= blk) ++q;
+  return q;
+}
+
+__global__ __launch_bounds__(256) void k_act_count(const int *__restrict__ ls, ActLevels L,
+                                                   int *__restrict__ blkcnt) {
   __shared__ int c[9];
   const int t = threadIdx.x;
   if (t < 9) c[t] = 0;
   __syncthreads();
-  int64_t b = (int64_t)blockIdx.x * 256 + t;
-  if (b < nb && box_active(ls, shift, b)) {
+  const int q = act_level(L, blockIdx.x);
+  const int64_t b = (int64_t)(blockIdx.x - L.blk0[q]) * 256 + t;
+  if (b < L.nb[q] && box_active(ls, L.shift[q], b)) {
     atomicAdd(&c[8], 1);
     atomicAdd(&c[b & 7], 1);
   }
@@ -205,79 +228,161 @@ __global__ __launch_bounds__(256) void k_act_count(const int *__restrict__ ls, i
   if (t < 9) blkcnt[(int64_t)blockIdx.x * 9 + t] = c[t];
 }
 
-// single block: exclusive scan of each of the 9 columns over the blocks; the
-// class offsets and totals go to counts[0..8] (offset of class c, total at 8)
-__global__ __launch_bounds__(1024) void k_act_scan(int *__restrict__ blkcnt, int nblk,
-                                                   int *__restrict__ counts) {
-  __shared__ int part[1024];
-  __shared__ int tot[9];
-  const int t = threadIdx.x;
-  for (int col = 0; col < 9; ++col) {
-    int per = (nblk + 1023) / 1024;
-    int a = t * per, b = min(nblk, a + per);
-    int s = 0;
-    for (int i = a; i < b; ++i) s += blkcnt[(int64_t)i * 9 + col];
-    part[t] = s;
+// one block per level: exclusive scan of the 9 columns over the level's blocks
+// (in place); the class offsets and the total go to the level's counts
+__global__ __launch_bounds__(1024) void k_act_scan(int *__restrict__ blkcnt, ActLevels L) {
+  __shared__ int part[9][1024];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const int b0 = L.blk0[q], nblk = L.blk0[q + 1] - b0;
+  const int per = (nblk + 1023) / 1024;
+  const int a = min(nblk, t * per), b = min(nblk, a + per);
+  int s[9], run[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) s[c] = 0;
+  for (int i = a; i < b; ++i)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) s[c] += blkcnt[(int64_t)(b0 + i) * 9 + c];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) part[c][t] = s[c];
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = t >= off ? part[c][t - off] : 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int v = t >= off ? part[t - off] : 0;
-      __syncthreads();
-      part[t] += v;
-      __syncthreads();
-    }
-    int run = part[t] - s;
-    for (int i = a; i < b; ++i) {
-      int v = blkcnt[(int64_t)i * 9 + col];
-      blkcnt[(int64_t)i * 9 + col] = run;
-      run += v;
-    }
-    if (t == 1023) tot[col] = part[1023];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) part[c][t] += v[c];
     __syncthreads();
   }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) run[c] = part[c][t] - s[c];
+  for (int i = a; i < b; ++i)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const int64_t o = (int64_t)(b0 + i) * 9 + c;
+      const int v = blkcnt[o];
+      blkcnt[o] = run[c];
+      run[c] += v;
+    }
   if (t == 0) {
     int off = 0;
     for (int c = 0; c < 8; ++c) {
-      counts[c] = off;
-      off += tot[c];
+      L.counts[q][c] = off;
+      off += part[c][1023];
     }
-    counts[8] = tot[8];
+    L.counts[q][8] = part[8][1023];
   }
 }
 
-__global__ __launch_bounds__(256) void k_act_scatter(const int *__restrict__ ls, int shift,
-                                                     int64_t nb, const int *__restrict__ blkoff,
-                                                     const int *__restrict__ counts,
-                                                     uint32_t *__restrict__ act,
-                                                     int *__restrict__ slot,
-                                                     int *__restrict__ cls) {
+__global__ __launch_bounds__(256) void k_act_scatter(const int *__restrict__ ls, ActLevels L,
+                                                     const int *__restrict__ blkoff) {
   __shared__ int wtot[4][9];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  int64_t b = (int64_t)blockIdx.x * 256 + t;
-  bool a = b < nb && box_active(ls, shift, b);
-  int c = (int)(b & 7);
+  const int q = act_level(L, blockIdx.x);
+  const int64_t b = (int64_t)(blockIdx.x - L.blk0[q]) * 256 + t;
+  const bool a = b < L.nb[q] && box_active(ls, L.shift[q], b);
+  const int c = (int)(b & 7);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t ball = __ballot(a);
+  const uint64_t ball = __ballot(a);
   uint64_t bc[8];
-  for (int q = 0; q < 8; ++q) bc[q] = __ballot(a && c == q);
+  for (int k = 0; k < 8; ++k) bc[k] = __ballot(a && c == k);
   if (lane == 0) {
     wtot[w][8] = (int)__popcll(ball);
-    for (int q = 0; q < 8; ++q) wtot[w][q] = (int)__popcll(bc[q]);
+    for (int k = 0; k < 8; ++k) wtot[w][k] = (int)__popcll(bc[k]);
   }
   __syncthreads();
-  if (b >= nb) return;
+  if (b >= L.nb[q]) return;
   if (!a) {
-    slot[b] = -1;
+    L.slot[q][b] = -1;
     return;
   }
   int rt = (int)__popcll(ball & lt), rc = (int)__popcll(bc[c] & lt);
-  for (int q = 0; q < w; ++q) {
-    rt += wtot[q][8];
-    rc += wtot[q][c];
+  for (int k = 0; k < w; ++k) {
+    rt += wtot[k][8];
+    rc += wtot[k][c];
   }
-  int pos = blkoff[(int64_t)blockIdx.x * 9 + 8] + rt;
-  act[pos] = (uint32_t)b;
-  slot[b] = pos;
-  cls[counts[c] + blkoff[(int64_t)blockIdx.x * 9 + c] + rc] = pos;
+  const int64_t bo = (int64_t)blockIdx.x * 9;
+  const int pos = blkoff[bo + 8] + rt;
+  L.act[q][pos] = (uint32_t)b;
+  L.slot[q][b] = pos;
+  L.cls[q][L.counts[q][c] + blkoff[bo + c] + rc] = pos;
+}
+
+// M2L target order (levels 2..kMaxOrderLevel).  A box of class c at level k has
+// parent coordinates p_a, and its sources lie at 2 p_a - 2 .. 2 p_a + 3 per axis,
+// so a source falls outside the domain only for p_a = 0 (below) or p_a =
+// 2^(k-1) - 1 (above): the boxes of one class and one face signature (3 states
+// per axis) miss the same offsets.  One block per (level, class): a stable
+// counting sort of the class's slots by signature.
+struct OrdLevels {
+  int n;
+  int level[kMaxLevels];
+  const uint32_t *act[kMaxLevels];
+  const int *cls[kMaxLevels];
+  const int *counts[kMaxLevels];  // class offsets [0, 8) and the total [8]
+  int *ord[kMaxLevels];
+};
+
+__device__ inline int face_signature(uint32_t key, int last) {
+  int s = 0, m = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int p = (int)morton_axis(key, a) >> 1;
+    s += m * (p == 0 ? 0 : (p == last ? 2 : 1));
+    m *= 3;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_m2l_order(OrdLevels L) {
+  __shared__ int base[27];
+  __shared__ int wcnt[16][27];
+  const int q = (int)blockIdx.x >> 3, c = (int)blockIdx.x & 7;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int last = (1 << (L.level[q] - 1)) - 1;
+  const int *cnt = L.counts[q];
+  const int beg = cnt[c], end = c < 7 ? cnt[c + 1] : cnt[8];
+  const uint32_t *act = L.act[q];
+  const int *cls = L.cls[q];
+  int *ord = L.ord[q];
+  if (t < 27) base[t] = 0;
+  __syncthreads();
+  for (int i = beg + t; i < end; i += 1024) atomicAdd(&base[face_signature(act[cls[i]], last)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int b = 0; b < 27; ++b) {
+      const int v = base[b];
+      base[b] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int c0 = beg; c0 < end; c0 += 1024) {
+    const int i = c0 + t;
+    const bool v = i < end;
+    const int sl = v ? cls[i] : 0;
+    const int b = v ? face_signature(act[sl], last) : -1;
+    int rk = 0;
+    for (int bb = 0; bb < 27; ++bb) {
+      const uint64_t m = __ballot(b == bb);
+      if (b == bb) rk = (int)__popcll(m & lt);
+      if (lane == 0) wcnt[w][bb] = (int)__popcll(m);
+    }
+    __syncthreads();
+    if (v) {
+      int o = base[b] + rk;
+      for (int ww = 0; ww < w; ++ww) o += wcnt[ww][b];
+      ord[beg + o] = sl;
+    }
+    __syncthreads();
+    if (t < 27) {
+      int sum = 0;
+      for (int ww = 0; ww < 16; ++ww) sum += wcnt[ww][t];
+      base[t] += sum;
+    }
+    __syncthreads();
+  }
 }
 
 // interaction-list entries of level `level` summed into *out (statistics):
@@ -405,16 +510,25 @@ int sort_points(Plan &P, hipStream_t s) {
   return EIFMM_OK;
 }
 
-void build_active(Plan &P, int k, hipStream_t s) {
-  const int64_t nb = (int64_t)1 << (3 * k);
-  const int shift = 3 * (P.depth - k);
-  const int nblk = (int)((nb + 255) / 256);
-  int *blk = P.blkcnt;  // nblk * 9 ints
-  int *counts = P.counts_dev + 16 * k;
-  hipLaunchKernelGGL(k_act_count, dim3(nblk), dim3(256), 0, s, P.leaf_start, shift, nb, blk);
-  hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(1024), 0, s, blk, nblk, counts);
-  hipLaunchKernelGGL(k_act_scatter, dim3(nblk), dim3(256), 0, s, P.leaf_start, shift, nb, blk,
-                     counts, P.ld[k].act, P.ld[k].slot, P.ld[k].cls);
+// active boxes of levels k0..k1
+void build_active(Plan &P, int k0, int k1, hipStream_t s) {
+  ActLevels L{};
+  int blk = 0;
+  for (int k = k0; k <= k1; ++k) {
+    const int q = L.n++;
+    L.shift[q] = 3 * (P.depth - k);
+    L.nb[q] = (int64_t)1 << (3 * k);
+    L.blk0[q] = blk;
+    blk += (int)((L.nb[q] + 255) / 256);
+    L.act[q] = P.ld[k].act;
+    L.slot[q] = P.ld[k].slot;
+    L.cls[q] = P.ld[k].cls;
+    L.counts[q] = P.counts_dev + 16 * k;
+  }
+  L.blk0[L.n] = blk;
+  hipLaunchKernelGGL(k_act_count, dim3(blk), dim3(256), 0, s, P.leaf_start, L, P.blkcnt);
+  hipLaunchKernelGGL(k_act_scan, dim3(L.n), dim3(1024), 0, s, P.blkcnt, L);
+  hipLaunchKernelGGL(k_act_scatter, dim3(blk), dim3(256), 0, s, P.leaf_start, L, P.blkcnt);
 }
 
 // CSR list for level k into (ptr, src, off).  bounded: the entry count cannot
@@ -467,7 +581,6 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   const int side = 1 << depth;
   const double scale = std::ldexp(1.0, depth) / P.cfg.L;
   const int tbit = P.nt ? 1 : 0;
-  const int *se = tbit ? P.tgt_begin : P.leaf_start + 1;
   const int *tb = tbit ? P.tgt_begin : P.leaf_start;
   hipMemsetAsync(P.errflag, 0, sizeof(int), s);
   hipMemsetAsync(P.counts_dev, 0, sizeof(int) * 16 * kMaxLevels, s);
@@ -485,14 +598,15 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   if (tbit)
     hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s,
                        n, P.keys, nleaf, 1, 1, P.tgt_begin);
-  for (int k = std::min(2, depth); k <= depth; ++k) build_active(P, k, s);
+  build_active(P, std::min(2, depth), depth, s);
   if (!P.il_lazy) il_count_launch(P, s);
-  int host_counts[16 * kMaxLevels + 1];
+  // the counts and the error flag, into pinned memory
+  int *host_counts = P.counts_pin;
   hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
                  s);
-  int err = 0;
-  hipMemcpyAsync(&err, P.errflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(host_counts + 16 * kMaxLevels, P.errflag, sizeof(int), hipMemcpyDeviceToHost, s);
   hipError_t e = hipStreamSynchronize(s);
+  const int err = host_counts[16 * kMaxLevels];
   if (e != hipSuccess) {
     P.last_hip_error = (int)e;
     return EIFMM_EHIP;
@@ -509,6 +623,20 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     }
   }
   P.il_pending = P.il_lazy;
+  // M2L target order of the levels that keep one
+  {
+    OrdLevels L{};
+    for (int k = 2; k <= std::min(depth, kMaxOrderLevel); ++k) {
+      if (P.nact[k] == 0 || !P.ld[k].ord) continue;
+      const int q = L.n++;
+      L.level[q] = k;
+      L.act[q] = P.ld[k].act;
+      L.cls[q] = P.ld[k].cls;
+      L.counts[q] = P.counts_dev + 16 * k;
+      L.ord[q] = P.ld[k].ord;
+    }
+    if (L.n) hipLaunchKernelGGL(k_m2l_order, dim3(8 * L.n), dim3(1024), 0, s, L);
+  }
   // near lists of the leaf level (used by the near-field pass); at most 27
   // entries per box, within near_cap = 27 cap
   build_list(P, depth, 0, P.near_ptr, P.near_src, nullptr, P.near_cap, true, s);
@@ -523,11 +651,7 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
   P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 31) / 32 : 0;
-  hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), s);
-  if (P.nact[depth] > 0)
-    hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
-                       s, P.ld[depth].act, P.leaf_start, se, tb, P.near_ptr, P.near_src,
-                       (int)P.nact[depth], P.npairs_dev);
+  // the near-field pair counts (statistics) are taken when they are read
   P.counts_pending = true;
   e = hipGetLastError();
   if (e != hipSuccess) {
@@ -560,6 +684,16 @@ int tree_counts(Plan &P) {
   const int depth = P.depth;
   int total = 0;
   unsigned long long npairs[2] = {0, 0};
+  if (P.nact[depth] > 0) {
+    // the tree is complete once the device is idle
+    if (hipDeviceSynchronize() != hipSuccess) return EIFMM_EHIP;
+    const int *se = P.nt ? P.tgt_begin : P.leaf_start + 1;
+    const int *tb = P.nt ? P.tgt_begin : P.leaf_start;
+    hipMemsetAsync(P.npairs_dev, 0, 2 * sizeof(unsigned long long), nullptr);
+    hipLaunchKernelGGL(k_near_pairs, dim3((unsigned)((P.nact[depth] + 255) / 256)), dim3(256), 0,
+                       nullptr, P.ld[depth].act, P.leaf_start, se, tb, P.near_ptr, P.near_src,
+                       (int)P.nact[depth], P.npairs_dev);
+  }
   if (P.nact[depth] > 0 &&
       (hipMemcpy(&total, P.near_ptr + P.nact[depth], sizeof(int), hipMemcpyDeviceToHost) !=
            hipSuccess ||
@@ -579,7 +713,7 @@ int lists_export(Plan &P, int level, int64_t *nactive, uint32_t *active, int64_t
   const int lo_level = std::min(2, P.depth);
   if (level < lo_level) {
     // levels 0 and 1 are not kept per query; build them on the fly
-    build_active(P, level, s);
+    build_active(P, level, level, s);
     int hc[16];
     hipMemcpy(hc, P.counts_dev + 16 * level, sizeof(int) * 16, hipMemcpyDeviceToHost);
     P.nact[level] = hc[8];

@@ -198,3 +198,16 @@ def test_compression_finite_rank_exact(oracle_lib):
     P = oracle_lib.Plan("sqdist", 0, [0, 0, 0], 1.0, 3, 1e-8, compress_tol=1e-12)
     fd = oracle_lib.direct("sqdist", 0, x, x, s)
     assert _rel(P.evaluate(x, s), fd) < 1e-11
+
+
+def test_compression_rank_filters_by_hand():
+    """The two filters of Sec. 4.2 on spectra whose ranks are counted by hand:
+    (i) 1000 unit values and one of 2e-6 at eps = 1e-6: the relative cut-off keeps
+    all 1001 (2e-6 > eps), the energy prefix stops at 1000; (ii) one unit value and
+    1000 of 5e-7: the relative cut-off keeps 1, the energy prefix needs
+    1 + 5e-7 m >= (1 - 1e-6) * 1.0005, i.e. m = 998 more values (rank 999);
+    (iii) both filters agree on a spectrum with a clean gap."""
+    from oracle import compression_rank
+    assert compression_rank(np.array([1.0] * 1000 + [2e-6]), 1e-6) == 1001
+    assert compression_rank(np.array([1.0] + [5e-7] * 1000), 1e-6) == 999
+    assert compression_rank(np.array([3.0, 2.0, 1.0, 1e-9, 1e-10]), 1e-6) == 3
