@@ -299,6 +299,11 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
     P.sk_ws = shared_ws;
   else
     TRY(dalloc(&P.sk_ws, stream_k_ws_len(P.sk_groups), tr));
+  // the gathered GEMM's tail counter, at the end of the workspace, starts at zero
+  if (!shared_ws &&
+      hipMemset(P.sk_ws + stream_k_ws_len(P.sk_groups) - kCounterDoubles, 0,
+                kCounterDoubles * sizeof(double)) != hipSuccess)
+    return EIFMM_EHIP;
   if (depth >= 2)
     TRY(dalloc(&P.lhat, P.ld[depth].cap * (size_t)R * (size_t)P.lh[depth].dpB, tr));
   // the gathered-GEMM job table at its largest size, so that no evaluation
@@ -1009,7 +1014,10 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
   }
   if (!st) {
     b->sk_groups = stream_k_groups(b->device);
-    if (hipMalloc(&b->sk_ws, sizeof(double) * stream_k_ws_len(b->sk_groups)) != hipSuccess)
+    if (hipMalloc(&b->sk_ws, sizeof(double) * stream_k_ws_len(b->sk_groups)) != hipSuccess ||
+        hipMemset(b->sk_ws + stream_k_ws_len(b->sk_groups) - kCounterDoubles, 0,
+                  kCounterDoubles * sizeof(double)) !=
+            hipSuccess)
       st = EIFMM_ENOMEM;
   }
   if (!st) {

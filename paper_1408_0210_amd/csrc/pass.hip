@@ -543,38 +543,68 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
   const int dp = D.dp, nb = dp >> 4, rs = lane >> 4;
   const double *x = D.in + (int64_t)(cv ? c : 0) * dp;
   double *y = D.out + (int64_t)(cv ? c : 0) * dp;
-  for (int bi = 0; bi < nb; ++bi) {
-    v4 acc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = cv ? x[16 * bi + rs + 4 * q] : 0.0;
-    const double *Ar = D.Tf + (int64_t)bi * nb * 256 + lane;
-    // two independent accumulation chains (even and odd tiles), added at the end
+  // acc += sum over tiles j in [j0, j1) of row Ar's tile j times z_j, in two
+  // accumulation chains (even and odd tiles).  The operator fragments of a pair
+  // of tiles are loaded a pair ahead; past the end the loads read the row's last
+  // tile, so the loads in flight do not depend on the data.
+  auto row_sum = [&](const double *Ar, int j0, int j1, v4 &acc) {
     v4 acc2 = {0, 0, 0, 0};
-    int bj = 0;
-    for (; bj + 1 < bi; bj += 2) {
-      const double *Ab = Ar + bj * 256;
+    const int npair = (j1 - j0) >> 1;
+    double fa[2][4], fb[2][4];
+    auto load = [&](double(&f)[2][4], int j) {
+      const int ja = min(j, nb - 1), jb = min(j + 1, nb - 1);
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
-                                                   0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[256 + ks * 64],
-                                                    zs[((bj + 1) * 4 + ks) * 64 + lane], acc2, 0,
-                                                    0, 0);
+        f[0][ks] = Ar[ja * 256 + ks * 64];
+        f[1][ks] = Ar[jb * 256 + ks * 64];
       }
+    };
+    auto mul = [&](const double(&f)[2][4], int j) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f[0][ks], zs[(j * 4 + ks) * 64 + lane], acc, 0,
+                                                   0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[1][ks], zs[((j + 1) * 4 + ks) * 64 + lane],
+                                                    acc2, 0, 0, 0);
+      }
+    };
+    int p = 0, j = j0;
+    load(fa, j);
+    for (; p + 2 <= npair; p += 2, j += 4) {
+      load(fb, j + 2);
+      mul(fa, j);
+      load(fa, j + 4);
+      mul(fb, j + 2);
     }
-    if (bj < bi) {
-      const double *Ab = Ar + bj * 256;
+    if (p < npair) {
+      mul(fa, j);
+      j += 2;
+    }
+    if (j < j1) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
-                                                   0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ar[j * 256 + ks * 64],
+                                                   zs[(j * 4 + ks) * 64 + lane], acc, 0, 0, 0);
     }
     acc += acc2;
-    const double *Ad = Ar + bi * 256;
+  };
+  v4 xn;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xn[q] = cv ? x[rs + 4 * q] : 0.0;
+  for (int bi = 0; bi < nb; ++bi) {
+    v4 acc = xn;
+    // the next row's right-hand side, loaded during this row's products
+    const int bn = min(bi + 1, nb - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xn[q] = cv ? x[16 * bn + rs + 4 * q] : 0.0;
+    const double *Ar = D.Tf + (int64_t)bi * nb * 256 + lane;
+    double dg[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) dg[ks] = Ar[bi * 256 + ks * 64];
+    row_sum(Ar, 0, bi, acc);
     v4 z = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      z = __builtin_amdgcn_mfma_f64_16x16x4f64(Ad[ks * 64], acc[ks], z, 0, 0, 0);
+    for (int ks = 0; ks < 4; ++ks) z = __builtin_amdgcn_mfma_f64_16x16x4f64(dg[ks], acc[ks], z, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = z[q];
     if (!D.Tb && cv) {
@@ -588,32 +618,13 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = zs[(bi * 4 + q) * 64 + lane];
     const double *Ar = D.Tb + (int64_t)bi * nb * 256 + lane;
-    v4 acc2 = {0, 0, 0, 0};
-    int bj = bi + 1;
-    for (; bj + 1 < nb; bj += 2) {
-      const double *Ab = Ar + bj * 256;
+    double dg[4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
-                                                   0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[256 + ks * 64],
-                                                    zs[((bj + 1) * 4 + ks) * 64 + lane], acc2, 0,
-                                                    0, 0);
-      }
-    }
-    if (bj < nb) {
-      const double *Ab = Ar + bj * 256;
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[ks * 64], zs[(bj * 4 + ks) * 64 + lane], acc,
-                                                   0, 0, 0);
-    }
-    acc += acc2;
-    const double *Ad = Ar + bi * 256;
+    for (int ks = 0; ks < 4; ++ks) dg[ks] = Ar[bi * 256 + ks * 64];
+    row_sum(Ar, bi + 1, nb, acc);
     v4 w = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      w = __builtin_amdgcn_mfma_f64_16x16x4f64(Ad[ks * 64], acc[ks], w, 0, 0, 0);
+    for (int ks = 0; ks < 4; ++ks) w = __builtin_amdgcn_mfma_f64_16x16x4f64(dg[ks], acc[ks], w, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = w[q];
     if (cv) {
@@ -653,13 +664,13 @@ __global__ __launch_bounds__(64) void k_trsm_list(const SolveDesc *__restrict__ 
 // group, where B_t[:, col] is the expansion of the source box that term t pairs
 // with the column's target box: M2L the box at offset delta; M2M child t; L2L the
 // parent; PROJ the box itself (compression projections).  A workgroup computes a
-// (16 RBT)-row x 128-column tile with 16x16x4 MFMAs; each of the 4 waves owns 32
-// columns and all RBT row blocks.  Operand chunks of 16 k values pass through LDS
-// in MFMA fragment order; the next chunk is loaded into registers while the
-// current one is multiplied.  With FOLD (FP32 operands) each term's product is
-// accumulated by the MFMA in FP32 and then added to an FP64 sum over the terms,
-// so FP32 rounding grows with one matrix product (d_k terms) rather than with
-// the whole interaction list.
+// (16 RBT)-row tile, 128 columns wide for 3 and 4 row blocks and 64 for 5 and 6,
+// with 16x16x4 MFMAs; each of the 4 waves owns a quarter of the columns and all
+// RBT row blocks.  The operator chunks of 16 k values pass through LDS in MFMA
+// fragment order, loaded two chunks ahead of their products.  With FOLD (FP32
+// operands) each term's product is accumulated by the MFMA in FP32 and then
+// added to an FP64 sum over the terms, so FP32 rounding grows with one matrix
+// product (d_k terms) rather than with the whole interaction list.
 constexpr int MODE_M2M = 0, MODE_M2L = 1, MODE_L2L = 2, MODE_PROJ = 3;
 // 16-column blocks per wave: 2 (128-column tiles) for 3- and 4-block tiles, 1
 // (64 columns) for taller ones, whose accumulators and three sets of prefetched
@@ -668,6 +679,12 @@ __host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 5 ? 1 : 2; }
 static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2 && gemm_cpw(3) == 2, "tile widths");
 __host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
 constexpr int kMaxTerms = 189;   // terms of one job (M2L: the offsets of a child class)
+// M2L: the tiles left after the whole-tile rounds are split in kTailParts term
+// ranges each, taken by the workgroups from a counter as they finish, so that
+// workgroups whose tiles skipped products take more of them.  The counter sits
+// in the last kCounterDoubles of the Stream-K workspace; it is zero when a
+// workspace is made, and the fixup that follows each such launch zeroes it.
+constexpr int kTailParts = 3;
 // zeros, read in place of a missing source column or of operator rows past the
 // operator, so that every chunk issues the same loads (static device memory is
 // zero-initialized; 1024 covers the longest column, d_k <= 1024)
@@ -1066,7 +1083,8 @@ template <typename T, int MODE, bool FOLD, int RBT>
 __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ jobs, int njobs,
                                                  int ntiles, int64_t units, int G, int GT,
                                                  double *__restrict__ ws,
-                                                 const int8_t *__restrict__ dvec) {
+                                                 const int8_t *__restrict__ dvec, int dyn_items,
+                                                 int *__restrict__ ctr) {
   constexpr int TILE = RBT * 16 * 64 * gemm_cpw(RBT);
   __shared__ T As[2][RBT * 4 * 64];
   __shared__ ColState cst[2 * 256];
@@ -1083,6 +1101,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
                                   cst, sdel);
   }
   if (full == ntiles) return;
+  if (MODE == MODE_M2L && dyn_items > 0) {
+    // the remaining tiles, kTailParts pieces each, taken in order from the counter
+    __shared__ int item_sh;
+    for (;;) {
+      if (threadIdx.x == 0) item_sh = atomicAdd(ctr, 1);
+      __syncthreads();
+      const int item = item_sh;
+      __syncthreads();
+      if ((unsigned)item >= (unsigned)dyn_items) return;  // done (or a stale counter)
+      const int tile = full + item / kTailParts, q = item % kTailParts;
+      const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
+      gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, q * J.nterms / kTailParts,
+                                    (q + 1) * J.nterms / kTailParts, ws + (size_t)item * TILE,
+                                    dvec, As, cst, sdel);
+    }
+  }
   // the remaining units, split evenly
   const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
   const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
@@ -1115,30 +1149,45 @@ constexpr int kFixupSplit = 4;
 template <int RBT>
 __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
                                                     int ntiles, int64_t units, int G, int GT,
-                                                    const double *__restrict__ ws) {
+                                                    const double *__restrict__ ws, int dyn_items,
+                                                    int *__restrict__ ctr) {
   constexpr int COLS = 64 * gemm_cpw(RBT), TILE = RBT * 16 * COLS;
   constexpr int SLICE = TILE / kFixupSplit;
   static_assert(SLICE % 256 == 0 && 256 % COLS == 0, "fixup slices");
   const int full = (ntiles / G) * G;
   const int tile = full + (int)(blockIdx.x / kFixupSplit);
   const int slice = (int)(blockIdx.x % kFixupSplit);
+  if (dyn_items > 0 && blockIdx.x == 0 && threadIdx.x == 0) stg(ctr, 0);  // for the next launch
   if (tile >= ntiles) return;
-  const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
-  const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
-  const int64_t R = units - S;
-  const int Gt = (int)min((int64_t)GT, R);
   const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
   const int tile_local = tile - J.tiles_start;
-  // unit range of the tile relative to S; workgroup g starts at unit
-  // sk_bound(g) = floor(g R / Gt), so the last one starting at or before ts is
-  // floor(((ts + 1) Gt - 1) / R) and the last one starting before te is
-  // floor((te Gt - 1) / R)
-  const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms - S, te = ts + J.nterms;
-  const int64_t glo = min(((ts + 1) * Gt - 1) / R, (int64_t)Gt - 1);
-  const int64_t ghi = min((te * Gt - 1) / R, (int64_t)Gt - 1);
-  if (ghi == glo) return;  // written directly
-  const int np = (int)(ghi - glo + 1);
-  const int first = (int)(2 * glo + (sk_bound(glo, R, Gt) == ts ? 0 : 1));
+  int64_t glo;
+  int np, first;
+  if (dyn_items > 0) {
+    // kTailParts pieces in slots (tile - full) kTailParts + q
+    np = kTailParts;
+    first = (tile - full) * kTailParts;
+    glo = 0;
+  } else {
+    const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
+    const int64_t S = Jr.units_start + (int64_t)(full - Jr.tiles_start) * Jr.nterms;
+    const int64_t R = units - S;
+    const int Gt = (int)min((int64_t)GT, R);
+    // unit range of the tile relative to S; workgroup g starts at unit
+    // sk_bound(g) = floor(g R / Gt), so the last one starting at or before ts is
+    // floor(((ts + 1) Gt - 1) / R) and the last one starting before te is
+    // floor((te Gt - 1) / R)
+    const int64_t ts = J.units_start + (int64_t)tile_local * J.nterms - S, te = ts + J.nterms;
+    glo = min(((ts + 1) * Gt - 1) / R, (int64_t)Gt - 1);
+    const int64_t ghi = min((te * Gt - 1) / R, (int64_t)Gt - 1);
+    if (ghi == glo) return;  // written directly
+    np = (int)(ghi - glo + 1);
+    first = (int)(2 * glo + (sk_bound(glo, R, Gt) == ts ? 0 : 1));
+  }
+  // slot of piece i: consecutive slots for the counter's pieces; for the even
+  // split, glo's piece then the first slot of each later workgroup
+  const bool dyn = dyn_items > 0;
+  auto slot_of = [&](int i) { return dyn ? first + i : (i == 0 ? first : (int)(2 * (glo + i))); };
   const int rowtile = tile_local % J.nrowtiles, coltile = tile_local / J.nrowtiles;
   const int rb0 = rowtile * RBT, col0 = coltile * COLS;
   const int nrows = min(RBT * 16, J.dpm - 16 * rb0);
@@ -1166,17 +1215,11 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
     for (; i + 8 <= np; i += 8) {
       double p[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int sl = i + u == 0 ? first : (int)(2 * (glo + i + u));
-        p[u] = ldg(ws + (size_t)sl * TILE + e);
-      }
+      for (int u = 0; u < 8; ++u) p[u] = ldg(ws + (size_t)slot_of(i + u) * TILE + e);
 #pragma unroll
       for (int u = 0; u < 8; ++u) v += p[u];
     }
-    for (; i < np; ++i) {
-      const int sl = i == 0 ? first : (int)(2 * (glo + i));
-      v += ldg(ws + (size_t)sl * TILE + e);
-    }
+    for (; i < np; ++i) v += ldg(ws + (size_t)slot_of(i) * TILE + e);
     const int64_t o = obase + rt;
     if (J.mode == MODE_L2L) v += ldg(J.Cadd + o);
     stg(Cout + o, v);
@@ -1681,15 +1724,22 @@ namespace {
 template <typename T, int MODE, int RBT>
 void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int gmax,
                      double *ws, size_t ws_len, const int8_t *dvec, hipStream_t s) {
+  const size_t TILE = (size_t)RBT * 16 * gemm_cols(RBT);
+  int *ctr = (int *)(ws + ws_len - kCounterDoubles);
+  const size_t len = ws_len - kCounterDoubles;  // pieces
   const int G = (int)std::min<int64_t>(units, gmax);
-  const int GT = (int)std::min<size_t>((size_t)G, ws_len / (2 * (size_t)RBT * 16 * gemm_cols(RBT)));
+  const int GT = (int)std::min<size_t>((size_t)G, len / (2 * TILE));
+  const int rest = tiles - (tiles / G) * G;
+  // the counter's split of the remaining tiles (M2L, when its pieces fit)
+  int dyn = 0;
+  if (MODE == MODE_M2L && G > 1 && rest > 0 && (size_t)rest * kTailParts * TILE <= len)
+    dyn = rest * kTailParts;
   constexpr bool fold = sizeof(T) == 4;
   hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, jobs, n, tiles,
-                     units, G, GT, ws, dvec);
-  const int rest = tiles - (tiles / G) * G;
+                     units, G, GT, ws, dvec, dyn, ctr);
   if (G > 1 && rest > 0)
     hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest * kFixupSplit), dim3(256), 0, s, jobs, n,
-                       tiles, units, G, GT, ws);
+                       tiles, units, G, GT, ws, dyn, ctr);
 }
 
 template <typename T, int MODE>

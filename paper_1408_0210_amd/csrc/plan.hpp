@@ -335,6 +335,9 @@ struct Plan {
 // Stream-K workspace of `groups` persistent workgroups: 2 pieces of the largest
 // tile (6 x 16 x 128 doubles) each
 inline size_t stream_k_ws_len(int groups) { return (size_t)2 * groups * 6 * 16 * 128; }
+// the last doubles of a Stream-K workspace hold the gathered GEMM's tail counter
+// (zero when the workspace is made)
+constexpr size_t kCounterDoubles = 32;
 // gathered-GEMM jobs a plan of this depth can have: M2M and the two projections
 // one per level, M2L and L2L one per level and child class
 inline size_t max_gemm_jobs(int depth) { return (size_t)19 * (depth > 0 ? depth : 1) + 16; }
