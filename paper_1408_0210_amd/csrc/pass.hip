@@ -689,6 +689,9 @@ constexpr int kTailParts = 3;
 // operator, so that every chunk issues the same loads (static device memory is
 // zero-initialized; 1024 covers the longest column, d_k <= 1024)
 __device__ double g_gemm_zero[1024];
+// the slots read for a missing source: no box (one per column of a lane, so that
+// the dummy loads stay distinct loads)
+__device__ int g_slot_none[2] = {-1, -1};
 
 // Operand layouts (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
 // Result layouts differ: FP64 keeps rows (l / 16) + 4 q of column l % 16 in
@@ -717,13 +720,14 @@ struct Mfma<float> {
 // Where the slot of the source box that term `term` pairs with target (tkey, ts)
 // is read: M2L the box at offset delta, M2M child `term`, L2L the parent (entries
 // of the source level's slot map, which holds -1 for an empty box); PROJ needs
-// no read (the box itself).  *ok is false for a missing column or a source
-// outside the domain; the address is then a valid dummy, so that every lane
-// reads and the number of loads in flight does not depend on the data.
+// no read (the box itself).  For a missing column or a source outside the
+// domain the address is g_slot_none[jj] (-1, no box), so that every lane reads,
+// the number of loads in flight does not depend on the data, and the value read
+// needs no select (a select right after the load would wait for it).
 template <int MODE>
 __device__ inline const int *gemm_source_addr(const GemmJob &J, int term, bool cvalid,
                                               uint32_t tkey, const int *sdel,
-                                              const int *__restrict__ src_slot, bool *ok) {
+                                              const int *__restrict__ src_slot, int jj) {
   uint32_t skey;
   bool v = cvalid;
   if constexpr (MODE == MODE_M2L) {
@@ -739,8 +743,7 @@ __device__ inline const int *gemm_source_addr(const GemmJob &J, int term, bool c
   } else {
     skey = tkey >> 3;
   }
-  *ok = v && src_slot;
-  return *ok ? src_slot + skey : (const int *)g_gemm_zero;
+  return (v && src_slot) ? src_slot + skey : &g_slot_none[jj];
 }
 
 template <typename T>
@@ -893,29 +896,25 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   P2 B0[CPW][2], B1[CPW][2], B2[CPW][2];   // B of a chunk: [column][pair]
   const T *srcp[CPW];
   const T *Ap = nullptr;
-  // source slots of the next term: read by the fetch of a term's last chunk
-  // (the other fetches read a dummy), used at the next term's first chunk
+  // source slots of the next term (-1: none): read by the fetch of a term's
+  // last chunk (the other fetches read g_slot_none), used at the next term's
+  // first chunk
   int nslot[CPW];
-  bool nok[CPW];
 #pragma unroll
   for (int jj = 0; jj < CPW; ++jj) {
     srcp[jj] = nullptr;
     nslot[jj] = -1;
-    nok[jj] = false;
   }
   auto lookup = [&](int term, bool real) {
 #pragma unroll
     for (int jj = 0; jj < CPW; ++jj) {
       const ColState c = my[jj];
       if constexpr (MODE == MODE_PROJ) {
-        nok[jj] = c.valid;
-        nslot[jj] = c.tsl;
+        nslot[jj] = c.valid ? c.tsl : -1;
       } else {
-        const int *addr = (const int *)g_gemm_zero;
-        bool ok = false;
-        if (real) addr = gemm_source_addr<MODE>(J, term, c.valid, c.tkey, sdel, c.slot_map, &ok);
+        const int *addr = &g_slot_none[jj];
+        if (real) addr = gemm_source_addr<MODE>(J, term, c.valid, c.tkey, sdel, c.slot_map, jj);
         nslot[jj] = ldg(addr);
-        nok[jj] = ok;
       }
     }
   };
@@ -937,7 +936,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
 #pragma unroll
         for (int jj = 0; jj < CPW; ++jj) {
           const ColState c = my[jj];
-          srcp[jj] = gemm_source_ptr<T>(J, nok[jj] ? nslot[jj] : -1, c.r, (const T *)c.B);
+          srcp[jj] = gemm_source_ptr<T>(J, nslot[jj], c.r, (const T *)c.B);
         }
         Ap = gemm_operand<T, MODE>(J, term, sdel);
         if constexpr (MODE == MODE_M2L) {
