@@ -199,9 +199,9 @@ __device__ inline NearSrc near_sources(const LeafDesc &D, int j, int *pre, int *
   return NearSrc{nq, pre[nq]};
 }
 
-// point index of source number v (0 <= v < total)
-__device__ inline int near_point(int v, int nq, const int *pre, const int *start) {
-  int e = 0;
+// point index of source number v (0 <= v < total); e is the neighbour of the
+// lane's previous (smaller) source number, so the search resumes there
+__device__ inline int near_point(int v, int nq, const int *pre, const int *start, int &e) {
   while (e + 1 < nq && pre[e + 1] <= v) ++e;
   return start[e] + (v - pre[e]);
 }
@@ -234,10 +234,11 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
     double px = 0, py = 0, pz = 0, ps[RB];
     // a block past the end is padded with the last source at zero potential, so
     // every block has 64 sources and the pair loop a fixed trip count
+    int ecur = 0;  // neighbour of this lane's last source number
     auto load = [&](int base) {
       const int v = base + lane;
       if (S.total > 0) {
-        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start);
+        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start, ecur);
         px = xyz[sidx];
         py = xyz[n + sidx];
         pz = xyz[2 * n + sidx];
@@ -313,10 +314,11 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
     float ps[RB];
     // padding past the end as in k_p2p64 (zero potential adds exactly zero to
     // the compensated sums)
+    int ecur = 0;  // neighbour of this lane's last source number
     auto load = [&](int base) {
       const int v = base + lane;
       if (S.total > 0) {
-        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start);
+        const int sidx = near_point(v < S.total ? v : S.total - 1, S.nq, pre, start, ecur);
         px = xyz[sidx];
         py = xyz[n + sidx];
         pz = xyz[2 * n + sidx];
@@ -419,7 +421,9 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
         for (int q = 0; q < cnt; ++q) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            if (u < nu) {
+            // skipped by a whole wave whose rows all lie past d (rows d..dp-1
+            // are stored as zeros)
+            if (u < nu && m0 + NT * u + (t & ~63) < d) {
               const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
               const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
 #pragma unroll
@@ -488,6 +492,7 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
     double acc[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = 0.0;
+#pragma unroll 4
     for (int l = l0; l < l1; ++l) {
       const double dx = xc - sX[3 * l], dy = yc - sX[3 * l + 1], dz = zc - sX[3 * l + 2];
       const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
