@@ -32,9 +32,12 @@
  *     Morton-ordered storage).  The library owns its tables and workspaces
  *     until eifmm_plan_destroy.
  *   - Calls enqueue work on the given HIP stream (NULL = default stream) and
- *     return before it finishes, except eifmm_set_points, which waits for the
- *     tree build so it can report invalid points, and the export calls, which
- *     copy to host memory and wait.
+ *     return before it finishes, except the export calls, which copy to host
+ *     memory and wait, and eifmm_set_points, which waits until the box counts
+ *     of the tree are on the host (to report invalid points and size the
+ *     pass); its last kernels (near lists, chunk table, M2L column order) are
+ *     still in flight on its stream when it returns, so an evaluate on another
+ *     stream must first wait for that stream.
  *   - Every call returns 0 (EIFMM_OK) or a negative status.  A failed call
  *     leaves the plan usable (or, for plan_create, nothing to destroy).
  *   - A plan is not thread-safe; distinct plans are independent.
@@ -190,7 +193,7 @@ int eifmm_plan_create(const eifmm_config *cfg, eifmm_plan *out);
  * the leaf cells, a stable sort by (key, input index), Morton-ordered copies,
  * leaf ranges, active boxes per level and the near lists.  Returns
  * EIFMM_EDOMAIN if a point is outside [lo, lo+L]^3 or not finite (the plan then
- * has no points).  Waits for the build. */
+ * has no points).  Waits for the box counts (see the conventions above). */
 int eifmm_set_points(eifmm_plan plan, const double *xyz_dev, void *hip_stream);
 
 /* For a plan with n_targets > 0: builds one octree over the n sources

@@ -107,6 +107,10 @@ void release(eifmm_plan h) {
     hipEventSynchronize(P.job_evt);
     hipEventDestroy(P.job_evt);
   }
+  if (P.ev_counts) {
+    hipEventSynchronize(P.ev_counts);
+    hipEventDestroy(P.ev_counts);
+  }
   if (P.job_dev) hipFree(P.job_dev);
   if (P.job_pin) hipHostFree(P.job_pin);
   if (P.counts_pin) hipHostFree(P.counts_pin);
@@ -318,7 +322,8 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
       return EIFMM_ENOMEM;
     }
     P.job_cap = cap;
-    if (hipEventCreateWithFlags(&P.job_evt, hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&P.job_evt, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P.ev_counts, hipEventDisableTiming) != hipSuccess)
       return EIFMM_EHIP;
   }
 #undef TRY

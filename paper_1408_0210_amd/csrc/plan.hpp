@@ -310,6 +310,7 @@ struct Plan {
   size_t job_cap = 0;             // jobs job_dev and job_pin hold
   GemmJob *job_pin = nullptr;     // pinned staging copy of the job table
   hipEvent_t job_evt = nullptr;   // recorded after the last copy from job_pin
+  hipEvent_t ev_counts = nullptr; // recorded after the tree's counts are copied to counts_pin
   // second stream of the pass: the near field runs on it beside the upward pass
   // (fork after the potentials are gathered, join before L2P)
   hipStream_t side = nullptr;

@@ -178,12 +178,13 @@ __global__ __launch_bounds__(256) void k_near_pairs(const uint32_t *__restrict__
 // 0 past the active count
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t *__restrict__ act,
                                                      const int *__restrict__ ls,
-                                                     const int *__restrict__ tb, int nact,
-                                                     int64_t len, int *__restrict__ cnt) {
+                                                     const int *__restrict__ tb,
+                                                     const int *__restrict__ nact, int64_t len,
+                                                     int *__restrict__ cnt) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= len) return;
   int c = 0;
-  if (j < nact) {
+  if (j < *nact) {
     const uint32_t key = act[j];
     c = (ls[key + 1] - tb[key] + 31) >> 5;
   }
@@ -600,34 +601,19 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
                        n, P.keys, nleaf, 1, 1, P.tgt_begin);
   build_active(P, std::min(2, depth), depth, s);
   if (!P.il_lazy) il_count_launch(P, s);
-  // the counts and the error flag, into pinned memory
+  // the counts and the error flag, into pinned memory; the host waits for this
+  // copy only, while the order, the near lists and the chunks below (which read
+  // the counts on the device) run
   int *host_counts = P.counts_pin;
   hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
                  s);
   hipMemcpyAsync(host_counts + 16 * kMaxLevels, P.errflag, sizeof(int), hipMemcpyDeviceToHost, s);
-  hipError_t e = hipStreamSynchronize(s);
-  const int err = host_counts[16 * kMaxLevels];
-  if (e != hipSuccess) {
-    P.last_hip_error = (int)e;
-    return EIFMM_EHIP;
-  }
-  if (err) return EIFMM_EDOMAIN;
-  for (int k = std::min(2, depth); k <= depth; ++k) {
-    P.nact[k] = host_counts[16 * k + 8];
-    for (int c = 0; c < 8; ++c) P.cls_off[k][c] = host_counts[16 * k + c];
-    P.cls_off[k][8] = P.nact[k];
-    if (!P.il_lazy) {
-      unsigned long long ilp = 0;
-      std::memcpy(&ilp, &host_counts[16 * k + 10], sizeof(ilp));
-      P.il_pairs[k] = k >= 2 ? (int64_t)ilp : 0;
-    }
-  }
-  P.il_pending = P.il_lazy;
+  hipEventRecord(P.ev_counts, s);
   // M2L target order of the levels that keep one
   {
     OrdLevels L{};
     for (int k = 2; k <= std::min(depth, kMaxOrderLevel); ++k) {
-      if (P.nact[k] == 0 || !P.ld[k].ord) continue;
+      if (!P.ld[k].ord) continue;
       const int q = L.n++;
       L.level[q] = k;
       L.act[q] = P.ld[k].act;
@@ -646,12 +632,29 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   {
     const int64_t cap = P.ld[depth].cap;
     hipLaunchKernelGGL(k_chunk_count, dim3((unsigned)((cap + 1 + 255) / 256)), dim3(256), 0, s,
-                       P.ld[depth].act, P.leaf_start, tb, (int)P.nact[depth], cap + 1,
+                       P.ld[depth].act, P.leaf_start, tb, P.counts_dev + 16 * depth + 8, cap + 1,
                        P.list_cnt);
     scan_exclusive_i32(P.list_cnt, P.chunk_ptr, cap + 1, P.scan_tmp, s);
   }
-  P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 31) / 32 : 0;
-  // the near-field pair counts (statistics) are taken when they are read
+  hipError_t e = hipEventSynchronize(P.ev_counts);
+  const int err = host_counts[16 * kMaxLevels];
+  if (e != hipSuccess) {
+    P.last_hip_error = (int)e;
+    return EIFMM_EHIP;
+  }
+  if (err) return EIFMM_EDOMAIN;
+  for (int k = std::min(2, depth); k <= depth; ++k) {
+    P.nact[k] = host_counts[16 * k + 8];
+    for (int c = 0; c < 8; ++c) P.cls_off[k][c] = host_counts[16 * k + c];
+    P.cls_off[k][8] = P.nact[k];
+    if (!P.il_lazy) {
+      unsigned long long ilp = 0;
+      std::memcpy(&ilp, &host_counts[16 * k + 10], sizeof(ilp));
+      P.il_pairs[k] = k >= 2 ? (int64_t)ilp : 0;
+    }
+  }
+  P.il_pending = P.il_lazy;
+  P.nchunk = P.nact[depth] > 0 ? P.nact[depth] + (n + 31) / 32 : 0;  // the near-field pair counts (statistics) are taken when they are read
   P.counts_pending = true;
   e = hipGetLastError();
   if (e != hipSuccess) {
