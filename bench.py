@@ -733,9 +733,11 @@ def main():
                      "flops_executed": st["m2l_flops_exec"],
                      "frac_executed": st["m2l_flops_exec"] / (m2l_ms * 1e-3) / (peak * 1e12),
                      "note": "flops_per_launch: 2 r_k^2 per interaction pair with r_k the rank "
-                             "of the Sec. 4.2 filters (the method's work); flops_executed: what "
-                             "the MFMAs run (rank padded to 16-row blocks, every offset of a "
-                             "child class including sources outside the domain)"},
+                             "of the Sec. 4.2 filters (the method's work); flops_executed: the "
+                             "products a launch issues at most (rank padded to 16-row blocks, "
+                             "every offset of a child class including sources outside the "
+                             "domain); a wave skips the terms none of its columns has a source "
+                             "for, so the MFMAs run less"},
         "phase_roofline": prow, "t_roof_ms": troof_ms, "t_roof_frac": troof_frac,
     }
     r["plan"].close()

@@ -983,10 +983,41 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   int mkc = 0;  // k chunk of the current term
   // the products of chunk it (its A in LDS buffer (it - it0) & 1, its B in Bc),
   // with the loads of chunk it + 2 into (Rf, Bf) and chunk it + 1 (Rn) stashed
-  // the products of one chunk
+  // The products of a chunk's last k-step are deferred to the start of the next
+  // step, after the barrier, so that their MFMAs run while the wave issues the
+  // next chunk's loads (a branch around the products, for the skipped terms,
+  // would otherwise keep the compiler from moving them there); their operands
+  // wait in registers.  With FOLD a term's sum is folded after them.
+  T a3[RBT], b3[CPW];
+  bool dpend = false, fpend = false;  // deferred products and fold pending (wave-uniform)
+  auto deferred = [&]() {
+    if (dpend) {
+#pragma unroll
+      for (int i = 0; i < RBT; ++i)
+        if (RBT != 6 || rowok[i]) {
+#pragma unroll
+          for (int jj = 0; jj < CPW; ++jj) acc[i][jj] = Mfma<T>::op(a3[i], b3[jj], acc[i][jj]);
+        }
+    }
+    if constexpr (FOLD) {
+      if (fpend) {  // a term is complete
+#pragma unroll
+        for (int i = 0; i < RBT; ++i)
+#pragma unroll
+          for (int jj = 0; jj < CPW; ++jj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
+            acc[i][jj] = V4{0, 0, 0, 0};
+          }
+      }
+    }
+    dpend = false;
+    fpend = false;
+  };
+  // k-steps 0..2 of one chunk, and the operands of k-step 3
   auto products = [&](int cur, const P2(&Bc)[CPW][2]) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < 3; ++ks) {
       T a[RBT], b[CPW];
 #pragma unroll
       for (int i = 0; i < RBT; ++i) a[i] = As[cur][(i * 4 + ks) * 64 + lane];
@@ -1003,25 +1034,23 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
           for (int jj = 0; jj < CPW; ++jj) acc[i][jj] = Mfma<T>::op(a[i], b[jj], acc[i][jj]);
         }
     }
+#pragma unroll
+    for (int i = 0; i < RBT; ++i) a3[i] = As[cur][(i * 4 + 3) * 64 + lane];
+#pragma unroll
+    for (int jj = 0; jj < CPW; ++jj) b3[jj] = Bc[jj][1].y;
   };
   auto step = [&](int it, const P2(&Bc)[CPW][2], uint32_t skc, const P2(&Rn)[QA], P2(&Rf)[QA],
                   P2(&Bf)[CPW][2], uint32_t &skf) {
     const int cur = (it - it0) & 1;
+    deferred();  // the previous chunk's last k-step
     fetch(Rf, Bf, skf, it + 2 < it1);
     stash(cur ^ 1, Rn);
-    if (MODE != MODE_M2L || skc == 0) products(cur, Bc);
+    const bool run = MODE != MODE_M2L || skc == 0;
+    if (run) products(cur, Bc);
+    dpend = run;
     if (++mkc == nkc) {
       mkc = 0;
-      if constexpr (FOLD) {  // a term is complete
-#pragma unroll
-        for (int i = 0; i < RBT; ++i)
-#pragma unroll
-          for (int jj = 0; jj < CPW; ++jj) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sum[i][jj][q] += (double)acc[i][jj][q];
-            acc[i][jj] = V4{0, 0, 0, 0};
-          }
-      }
+      fpend = FOLD;
     }
     lds_barrier();
   };
@@ -1041,6 +1070,7 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
     }
     if (it < it1) step(it, B0, S0, R1, R2, B2, S2);
     if (it + 1 < it1) step(it + 1, B1, S1, R2, R0, B0, S0);
+    deferred();
   }
 
 #pragma unroll
