@@ -684,12 +684,13 @@ __host__ __device__ constexpr int gemm_cpw(int rbt) { return rbt >= 5 ? 1 : 2; }
 static_assert(gemm_cpw(6) == 1 && gemm_cpw(4) == 2 && gemm_cpw(3) == 2, "tile widths");
 __host__ __device__ constexpr int gemm_cols(int rbt) { return 64 * gemm_cpw(rbt); }
 constexpr int kMaxTerms = 189;   // terms of one job (M2L: the offsets of a child class)
-// M2L: the tiles left after the whole-tile rounds are split in kTailParts term
-// ranges each, taken by the workgroups from a counter as they finish, so that
-// workgroups whose tiles skipped products take more of them.  The counter sits
-// in the last kCounterDoubles of the Stream-K workspace; it is zero when a
-// workspace is made, and the fixup that follows each such launch zeroes it.
-constexpr int kTailParts = 3;
+// M2L: the tiles left after the whole-tile rounds are split in `parts` term
+// ranges each (as many as the workspace holds pieces for, up to kMaxTailParts),
+// taken by the workgroups from a counter as they finish, so that workgroups
+// whose tiles skipped products take more of them.  The counter sits in the last
+// kCounterDoubles of the Stream-K workspace; it is zero when a workspace is
+// made, and the fixup that follows each such launch zeroes it.
+constexpr int kMaxTailParts = 16;
 // zeros, read in place of a missing source column or of operator rows past the
 // operator, so that every chunk issues the same loads (static device memory is
 // zero-initialized; 1024 covers the longest column, d_k <= 1024)
@@ -1118,7 +1119,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
                                                  int ntiles, int64_t units, int G, int GT,
                                                  double *__restrict__ ws,
                                                  const int8_t *__restrict__ dvec, int dyn_items,
-                                                 int *__restrict__ ctr) {
+                                                 int parts, int *__restrict__ ctr) {
   constexpr int TILE = RBT * 16 * 64 * gemm_cpw(RBT);
   __shared__ T As[2][RBT * 4 * 64];
   __shared__ ColState cst[2 * 256];
@@ -1136,7 +1137,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
   }
   if (full == ntiles) return;
   if (MODE == MODE_M2L && dyn_items > 0) {
-    // the remaining tiles, kTailParts pieces each, taken in order from the counter
+    // the remaining tiles, `parts` pieces each, taken in order from the counter
     __shared__ int item_sh;
     for (;;) {
       if (threadIdx.x == 0) item_sh = atomicAdd(ctr, 1);
@@ -1144,10 +1145,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const GemmJob *__restrict__ job
       const int item = item_sh;
       __syncthreads();
       if ((unsigned)item >= (unsigned)dyn_items) return;  // done (or a stale counter)
-      const int tile = full + item / kTailParts, q = item % kTailParts;
+      const int tile = full + item / parts, q = item % parts;
       const GemmJob J = jobs[find_job_tiles(jobs, njobs, tile)];
-      gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, q * J.nterms / kTailParts,
-                                    (q + 1) * J.nterms / kTailParts, ws + (size_t)item * TILE,
+      gemm_tile<T, MODE, FOLD, RBT>(J, tile - J.tiles_start, q * J.nterms / parts,
+                                    (q + 1) * J.nterms / parts, ws + (size_t)item * TILE,
                                     dvec, As, cst, sdel);
     }
   }
@@ -1184,7 +1185,7 @@ template <int RBT>
 __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ jobs, int njobs,
                                                     int ntiles, int64_t units, int G, int GT,
                                                     const double *__restrict__ ws, int dyn_items,
-                                                    int *__restrict__ ctr) {
+                                                    int parts, int *__restrict__ ctr) {
   constexpr int COLS = 64 * gemm_cpw(RBT), TILE = RBT * 16 * COLS;
   constexpr int SLICE = TILE / kFixupSplit;
   static_assert(SLICE % 256 == 0 && 256 % COLS == 0, "fixup slices");
@@ -1198,9 +1199,9 @@ __global__ __launch_bounds__(256) void k_gemm_fixup(const GemmJob *__restrict__ 
   int64_t glo;
   int np, first;
   if (dyn_items > 0) {
-    // kTailParts pieces in slots (tile - full) kTailParts + q
-    np = kTailParts;
-    first = (tile - full) * kTailParts;
+    // `parts` pieces in slots (tile - full) parts + q
+    np = parts;
+    first = (tile - full) * parts;
     glo = 0;
   } else {
     const GemmJob Jr = jobs[find_job_tiles(jobs, njobs, full)];
@@ -1766,14 +1767,18 @@ void launch_gemm_rbt(const GemmJob *jobs, int n, int tiles, int64_t units, int g
   const int rest = tiles - (tiles / G) * G;
   // the counter's split of the remaining tiles (M2L, when its pieces fit)
   int dyn = 0;
-  if (MODE == MODE_M2L && G > 1 && rest > 0 && (size_t)rest * kTailParts * TILE <= len)
-    dyn = rest * kTailParts;
+  int parts = 0;
+  if (MODE == MODE_M2L && G > 1 && rest > 0) {
+    // (an M2L job has 189 terms, more than kMaxTailParts)
+    parts = (int)std::min<size_t>(kMaxTailParts, len / ((size_t)rest * TILE));
+    if (parts >= 2) dyn = rest * parts;
+  }
   constexpr bool fold = sizeof(T) == 4;
   hipLaunchKernelGGL((k_gemm<T, MODE, fold, RBT>), dim3(G), dim3(256), 0, s, jobs, n, tiles,
-                     units, G, GT, ws, dvec, dyn, ctr);
+                     units, G, GT, ws, dvec, dyn, parts, ctr);
   if (G > 1 && rest > 0)
     hipLaunchKernelGGL((k_gemm_fixup<RBT>), dim3(rest * kFixupSplit), dim3(256), 0, s, jobs, n,
-                       tiles, units, G, GT, ws, dyn, ctr);
+                       tiles, units, G, GT, ws, dyn, parts, ctr);
 }
 
 template <typename T, int MODE>

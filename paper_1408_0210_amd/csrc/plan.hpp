@@ -317,7 +317,7 @@ struct Plan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
-  double *sk_ws = nullptr;   // Stream-K pieces: 2 per workgroup, 6 x 16 x 128 doubles each
+  double *sk_ws = nullptr;   // Stream-K pieces and tail counter, stream_k_ws_len doubles
   // a Stream-K workspace lent for one pass (null: sk_ws), run_ws_len doubles
   double *run_ws = nullptr;
   size_t run_ws_len = 0;
@@ -335,7 +335,9 @@ struct Plan {
 
 // Stream-K workspace of `groups` persistent workgroups: 2 pieces of the largest
 // tile (6 x 16 x 128 doubles) each
-inline size_t stream_k_ws_len(int groups) { return (size_t)2 * groups * 6 * 16 * 128; }
+// (2 pieces per workgroup for the even split, and room for the M2L tail's finer
+// pieces: 4 tiles of 6 x 16 x 128 doubles per workgroup, 201 MB for 512 groups)
+inline size_t stream_k_ws_len(int groups) { return (size_t)4 * groups * 6 * 16 * 128; }
 // the last doubles of a Stream-K workspace hold the gathered GEMM's tail counter
 // (zero when the workspace is made)
 constexpr size_t kCounterDoubles = 32;
