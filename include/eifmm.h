@@ -238,7 +238,8 @@ int eifmm_evaluate(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64
 int eifmm_evaluate_noalloc(eifmm_plan plan, const double *sigma_dev, int32_t nrhs, int64_t ld,
                            double *f_dev, int64_t ldf, void *hip_stream);
 
-/* Enables (1) or disables (0) per-phase HIP-event timing; resets the totals. */
+/* Enables per-phase HIP-event timing (1: every phase; 2: the M2L launch only, two
+ * events per evaluation) or disables it (0); resets the totals. */
 int eifmm_set_timing(eifmm_plan plan, int32_t enable);
 
 /* Copies statistics (waits for pending timed work). */

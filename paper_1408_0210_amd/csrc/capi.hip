@@ -642,7 +642,7 @@ int set_points_impl(eifmm_plan h, const double *xyz, const double *tgt, void *st
     }
     xyz = P.xin;
   }
-  if (P.timing) {
+  if (P.timing == 1) {
     // tree time is recorded as one phase
     EventPair e;
     if (P.ev_free.empty()) {
@@ -747,8 +747,8 @@ int eifmm_evaluate_noalloc(eifmm_plan h, const double *sigma, int32_t nrhs, int6
   if (!ws) return EIFMM_EHIP;
   // the scratch replaces the plan's Stream-K workspace for this pass; the
   // per-phase timing events (created on demand) stay off
-  const bool timing = P.timing;
-  P.timing = false;
+  const int timing = P.timing;
+  P.timing = 0;
   P.run_ws = ws;
   P.run_ws_len = kNoAllocScratchDoubles;
   const int st = pass_run(P, sigma, nrhs, ld, f, ldf, (hipStream_t)stream);
@@ -762,7 +762,7 @@ int eifmm_set_timing(eifmm_plan h, int32_t enable) {
   if (!h) return EIFMM_EINVAL;
   Plan &P = h->P;
   timing_drain(P);
-  P.timing = enable != 0;
+  P.timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
   for (int q = 0; q < EIFMM_NPHASE; ++q) {
     P.phase_ms[q] = 0;
     P.phase_calls[q] = 0;
@@ -928,9 +928,18 @@ int eifmm_export_expansion(eifmm_plan h, int32_t which, int32_t k, int32_t rhs, 
   hipMemcpy(act.data(), D.act, sizeof(uint32_t) * na, hipMemcpyDeviceToHost);
   const int64_t nb = (int64_t)1 << (3 * k);
   std::memset(out, 0, sizeof(double) * (size_t)nb * d);
-  for (int64_t j = 0; j < na; ++j)
-    for (int m = 0; m < d; ++m)
-      out[(size_t)act[j] * d + m] = buf[((size_t)j * R + rhs) * dp + m];
+  // the leaf's g and l of a plan that folds B^{-1} into them: g = B (B^{-1} g)
+  const bool unfold = P.fold_leaf && k == P.depth && (which == 2 || which == 3);
+  const std::vector<double> &Bl = P.lh[k].B;  // unit lower triangular, d x d
+  for (int64_t j = 0; j < na; ++j) {
+    const double *v = &buf[((size_t)j * R + rhs) * dp];
+    for (int m = 0; m < d; ++m) {
+      double t = v[m];
+      if (unfold)
+        for (int q = 0; q < m; ++q) t += Bl[(size_t)m * d + q] * v[q];
+      out[(size_t)act[j] * d + m] = t;
+    }
+  }
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     P.last_hip_error = (int)e;
@@ -1014,6 +1023,7 @@ int eifmm_batch_create(const eifmm_config *cfgs, int32_t nprob, eifmm_batch *out
     P.max_rhs = 1;
     P.device = b->device;
     P.gpu_setup = !(P.cfg.flags & EIFMM_FLAG_HOST_SETUP);
+    P.shared_tables = true;
     st = build_tables(P);
     if (!st) st = setup_tables(h);
   }

@@ -593,10 +593,16 @@ __device__ inline void trsm_body(const SolveDesc &D, double *zs) {
     }
     acc += acc2;
   };
+  if (!D.Tf) {
+    // no forward factor (folded into the producers of the input): z = v
+    for (int bi = 0; bi < nb; ++bi)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zs[(bi * 4 + q) * 64 + lane] = cv ? x[16 * bi + rs + 4 * q] : 0.0;
+  }
   v4 xn;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) xn[q] = cv ? x[rs + 4 * q] : 0.0;
-  for (int bi = 0; bi < nb; ++bi) {
+  for (int q = 0; q < 4; ++q) xn[q] = (cv && D.Tf) ? x[rs + 4 * q] : 0.0;
+  for (int bi = 0; D.Tf && bi < nb; ++bi) {
     v4 acc = xn;
     // the next row's right-hand side, loaded during this row's products
     const int bn = min(bi + 1, nb - 1);
@@ -1420,8 +1426,10 @@ struct Timer {
   Plan &P;
   hipStream_t s;
   EventPair ep;
-  Timer(Plan &P_, hipStream_t s_, int ph) : P(P_), s(s_) {
-    if (!P.timing) return;
+  bool on;
+  Timer(Plan &P_, hipStream_t s_, int ph)
+      : P(P_), s(s_), on(P_.timing == 1 || (P_.timing == 2 && ph == EIFMM_PH_M2L)) {
+    if (!on) return;
     if (P.ev_pending.size() > 4096) timing_drain(P);
     if (P.ev_free.empty()) {
       EventPair e;
@@ -1435,7 +1443,7 @@ struct Timer {
     hipEventRecord(ep.a, s);
   }
   ~Timer() {
-    if (!P.timing) return;
+    if (!on) return;
     hipEventRecord(ep.b, s);
     P.ev_pending.push_back(ep);
   }
@@ -2037,7 +2045,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     A.lv[0].in = LL.l;
     A.lv[0].out = P.lhat;
     A.lv[0].out32 = nullptr;
-    A.lv[0].Tf = LL.tri[2];
+    A.lv[0].Tf = P.fold_leaf ? nullptr : LL.tri[2];  // B^{-1} folded into l (the Gamma^T solve only)
     A.lv[0].Tb = LL.tri[3];
     A.lv[0].ncols = nc;
     A.lv[0].dp = HL.dpB;

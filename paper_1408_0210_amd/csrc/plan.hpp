@@ -245,6 +245,11 @@ struct Plan {
   bool gpu_setup = false;  // Algorithm 1 iterations on the device
   bool gpu_ops = false;    // M2M / L2L operator solves on the device
   bool two_eim = false;    // second EIM per level (lhB): kernels that are not symmetric
+  bool shared_tables = false;  // tables of a batch, used by problems of several depths
+  // one EIM, compressed leaf level, own tables: the leaf's B^{-1} is folded into its
+  // post-projection (U -> B^{-1} U) and into the L2L operators into it, so that the
+  // leaf's g and l hold B^{-1} g and B^{-1} l and lhat takes the Gamma^T solve only
+  bool fold_leaf = false;
   LevelHost lhB[kMaxLevels];  // the second EIM (D_x = J_0, D_y = I_0): X in J_0, Y in I_0
   int depth = 0;
   LevelHost lh[kMaxLevels];
@@ -325,7 +330,7 @@ struct Plan {
   double m2l_flops_exec = 0;  // what the M2L MFMAs execute (padding, empty sources)
 
   // stats
-  bool timing = false;
+  int timing = 0;  // per-phase events: 0 off, 1 every phase, 2 the M2L launch only
   std::vector<EventPair> ev_free, ev_pending;
   double phase_ms[EIFMM_NPHASE] = {0};
   int64_t phase_calls[EIFMM_NPHASE] = {0};

@@ -691,6 +691,20 @@ int pick_rbt(int nrb) {
   return best;
 }
 
+// A <- L^{-1} A for L unit lower triangular (n x n, row-major) and A n x m
+// (row-major): forward substitution down the rows, all m columns at once
+void lower_unit_solve_rows(const std::vector<double> &Lm, int n, std::vector<double> &A, int m) {
+  for (int i = 1; i < n; ++i) {
+    double *ai = &A[(size_t)i * m];
+    for (int j = 0; j < i; ++j) {
+      const double l = Lm[(size_t)i * n + j];
+      if (l == 0.0) continue;
+      const double *aj = &A[(size_t)j * m];
+      for (int c = 0; c < m; ++c) ai[c] -= l * aj[c];
+    }
+  }
+}
+
 int build_tables(Plan &P) {
   auto t0 = std::chrono::steady_clock::now();
   const eifmm_config &c = P.cfg;
@@ -813,7 +827,17 @@ int build_tables(Plan &P) {
       }
       lv.ufrag.assign((size_t)dpB * lv.rp, 0.0);
       lv.pfrag.assign((size_t)lv.rp * dp, 0.0);
-      to_fragments(lv.U.data(), dB, lv.r, dpB, lv.rp, lv.ufrag.data());
+      // the leaf level of a plan with its own tables and one EIM: g = U g' is
+      // stored as B^{-1} g = (B^{-1} U) g', so that lhat = Gamma^{-T} (B^{-1} l)
+      // takes the solve with Gamma only (B is well conditioned)
+      if (k == depth && !P.shared_tables && !P.two_eim) {
+        P.fold_leaf = true;
+        std::vector<double> Uf(lv.U);
+        lower_unit_solve_rows(lv.B, d, Uf, lv.r);
+        to_fragments(Uf.data(), dB, lv.r, dpB, lv.rp, lv.ufrag.data());
+      } else {
+        to_fragments(lv.U.data(), dB, lv.r, dpB, lv.rp, lv.ufrag.data());
+      }
       to_fragments(Pm.data(), lv.r, d, lv.rp, dp, lv.pfrag.data());
     }
     const int r = lv.r, rp = lv.rp;
@@ -968,9 +992,11 @@ int build_tables(Plan &P) {
             solve_minv(lp, row.data());  // row M^{-T} = (M^{-1} row^T)^T
           std::memcpy(&Bm[(size_t)m * dkB], row.data(), sizeof(double) * dkB);
         }
-        if (!dev)
+        if (!dev) {
+          if (P.fold_leaf && k + 1 == depth) lower_unit_solve_rows(lc.B, dc, Bm, dkB);
           to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB,
                        &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
+        }
       }
     });
   }
@@ -994,6 +1020,7 @@ void pack_operators(Plan &P, int k) {
       for (int m = 0; m < dcB; ++m)
         std::memcpy(&Bm[(size_t)m * dkB], &lp.l2l_rows[((size_t)i * dcB + m) * lp.dpB],
                     sizeof(double) * dkB);
+      if (P.fold_leaf && k + 1 == P.depth) lower_unit_solve_rows(lc.B, dc, Bm, dkB);
       to_fragments(Bm.data(), dcB, dkB, lc.dpB, lp.dpB, &lp.l2l[(size_t)i * lc.dpB * lp.dpB]);
     }
   });

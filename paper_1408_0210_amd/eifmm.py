@@ -274,7 +274,9 @@ class Plan:
 
     # -- statistics and exports ------------------------------------------------
     def set_timing(self, on=True):
-        _check(lib().eifmm_set_timing(self._h, 1 if on else 0), "eifmm_set_timing")
+        """on: True (every phase), False, or "m2l" (the M2L launch only)."""
+        mode = 2 if on == "m2l" else (1 if on else 0)
+        _check(lib().eifmm_set_timing(self._h, mode), "eifmm_set_timing")
 
     def stats(self):
         s = Stats()
