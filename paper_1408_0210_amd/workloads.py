@@ -117,8 +117,10 @@ def make_sigma(w):
 
 # EIM and compression tolerances per kernel for the uneven batch: exp(-r^2/0.01)
 # uses the absolute stopping rule (tol_mode 1) and a tolerance of 5e-7, which
-# keeps its rel-L2 error below 1e-6; 1/r meets 1e-6 with tau = 1e-6.
-BATCH_TOLERANCES = {"laplace": dict(tau=1e-6, tol_mode=0, compress_tol=1e-6),
+# keeps its rel-L2 error below 1e-6; 1/r meets 1e-6 with tau = 1e-6 and M2L
+# compressed at 3e-6 (largest error over its 128 problems, 200 sampled targets
+# each: 6.7e-7; 1.1e-6 at 6e-6, 1.9e-7 at 1e-6).
+BATCH_TOLERANCES = {"laplace": dict(tau=1e-6, tol_mode=0, compress_tol=3e-6),
                     "gauss": dict(tau=5e-7, tol_mode=1, compress_tol=5e-7)}
 
 
