@@ -1947,10 +1947,18 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   const int64_t nchunk = P.nchunk;
   const LeafDesc LD = leaf_desc(P, nrhs);
   LevelDev &LL = P.ld[depth];
-  // near field: with a far field to compute it runs on the plan's second stream,
-  // started after P2M so that it overlaps M2M, the solves and the projections
-  // (small MFMA launches that leave the vector units idle); L2P waits for it
+  // near field: with a far field to compute it runs on the plan's second stream
+  // and L2P waits for it. In FP64 it starts after P2M, so that it overlaps M2M,
+  // the solves and the projections (small MFMA launches that leave the vector
+  // units idle); the FP64 M2L holds 230 VGPRs per lane at two waves per SIMD,
+  // which leaves no room for the near-field waves beside it. In mixed precision
+  // it starts just before M2L: the FP32 M2L and FP32 near-field waves fit on a
+  // SIMD together, and the near field then fills the M2L's ramp-down as well.
+  // With many right-hand sides the near field is long enough to take CUs from
+  // the M2L's persistent workgroups when it is dispatched first (the order of
+  // the two streams' first dispatches is not fixed), so it starts after P2M.
   const bool fork = depth >= 2 && nleafa > 0 && P.side;
+  const bool fork_late = fork && mixed && nrhs == 1;
   auto near_field = [&](hipStream_t sn) {
     if (sn != s) {
       hipEventRecord(P.ev_fork, s);
@@ -1976,7 +1984,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     Timer tm(P, s, EIFMM_PH_P2M);
     launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, HL.dp, LD, nullptr, 0, s);
   }
-  if (fork) near_field(P.side);
+  if (fork && !fork_late) near_field(P.side);
   // step 2: M2M
   {
     Timer tm(P, s, EIFMM_PH_M2M);
@@ -2015,6 +2023,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     launch_gemm<double, MODE_PROJ>(P, P.jobs.pre_first, P.jobs.pre_n, P.jobs.pre_tiles,
                                    P.jobs.pre_units, s, P.jobs.pre_rbt);
   }
+  if (fork_late) hipEventRecord(P.ev_fork, s);
   {
     Timer tm(P, s, EIFMM_PH_M2L);
     if (mixed)
@@ -2024,6 +2033,15 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
       launch_gemm<double, MODE_M2L>(P, P.jobs.m2l_first, P.jobs.m2l_n, P.jobs.m2l_tiles,
                                     P.jobs.m2l_units, s, P.jobs.m2l_rbt);
     for (const M2l2Launch &L : P.m2l2_launch) launch_m2l2(P.m2l2_dev, L, P.dvec, P.m2l2_ws, s);
+  }
+  // launched after the M2L so that the M2L's workgroups are dispatched first
+  if (fork_late) {
+    hipStreamWaitEvent(P.side, P.ev_fork, 0);
+    {
+      Timer tm(P, P.side, EIFMM_PH_P2P);
+      launch_p2p<KIND, false>(mixed, nrhs, nchunk, LD, nullptr, 0, P.side);
+    }
+    hipEventRecord(P.ev_join, P.side);
   }
   if (P.jobs.post_n) {
     Timer tm(P, s, EIFMM_PH_PROJ);
