@@ -173,7 +173,10 @@ typedef struct {
                                         g, l and lhat), 0 with one EIM           */
   int32_t rpad[EIFMM_MAX_DEPTH + 1]; /* compressed levels: the rank padded to whole
                                         16-row MFMA blocks, as the device runs it */
-  int32_t reserved_st;
+  int32_t near_mode;                 /* where the last evaluate ran the near
+                                        field: 0 on the caller's stream; 1 on the
+                                        plan's second stream from P2M on; 2 there
+                                        from the M2L on                          */
   double m2l_flops_exec;             /* M2L flops the MFMAs of the last evaluate
                                         execute: padded rows and columns (rpad or
                                         dpad), and every one of the 189 offsets of

@@ -797,6 +797,7 @@ int eifmm_get_stats(eifmm_plan h, eifmm_stats *out) {
   }
   s.m2l_flops = P.m2l_flops;
   s.m2l_flops_exec = P.m2l_flops_exec;
+  s.near_mode = P.near_mode;
   s.proj_flops = P.proj_flops;
   if (P.cfg.tol_mode == 1) s.scale_level = P.cfg.scale_level > 0 ? P.cfg.scale_level : P.depth;
   for (int k = 0; k <= P.depth; ++k) {

@@ -13,6 +13,7 @@
 //   7  L2P and f = f_far + f_near, input order  k_l2p  one wave per 64 targets
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "devutil.hpp"
@@ -174,6 +175,9 @@ __global__ void k_gather_sigma(LeafDesc one, IoDesc ione, const LeafDesc *__rest
 struct NearSrc {
   int nq;        // neighbour leaves
   int total;     // sources over all of them
+  // source numbers of the chunk's own leaf, the one neighbour with pairs at r = 0
+  // (a target and itself, or coincident points)
+  int own_lo, own_hi;
 };
 
 // pre[e] = first source number of neighbour e, start[e] = its first point
@@ -181,11 +185,15 @@ __device__ inline NearSrc near_sources(const LeafDesc &D, int j, int *pre, int *
   const int lane = threadIdx.x;
   const int q0 = D.near_ptr[j], nq = D.near_ptr[j + 1] - q0;
   int cnt = 0;
+  bool own = false;
   if (lane < nq) {
-    const uint32_t sk = D.act[D.near_src[q0 + lane]];
+    const int a = D.near_src[q0 + lane];
+    const uint32_t sk = D.act[a];
     start[lane] = D.ls[sk];
     cnt = D.se[sk] - D.ls[sk];
+    own = a == j;
   }
+  const unsigned long long ob = __ballot(own);
   // inclusive scan of cnt over the (at most 27) lanes
   int v = cnt;
 #pragma unroll
@@ -196,7 +204,8 @@ __device__ inline NearSrc near_sources(const LeafDesc &D, int j, int *pre, int *
   if (lane < nq) pre[lane + 1] = v;
   if (lane == 0) pre[0] = 0;
   __syncthreads();
-  return NearSrc{nq, pre[nq]};
+  const int eo = __ffsll(ob) - 1;  // the own leaf's place in the list (-1: absent)
+  return NearSrc{nq, pre[nq], eo >= 0 ? pre[eo] : 0, eo >= 0 ? pre[eo + 1] : 0};
 }
 
 // point index of source number v (0 <= v < total); e is the neighbour of the
@@ -258,16 +267,29 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
       const int u0 = 32 * half;
-      constexpr int kUnroll = RB == 1 ? 8 : 2;  // several RHS hold RB sums per pair already
+      // r = 0 (a pair the sum leaves out) needs the mask only in the batches that
+      // hold sources of the own leaf: points of two different leaves are apart (a
+      // leaf boundary lies between them), so r2 > 0 there, unless both lie within
+      // about 1e-154 of a boundary at the origin, which the library does not
+      // support.  The padding past the end repeats the last source, so it needs
+      // the mask only when that source is the own leaf's, whose batch has it.
+      const bool own = KF<KIND>::singular && base < S.own_hi && base + 64 > S.own_lo;
+      auto pairs = [&](auto masked) {
+        constexpr int kUnroll = RB == 1 ? 8 : 2;  // several RHS hold RB sums per pair already
 #pragma unroll kUnroll
-      for (int u = u0; u < u0 + 32; ++u) {
-        const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        double kv = KF<KIND>::eval(r2, dx, D.p);
-        if (KF<KIND>::singular) kv = (r2 == 0.0) ? 0.0 : kv;
+        for (int u = u0; u < u0 + 32; ++u) {
+          const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          double kv = KF<KIND>::eval(r2, dx, D.p);
+          if constexpr (decltype(masked)::value) kv = (r2 == 0.0) ? 0.0 : kv;
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
-      }
+          for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
+        }
+      };
+      if (own)
+        pairs(std::true_type{});
+      else
+        pairs(std::false_type{});
     }
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
@@ -1959,6 +1981,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   // the two streams' first dispatches is not fixed), so it starts after P2M.
   const bool fork = depth >= 2 && nleafa > 0 && P.side;
   const bool fork_late = fork && mixed && nrhs == 1;
+  P.near_mode = fork_late ? 2 : fork ? 1 : 0;
   auto near_field = [&](hipStream_t sn) {
     if (sn != s) {
       hipEventRecord(P.ev_fork, s);

@@ -320,6 +320,7 @@ struct Plan {
   // (fork after the potentials are gathered, join before L2P)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int near_mode = 0;  // the last pass's near-field placement (eifmm_stats.near_mode)
   std::vector<GemmJob> jobs_host;  // host copy of the job table (batches concatenate it)
   int sk_groups = 512;       // persistent workgroups of a gathered-GEMM launch
   double *sk_ws = nullptr;   // Stream-K pieces and tail counter, stream_k_ws_len doubles

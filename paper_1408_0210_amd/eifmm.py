@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
                 ("il_pairs", ctypes.c_int64 * (MAX_DEPTH + 1)), ("near_pairs", ctypes.c_int64),
                 ("hip_error", ctypes.c_int32), ("scale_level", ctypes.c_int32),
                 ("near_point_pairs", ctypes.c_int64), ("d2", ctypes.c_int32 * (MAX_DEPTH + 1)),
-                ("rpad", ctypes.c_int32 * (MAX_DEPTH + 1)), ("reserved_st", ctypes.c_int32),
+                ("rpad", ctypes.c_int32 * (MAX_DEPTH + 1)), ("near_mode", ctypes.c_int32),
                 ("m2l_flops_exec", ctypes.c_double)]
 
 
@@ -174,6 +174,7 @@ def _stats_dict(s, depth):
     return dict(depth=s.depth, d={k: s.d[k] for k in lv}, dpad={k: s.dpad[k] for k in lv},
                 rank={k: s.rank[k] for k in lv}, rpad={k: s.rpad[k] for k in lv},
                 proj_flops=s.proj_flops, m2l_flops_exec=s.m2l_flops_exec,
+                near_mode=s.near_mode,
                 scale_level=s.scale_level,
                 eim_err={k: s.eim_err[k] for k in lv}, setup_ms=s.setup_ms,
                 phase_ms={PHASES[q]: s.phase_ms[q] for q in range(NPHASE)},

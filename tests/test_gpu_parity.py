@@ -189,6 +189,28 @@ def test_c1_stages_vs_oracle(E, torch_dev, oracle_lib, c1_inputs, c1_plan):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,depth,nrhs,mode", [("fp64", 3, 1, 1), ("mixed", 3, 1, 2),
+                                                      ("mixed", 3, 2, 1), ("fp64", 1, 1, 0)])
+def test_near_field_placement(precision, depth, nrhs, mode, E, torch_dev, oracle_lib):
+    """Where the pass runs the near field (eifmm_stats.near_mode): on the plan's
+    second stream from P2M on in FP64 and with several right-hand sides, from the
+    M2L on in mixed precision with one, on the caller's stream below depth 2 (no
+    far field); each placement against the direct sum."""
+    torch, dev = torch_dev
+    n = 12000
+    x = W.uniform_points(n, 81)
+    S = np.stack([W.potentials(n, 82), W.potentials(n, 83)])[:nrhs]
+    plan = E.Plan("laplace", 0, [0, 0, 0], 1.0, n, depth, 1e-6, max_rhs=2, precision=precision)
+    plan.set_points(torch.from_numpy(x).to(dev))
+    F = plan.evaluate(torch.from_numpy(np.ascontiguousarray(S if nrhs > 1 else S[0])).to(dev))
+    F = F.cpu().numpy().reshape(nrhs, n)
+    assert plan.stats()["near_mode"] == mode
+    for r in range(nrhs):
+        err = _rel(F[r], oracle_lib.direct("laplace", 0, x, x, S[r]))
+        assert err <= (1e-13 if depth < 2 else 1e-6), (r, err)
+    plan.close()
+
+
 def test_multi_rhs_matches_single(E, torch_dev, oracle_lib):
     """nrhs = 5 (several column tiles with a ragged tail) equals 5 single passes."""
     torch, dev = torch_dev
