@@ -273,7 +273,9 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       // about 1e-154 of a boundary at the origin, which the library does not
       // support.  The padding past the end repeats the last source, so it needs
       // the mask only when that source is the own leaf's, whose batch has it.
-      const bool own = KF<KIND>::singular && base < S.own_hi && base + 64 > S.own_lo;
+      // (several RHS share each pair's mask: they keep the one loop)
+      const bool own =
+          KF<KIND>::singular && (RB > 1 || (base < S.own_hi && base + 64 > S.own_lo));
       auto pairs = [&](auto masked) {
         constexpr int kUnroll = RB == 1 ? 8 : 2;  // several RHS hold RB sums per pair already
 #pragma unroll kUnroll
@@ -361,24 +363,37 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
       const int u0 = 32 * half;
-      constexpr int kUnroll = RB == 1 ? 4 : 2;
+      // the r = 0 mask only in batches with the own leaf's sources, as in
+      // k_p2p64 (here r2 is FP32: two points of different leaves give r2 = 0
+      // only when under about 1e-22 apart, next to a boundary at the origin)
+      // (several RHS share each pair's mask: they keep the one loop)
+      const bool own =
+          KF<KIND>::singular && (RB > 1 || (base < S.own_hi && base + 64 > S.own_lo));
+      auto pairs = [&](auto masked) {
+        constexpr int kUnroll = RB == 1 ? 4 : 2;
 #pragma unroll kUnroll
-      for (int u = u0; u < u0 + 32; ++u) {
-        const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]), dz = (float)(zi - sz[u]);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        float kv = KF<KIND>::evalf(r2, dx, p);
-        if (KF<KIND>::singular) kv = (r2 == 0.f) ? 0.f : kv;
+        for (int u = u0; u < u0 + 32; ++u) {
+          const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]),
+                      dz = (float)(zi - sz[u]);
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          float kv = KF<KIND>::evalf(r2, dx, p);
+          if constexpr (decltype(masked)::value) kv = (r2 == 0.f) ? 0.f : kv;
 #pragma unroll
-        for (int rr = 0; rr < RB; ++rr) {
-          // the rounding error of sum + w, exactly, by the branch-free two-sum
-          // (Knuth): no magnitude comparison as in Neumaier's form
-          const float w = ss[u * RB + rr] * kv;
-          const float tsum = sum[rr] + w;
-          const float bv = tsum - sum[rr];
-          cmp[rr] += (sum[rr] - (tsum - bv)) + (w - bv);
-          sum[rr] = tsum;
+          for (int rr = 0; rr < RB; ++rr) {
+            // the rounding error of sum + w, exactly, by the branch-free two-sum
+            // (Knuth): no magnitude comparison as in Neumaier's form
+            const float w = ss[u * RB + rr] * kv;
+            const float tsum = sum[rr] + w;
+            const float bv = tsum - sum[rr];
+            cmp[rr] += (sum[rr] - (tsum - bv)) + (w - bv);
+            sum[rr] = tsum;
+          }
         }
-      }
+      };
+      if (own)
+        pairs(std::true_type{});
+      else
+        pairs(std::false_type{});
     }
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
