@@ -552,14 +552,15 @@ def run_uneven(args):
 # vector peak of 78.6 TFLOP/s counts an FMA slot as 2 flops).  VALU_SLOTS: issue
 # slots per kernel evaluation of the built gfx950 inner loops for 1/r in FP64 with
 # one right-hand side, read from the AMD assembly of these kernels, with the
-# quarter-rate reciprocal square root counted 4 times: near field 16 instructions
-# (3 differences, r^2 in 3, v_rsq_f64, 5 refinement steps, compare and 2 selects
-# for r = 0, the accumulation) = 19 slots; P2M 13 + 4 = 17; L2P 16 + 4 = 20 (its
+# quarter-rate reciprocal square root counted 4 times: near field 13 instructions
+# (3 differences, r^2 in 3, v_rsq_f64, 5 refinement steps, the accumulation) = 16
+# slots (the batches with the own leaf's sources add a compare and 2 selects for
+# r = 0; the model leaves them out); P2M 13 + 4 = 17; L2P 16 + 4 = 20 (its
 # loop is not unrolled and carries 3 integer instructions).  Tree: bytes per point
 # of the sort and gathers (points read 24 B, keys written 4 B, two radix passes of
 # 16 B each way, sorted points written 24 B, permutation 4 B).
 VALU_PEAK_SLOTS = 256 * 4 * (2.4e9 / 4) * 64
-VALU_SLOTS = {"p2p": 19, "p2m": 17, "l2p": 20}
+VALU_SLOTS = {"p2p": 16, "p2m": 17, "l2p": 20}
 HBM_PEAK = 8.0e12
 TREE_BYTES_PER_POINT = 24 + 4 + 2 * 32 + 24 + 4
 
