@@ -12,6 +12,7 @@
 //   6  lhat = Delta^T l         k_trsm
 //   7  L2P and f = f_far + f_near, input order  k_l2p  one wave per 64 targets
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -913,14 +914,70 @@ __device__ inline void gemm_tile(const GemmJob &J, int tile_local, int term0, in
   }
   // the job's terms in LDS, packed (dx+3) | (dy+3) << 3 | (dz+3) << 6 | id << 9
   // (offset and offset id): a source lookup then waits on no global load but
-  // the slot map's, and the operator address on none
+  // the slot map's, and the operator address on none.  Only the terms of
+  // [term0, term1) whose source box lies inside the domain for some column of
+  // the tile are kept, in order (the others would add zeros): the tile's target
+  // boxes span [lo, hi] per axis, and offset delta reaches inside for some of
+  // them on an axis when hi + delta >= 0 and lo + delta < side.  Boxes of one
+  // child class and one face signature (the M2L column order) share their
+  // missing offsets, so a tile of them drops those terms whole: their loads,
+  // LDS staging and barriers as well as their products.
   if constexpr (MODE == MODE_M2L) {
-    for (int i = t; i < J.nterms; i += 256) {
-      const int id = ldg(J.terms + i);
-      sdel[i] = (dvec[3 * id] + 3) | ((dvec[3 * id + 1] + 3) << 3) |
-                ((dvec[3 * id + 2] + 3) << 6) | (id << 9);
+    __shared__ int sbox[4][6];
+    __shared__ int snk;
+    int bb[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+    for (int jj = 0; jj < CPW; ++jj) {
+      const ColState c = my[jj];
+      if (c.valid) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int m = (int)morton_axis(c.tkey, a);
+          bb[a] = min(bb[a], m);
+          bb[3 + a] = max(bb[3 + a], m);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bb[a] = min(bb[a], __shfl_xor(bb[a], o));
+        bb[3 + a] = max(bb[3 + a], __shfl_xor(bb[3 + a], o));
+      }
+    }
+    if (lane < 6) sbox[w][lane] = bb[lane];
+    lds_barrier();
+    if (w == 0) {
+      int lo[3], hi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = min(min(sbox[0][a], sbox[1][a]), min(sbox[2][a], sbox[3][a]));
+        hi[a] = max(max(sbox[0][3 + a], sbox[1][3 + a]), max(sbox[2][3 + a], sbox[3][3 + a]));
+      }
+      const int side = 1 << J.level;
+      const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      int nk = 0;
+      for (int b = term0; b < term1; b += 64) {
+        const int i = b + lane;
+        bool keep = false;
+        int pk = 0;
+        if (i < term1) {
+          const int id = ldg(J.terms + i);
+          const int d0 = dvec[3 * id], d1 = dvec[3 * id + 1], d2 = dvec[3 * id + 2];
+          pk = (d0 + 3) | ((d1 + 3) << 3) | ((d2 + 3) << 6) | (id << 9);
+          keep = hi[0] + d0 >= 0 && lo[0] + d0 < side && hi[1] + d1 >= 0 && lo[1] + d1 < side &&
+                 hi[2] + d2 >= 0 && lo[2] + d2 < side;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) sdel[nk + (int)__popcll(m & below)] = pk;
+        nk += (int)__popcll(m);
+      }
+      if (lane == 0) snk = nk;
     }
     lds_barrier();
+    term0 = 0;
+    term1 = snk;
   }
   V4 acc[RBT][CPW];
   D4 sum[RBT][CPW];
