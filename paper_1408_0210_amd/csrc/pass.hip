@@ -407,16 +407,23 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
 
 // ------------------------------------------------------------------ P2M
 // W^I_m = sum_{y_j in I} sigma_j K(x_m^{I_0}, y_j - c_I)  (Algorithm 3, step 1)
-// One NT-thread workgroup per leaf (NT = 64 when d <= 64, else 256); rows are
-// taken in groups of 4 NT, thread t owning rows m0 + t + NT u, u < 4, of group m0.
+// One NT-thread workgroup per leaf; rows are taken in groups of 4 NT, thread t
+// owning rows m0 + t + NT u, u < 4, of group m0.  NT = 0: the launch's block size
+// (one right-hand side on leaves of many points: a whole number of waves
+// covering d_p, up to 1024, so that every wave takes one row per lane and none
+// waits at the batch barriers for a wave with two); otherwise 256 threads
+// (several right-hand sides: their registers rule out 1024-thread blocks), or
+// one wave when d_p <= 64.
 template <int KIND, int RB, bool BATCH, int NT>
-__global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__restrict__ many,
-                                             int nmany) {
+__global__ __launch_bounds__(NT ? NT : 1024) void k_p2m(LeafDesc one,
+                                                        const LeafDesc *__restrict__ many,
+                                                        int nmany) {
   __shared__ double px[64], py[64], pz[64], ps[64 * RB];
   LeafDesc D;
   int j, prob;
   pick_desc<BATCH, 1>(one, many, nmany, D, j, prob);
   const int t = threadIdx.x;
+  const int nt = NT ? NT : (int)blockDim.x;
   const int64_t n = D.n;
   const int nrhs = D.nrhs, d = D.d, dp = D.dp;
   const double *__restrict__ xyz = D.xyz;
@@ -426,12 +433,12 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
-  for (int m0 = 0; m0 < dp; m0 += 4 * NT) {
-    const int nu = min(4, (dp - m0 + NT - 1) / NT);
+  for (int m0 = 0; m0 < dp; m0 += 4 * nt) {
+    const int nu = min(4, (dp - m0 + nt - 1) / nt);
     double xm[4], ym[4], zm[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int m = m0 + t + NT * u;
+      const int m = m0 + t + nt * u;
       const bool ok = u < nu && m < d;
       xm[u] = ok ? D.X[3 * m] : 0.0;
       ym[u] = ok ? D.X[3 * m + 1] : 0.0;
@@ -461,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
           for (int u = 0; u < 4; ++u) {
             // skipped by a whole wave whose rows all lie past d (rows d..dp-1
             // are stored as zeros)
-            if (u < nu && m0 + NT * u + (t & ~63) < d) {
+            if (u < nu && m0 + nt * u + (t & ~63) < d) {
               const double dx = xm[u] - px[q], dy = ym[u] - py[q], dz = zm[u] - pz[q];
               const double kv = KF<KIND>::eval(dx * dx + dy * dy + dz * dz, dx, D.p);
 #pragma unroll
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_p2m(LeafDesc one, const LeafDesc *__rest
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int m = m0 + t + NT * u;
+        const int m = m0 + t + nt * u;
         if (u < nu && m < dp) {
 #pragma unroll
           for (int rr = 0; rr < RB; ++rr)
@@ -1955,9 +1962,13 @@ void launch_p2p(bool mixed, int nrhs, int64_t nchunk, const LeafDesc &one, const
   }
 }
 
+// crowded: the leaves hold more than 64 points on average, so that a workgroup
+// spends its time in the batch loop (1e6 clustered points at depth 5: P2M 2.95
+// -> 2.66 ms); on leaves of a few dozen points the 256-thread form is faster
+// (1e6 uniform points at depth 5: 0.21 against 0.25 ms)
 template <int KIND, bool BATCH>
 void launch_p2m(int nrhs, unsigned grid, int dpmax, const LeafDesc &one, const LeafDesc *many,
-                int nmany, hipStream_t s) {
+                int nmany, hipStream_t s, bool crowded = false) {
   if (grid == 0) return;
   if (dpmax <= 64) {  // one row per thread: a 64-lane workgroup wastes no lanes on small d
     if (nrhs == 1)
@@ -1967,12 +1978,17 @@ void launch_p2m(int nrhs, unsigned grid, int dpmax, const LeafDesc &one, const L
       hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH, 64>), dim3(grid), dim3(64), 0, s, one, many,
                          nmany);
   } else {
-    if (nrhs == 1)
+    if (nrhs == 1 && crowded) {
+      const int nt = std::min(1024, (dpmax + 63) / 64 * 64);
+      hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH, 0>), dim3(grid), dim3(nt), 0, s, one, many,
+                         nmany);
+    } else if (nrhs == 1) {
       hipLaunchKernelGGL((k_p2m<KIND, 1, BATCH, 256>), dim3(grid), dim3(256), 0, s, one, many,
                          nmany);
-    else
+    } else {
       hipLaunchKernelGGL((k_p2m<KIND, 8, BATCH, 256>), dim3(grid), dim3(256), 0, s, one, many,
                          nmany);
+    }
   }
 }
 
@@ -2077,7 +2093,8 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
   // step 1: P2M
   if (nleafa > 0) {
     Timer tm(P, s, EIFMM_PH_P2M);
-    launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, HL.dp, LD, nullptr, 0, s);
+    launch_p2m<KIND, false>(nrhs, (unsigned)nleafa, HL.dp, LD, nullptr, 0, s,
+                            n > 64 * (int64_t)nleafa);
   }
   if (fork && !fork_late) near_field(P.side);
   // step 2: M2M
