@@ -216,25 +216,49 @@ __device__ inline int near_point(int v, int nq, const int *pre, const int *start
   return start[e] + (v - pre[e]);
 }
 
+// The lanes of chunk c of leaf j: with k targets (a chunk holds up to 32) and P
+// the smallest power of two >= k, lane l holds target l mod P and takes sources
+// [P (l / P), P (l / P + 1)) of every 64-source batch, so that a chunk of few
+// targets (the last of a leaf) spreads each target's sources over 64 / P lanes
+// instead of leaving lanes idle.  A full chunk has P = 32: lanes l and l + 32
+// share a target and take the two halves of each batch.
+struct ChunkLanes {
+  int i;     // the lane's target point
+  bool tv;   // the target exists
+  int P;     // targets' lane period
+  int u0;    // first source of the lane's range in a batch
+};
+// (spread: false keeps P = 32, for several right-hand sides, whose RB sums per
+// pair already fill the lanes' registers)
+__device__ inline ChunkLanes chunk_lanes(const LeafDesc &D, int j, int c, int lane, bool spread) {
+  const uint32_t key = D.act[j];
+  const int i0 = D.tb[key] + 32 * (c - D.chunk_ptr[j]);
+  const int k = min(32, D.ls[key + 1] - i0);
+  const int P = !spread ? 32 : k <= 1 ? 1 : 1 << (32 - __clz(k - 1));
+  const int ti = lane & (P - 1);
+  return ChunkLanes{i0 + ti, ti < k, P, lane - ti};
+}
+
+// (cos(wr)/r asks for three waves per SIMD: its kernel value would otherwise
+// take registers for two only)
 template <int KIND, int RB, bool BATCH>
-__global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__restrict__ many,
-                                              int nmany) {
+__global__ __launch_bounds__(64, KIND == EIFMM_K_COSR ? 3 : 1) void k_p2p64(
+    LeafDesc one, const LeafDesc *__restrict__ many, int nmany) {
   __shared__ double sx[64], sy[64], sz[64], ss[64 * RB];
   __shared__ int pre[28], start[27];
   LeafDesc D;
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
   if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
-  const int lane = threadIdx.x, half = lane >> 5;
+  const int lane = threadIdx.x;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
   const double *__restrict__ xyz = D.xyz;
   const double *__restrict__ sig = D.sig;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
-  const uint32_t key = D.act[j];
-  const int b = D.ls[key + 1];
-  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
-  const bool tv = i < b;
+  const ChunkLanes CL = chunk_lanes(D, j, c, lane, RB == 1);
+  const int i = CL.i;
+  const bool tv = CL.tv;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
   const NearSrc S = near_sources(D, j, pre, start);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
@@ -267,7 +291,6 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
-      const int u0 = 32 * half;
       // r = 0 (a pair the sum leaves out) needs the mask only in the batches that
       // hold sources of the own leaf: points of two different leaves are apart (a
       // leaf boundary lies between them), so r2 > 0 there, unless both lie within
@@ -277,10 +300,16 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
       // (several RHS share each pair's mask: they keep the one loop)
       const bool own =
           KF<KIND>::singular && (RB > 1 || (base < S.own_hi && base + 64 > S.own_lo));
-      auto pairs = [&](auto masked) {
-        constexpr int kUnroll = RB == 1 ? 8 : 2;  // several RHS hold RB sums per pair already
+      // (a full chunk's loop has a fixed trip count of 32)
+      // (several RHS hold RB sums per pair already; a partial chunk's loop runs
+      // at most 16 times)
+      auto pairs = [&](auto masked, auto full) {
+        constexpr bool F = decltype(full)::value;
+        constexpr int kUnroll = RB > 1 ? 2 : (F ? 8 : 1);
+        const int cnt = F ? 32 : CL.P;
 #pragma unroll kUnroll
-        for (int u = u0; u < u0 + 32; ++u) {
+        for (int q = 0; q < cnt; ++q) {
+          const int u = CL.u0 + q;
           const double dx = xi - sx[u], dy = yi - sy[u], dz = zi - sz[u];
           const double r2 = dx * dx + dy * dy + dz * dz;
           double kv = KF<KIND>::eval(r2, dx, D.p);
@@ -289,14 +318,24 @@ __global__ __launch_bounds__(64) void k_p2p64(LeafDesc one, const LeafDesc *__re
           for (int rr = 0; rr < RB; ++rr) acc[rr] += ss[u * RB + rr] * kv;
         }
       };
-      if (own)
-        pairs(std::true_type{});
-      else
-        pairs(std::false_type{});
+      if (RB > 1 || CL.P == 32) {
+        if (own)
+          pairs(std::true_type{}, std::true_type{});
+        else
+          pairs(std::false_type{}, std::true_type{});
+      } else {
+        if (own)
+          pairs(std::true_type{}, std::false_type{});
+        else
+          pairs(std::false_type{}, std::false_type{});
+      }
     }
+    // the target's 64 / P partial sums (lanes l, l + P, ...)
+    for (int o = CL.P; o < 64; o <<= 1) {
 #pragma unroll
-    for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
-    if (tv && half == 0) {
+      for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], o);
+    }
+    if (tv && lane < CL.P) {
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = acc[rr];
@@ -318,17 +357,16 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
   int c, prob;
   pick_desc<BATCH, 0>(one, many, nmany, D, c, prob);
   if (c >= D.chunk_ptr[D.nleaf]) return;  // past the last chunk (the grid is a bound)
-  const int lane = threadIdx.x, half = lane >> 5;
+  const int lane = threadIdx.x;
   const int64_t n = D.n;
   const int nrhs = D.nrhs;
   const float p = (float)D.p;
   const double *__restrict__ xyz = D.xyz;
   const double *__restrict__ sig = D.sig;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
-  const uint32_t key = D.act[j];
-  const int b = D.ls[key + 1];
-  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
-  const bool tv = i < b;
+  const ChunkLanes CL = chunk_lanes(D, j, c, lane, RB == 1);
+  const int i = CL.i;
+  const bool tv = CL.tv;
   const double xi = tv ? xyz[i] : 0.0, yi = tv ? xyz[n + i] : 0.0, zi = tv ? xyz[2 * n + i] : 0.0;
   const NearSrc S = near_sources(D, j, pre, start);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
@@ -363,17 +401,19 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
       for (int rr = 0; rr < RB; ++rr) ss[lane * RB + rr] = ps[rr];
       __syncthreads();
       if (base + 64 < S.total) load(base + 64);
-      const int u0 = 32 * half;
       // the r = 0 mask only in batches with the own leaf's sources, as in
       // k_p2p64 (here r2 is FP32: two points of different leaves give r2 = 0
       // only when under about 1e-22 apart, next to a boundary at the origin)
       // (several RHS share each pair's mask: they keep the one loop)
       const bool own =
           KF<KIND>::singular && (RB > 1 || (base < S.own_hi && base + 64 > S.own_lo));
-      auto pairs = [&](auto masked) {
-        constexpr int kUnroll = RB == 1 ? 4 : 2;
+      auto pairs = [&](auto masked, auto full) {
+        constexpr bool F = decltype(full)::value;
+        constexpr int kUnroll = RB > 1 ? 2 : (F ? 4 : 2);
+        const int cnt = F ? 32 : CL.P;
 #pragma unroll kUnroll
-        for (int u = u0; u < u0 + 32; ++u) {
+        for (int q = 0; q < cnt; ++q) {
+          const int u = CL.u0 + q;
           const float dx = (float)(xi - sx[u]), dy = (float)(yi - sy[u]),
                       dz = (float)(zi - sz[u]);
           const float r2 = dx * dx + dy * dy + dz * dz;
@@ -391,16 +431,24 @@ __global__ __launch_bounds__(64) void k_p2p32(LeafDesc one, const LeafDesc *__re
           }
         }
       };
-      if (own)
-        pairs(std::true_type{});
-      else
-        pairs(std::false_type{});
+      if (RB > 1 || CL.P == 32) {
+        if (own)
+          pairs(std::true_type{}, std::true_type{});
+        else
+          pairs(std::false_type{}, std::true_type{});
+      } else {
+        if (own)
+          pairs(std::true_type{}, std::false_type{});
+        else
+          pairs(std::false_type{}, std::false_type{});
+      }
     }
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
-      const double mine = (double)sum[rr] + (double)cmp[rr];
-      const double other = __shfl_xor(mine, 32);
-      if (tv && half == 0 && r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = mine + other;
+      // the target's 64 / P partial sums (lanes l, l + P, ...), in FP64
+      double mine = (double)sum[rr] + (double)cmp[rr];
+      for (int o = CL.P; o < 64; o <<= 1) mine += __shfl_xor(mine, o);
+      if (tv && lane < CL.P && r0 + rr < nrhs) D.fnear[(int64_t)i * nrhs + r0 + rr] = mine;
     }
   }
 }
