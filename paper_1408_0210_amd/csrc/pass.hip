@@ -543,7 +543,8 @@ __global__ __launch_bounds__(NT ? NT : 1024) void k_p2m(LeafDesc one,
 // f(x_i) = sum_{l'} K(x_i - c_I, y_{l'}^{I_0}) lhat_{l'}^I + f_near(x_i), written to
 // the input position of x_i (Algorithm 3, step 7).  One 64-lane workgroup per
 // chunk of up to 32 targets: lane l and lane l + 32 hold the same target and sum
-// the first and the second half of the d terms.
+// the first and the second half of the d terms (a chunk of fewer targets, with
+// one right-hand side, spreads each over more lanes: chunk_lanes).
 template <int KIND, int RB, bool BATCH>
 __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
                                             const LeafDesc *__restrict__ many,
@@ -562,19 +563,22 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
   const int dp = D.dpL, d = D.dL, nrhs = D.nrhs;
   const int64_t n = D.n;
   double *sX = sm, *sl = sm + 3 * dp;
-  const int lane = threadIdx.x, half = lane >> 5;
+  const int lane = threadIdx.x;
   const int j = chunk_leaf(D.chunk_ptr, D.nleaf, c);
   const uint32_t key = D.act[j];
-  const int b = D.ls[key + 1];
-  const int i = D.tb[key] + 32 * (c - D.chunk_ptr[j]) + (lane & 31);
+  // the chunk's lanes as in the near field: 64 / P lanes per target, each
+  // summing one of 64 / P equal ranges of the d terms (P = 32: two halves)
+  const ChunkLanes CL = chunk_lanes(D, j, c, lane, RB == 1);
+  const int i = CL.i;
   const double cx = D.lo0 + ((double)morton_axis(key, 0) + 0.5) * D.h;
   const double cy = D.lo1 + ((double)morton_axis(key, 1) + 0.5) * D.h;
   const double cz = D.lo2 + ((double)morton_axis(key, 2) + 0.5) * D.h;
   for (int e = lane; e < 3 * d; e += 64) sX[e] = D.XL[e];
-  const bool tv = i < b;
+  const bool tv = CL.tv;
   const double xc = tv ? D.xyz[i] - cx : 0.0, yc = tv ? D.xyz[n + i] - cy : 0.0,
                zc = tv ? D.xyz[2 * n + i] - cz : 0.0;
-  const int dh = (d + 1) >> 1, l0 = half * dh, l1 = min(d, l0 + dh);
+  const int ng = 64 / CL.P, grp = lane / CL.P;
+  const int dh = (d + ng - 1) / ng, l0 = grp * dh, l1 = min(d, l0 + dh);
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     __syncthreads();
     for (int e = lane; e < RB * d; e += 64) {
@@ -592,9 +596,11 @@ __global__ __launch_bounds__(64) void k_l2p(LeafDesc one, IoDesc ione,
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) acc[rr] += kv * sl[rr * dp + l];
     }
+    for (int o = CL.P; o < 64; o <<= 1) {
 #pragma unroll
-    for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], 32);
-    if (tv && half == 0) {
+      for (int rr = 0; rr < RB; ++rr) acc[rr] += __shfl_xor(acc[rr], o);
+    }
+    if (tv && lane < CL.P) {
       const int64_t o = D.perm[i] - D.toff;
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
