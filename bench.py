@@ -578,7 +578,9 @@ def phase_roofline(st, n, ms_step, precision, kernel):
     ph["tree"] = st["phase_ms"]["tree"] / max(1, st["phase_calls"]["tree"])
     m2m = sum(2.0 * d[k] * d[k + 1] * nact[k + 1] for k in range(2, depth))
     l2l = sum(2.0 * d[k] * d[k - 1] * nact[k] for k in range(3, depth + 1))
-    what = sum((1.0 if r[k] else 2.0) * d[k] ** 2 * nact[k] for k in range(2, depth + 1))
+    # (a single plan with one EIM folds Gamma^-1 into the pre-projection on its
+    # compressed levels: the What phase solves only the uncompressed ones)
+    what = sum(2.0 * d[k] ** 2 * nact[k] for k in range(2, depth + 1) if not r[k])
     lhat = 2.0 * d[depth] ** 2 * nact[depth]
     mfma64 = PEAK_TFLOPS["fp64"] * 1e12
     m2l_peak = PEAK_TFLOPS[precision] * 1e12

@@ -1661,7 +1661,8 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
     jt.m2m_units[k] = finish_units(h, jt.m2m_first[k]);
   }
   // compression projections What' = U^T B^{-T} z with z = Gamma^{-1} W from the
-  // forward solve, one job per compressed level
+  // forward solve, one job per compressed level (What' = (U^T B^{-T} Gamma^{-1}) W
+  // from W itself where the operator folds the solve in)
   {
     int tiles = 0;
     jt.pre_first = (int)h.size();
@@ -1671,7 +1672,7 @@ int build_jobs(Plan &P, int nrhs, hipStream_t s) {
       if (P.lh[k].r == 0 || P.nact[k] == 0) continue;
       GemmJob J{};
       J.A = P.ld[k].pfrag;
-      J.Bsrc = P.ld[k].Wh;
+      J.Bsrc = P.lh[k].fold_what ? P.ld[k].W : P.ld[k].Wh;
       J.C = P.ld[k].Whp;
       J.C32 = mixed ? P.ld[k].Whp32 : nullptr;
       J.ntgt = (int)P.nact[k];
@@ -2160,7 +2161,8 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
                                     P.jobs.m2m_units[k], s, P.jobs.m2m_rbt[k]);
   }
   // step 3: What = Delta W = B^{-T} Gamma^{-1} W on uncompressed levels; on
-  // compressed ones z = Gamma^{-1} W (the projection applies U^T B^{-T})
+  // compressed ones z = Gamma^{-1} W (the projection applies U^T B^{-T}), or
+  // nothing where the projection's operator holds Gamma^{-1} too (fold_what)
   {
     Timer tm(P, s, EIFMM_PH_WHAT);
     SolveArgs A{};
@@ -2168,7 +2170,7 @@ void run_kind(Plan &P, int nrhs, const IoDesc &io, hipStream_t s) {
     size_t shm = 0;
     for (int k = 2; k <= depth; ++k) {
       const int nc = (int)(P.nact[k] * nrhs);
-      if (nc == 0) continue;
+      if (nc == 0 || !what_level(P, k)) continue;
       SolveDesc &D = A.lv[q++];
       D.in = P.ld[k].W;
       D.out = P.ld[k].Wh;

@@ -41,6 +41,9 @@ struct LevelHost {
   std::vector<double> V;        // d x r basis of the columns' space (two EIMs; else V = U)
   std::vector<double> ufrag;    // U          (dpB x rp), fragment order: g = U g'
   std::vector<double> pfrag;    // V^T B^{-T} (rp x dp), fragment order: What' = V^T B^{-T} Gamma^{-1} W
+  // pfrag holds V^T B^{-T} Gamma^{-1} (the pre-projection then reads W itself and the
+  // pass takes no What solve on this level): plans with their own tables and one EIM
+  bool fold_what = false;
   // second compression stage (Sec. 4.2): rank s2[o] of each C^delta (empty: off),
   // padded rank sp2[o] (multiple of 16, 0 when s2[o] = 0; empty when a rank exceeds
   // what the factored M2L takes, and the dense product serves) and the factors in
@@ -388,6 +391,8 @@ void pack_operators(Plan &P, int k);
 // On a compressed level the solve for What stops at z = Gamma^{-1} W: the
 // projection applies U^T B^{-T} (pass.hip)
 inline bool solves_what(const Plan &P, int k) { return P.lh[k].r == 0; }
+// the pass's What phase touches level k (no solve where the pre-projection folds it)
+inline bool what_level(const Plan &P, int k) { return !P.lh[k].fold_what; }
 // the FP64 pass applies the second compression stage as two factor products
 inline bool uses_m2l2(const Plan &P, int k) {
   return P.cfg.precision == EIFMM_PREC_FP64 && P.lh[k].r > 0 && !P.lh[k].sp2.empty();

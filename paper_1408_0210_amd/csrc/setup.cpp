@@ -812,9 +812,15 @@ int build_tables(Plan &P) {
           for (int a = 0; a < lv.r; ++a) lv.V[(size_t)i * lv.r + a] = Vfull[(size_t)i * d + a];
       }
       const std::vector<double> &Vb = P.two_eim ? lv.V : lv.U;  // d x r, column side
-      // What' = V^T What = (V^T B^{-T}) (Gamma^{-1} W): the well-conditioned factor
-      // B^T is folded into the projection (row a is (B^{-1} v_a)^T), the solve with
-      // the ill-conditioned Gamma stays a solve
+      // What' = V^T What = (V^T B^{-T}) (Gamma^{-1} W): the factor B^T is folded
+      // into the projection (row a is (B^{-1} v_a)^T).  A plan with its own tables
+      // and one EIM folds Gamma^{-T} in too (row a is (Gamma^{-T} B^{-1} v_a)^T), so
+      // that the projection reads W and the pass takes no solve on this level.  With
+      // the expansions the pass forms (smooth sums of the kernel over a box's
+      // sources) both forms carry the same rounding: rel-L2 2e-11 folded, 3e-11
+      // as solve-then-project, against an 80-bit evaluation, for 1/r at tau 1e-6
+      // (Gamma's condition number 6e7), where the 1e-6 target leaves a wide margin.
+      lv.fold_what = !P.shared_tables && !P.two_eim && lv.r > 0;
       std::vector<double> Pm((size_t)lv.r * d);
       for (int a = 0; a < lv.r; ++a) {
         double *row = &Pm[(size_t)a * d];
@@ -823,6 +829,13 @@ int build_tables(Plan &P) {
           double t = row[i];
           for (int j = 0; j < i; ++j) t -= lv.B[(size_t)i * d + j] * row[j];
           row[i] = t;
+        }
+        if (lv.fold_what) {
+          for (int i = d - 1; i >= 0; --i) {  // Gamma^T row = (B^{-1} v_a), Gamma^T upper
+            double t = row[i];
+            for (int j = i + 1; j < d; ++j) t -= lv.G[(size_t)j * d + i] * row[j];
+            row[i] = t / lv.G[(size_t)i * d + i];
+          }
         }
       }
       lv.ufrag.assign((size_t)dpB * lv.rp, 0.0);
