@@ -210,14 +210,12 @@ class Plan:
     def set_points(self, xyz, targets=None):
         """xyz: CUDA float64 tensor of shape (3, n), contiguous (the sources); targets:
         (3, n_targets) for a plan with separate targets."""
-        assert xyz.is_cuda and xyz.dtype.is_floating_point and xyz.element_size() == 8
-        assert tuple(xyz.shape) == (3, self.n) and xyz.is_contiguous()
+        self.check_in(xyz, (3, self.n), "xyz")
         if targets is None:
             _check(lib().eifmm_set_points(self._h, ctypes.c_void_p(xyz.data_ptr()), _stream()),
                    "eifmm_set_points")
             return
-        assert targets.is_cuda and targets.element_size() == 8 and targets.is_contiguous()
-        assert tuple(targets.shape) == (3, self.n_targets)
+        self.check_in(targets, (3, self.n_targets), "targets")
         _check(lib().eifmm_set_points_targets(self._h, ctypes.c_void_p(xyz.data_ptr()),
                                               ctypes.c_void_p(targets.data_ptr()), _stream()),
                "eifmm_set_points_targets")
@@ -226,10 +224,7 @@ class Plan:
         """sigma: CUDA float64 tensor (n,) or (nrhs, n) (column-major n x nrhs).
         Returns f, (m,) or (nrhs, m) with m the target count, in input order."""
         import torch
-        assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
-        assert sigma.dim() in (1, 2)
-        nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
-        assert sigma.shape[-1] == self.n
+        nrhs = self.check_sigma(sigma, self.n)
         shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
         if out is None:
             out = torch.empty(shape, dtype=torch.float64, device=sigma.device)
@@ -244,16 +239,37 @@ class Plan:
     def evaluate_noalloc(self, sigma, out):
         """eifmm_evaluate_noalloc: as evaluate, into a caller-allocated `out`, with
         no device allocation inside the call."""
-        import torch
-        assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.is_contiguous()
-        assert sigma.dim() in (1, 2) and sigma.shape[-1] == self.n
-        nrhs = 1 if sigma.dim() == 1 else sigma.shape[0]
+        nrhs = self.check_sigma(sigma, self.n)
         shape = (self.n_out,) if sigma.dim() == 1 else (nrhs, self.n_out)
         self.check_out(out, shape, sigma.device)
         _check(lib().eifmm_evaluate_noalloc(self._h, ctypes.c_void_p(sigma.data_ptr()), nrhs,
                                             self.n, ctypes.c_void_p(out.data_ptr()), self.n_out,
                                             _stream()), "eifmm_evaluate_noalloc")
         return out
+
+    @staticmethod
+    def check_in(t, shape, name):
+        """A tensor the library reads (or, for a batch's outputs, writes): float64,
+        contiguous, of the expected shape, on a GPU (raises ValueError otherwise,
+        before any launch)."""
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+            raise ValueError(f"{name} must be a float64 tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on a GPU, not {t.device}")
+
+    @staticmethod
+    def check_sigma(sigma, n):
+        """Checks sigma, (n,) or (nrhs, n), as check_in does; returns nrhs."""
+        import torch
+        if not isinstance(sigma, torch.Tensor) or sigma.dim() not in (1, 2):
+            raise ValueError("sigma must be a tensor of shape (n,) or (nrhs, n)")
+        Plan.check_in(sigma, (n,) if sigma.dim() == 1 else (sigma.shape[0], n), "sigma")
+        return 1 if sigma.dim() == 1 else int(sigma.shape[0])
 
     @staticmethod
     def check_out(out, shape, device):
@@ -391,11 +407,11 @@ class Batch:
 
     @staticmethod
     def _ptrs(tensors, ns, shape):
-        assert len(tensors) == len(ns)
+        if len(tensors) != len(ns):
+            raise ValueError(f"{len(tensors)} tensors for {len(ns)} problems")
         a = (ctypes.c_void_p * len(ns))()
         for i, (t, n) in enumerate(zip(tensors, ns)):
-            assert t.is_cuda and t.element_size() == 8 and t.is_contiguous()
-            assert tuple(t.shape) == shape(n)
+            Plan.check_in(t, shape(n), f"tensor of problem {i}")
             a[i] = t.data_ptr() if n > 0 else None
         return a
 

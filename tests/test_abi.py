@@ -194,6 +194,32 @@ def test_host_ranks_match_oracle(E, oracle_lib):
     P.close()
 
 
+def test_inputs_checked(E):
+    """Points and densities the library would read through a wrong layout, or from
+    host memory, are refused on the host, before any launch."""
+    import torch
+    f64 = torch.float64
+    for bad, exc in ((torch.empty(3, 10, dtype=torch.float32), "float64"),
+                     (torch.empty(3, 10, dtype=torch.int64), "float64"),
+                     (torch.empty(10, 3, dtype=f64).t(), "contiguous"),
+                     (torch.empty(3, 9, dtype=f64), "shape"),
+                     (torch.empty(3, 10, dtype=f64), "GPU")):
+        with pytest.raises(ValueError, match=exc):
+            E.Plan.check_in(bad, (3, 10), "xyz")
+    for bad, exc in ((torch.empty(10, dtype=torch.float32), "float64"),
+                     (torch.empty(2, 3, 10, dtype=f64), "shape"),
+                     (torch.empty(2, 9, dtype=f64), "shape"),
+                     (torch.empty(10, 2, dtype=f64).t(), "contiguous"),
+                     (torch.empty(2, 10, dtype=f64), "GPU"),
+                     ([0.0] * 10, "tensor")):
+        with pytest.raises(ValueError, match=exc):
+            E.Plan.check_sigma(bad, 10)
+    with pytest.raises(ValueError, match="problems"):
+        E.Batch._ptrs([torch.empty(3, 4, dtype=f64)], [4, 5], lambda n: (3, n))
+    with pytest.raises(ValueError, match="problem 0"):
+        E.Batch._ptrs([torch.empty(3, 4, dtype=f64)], [4], lambda n: (3, n))
+
+
 def test_evaluate_out_checked(E):
     """An output tensor the library would write past or through a wrong layout is
     refused on the host, before any launch."""
