@@ -238,6 +238,7 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
   const int64_t nn = std::max<int64_t>(n, 1);
   P.ntiles_sort = (int)((nn + 1023) / 1024);
   TRY(dalloc(&P.xyz, 3 * nn, tr));
+  TRY(dalloc(&P.xyz4, 4 * nn, tr));
   TRY(dalloc(&P.keys, nn, tr));
   TRY(dalloc(&P.keys_tmp, nn, tr));
   TRY(dalloc(&P.idx, nn, tr));

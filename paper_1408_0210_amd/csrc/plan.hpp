@@ -267,6 +267,7 @@ struct Plan {
   int *tgt_begin = nullptr;     // separate targets: first target of each leaf [8^depth + 1]
   int ntiles_sort = 0;
   double *xyz = nullptr;        // sorted points, SoA 3 x n
+  double *xyz4 = nullptr;       // tree build staging: (x, y, z, 0) per point, input order [4 n]
   uint32_t *keys = nullptr, *keys_tmp = nullptr;
   int *idx = nullptr, *idx_tmp = nullptr;  // idx = perm after the sort
   unsigned *hist = nullptr;

@@ -22,18 +22,24 @@ namespace eifmm {
 
 // ---------------------------------------------------------------- keys
 // With separate targets (tbit = 1) the sort key is 2 * leaf key + (i >= tsplit),
-// so each leaf's sources precede its targets.
+// so each leaf's sources precede its targets.  Each point is also written as one
+// 32-byte record (x, y, z, 0) to x4, so that the gather into Morton order reads
+// one cache line per point instead of one per coordinate.
 __global__ void k_keys(int64_t n, const double *__restrict__ xyz, double lo0, double lo1,
                        double lo2, double L, double scale, int side, int64_t tsplit, int tbit,
                        uint32_t *__restrict__ keys, int *__restrict__ idx,
-                       int *__restrict__ err) {
+                       int *__restrict__ err, double *__restrict__ x4) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double lo[3] = {lo0, lo1, lo2};
+  const double xv[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+  double2 *rec = reinterpret_cast<double2 *>(x4 + 4 * i);
+  rec[0] = make_double2(xv[0], xv[1]);
+  rec[1] = make_double2(xv[2], 0.0);
   uint32_t c[3];
   bool bad = false;
   for (int a = 0; a < 3; ++a) {
-    double x = xyz[a * n + i];
+    double x = xv[a];
     // closed domain [lo, lo+L]; NaN and +-inf fail the comparison
     if (!(x >= lo[a] && x <= lo[a] + L)) {
       bad = true;
@@ -117,12 +123,16 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *__restrict
 }
 
 // ---------------------------------------------------------------- gather
-__global__ void k_gather_points(int64_t n, const double *__restrict__ xin,
+// xs (SoA 3 x n, Morton order) from the records k_keys wrote in input order
+__global__ void k_gather_points(int64_t n, const double *__restrict__ x4,
                                 const int *__restrict__ perm, double *__restrict__ xs) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const int i = perm[s];
-  for (int a = 0; a < 3; ++a) xs[a * n + s] = xin[a * n + i];
+  const double2 *rec = reinterpret_cast<const double2 *>(x4 + 4 * (int64_t)perm[s]);
+  const double2 a = rec[0], b = rec[1];
+  xs[s] = a.x;
+  xs[n + s] = a.y;
+  xs[2 * n + s] = b.x;
 }
 
 // ls[k] = first sorted position with key >= (k << shift) + add, k = 0..nleaf
@@ -588,10 +598,10 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz_in,
                        P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], P.cfg.L, scale, side, P.ns, tbit,
-                       P.keys, P.idx, P.errflag);
+                       P.keys, P.idx, P.errflag, P.xyz4);
     sort_points(P, s);
     hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       xyz_in, P.idx, P.xyz);
+                       P.xyz4, P.idx, P.xyz);
   }
   const int64_t nleaf = (int64_t)1 << (3 * depth);
   hipLaunchKernelGGL(k_leaf_start, dim3((unsigned)((nleaf + 1 + 255) / 256)), dim3(256), 0, s, n,
