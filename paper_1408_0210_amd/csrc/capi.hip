@@ -269,8 +269,10 @@ int setup_workspaces(eifmm_plan h, double *shared_ws) {
     TRY(dalloc(&P.blkcnt, blocks * 9, tr));
   }
   TRY(dalloc(&P.list_cnt, maxcap + 2, tr));
-  TRY(dalloc(&P.counts_dev, (size_t)16 * kMaxLevels, tr));
-  TRY(dalloc(&P.errflag, 1, tr));
+  // the counter block and, right after it, the tree's error flag (one clear and
+  // one copy to the host cover both)
+  TRY(dalloc(&P.counts_dev, (size_t)16 * kMaxLevels + 1, tr));
+  P.errflag = P.counts_dev + 16 * kMaxLevels;
   P.near_cap = (size_t)27 * P.ld[depth].cap;
   TRY(dalloc(&P.near_ptr, P.ld[depth].cap + 2, tr));
   TRY(dalloc(&P.near_src, P.near_cap, tr));

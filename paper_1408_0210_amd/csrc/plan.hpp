@@ -276,7 +276,7 @@ struct Plan {
   int *blkcnt = nullptr;         // per-block counts of the active-box compaction
   int *list_cnt = nullptr;       // per-box entry counts of a list build
   int *counts_dev = nullptr;    // small counter block
-  int *errflag = nullptr;
+  int *errflag = nullptr;       // counts_dev + 16 kMaxLevels
   int *counts_pin = nullptr;    // pinned host copy of counts_dev and errflag
   int *near_ptr = nullptr;      // leaf level near lists (CSR over active slots)
   int *near_src = nullptr;      // source leaf slots

@@ -593,8 +593,8 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   const double scale = std::ldexp(1.0, depth) / P.cfg.L;
   const int tbit = P.nt ? 1 : 0;
   const int *tb = tbit ? P.tgt_begin : P.leaf_start;
-  hipMemsetAsync(P.errflag, 0, sizeof(int), s);
-  hipMemsetAsync(P.counts_dev, 0, sizeof(int) * 16 * kMaxLevels, s);
+  // the counter block and the error flag after it
+  hipMemsetAsync(P.counts_dev, 0, sizeof(int) * (16 * kMaxLevels + 1), s);
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz_in,
                        P.cfg.lo[0], P.cfg.lo[1], P.cfg.lo[2], P.cfg.L, scale, side, P.ns, tbit,
@@ -615,9 +615,8 @@ int tree_build(Plan &P, const double *xyz_in, hipStream_t s) {
   // copy only, while the order, the near lists and the chunks below (which read
   // the counts on the device) run
   int *host_counts = P.counts_pin;
-  hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * 16 * kMaxLevels, hipMemcpyDeviceToHost,
-                 s);
-  hipMemcpyAsync(host_counts + 16 * kMaxLevels, P.errflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(host_counts, P.counts_dev, sizeof(int) * (16 * kMaxLevels + 1),
+                 hipMemcpyDeviceToHost, s);
   hipEventRecord(P.ev_counts, s);
   // M2L target order of the levels that keep one
   {
